@@ -1,0 +1,163 @@
+/*
+ * lqr_kkt.h -- C ABI of the MI355X (gfx950) LQR-KKT solver.
+ *
+ * The library solves, for a batch of independent instances, the
+ * equality-constrained linear-quadratic subproblem that each primal-dual
+ * iLQR / SQP iteration produces (Amatucci, Sousa-Pinto et al., arXiv
+ * 2506.07823, Sec. II-B, eq. (QP)):
+ *
+ *   min  sum_{k<N} 1/2 x_k'Q_k x_k + 1/2 u_k'R_k u_k + x_k'M_k u_k + q_k'x_k + r_k'u_k
+ *        + 1/2 x_N'Q_N x_N + q_N'x_N
+ *   s.t. x_0 = x0,   x_{k+1} = A_k x_k + B_k u_k + c_k   (k = 0..N-1)
+ *
+ * and returns the primal solution (x, u) and the costates lam of the
+ * Lagrangian of Sec. II-B (lam_0 multiplies x0 - x_0, lam_{k+1} multiplies
+ * A_k x_k + B_k u_k + c_k - x_{k+1}), so that lam_k = P_k x_k + p_k with the
+ * value function (P_k, p_k) of Sec. II-C.  M_k is the transpose of the paper's
+ * cross-Hessian block S_k; c_k is the paper's affine dynamics term b_k; the
+ * paper's stages i = 0..N with terminal N+1 are this ABI's k = 0..N-1 with
+ * terminal N.
+ *
+ * Method (LQR_METHOD_SCAN): the value function is obtained by a reverse
+ * parallel associative scan over conditional value functions (Sec. II-D,
+ * eqs. (initialization) and (combination_rule)), the policy K_k, k_k in
+ * parallel over stages (eq. (lqr)), the states by a parallel scan of the
+ * closed-loop affine maps (eq. (controlled_dynamics)) and the costates by
+ * lam_k = P_k x_k + p_k.  Depth is O(log N) combine levels instead of the N
+ * dependent steps of the Riccati sweep.  LQR_METHOD_SEQ_RICCATI runs the
+ * sequential Riccati recursion of Sec. II-C (one wavefront per instance); it
+ * is the comparison baseline.
+ *
+ * Layout: every array is contiguous, row-major and batch-major, of the
+ * dtype selected in lqr_opts (all arrays share it):
+ *   A [batch][N][n][n]    B [batch][N][n][m]    c [batch][N][n]
+ *   Q [batch][N+1][n][n]  R [batch][N][m][m]    M [batch][N][n][m]
+ *   q [batch][N+1][n]     r [batch][N][m]       x0 [batch][n]
+ *   x [batch][N+1][n]     u [batch][N][m]       lam [batch][N+1][n]
+ *   status [batch] (int32)
+ * Pointers must be device pointers (or pointers the device can access),
+ * aligned to the element size.  Inputs are read-only; outputs may not alias
+ * inputs or each other.
+ *
+ * Ownership: the caller allocates every input, output, status and the
+ * workspace; the library never allocates or frees memory on the solve path.
+ * A handle owns only its launch plans.  Calls are asynchronous on `stream`
+ * (a hipStream_t; NULL selects the default stream): results are valid once
+ * the stream has been synchronized.  A handle may be used by one host thread
+ * at a time; concurrent solves on different streams need separate workspaces.
+ *
+ * Preconditions (documented, not silently regularized): R_k > 0, the stage
+ * Schur complement Q_k - M_k R_k^{-1} M_k' >= 0 (> 0 for the scan's
+ * Cholesky of the value function), Q_N > 0.  Then the KKT matrix is
+ * nonsingular and every scan value matrix is positive definite.
+ *
+ * Errors: functions return LQR_OK (0) or a negative code; nothing is launched
+ * when argument checking fails.  Per-instance numerical problems are
+ * reported in `status` (bit flags below) and make lqr_kkt_solve return
+ * LQR_OK: the status array is written on the device, so the host learns of
+ * them only after synchronizing and reading it.
+ */
+#ifndef LQR_KKT_H
+#define LQR_KKT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define LQR_OK 0
+#define LQR_EINVAL (-1)   /* bad size, null or misaligned pointer, bad option */
+#define LQR_ENOMEM (-2)   /* workspace smaller than lqr_workspace_size reports */
+#define LQR_EDEVICE (-4)  /* a HIP runtime call failed (see lqr_last_error) */
+#define LQR_EUNSUPPORTED (-5) /* shape class not built into this library */
+
+/* per-instance status bits (OR-ed) */
+#define LQR_ST_NONFINITE 1    /* a non-finite value reached the output */
+#define LQR_ST_NOT_SPD 2      /* R_k or G_k = R_k + B_k'P_{k+1}B_k not positive definite, even in FP64 */
+#define LQR_ST_P_NOT_SPD 4    /* a scan value matrix lost positive definiteness */
+#define LQR_ST_FP64_FALLBACK 8 /* an R_k / G_k factorization was redone in FP64 (informational) */
+
+typedef enum { LQR_F32 = 0, LQR_F64 = 1 } lqr_dtype;
+typedef enum { LQR_METHOD_SCAN = 0, LQR_METHOD_SEQ_RICCATI = 1 } lqr_method;
+
+typedef struct lqr_handle_s* lqr_handle_t;
+
+typedef struct {
+    int32_t dtype;          /* lqr_dtype of every array */
+    int32_t method;         /* lqr_method */
+    int32_t refine_sweeps;  /* 0 or 1 iterative-refinement sweeps: FP64 KKT residual, FP32/FP64
+                               correction re-solve with the factors of the first solve. Default:
+                               1 for LQR_F32 scan, 0 otherwise. */
+    int32_t fallback;       /* 1 (default): redo ill-conditioned R_k / G_k factorizations in FP64 */
+    double cond_threshold;  /* condition estimate above which the FP64 fallback fires (default 1e6) */
+    double* resid_out;      /* optional device [batch] FP64: relative KKT residual of the returned
+                               solution, ||r(x,u,lam)||_2 / ||(x0, c, q, r)||_2; NULL to skip */
+} lqr_opts;
+
+/* Fill *o with the defaults for `dtype` (scan method, refinement as above). */
+void lqr_opts_default(lqr_opts* o, int32_t dtype);
+
+/* Create a handle bound to HIP device `device`.  Returns LQR_OK,
+ * LQR_EINVAL (null h, bad device) or LQR_EDEVICE. */
+int lqr_create(lqr_handle_t* h, int device);
+
+/* Destroy a handle (NULL is accepted). */
+int lqr_destroy(lqr_handle_t h);
+
+/* Bytes of device workspace lqr_kkt_solve needs for this problem shape;
+ * opts may be NULL (defaults for LQR_F32).  A pure size computation: h may
+ * be NULL and no device is touched. */
+int lqr_workspace_size(lqr_handle_t h, int64_t batch, int N, int n, int m,
+                       const lqr_opts* opts, size_t* bytes);
+
+/* Solve `batch` independent instances (see the top of this file for the
+ * problem, layout, ownership and error behaviour).  `workspace` is a device
+ * buffer of at least lqr_workspace_size bytes, 256-byte aligned; its
+ * contents need not be initialized and are clobbered.  `status` (device,
+ * [batch]) receives the per-instance bit flags. */
+int lqr_kkt_solve(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int m,
+                  const void* A, const void* B, const void* c, const void* Q,
+                  const void* R, const void* M, const void* q, const void* r,
+                  const void* x0, void* x, void* u, void* lam, int32_t* status,
+                  void* workspace, size_t workspace_bytes, const lqr_opts* opts);
+
+/* FP64 KKT residual of a given solution (x, u, lam) of the problem above:
+ * writes rel[b] = ||r||_2 / ||(x0, c, q, r)||_2 per instance (device FP64
+ * array).  The residual blocks are the stationarity conditions of the
+ * Lagrangian of Sec. II-B plus the initial-condition and dynamics
+ * constraints.  Uses `workspace` of lqr_workspace_size bytes. */
+int lqr_kkt_residual(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int m,
+                     int32_t dtype, const void* A, const void* B, const void* c,
+                     const void* Q, const void* R, const void* M, const void* q,
+                     const void* r, const void* x0, const void* x, const void* u,
+                     const void* lam, double* rel, void* workspace,
+                     size_t workspace_bytes);
+
+/* Diagnostics: while enabled, every kernel launch of lqr_kkt_solve /
+ * lqr_kkt_residual on this handle is bracketed by two HIP events recorded on
+ * the call's stream (adds two event records per launch).  Not for use under
+ * stream capture. */
+int lqr_timing_enable(lqr_handle_t h, int enable);
+
+/* Waits for the recorded events and writes one text line per kernel family,
+ * "name launches total_ms algorithmic_flops algorithmic_bytes", into buf
+ * (NUL-terminated, at most len bytes), then forgets them.  The flops and
+ * bytes are the algorithmic work of those launches (what the method must
+ * compute and move, not what the padded tiles execute).  Returns
+ * LQR_ENOMEM if buf is too small. */
+int lqr_timing_report(lqr_handle_t h, char* buf, size_t len);
+
+/* Largest n, m supported by the built shape classes (n, m <= this). */
+int lqr_max_dim(void);
+
+/* Message describing the last error returned on this host thread. */
+const char* lqr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LQR_KKT_H */

@@ -1,0 +1,251 @@
+"""MI355X (gfx950) LQR-KKT solver: thin Python binding of liblqr_kkt.so.
+
+The solver is the C-ABI library declared in ``include/lqr_kkt.h`` (HIP
+kernels in ``csrc/``).  This module only marshals torch tensors (device
+memory) and the current torch stream into those calls; every step of the
+solve runs in the library's kernels.  There is no CPU fallback: importing
+this package raises if the built library is missing.
+
+Functions with the C names (``lqr_create``, ``lqr_workspace_size``,
+``lqr_kkt_solve``, ``lqr_kkt_residual``, ...) are exposed as-is; ``solve``
+and ``kkt_residual`` wrap them for tensors with a leading batch axis:
+
+    A [B][N][n][n]  B [B][N][n][m]  c [B][N][n]  Q [B][N+1][n][n]  R [B][N][m][m]
+    M [B][N][n][m]  q [B][N+1][n]   r [B][N][m]  x0 [B][n]
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch  # loads the HIP runtime the library links against (must come first)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblqr_kkt.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "lqr_kkt.h")
+
+LQR_OK, LQR_EINVAL, LQR_ENOMEM, LQR_EDEVICE, LQR_EUNSUPPORTED = 0, -1, -2, -4, -5
+LQR_F32, LQR_F64 = 0, 1
+LQR_METHOD_SCAN, LQR_METHOD_SEQ_RICCATI = 0, 1
+ST_NONFINITE, ST_NOT_SPD, ST_P_NOT_SPD, ST_FP64_FALLBACK = 1, 2, 4, 8
+
+
+class lqr_opts(ctypes.Structure):
+    _fields_ = [
+        ("dtype", ctypes.c_int32),
+        ("method", ctypes.c_int32),
+        ("refine_sweeps", ctypes.c_int32),
+        ("fallback", ctypes.c_int32),
+        ("cond_threshold", ctypes.c_double),
+        ("resid_out", ctypes.c_void_p),
+    ]
+
+
+class LqrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"lqr error {code}: {msg}")
+        self.code = code
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python paper_2506_07823_amd/build.py`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_vp, _i32, _i64, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+_lib.lqr_opts_default.argtypes = [ctypes.POINTER(lqr_opts), _i32]
+_lib.lqr_opts_default.restype = None
+_lib.lqr_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int]
+_lib.lqr_create.restype = ctypes.c_int
+_lib.lqr_destroy.argtypes = [_vp]
+_lib.lqr_destroy.restype = ctypes.c_int
+_lib.lqr_workspace_size.argtypes = [_vp, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                    ctypes.POINTER(lqr_opts), ctypes.POINTER(_sz)]
+_lib.lqr_workspace_size.restype = ctypes.c_int
+_lib.lqr_kkt_solve.argtypes = [_vp, _vp, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int] + [_vp] * 9 + \
+    [_vp, _vp, _vp, _vp, _vp, _sz, ctypes.POINTER(lqr_opts)]
+_lib.lqr_kkt_solve.restype = ctypes.c_int
+_lib.lqr_kkt_residual.argtypes = [_vp, _vp, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, _i32] + \
+    [_vp] * 9 + [_vp] * 3 + [_vp, _vp, _sz]
+_lib.lqr_kkt_residual.restype = ctypes.c_int
+_lib.lqr_max_dim.argtypes = []
+_lib.lqr_max_dim.restype = ctypes.c_int
+_lib.lqr_last_error.argtypes = []
+_lib.lqr_last_error.restype = ctypes.c_char_p
+_lib.lqr_timing_enable.argtypes = [_vp, ctypes.c_int]
+_lib.lqr_timing_enable.restype = ctypes.c_int
+_lib.lqr_timing_report.argtypes = [_vp, ctypes.c_char_p, _sz]
+_lib.lqr_timing_report.restype = ctypes.c_int
+
+# the C entry points under their own names
+lqr_opts_default = _lib.lqr_opts_default
+lqr_create = _lib.lqr_create
+lqr_destroy = _lib.lqr_destroy
+lqr_workspace_size = _lib.lqr_workspace_size
+lqr_kkt_solve = _lib.lqr_kkt_solve
+lqr_kkt_residual = _lib.lqr_kkt_residual
+lqr_max_dim = _lib.lqr_max_dim
+lqr_last_error = _lib.lqr_last_error
+lqr_timing_enable = _lib.lqr_timing_enable
+lqr_timing_report = _lib.lqr_timing_report
+
+FIELDS = ("A", "B", "c", "Q", "R", "M", "q", "r", "x0")
+
+
+def _check(rc):
+    if rc != LQR_OK:
+        raise LqrError(rc, (_lib.lqr_last_error() or b"").decode())
+
+
+def default_opts(dtype=torch.float32) -> lqr_opts:
+    o = lqr_opts()
+    _lib.lqr_opts_default(ctypes.byref(o), LQR_F32 if dtype == torch.float32 else LQR_F64)
+    return o
+
+
+_handles = {}
+_hlock = threading.Lock()
+
+
+def handle(device: int = 0):
+    with _hlock:
+        h = _handles.get(device)
+        if h is None:
+            hp = _vp()
+            _check(_lib.lqr_create(ctypes.byref(hp), int(device)))
+            h = _handles[device] = hp
+    return h
+
+
+def workspace_bytes(batch, N, n, m, opts=None) -> int:
+    out = _sz()
+    _check(_lib.lqr_workspace_size(handle(torch.cuda.current_device()), batch, N, n, m,
+                                   ctypes.byref(opts or default_opts()), ctypes.byref(out)))
+    return out.value
+
+
+def dims_of(A, B):
+    """(batch, N, n, m) from A [B][N][n][n] and B [B][N][n][m]."""
+    batch, N, n, _ = A.shape
+    return batch, N, n, B.shape[-1]
+
+
+def _validate(tensors, dtype, device):
+    for name, t in tensors.items():
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor")
+        if t.device.type != "cuda" or t.device.index != device:
+            raise ValueError(f"{name} must live on cuda:{device}")
+        if t.dtype != dtype:
+            raise TypeError(f"{name} has dtype {t.dtype}, expected {dtype}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+
+
+def _expect_shapes(d, batch, N, n, m):
+    want = {"A": (batch, N, n, n), "B": (batch, N, n, m), "c": (batch, N, n), "Q": (batch, N + 1, n, n),
+            "R": (batch, N, m, m), "M": (batch, N, n, m), "q": (batch, N + 1, n), "r": (batch, N, m),
+            "x0": (batch, n)}
+    for k, s in want.items():
+        if tuple(d[k].shape) != s:
+            raise ValueError(f"{k} has shape {tuple(d[k].shape)}, expected {s}")
+
+
+class Workspace:
+    """Caller-owned device workspace (grown on demand, reused across calls)."""
+
+    def __init__(self, device=None):
+        self.device = torch.cuda.current_device() if device is None else device
+        self.buf = None
+
+    def get(self, nbytes: int) -> torch.Tensor:
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=f"cuda:{self.device}")
+        return self.buf
+
+
+_default_ws = {}
+
+
+def solve(A, B, c, Q, R, M, q, r, x0, *, method: str = "scan", refine: int | None = None,
+          fallback: bool = True, cond_threshold: float = 1e6, want_resid: bool = False,
+          workspace: Workspace | None = None, out=None, stream=None):
+    """Batched LQR-KKT solve; returns dict x, u, lam, status (+ resid).
+
+    All tensors are device tensors of one dtype (float32 or float64) with a
+    leading batch axis; the call is asynchronous on ``stream`` (default: the
+    current torch stream)."""
+    d = dict(A=A, B=B, c=c, Q=Q, R=R, M=M, q=q, r=r, x0=x0)
+    dtype = A.dtype
+    device = A.device.index
+    batch, N, n, m = dims_of(A, B)
+    _validate(d, dtype, device)
+    _expect_shapes(d, batch, N, n, m)
+    o = default_opts(dtype)
+    o.method = LQR_METHOD_SCAN if method == "scan" else LQR_METHOD_SEQ_RICCATI
+    if refine is not None:
+        o.refine_sweeps = int(refine)
+    o.fallback = 1 if fallback else 0
+    o.cond_threshold = float(cond_threshold)
+    if out is None:
+        out = {
+            "x": torch.empty((batch, N + 1, n), dtype=dtype, device=A.device),
+            "u": torch.empty((batch, N, m), dtype=dtype, device=A.device),
+            "lam": torch.empty((batch, N + 1, n), dtype=dtype, device=A.device),
+            "status": torch.empty((batch,), dtype=torch.int32, device=A.device),
+        }
+    if want_resid:
+        if "resid" not in out:
+            out["resid"] = torch.empty((batch,), dtype=torch.float64, device=A.device)
+        o.resid_out = out["resid"].data_ptr()
+    h = handle(device)
+    nbytes = _sz()
+    _check(_lib.lqr_workspace_size(h, batch, N, n, m, ctypes.byref(o), ctypes.byref(nbytes)))
+    if workspace is None:
+        workspace = _default_ws.setdefault(device, Workspace(device))
+    wbuf = workspace.get(nbytes.value)
+    s = (stream or torch.cuda.current_stream(device)).cuda_stream
+    rc = _lib.lqr_kkt_solve(h, s, batch, N, n, m, *[d[k].data_ptr() for k in FIELDS],
+                            out["x"].data_ptr(), out["u"].data_ptr(), out["lam"].data_ptr(),
+                            out["status"].data_ptr(), wbuf.data_ptr(), wbuf.numel(), ctypes.byref(o))
+    _check(rc)
+    return out
+
+
+def kkt_residual(A, B, c, Q, R, M, q, r, x0, x, u, lam, *, workspace=None, stream=None):
+    """FP64 relative KKT residual per instance of a given (x, u, lam)."""
+    d = dict(A=A, B=B, c=c, Q=Q, R=R, M=M, q=q, r=r, x0=x0, x=x, u=u, lam=lam)
+    dtype = A.dtype
+    device = A.device.index
+    batch, N, n, m = dims_of(A, B)
+    _validate(d, dtype, device)
+    rel = torch.empty((batch,), dtype=torch.float64, device=A.device)
+    h = handle(device)
+    o = default_opts(dtype)
+    nbytes = _sz()
+    _check(_lib.lqr_workspace_size(h, batch, N, n, m, ctypes.byref(o), ctypes.byref(nbytes)))
+    if workspace is None:
+        workspace = _default_ws.setdefault(device, Workspace(device))
+    wbuf = workspace.get(nbytes.value)
+    s = (stream or torch.cuda.current_stream(device)).cuda_stream
+    _check(_lib.lqr_kkt_residual(h, s, batch, N, n, m, LQR_F32 if dtype == torch.float32 else LQR_F64,
+                                 *[d[k].data_ptr() for k in FIELDS + ("x", "u", "lam")],
+                                 rel.data_ptr(), wbuf.data_ptr(), wbuf.numel()))
+    return rel
+
+
+def kernel_timing(enable: bool, device: int = 0):
+    """Turn per-launch event timing of this device's handle on or off."""
+    _check(_lib.lqr_timing_enable(handle(device), 1 if enable else 0))
+
+
+def kernel_report(device: int = 0) -> dict:
+    """Per kernel family: launches, total ms, algorithmic flops and bytes of
+    the launches timed since the last report (waits for them)."""
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(_lib.lqr_timing_report(handle(device), buf, len(buf)))
+    fams = {}
+    for line in buf.value.decode().strip().splitlines():
+        name, launches, ms, fl, by = line.split()
+        fams[name] = dict(launches=int(launches), ms=float(ms), flops=float(fl), bytes=float(by))
+    return fams

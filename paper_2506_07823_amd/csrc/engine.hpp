@@ -1,0 +1,327 @@
+// engine.hpp -- wavefront-level dense linear algebra on small blocks (gfx950).
+//
+// One *group* of G x G lanes of a 64-wide wavefront owns one task (one scan
+// combine, one stage, ...).  A G=8 group is a whole wavefront; G=4 packs four
+// independent tasks into one wavefront.  Working matrices of padded order
+// NP = G*TS live in registers as TS x TS tiles: lane (ty, tx) owns the
+// entries (ty + G*a, tx + G*b), a, b < TS.  Matrices that other lanes must
+// read (the right-hand operands of a product, triangular factors) are staged
+// in the group's LDS slots with an odd leading dimension LD = NP + 1, so
+// that the strided row/column reads of one k-step fall into distinct banks.
+// Every matrix keeps zeros outside its logical size, which lets products run
+// over the padded tile without masks.
+//
+// Vectors use the "lane vector" layout: lane lg (0 <= lg < G*G) of the group
+// holds element lg (NP <= G*G is required).
+//
+// Sequential chains (Cholesky, triangular solves) run right-looking: at step
+// k the owners of column (row) k publish it through a small LDS buffer and
+// every lane updates its own tile entries, so the chain costs one
+// workgroup barrier per step and the update work is spread over all lanes.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lqr {
+
+template <typename T> __device__ __forceinline__ T dsqrt(T x);
+template <> __device__ __forceinline__ float dsqrt<float>(float x) { return __builtin_sqrtf(x); }
+template <> __device__ __forceinline__ double dsqrt<double>(double x) { return __builtin_sqrt(x); }
+
+__device__ __forceinline__ void wg_sync() { __syncthreads(); }
+
+template <typename T_, int G_, int TS_>
+struct Eng {
+    using T = T_;
+    static constexpr int G = G_;
+    static constexpr int TS = TS_;
+    static constexpr int NP = G * TS;        // padded order
+    static constexpr int LD = NP + 1;        // LDS leading dimension
+    static constexpr int MAT = NP * LD;      // LDS elements per matrix slot
+    static constexpr int GL = G * G;         // lanes per group
+    static_assert(NP <= GL, "lane-vector layout needs NP <= G*G");
+    static_assert(64 % GL == 0, "groups must tile a wavefront");
+
+    int lg, ty, tx;
+    __device__ explicit Eng(int lane_in_group)
+        : lg(lane_in_group), ty(lane_in_group / G), tx(lane_in_group % G) {}
+
+    __device__ __forceinline__ int row(int a) const { return ty + G * a; }
+    __device__ __forceinline__ int col(int b) const { return tx + G * b; }
+
+    using Tile = T[TS][TS];
+
+    // ---------------------------------------------------------------- tiles
+    __device__ __forceinline__ static void zero(Tile& t) {
+#pragma unroll
+        for (int a = 0; a < TS; ++a)
+#pragma unroll
+            for (int b = 0; b < TS; ++b) t[a][b] = T(0);
+    }
+
+    // t = G[rows x cols] (row-major, leading dim ldg), or its transpose when
+    // TR (then G is cols x rows and t = G'); zero outside.
+    template <bool TR = false, typename S>
+    __device__ __forceinline__ void load(Tile& t, const S* g, int rows, int cols, int ldg) const {
+#pragma unroll
+        for (int a = 0; a < TS; ++a)
+#pragma unroll
+            for (int b = 0; b < TS; ++b) {
+                const int i = row(a), j = col(b);
+                T v = T(0);
+                if (i < rows && j < cols) v = T(TR ? g[(int64_t)j * ldg + i] : g[(int64_t)i * ldg + j]);
+                t[a][b] = v;
+            }
+    }
+
+    // t += G (same conventions)
+    template <bool TR = false, typename S>
+    __device__ __forceinline__ void add_global(Tile& t, const S* g, int rows, int cols, int ldg, T scale = T(1)) const {
+#pragma unroll
+        for (int a = 0; a < TS; ++a)
+#pragma unroll
+            for (int b = 0; b < TS; ++b) {
+                const int i = row(a), j = col(b);
+                if (i < rows && j < cols)
+                    t[a][b] += scale * T(TR ? g[(int64_t)j * ldg + i] : g[(int64_t)i * ldg + j]);
+            }
+    }
+
+    template <typename S>
+    __device__ __forceinline__ void store(const Tile& t, S* g, int rows, int cols, int ldg) const {
+#pragma unroll
+        for (int a = 0; a < TS; ++a)
+#pragma unroll
+            for (int b = 0; b < TS; ++b) {
+                const int i = row(a), j = col(b);
+                if (i < rows && j < cols) g[(int64_t)i * ldg + j] = S(t[a][b]);
+            }
+    }
+
+    // store the lower triangle of t mirrored into both triangles of g (n x n):
+    // the output is exactly symmetric.
+    template <typename S>
+    __device__ __forceinline__ void store_sym(const Tile& t, S* g, int n) const {
+#pragma unroll
+        for (int a = 0; a < TS; ++a)
+#pragma unroll
+            for (int b = 0; b < TS; ++b) {
+                const int i = row(a), j = col(b);
+                if (i < n && j <= i) {
+                    g[(int64_t)i * n + j] = S(t[a][b]);
+                    if (j < i) g[(int64_t)j * n + i] = S(t[a][b]);
+                }
+            }
+    }
+
+    __device__ __forceinline__ void to_lds(const Tile& t, T* s) const {
+#pragma unroll
+        for (int a = 0; a < TS; ++a)
+#pragma unroll
+            for (int b = 0; b < TS; ++b) s[row(a) * LD + col(b)] = t[a][b];
+    }
+
+    __device__ __forceinline__ void from_lds(Tile& t, const T* s) const {
+#pragma unroll
+        for (int a = 0; a < TS; ++a)
+#pragma unroll
+            for (int b = 0; b < TS; ++b) t[a][b] = s[row(a) * LD + col(b)];
+    }
+
+    __device__ __forceinline__ void add_identity(Tile& t, int n, T s = T(1)) const {
+#pragma unroll
+        for (int a = 0; a < TS; ++a)
+#pragma unroll
+            for (int b = 0; b < TS; ++b)
+                if (row(a) == col(b) && row(a) < n) t[a][b] += s;
+    }
+
+    // acc (+)= op(X) op(Y) over k < K, X and Y in LDS slots.
+    // op(X)(i,k) = TX ? X[k][i] : X[i][k];  op(Y)(k,j) = TY ? Y[j][k] : Y[k][j].
+    template <bool TX, bool TY>
+    __device__ __forceinline__ void gemm(Tile& acc, const T* X, const T* Y, int K) const {
+#pragma unroll 2
+        for (int k = 0; k < K; ++k) {
+            T xa[TS], yb[TS];
+#pragma unroll
+            for (int a = 0; a < TS; ++a) xa[a] = TX ? X[k * LD + row(a)] : X[row(a) * LD + k];
+#pragma unroll
+            for (int b = 0; b < TS; ++b) yb[b] = TY ? Y[col(b) * LD + k] : Y[k * LD + col(b)];
+#pragma unroll
+            for (int a = 0; a < TS; ++a)
+#pragma unroll
+                for (int b = 0; b < TS; ++b) acc[a][b] = __builtin_fma(xa[a], yb[b], acc[a][b]);
+        }
+    }
+
+    template <bool TX, bool TY>
+    __device__ __forceinline__ void gemm_sub(Tile& acc, const T* X, const T* Y, int K) const {
+#pragma unroll 2
+        for (int k = 0; k < K; ++k) {
+            T xa[TS], yb[TS];
+#pragma unroll
+            for (int a = 0; a < TS; ++a) xa[a] = TX ? X[k * LD + row(a)] : X[row(a) * LD + k];
+#pragma unroll
+            for (int b = 0; b < TS; ++b) yb[b] = TY ? Y[col(b) * LD + k] : Y[k * LD + col(b)];
+#pragma unroll
+            for (int a = 0; a < TS; ++a)
+#pragma unroll
+                for (int b = 0; b < TS; ++b) acc[a][b] = __builtin_fma(-xa[a], yb[b], acc[a][b]);
+        }
+    }
+
+    // ------------------------------------------------------- lane vectors
+    template <typename S>
+    __device__ __forceinline__ T vload(const S* g, int n) const { return lg < n ? T(g[lg]) : T(0); }
+    template <typename S>
+    __device__ __forceinline__ void vstore(S* g, int n, T v) const { if (lg < n) g[lg] = S(v); }
+
+    // y = op(X) v over k < K for rows < rows (X in LDS; v staged through vb).
+    // Callers must barrier between successive uses of the same vb.
+    template <bool TX>
+    __device__ __forceinline__ T matvec(const T* X, T v, T* vb, int K, int rows) const {
+        if (lg < NP) vb[lg] = v;
+        wg_sync();
+        T s = T(0);
+        if (lg < rows) {
+            for (int k = 0; k < K; ++k)
+                s = __builtin_fma(TX ? X[k * LD + lg] : X[lg * LD + k], vb[k], s);
+        }
+        return s;
+    }
+
+    // --------------------------------------------------------- Cholesky
+    // In-register right-looking Cholesky of the n x n SPD matrix held in S
+    // (lower triangle used).  On return S holds L (lower, zero above), dinv
+    // (LDS, >= n) holds 1/L_kk.  NV lane vectors in gv are forward-solved
+    // with L on the way (gv <- L^{-1} gv).  cb is an LDS scratch of
+    // 2*(NP+NV) elements.  Returns false if a pivot is not positive (the
+    // factorization continues with a unit pivot so values stay finite).
+    // dmin/dmax receive the extreme diagonal entries of L.
+    template <int NV>
+    __device__ bool chol(Tile& S, int n, T* cb, T* dinv, T (&gv)[NV > 0 ? NV : 1], T& dmin, T& dmax) const {
+        bool ok = true;
+        dmin = T(0);
+        dmax = T(0);
+        bool first = true;
+#pragma unroll
+        for (int a0 = 0; a0 < TS; ++a0) {
+            for (int t = 0; t < G; ++t) {
+                const int k = G * a0 + t;
+                if (k >= n) break;
+                T* c = cb + (k & 1) * (NP + (NV > 0 ? NV : 1));
+                if (tx == t) {
+#pragma unroll
+                    for (int a = 0; a < TS; ++a) c[row(a)] = S[a][a0];
+                }
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+                    if (lg == k) c[NP + v] = gv[v];
+                wg_sync();
+                T d = c[k];
+                const bool good = d > T(0);
+                ok = ok && good;
+                if (!good) d = T(1);
+                const T s = dsqrt(d);
+                const T inv = T(1) / s;
+                if (first) { dmin = s; dmax = s; first = false; }
+                dmin = s < dmin ? s : dmin;
+                dmax = s > dmax ? s : dmax;
+                T li[TS], lj[TS];
+#pragma unroll
+                for (int a = 0; a < TS; ++a) li[a] = c[row(a)] * inv;
+#pragma unroll
+                for (int b = 0; b < TS; ++b) lj[b] = c[col(b)] * inv;
+#pragma unroll
+                for (int a = 0; a < TS; ++a)
+#pragma unroll
+                    for (int b = 0; b < TS; ++b)
+                        if (row(a) > k && col(b) > k) S[a][b] = __builtin_fma(-li[a], lj[b], S[a][b]);
+                if (tx == t) {
+#pragma unroll
+                    for (int a = 0; a < TS; ++a)
+                        S[a][a0] = row(a) > k ? li[a] : (row(a) == k ? s : T(0));
+                }
+                if (ty == t) {
+#pragma unroll
+                    for (int b = 0; b < TS; ++b)
+                        if (col(b) > k) S[a0][b] = T(0);
+                }
+                if (lg == 0) dinv[k] = inv;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    const T gk = c[NP + v] * inv;
+                    if (lg == k) gv[v] = gk;
+                    else if (lg > k && lg < n) gv[v] = __builtin_fma(-c[lg] * inv, gk, gv[v]);
+                }
+            }
+        }
+        wg_sync();
+        return ok;
+    }
+
+    // ------------------------------------------------ triangular solves
+    // X <- L^{-1} X (LOWER=true, forward) or X <- L^{-T} X (LOWER=false,
+    // backward with the transpose), L (n x n lower) in LDS slot sL with
+    // reciprocal diagonal dinv.  Solves NT register tiles (their first n rows)
+    // and NV lane vectors at once.  rb is LDS scratch of 2*(NT*NP+NV).
+    template <bool LOWER, int NT, int NV>
+    __device__ void trsm(const T* sL, const T* dinv, int n, Tile (&X)[NT > 0 ? NT : 1],
+                         T (&vv)[NV > 0 ? NV : 1], T* rb) const {
+        constexpr int RBS = (NT > 0 ? NT : 0) * NP + (NV > 0 ? NV : 0) + 1;
+#pragma unroll
+        for (int a0s = 0; a0s < TS; ++a0s) {
+            const int a0 = LOWER ? a0s : TS - 1 - a0s;
+            for (int ts = 0; ts < G; ++ts) {
+                const int t = LOWER ? ts : G - 1 - ts;
+                const int k = G * a0 + t;
+                if (k >= n) {
+                    if (LOWER) break;
+                    continue;
+                }
+                T* r = rb + (k & 1) * RBS;
+                const T dk = dinv[k];
+                if (ty == t) {
+#pragma unroll
+                    for (int it = 0; it < NT; ++it)
+#pragma unroll
+                        for (int b = 0; b < TS; ++b) r[it * NP + col(b)] = X[it][a0][b] * dk;
+                }
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+                    if (lg == k) r[NT * NP + v] = vv[v] * dk;
+                wg_sync();
+                T lik[TS];
+#pragma unroll
+                for (int a = 0; a < TS; ++a) {
+                    const int i = row(a);
+                    const bool act = LOWER ? (i > k && i < n) : (i < k);
+                    lik[a] = act ? (LOWER ? sL[i * LD + k] : sL[k * LD + i]) : T(0);
+                }
+#pragma unroll
+                for (int it = 0; it < NT; ++it) {
+                    T rk[TS];
+#pragma unroll
+                    for (int b = 0; b < TS; ++b) rk[b] = r[it * NP + col(b)];
+#pragma unroll
+                    for (int a = 0; a < TS; ++a)
+#pragma unroll
+                        for (int b = 0; b < TS; ++b)
+                            X[it][a][b] = (a == a0 && ty == t) ? rk[b] : __builtin_fma(-lik[a], rk[b], X[it][a][b]);
+                }
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    const T vk = r[NT * NP + v];
+                    if (lg == k) vv[v] = vk;
+                    else {
+                        const bool act = LOWER ? (lg > k && lg < n) : (lg < k);
+                        if (act) vv[v] = __builtin_fma(-(LOWER ? sL[lg * LD + k] : sL[k * LD + lg]), vk, vv[v]);
+                    }
+                }
+            }
+        }
+        wg_sync();
+    }
+};
+
+}  // namespace lqr

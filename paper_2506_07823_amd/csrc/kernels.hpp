@@ -1,0 +1,1025 @@
+// kernels.hpp -- HIP kernels of the LQR-KKT solve (gfx950).
+//
+// Paper: Amatucci, Sousa-Pinto et al., "Primal-Dual iLQR for GPU-Accelerated
+// Learning and Control in Legged Robots" (arXiv 2506.07823), Sec. II.
+//
+// Kernels of the scan path, in launch order:
+//   k_element   one-stage conditional value function, eq. (initialization)
+//               (+ FP64 redo of ill-conditioned R_k factorizations)
+//   k_up        up-sweep of the reverse scan: node = left (x) right, with the
+//               combine of eq. (combination_rule) in Cholesky form
+//   k_root/k_down  down-sweep: complete suffixes e_k (x) ... (x) e_N, whose
+//               (P, p) is the value function (P_k, p_k) (Sec. II-D)
+//   k_policy    K_k, k_k of eq. (lqr) from P_{k+1}, p_{k+1}, and the
+//               closed-loop map (Abar_k, bbar_k) of eq. (controlled_dynamics)
+//   k_fup/k_fdown  parallel scan of the closed-loop affine maps: up-sweep
+//               composes maps, down-sweep pushes the initial state to every
+//               node (Sec. II-D, conditional optimal trajectories)
+//   k_recover   u_k = K_k x_k + k_k, lambda_k = P_k x_k + p_k (Sec. II-C)
+// Refinement (one sweep): k_resid (FP64 KKT residual) -> k_ref_d ->
+// k_bvec_up/k_bvec_down (backward affine scan of the gradient recursion with
+// the stored closed-loop products) -> k_ref_kff -> k_fvec_up/k_fdown ->
+// k_recover<ADD>.
+// Plain baseline: k_plain runs the sequential Riccati sweep of eq. (lqr).
+//
+// One 64-lane group (G = 8) owns one task; E::TS selects the padded order.
+#pragma once
+#include "engine.hpp"
+
+namespace lqr {
+
+#define LQR_MAXLEV 24
+
+struct Tree {
+    int nlev, total;
+    int cnt[LQR_MAXLEV];
+    int off[LQR_MAXLEV];
+};
+
+struct Plan {
+    int64_t batch;
+    int N, n, m;
+    int rec, srec, frec;   // record sizes (elements): tree node, suffix, forward node
+    Tree rt, ft;           // reverse tree over N+1 leaves, forward tree over N leaves
+    int64_t stride;        // elements of the storage type per instance
+    int64_t o_tree, o_suf, o_K, o_kff, o_LG, o_ftree, o_xs, o_w, o_pend;
+    int64_t o_cp, o_qp, o_rp, o_x0p, o_pp, o_kffp;
+    int64_t dstride;       // doubles per instance: partial norms 2*(N+1)
+    double cond_thr;
+    int fallback;
+};
+
+template <typename S>
+struct In {
+    const S *A, *B, *c, *Q, *R, *M, *q, *r, *x0;
+};
+
+template <typename S>
+struct Out {
+    S *x, *u, *lam;
+    int32_t* status;
+};
+
+// pointer helpers (instance b, stage k)
+template <typename S> struct Ptr {
+    const Plan& p;
+    const In<S>& in;
+    __device__ Ptr(const Plan& p_, const In<S>& in_) : p(p_), in(in_) {}
+    __device__ const S* A(int64_t b, int k) const { return in.A + ((b * p.N + k) * p.n) * p.n; }
+    __device__ const S* B(int64_t b, int k) const { return in.B + ((b * p.N + k) * p.n) * p.m; }
+    __device__ const S* c(int64_t b, int k) const { return in.c + (b * p.N + k) * p.n; }
+    __device__ const S* Q(int64_t b, int k) const { return in.Q + ((b * (p.N + 1) + k) * p.n) * p.n; }
+    __device__ const S* R(int64_t b, int k) const { return in.R + ((b * p.N + k) * p.m) * p.m; }
+    __device__ const S* M(int64_t b, int k) const { return in.M + ((b * p.N + k) * p.n) * p.m; }
+    __device__ const S* q(int64_t b, int k) const { return in.q + (b * (p.N + 1) + k) * p.n; }
+    __device__ const S* r(int64_t b, int k) const { return in.r + (b * p.N + k) * p.m; }
+    __device__ const S* x0(int64_t b) const { return in.x0 + b * p.n; }
+};
+
+__device__ __forceinline__ int suffix_id(const Tree& t, int l, int j) {
+    while (l < t.nlev - 1 && (j & 1) == 0) { j >>= 1; ++l; }
+    return t.off[l] + j;
+}
+
+template <class E>
+struct Lds {
+    using T = typename E::T;
+    T sA[E::MAT];
+    T sX[E::MAT];
+    T cb[2 * (E::NP + 2)];
+    T dA[E::NP];
+    T dB[E::NP];
+    T rb[2 * (2 * E::NP + 3)];
+    T vb[2][E::NP];
+};
+
+template <class E>
+struct Lds3 : Lds<E> {
+    typename E::T sP[E::MAT];
+};
+
+// strided cooperative copy of `count` elements (all 64 lanes)
+template <typename D, typename S>
+__device__ __forceinline__ void coop_copy(D* dst, const S* src, int count) {
+    for (int i = threadIdx.x; i < count; i += 64) dst[i] = D(src[i]);
+}
+template <typename D>
+__device__ __forceinline__ void coop_zero(D* dst, int count) {
+    for (int i = threadIdx.x; i < count; i += 64) dst[i] = D(0);
+}
+
+// load a rows x cols global matrix (optionally transposed) into an LDS slot
+template <class E, bool TR = false, typename S>
+__device__ __forceinline__ void stage(const E& e, typename E::T* slot, const S* g, int rows, int cols, int ldg) {
+    typename E::Tile t;
+    e.template load<TR>(t, g, rows, cols, ldg);
+    e.to_lds(t, slot);
+}
+
+template <class E>
+__device__ __forceinline__ void to_lds_sym(const E& e, const typename E::Tile& t, typename E::T* s) {
+#pragma unroll
+    for (int a = 0; a < E::TS; ++a)
+#pragma unroll
+        for (int b = 0; b < E::TS; ++b) {
+            const int i = e.row(a), j = e.col(b);
+            if (j <= i) {
+                s[i * E::LD + j] = t[a][b];
+                s[j * E::LD + i] = t[a][b];
+            }
+        }
+}
+
+template <class E>
+__device__ __forceinline__ void negate(typename E::Tile& t) {
+#pragma unroll
+    for (int a = 0; a < E::TS; ++a)
+#pragma unroll
+        for (int b = 0; b < E::TS; ++b) t[a][b] = -t[a][b];
+}
+
+// reciprocal diagonal of a staged lower-triangular factor
+template <class E>
+__device__ __forceinline__ void fill_dinv(const typename E::T* s, typename E::T* d, int n) {
+    for (int i = threadIdx.x; i < n; i += 64) d[i] = typename E::T(1) / s[i * E::LD + i];
+}
+
+__device__ __forceinline__ void set_status(int32_t* status, int64_t b, int bits) {
+    if (threadIdx.x == 0) atomicOr(status + b, bits);
+}
+
+template <typename T>
+__device__ __forceinline__ bool finite_(T v) { return __builtin_isfinite(v); }
+
+__device__ __forceinline__ bool wave_all(bool v) {
+    return __builtin_amdgcn_ballot_w64(!v) == 0;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 fallback queues.  An FP32 task whose Cholesky factorization fails or
+// whose condition estimate (max L_ii / min L_ii)^2 exceeds the threshold
+// appends its task id; the FP64 instance of the same kernel then drains the
+// queue with a small grid (no host synchronization, near-free when empty).
+// ---------------------------------------------------------------------------
+struct FbQueue {
+    int32_t* count;
+    int32_t* ids;
+};
+
+__device__ __forceinline__ void fb_push(FbQueue q, int64_t task) {
+    if (threadIdx.x == 0) {
+        const int slot = atomicAdd(q.count, 1);
+        q.ids[slot] = (int32_t)task;
+    }
+}
+
+// decide what a finished factorization means for this task
+template <bool FB, typename T>
+__device__ __forceinline__ void fb_decide(const Plan& p, bool ok, T kappa, int64_t b, int64_t task, FbQueue q,
+                                          int32_t* status, int failbit) {
+    if (!FB) {
+        const bool bad = !ok || !(kappa <= T(p.cond_thr));
+        if (bad) {
+            if (p.fallback) {
+                fb_push(q, task);
+                set_status(status, b, 8);
+            } else if (!ok) {
+                set_status(status, b, failbit);
+            }
+        }
+    } else if (!ok) {
+        set_status(status, b, failbit);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T cond_est(T dmin, T dmax) {
+    return dmin > T(0) ? (dmax / dmin) * (dmax / dmin) : T(3.0e38);
+}
+
+// clear the status words and the fallback queue counters (graph-safe fill)
+template <typename I>
+__global__ void k_clear(I* status, int64_t batch, I* counters, int64_t ncount) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < batch) status[i] = 0;
+    if (i < ncount) counters[i] = 0;
+}
+
+// Run `body(task)` for every task of the launch (FP32 pass: one task per
+// workgroup) or for every queued task (FP64 pass: grid-stride over the queue).
+#define LQR_TASKS(FB, q, body)                                                    \
+    do {                                                                          \
+        if (!(FB)) {                                                              \
+            body((int64_t)blockIdx.x);                                            \
+        } else {                                                                  \
+            const int cnt_ = *(q).count;                                          \
+            for (int i_ = blockIdx.x; i_ < cnt_; i_ += gridDim.x) {               \
+                body((int64_t)(q).ids[i_]);                                       \
+                wg_sync();                                                        \
+            }                                                                     \
+        }                                                                         \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Sec. II-D, eq. (initialization): one-stage element with S_k = M_k'.
+//   R = L_R L_R',  W_B = L_R^{-1} B',  W_M = L_R^{-1} M',  w_r = L_R^{-1} r
+//   At = A - W_B' W_M,  Ct = W_B' W_B,  Pt = Q - W_M' W_M,
+//   bt = c - W_B' w_r,  pt = q - W_M' w_r.
+// The terminal element (k = N) is (0, 0, 0, Q_N, q_N).  FB: the FP64 redo
+// of stages flagged by the FP32 pass (condition estimate of L_R above the
+// threshold, or a non-positive pivot).
+// Record layout: A | C | P | b | p.
+// ---------------------------------------------------------------------------
+template <typename S, class E, bool FB>
+__device__ void element_task(Lds<E>& L, const Plan& p, const In<S>& in, S* ws, int32_t* status, FbQueue q,
+                             int64_t task) {
+    using T = typename E::T;
+    const E e(threadIdx.x);
+    const int N = p.N, n = p.n, m = p.m, nn = n * n;
+    const int64_t b = task / (N + 1);
+    const int k = (int)(task % (N + 1));
+    S* rec = ws + b * p.stride + p.o_tree + (int64_t)k * p.rec;
+    const Ptr<S> P(p, in);
+    if (k == N) {
+        if (FB) return;
+        coop_zero(rec, 2 * nn);
+        coop_copy(rec + 2 * nn, P.Q(b, N), nn);
+        coop_zero(rec + 3 * nn, n);
+        coop_copy(rec + 3 * nn + n, P.q(b, N), n);
+        return;
+    }
+    typename E::Tile tR;
+    e.load(tR, P.R(b, k), m, m, m);
+    T dmin, dmax, nov[1];
+    const bool ok = e.template chol<0>(tR, m, L.cb, L.dA, nov, dmin, dmax);
+    fb_decide<FB>(p, ok, cond_est(dmin, dmax), b, task, q, status, 2);
+    e.to_lds(tR, L.sA);
+    typename E::Tile W[2];
+    e.template load<true>(W[0], P.B(b, k), m, n, m);   // B' (m x n)
+    e.template load<true>(W[1], P.M(b, k), m, n, m);   // M' (m x n)
+    T vv[1] = {e.vload(P.r(b, k), m)};
+    wg_sync();
+    e.template trsm<true, 2, 1>(L.sA, L.dA, m, W, vv, L.rb);
+    e.to_lds(W[0], L.sA);
+    e.to_lds(W[1], L.sX);
+    wg_sync();
+    typename E::Tile t;
+    e.load(t, P.A(b, k), n, n, n);
+    e.template gemm_sub<true, false>(t, L.sA, L.sX, m);
+    e.store(t, rec, n, n, n);                          // At
+    e.zero(t);
+    e.template gemm<true, false>(t, L.sA, L.sA, m);
+    e.store_sym(t, rec + nn, n);                       // Ct
+    e.load(t, P.Q(b, k), n, n, n);
+    e.template gemm_sub<true, false>(t, L.sX, L.sX, m);
+    e.store_sym(t, rec + 2 * nn, n);                   // Pt
+    const T bw = e.template matvec<true>(L.sA, vv[0], L.vb[0], m, n);
+    e.vstore(rec + 3 * nn, n, e.vload(P.c(b, k), n) - bw);
+    const T pw = e.template matvec<true>(L.sX, vv[0], L.vb[1], m, n);
+    e.vstore(rec + 3 * nn + n, n, e.vload(P.q(b, k), n) - pw);
+}
+
+template <typename S, class E, bool FB>
+__global__ __launch_bounds__(64) void k_element(Plan p, In<S> in, S* ws, int32_t* status, FbQueue q) {
+    __shared__ Lds<E> L;
+    auto body = [&](int64_t t) { element_task<S, E, FB>(L, p, in, ws, status, q, t); };
+    LQR_TASKS(FB, q, body);
+}
+
+// ---------------------------------------------------------------------------
+// Sec. II-D, eq. (combination_rule), e1 (x) e2 with e1 the earlier segment.
+// With P2 = L L', S = I + L' C1 L = L_S L_S':
+//   Y = L_S^{-1} L' A1,  Z1 = L^{-1} A2',  Z = L_S^{-1} Z1
+//   w1 = L_S^{-1}(L^{-1} p2 + L' b1),  w2 = L_S^{-1} L'(b1 - C1 p2)
+//   P = Y'Y + P1,   p = Y'w1 + p1,   A = Z'Y,
+//   C = Z1'Z1 - Z'Z + C2,   b = Z'w2 + b2.
+// (equal to A2 (I+C1P2)^{-1} A1, A2 (I+C1P2)^{-1} C1 A2' + C2, ... since
+// (I + C1 P2)^{-1} = L^{-T} S^{-1} L').  CHEAP: e2 is a complete suffix
+// (A2 = C2 = b2 = 0), only P and p are formed and written to a suffix record.
+// ---------------------------------------------------------------------------
+template <class E, bool CHEAP, typename S>
+__device__ void combine(const E& e, Lds<E>& L, int n, const S* e1, const S* P2, const S* p2v,
+                        const S* e2, S* outA, S* outC, S* outP, S* outb, S* outp, bool& okp,
+                        typename E::T& kappa) {
+    using T = typename E::T;
+    const int nn = n * n;
+    typename E::Tile tS;
+    T dmin, dmax;
+    // L = chol(P2), g = L^{-1} p2
+    e.load(tS, P2, n, n, n);
+    T g[1] = {e.vload(p2v, n)};
+    const T p2l = g[0];
+    bool ok = e.template chol<1>(tS, n, L.cb, L.dA, g, dmin, dmax);
+    T kap = cond_est(dmin, dmax);
+    e.to_lds(tS, L.sA);                                   // sA = L
+    {
+        typename E::Tile tX;
+        e.load(tX, e1 + nn, n, n, n);                      // C1
+        e.to_lds(tX, L.sX);
+    }
+    wg_sync();
+    T cp = T(0);
+    if (!CHEAP) cp = e.template matvec<false>(L.sX, p2l, L.vb[0], n, n);   // C1 p2
+    e.zero(tS);
+    e.template gemm<false, false>(tS, L.sX, L.sA, n);      // W = C1 L
+    wg_sync();
+    e.to_lds(tS, L.sX);
+    wg_sync();
+    e.zero(tS);
+    e.template gemm<true, false>(tS, L.sA, L.sX, n);       // L' W
+    e.add_identity(tS, n);
+    T nov[1];
+    ok = e.template chol<0>(tS, n, L.cb, L.dB, nov, dmin, dmax) && ok;   // tS = L_S
+    {
+        const T ks = cond_est(dmin, dmax);
+        kap = ks > kap ? ks : kap;
+    }
+    typename E::Tile YZ[2];
+    typename E::Tile tC;
+    if (!CHEAP) {
+        typename E::Tile Z1[1];
+        e.template load<true>(Z1[0], e2, n, n, n);         // A2'
+        e.template trsm<true, 1, 0>(L.sA, L.dA, n, Z1, nov, L.rb);   // Z1 = L^{-1} A2'
+#pragma unroll
+        for (int a = 0; a < E::TS; ++a)
+#pragma unroll
+            for (int bb = 0; bb < E::TS; ++bb) YZ[1][a][bb] = Z1[0][a][bb];
+    }
+    {
+        typename E::Tile tX;
+        e.load(tX, e1, n, n, n);                           // A1
+        wg_sync();
+        e.to_lds(tX, L.sX);
+    }
+    wg_sync();
+    e.zero(YZ[0]);
+    e.template gemm<true, false>(YZ[0], L.sA, L.sX, n);    // L' A1
+    const T b1 = e.vload(e1 + 3 * nn, n);
+    T vv[2];
+    vv[0] = g[0] + e.template matvec<true>(L.sA, b1, L.vb[1], n, n);
+    wg_sync();
+    if (!CHEAP) {
+        vv[1] = e.template matvec<true>(L.sA, b1 - cp, L.vb[0], n, n);
+        wg_sync();
+        e.to_lds(YZ[1], L.sX);                             // sX = Z1
+        wg_sync();
+        e.zero(tC);
+        e.template gemm<true, false>(tC, L.sX, L.sX, n);   // Z1' Z1
+    } else {
+        vv[1] = T(0);
+    }
+    wg_sync();
+    e.to_lds(tS, L.sA);                                    // sA = L_S
+    wg_sync();
+    if (!CHEAP) {
+        e.template trsm<true, 2, 2>(L.sA, L.dB, n, YZ, vv, L.rb);
+    } else {
+        typename E::Tile Y1[1];
+#pragma unroll
+        for (int a = 0; a < E::TS; ++a)
+#pragma unroll
+            for (int bb = 0; bb < E::TS; ++bb) Y1[0][a][bb] = YZ[0][a][bb];
+        T v1[1] = {vv[0]};
+        e.template trsm<true, 1, 1>(L.sA, L.dB, n, Y1, v1, L.rb);
+#pragma unroll
+        for (int a = 0; a < E::TS; ++a)
+#pragma unroll
+            for (int bb = 0; bb < E::TS; ++bb) YZ[0][a][bb] = Y1[0][a][bb];
+        vv[0] = v1[0];
+    }
+    e.to_lds(YZ[0], L.sX);                                 // sX = Y
+    wg_sync();
+    e.load(tS, e1 + 2 * nn, n, n, n);                      // P1
+    e.template gemm<true, false>(tS, L.sX, L.sX, n);       // + Y'Y
+    e.store_sym(tS, outP, n);
+    const T pv = e.template matvec<true>(L.sX, vv[0], L.vb[1], n, n) + e.vload(e1 + 3 * nn + n, n);
+    e.vstore(outp, n, pv);
+    if (!CHEAP) {
+        wg_sync();
+        e.to_lds(YZ[1], L.sA);                             // sA = Z
+        wg_sync();
+        e.zero(tS);
+        e.template gemm<true, false>(tS, L.sA, L.sX, n);   // A = Z'Y
+        e.store(tS, outA, n, n, n);
+        e.template gemm_sub<true, false>(tC, L.sA, L.sA, n);   // Z1'Z1 - Z'Z
+        e.add_global(tC, e2 + nn, n, n, n);                // + C2
+        e.store_sym(tC, outC, n);
+        const T bv = e.template matvec<true>(L.sA, vv[1], L.vb[0], n, n) + e.vload(e2 + 3 * nn, n);
+        e.vstore(outb, n, bv);
+    }
+    wg_sync();
+    okp = ok;
+    kappa = kap;
+}
+
+template <typename S, class E, bool FB>
+__device__ void up_task(Lds<E>& L, const Plan& p, S* ws, int lvl, int32_t* status, FbQueue q, int64_t task) {
+    const E e(threadIdx.x);
+    const int n = p.n, nn = n * n;
+    const int cout = p.rt.cnt[lvl + 1], cin = p.rt.cnt[lvl];
+    const int64_t b = task / cout;
+    const int i = (int)(task % cout);
+    S* base = ws + b * p.stride + p.o_tree;
+    const S* e1 = base + (int64_t)(p.rt.off[lvl] + 2 * i) * p.rec;
+    S* out = base + (int64_t)(p.rt.off[lvl + 1] + i) * p.rec;
+    if (2 * i + 1 >= cin) {
+        if (!FB) coop_copy(out, e1, p.rec);
+        return;
+    }
+    const S* e2 = e1 + p.rec;
+    bool ok;
+    typename E::T kappa;
+    combine<E, false>(e, L, n, e1, e2 + 2 * nn, e2 + 3 * nn + n, e2, out, out + nn, out + 2 * nn, out + 3 * nn,
+                      out + 3 * nn + n, ok, kappa);
+    fb_decide<FB>(p, ok, kappa, b, task, q, status, 4);
+}
+
+template <typename S, class E, bool FB>
+__global__ __launch_bounds__(64) void k_up(Plan p, S* ws, int lvl, int32_t* status, FbQueue q) {
+    __shared__ Lds<E> L;
+    auto body = [&](int64_t t) { up_task<S, E, FB>(L, p, ws, lvl, status, q, t); };
+    LQR_TASKS(FB, q, body);
+}
+
+// root of the reverse tree: its (P, p) is the complete suffix starting at 0
+template <typename S>
+__global__ void k_root(Plan p, S* ws) {
+    const int64_t b = blockIdx.x;
+    const int n = p.n, nn = n * n;
+    const int root = p.rt.off[p.rt.nlev - 1];
+    const S* src = ws + b * p.stride + p.o_tree + (int64_t)root * p.rec;
+    S* dst = ws + b * p.stride + p.o_suf + (int64_t)root * p.srec;
+    coop_copy(dst, src + 2 * nn, nn);          // P
+    coop_copy(dst + nn, src + 3 * nn + n, n);  // p (the record stores b between P and p)
+}
+
+// down-sweep at level lvl: odd node j gets node_j (x) suffix(level lvl+1, (j+1)/2)
+template <typename S, class E, bool FB>
+__device__ void down_task(Lds<E>& L, const Plan& p, S* ws, int lvl, int32_t* status, FbQueue q, int64_t task) {
+    const E e(threadIdx.x);
+    const int n = p.n, nn = n * n;
+    const int half = p.rt.cnt[lvl] / 2;
+    const int64_t b = task / half;
+    const int j = 2 * (int)(task % half) + 1;
+    S* tree = ws + b * p.stride + p.o_tree;
+    S* suf = ws + b * p.stride + p.o_suf;
+    const S* node = tree + (int64_t)(p.rt.off[lvl] + j) * p.rec;
+    S* out = suf + (int64_t)(p.rt.off[lvl] + j) * p.srec;
+    const int i1 = (j + 1) / 2;
+    if (i1 >= p.rt.cnt[lvl + 1]) {
+        if (!FB) {
+            coop_copy(out, node + 2 * nn, nn);
+            coop_copy(out + nn, node + 3 * nn + n, n);
+        }
+        return;
+    }
+    const S* s2 = suf + (int64_t)suffix_id(p.rt, lvl + 1, i1) * p.srec;
+    bool ok;
+    typename E::T kappa;
+    combine<E, true>(e, L, n, node, s2, s2 + nn, (const S*)nullptr, (S*)nullptr, (S*)nullptr, out,
+                     (S*)nullptr, out + nn, ok, kappa);
+    fb_decide<FB>(p, ok, kappa, b, task, q, status, 4);
+}
+
+template <typename S, class E, bool FB>
+__global__ __launch_bounds__(64) void k_down(Plan p, S* ws, int lvl, int32_t* status, FbQueue q) {
+    __shared__ Lds<E> L;
+    auto body = [&](int64_t t) { down_task<S, E, FB>(L, p, ws, lvl, status, q, t); };
+    LQR_TASKS(FB, q, body);
+}
+
+// ---------------------------------------------------------------------------
+// eq. (lqr) per stage, from the value function P_{k+1}, p_{k+1}:
+//   G = R + B'P'B = R + (P'B)'B,  H = M' + (P'B)'A,  h = B'(p' + P'c) + r,
+//   G = L_G L_G',  K = -G^{-1}H,  k = -G^{-1}h,
+// then eq. (controlled_dynamics): Abar = A + B K, bbar = B k + c, written as
+// the leaf of the forward tree.  Stores K, k and L_G (reused by refinement).
+// ---------------------------------------------------------------------------
+template <typename S, class E, bool FB>
+__device__ void policy_task(Lds<E>& L, const Plan& p, const In<S>& in, S* ws, int32_t* status, FbQueue q,
+                            int64_t task) {
+    using T = typename E::T;
+    const E e(threadIdx.x);
+    const int N = p.N, n = p.n, m = p.m, nn = n * n;
+    const int64_t b = task / N;
+    const int k = (int)(task % N);
+    const Ptr<S> P(p, in);
+    S* inst = ws + b * p.stride;
+    const S* Pn = inst + p.o_suf + (int64_t)suffix_id(p.rt, 0, k + 1) * p.srec;
+    typename E::Tile t, tG, tH;
+    stage(e, L.sA, Pn, n, n, n);                          // sA = P'
+    stage(e, L.sX, P.B(b, k), n, m, m);                   // sX = B
+    wg_sync();
+    const T v = e.template matvec<false>(L.sA, e.vload(P.c(b, k), n), L.vb[0], n, n) + e.vload(Pn + nn, n);
+    e.zero(t);
+    e.template gemm<false, false>(t, L.sA, L.sX, n);       // P'B
+    const T h = e.template matvec<true>(L.sX, v, L.vb[1], n, m) + e.vload(P.r(b, k), m);
+    wg_sync();
+    e.to_lds(t, L.sA);                                    // sA = P'B
+    wg_sync();
+    e.load(tG, P.R(b, k), m, m, m);
+    e.template gemm<true, false>(tG, L.sA, L.sX, n);       // R + (P'B)'B
+    wg_sync();
+    stage(e, L.sX, P.A(b, k), n, n, n);                   // sX = A
+    wg_sync();
+    e.template load<true>(tH, P.M(b, k), m, n, m);        // M'
+    e.template gemm<true, false>(tH, L.sA, L.sX, n);       // + (P'B)'A
+    T dmin, dmax, nov[1];
+    const bool ok = e.template chol<0>(tG, m, L.cb, L.dA, nov, dmin, dmax);
+    fb_decide<FB>(p, ok, cond_est(dmin, dmax), b, task, q, status, 2);
+    e.to_lds(tG, L.sA);                                   // sA = L_G
+    wg_sync();
+    typename E::Tile KK[1];
+#pragma unroll
+    for (int a = 0; a < E::TS; ++a)
+#pragma unroll
+        for (int c = 0; c < E::TS; ++c) KK[0][a][c] = tH[a][c];
+    T hv[1] = {h};
+    e.template trsm<true, 1, 1>(L.sA, L.dA, m, KK, hv, L.rb);
+    e.template trsm<false, 1, 1>(L.sA, L.dA, m, KK, hv, L.rb);
+    negate<E>(KK[0]);
+    hv[0] = -hv[0];
+    e.store(KK[0], inst + p.o_K + (int64_t)k * m * n, m, n, n);
+    e.vstore(inst + p.o_kff + (int64_t)k * m, m, hv[0]);
+    e.store(tG, inst + p.o_LG + (int64_t)k * m * m, m, m, m);
+    // closed loop: Abar = A + B K, bbar = B k + c
+    e.to_lds(KK[0], L.sA);                                // sA = K (m x n)
+    stage(e, L.sX, P.B(b, k), n, m, m);                   // sX = B
+    wg_sync();
+    e.load(t, P.A(b, k), n, n, n);
+    e.template gemm<false, false>(t, L.sX, L.sA, m);
+    S* leaf = inst + p.o_ftree + (int64_t)k * p.frec;
+    e.store(t, leaf, n, n, n);
+    const T bb = e.template matvec<false>(L.sX, hv[0], L.vb[0], m, n) + e.vload(P.c(b, k), n);
+    e.vstore(leaf + nn, n, bb);
+}
+
+template <typename S, class E, bool FB>
+__global__ __launch_bounds__(64) void k_policy(Plan p, In<S> in, S* ws, int32_t* status, FbQueue q) {
+    __shared__ Lds<E> L;
+    auto body = [&](int64_t t) { policy_task<S, E, FB>(L, p, in, ws, status, q, t); };
+    LQR_TASKS(FB, q, body);
+}
+
+// ---------------------------------------------------------------------------
+// forward tree up-sweep: node (l+1, i) = later (2i+1) after earlier (2i):
+//   M = M_r M_l,  v = M_r v_l + v_r   (apply the earlier map first)
+// VEC: only the vector part (matrices kept from the first solve).
+// ---------------------------------------------------------------------------
+template <typename S, class E, bool VEC>
+__global__ __launch_bounds__(64) void k_fup(Plan p, S* ws, int lvl) {
+    using T = typename E::T;
+    __shared__ Lds<E> L;
+    const E e(threadIdx.x);
+    const int n = p.n, nn = n * n;
+    const int cout = p.ft.cnt[lvl + 1], cin = p.ft.cnt[lvl];
+    const int64_t b = blockIdx.x / cout;
+    const int i = blockIdx.x % cout;
+    S* base = ws + b * p.stride + p.o_ftree;
+    const S* l = base + (int64_t)(p.ft.off[lvl] + 2 * i) * p.frec;
+    S* out = base + (int64_t)(p.ft.off[lvl + 1] + i) * p.frec;
+    if (2 * i + 1 >= cin) {
+        if (VEC) coop_copy(out + nn, l + nn, n);
+        else coop_copy(out, l, p.frec);
+        return;
+    }
+    const S* r = l + p.frec;
+    stage(e, L.sA, r, n, n, n);                           // M_r
+    if (!VEC) stage(e, L.sX, l, n, n, n);                 // M_l
+    wg_sync();
+    const T v = e.template matvec<false>(L.sA, e.vload(l + nn, n), L.vb[0], n, n) + e.vload(r + nn, n);
+    if (!VEC) {
+        typename E::Tile t;
+        e.zero(t);
+        e.template gemm<false, false>(t, L.sA, L.sX, n);
+        e.store(t, out, n, n, n);
+    }
+    e.vstore(out + nn, n, v);
+}
+
+// forward tree down-sweep root: start state of the whole horizon
+template <typename S>
+__global__ void k_froot(Plan p, S* ws, const S* x0, int64_t x0_stride) {
+    const int64_t b = blockIdx.x;
+    const int root = p.ft.off[p.ft.nlev - 1];
+    coop_copy(ws + b * p.stride + p.o_xs + (int64_t)root * p.n, x0 + b * x0_stride, p.n);
+}
+
+// node (l, j): even j starts where its parent starts; odd j starts after its
+// left sibling:  xs = M_{j-1} xs(parent) + v_{j-1}
+template <typename S, class E>
+__global__ __launch_bounds__(64) void k_fdown(Plan p, S* ws, int lvl) {
+    using T = typename E::T;
+    __shared__ Lds<E> L;
+    const E e(threadIdx.x);
+    const int n = p.n, nn = n * n;
+    const int cnt = p.ft.cnt[lvl];
+    const int64_t b = blockIdx.x / cnt;
+    const int j = blockIdx.x % cnt;
+    S* inst = ws + b * p.stride;
+    const S* par = inst + p.o_xs + (int64_t)(p.ft.off[lvl + 1] + j / 2) * n;
+    S* out = inst + p.o_xs + (int64_t)(p.ft.off[lvl] + j) * n;
+    if ((j & 1) == 0) {
+        coop_copy(out, par, n);
+        return;
+    }
+    const S* sib = inst + p.o_ftree + (int64_t)(p.ft.off[lvl] + j - 1) * p.frec;
+    stage(e, L.sA, sib, n, n, n);
+    wg_sync();
+    const T x = e.template matvec<false>(L.sA, e.vload(par, n), L.vb[0], n, n) + e.vload(sib + nn, n);
+    e.vstore(out, n, x);
+}
+
+// ---------------------------------------------------------------------------
+// u_k = K_k x_k + k_k,  lambda_k = P_k x_k + p_k  (Sec. II-C); x_N from the
+// last leaf map.  ADD: the refinement's correction is added to the outputs.
+// ---------------------------------------------------------------------------
+template <typename S, class E, bool ADD>
+__global__ __launch_bounds__(64) void k_recover(Plan p, S* ws, Out<S> out) {
+    using T = typename E::T;
+    __shared__ Lds<E> L;
+    const E e(threadIdx.x);
+    const int N = p.N, n = p.n, m = p.m, nn = n * n;
+    const int64_t b = blockIdx.x / (N + 1);
+    const int k = blockIdx.x % (N + 1);
+    S* inst = ws + b * p.stride;
+    T x;
+    if (k < N) {
+        x = e.vload(inst + p.o_xs + (int64_t)k * n, n);
+    } else {
+        const S* leaf = inst + p.o_ftree + (int64_t)(N - 1) * p.frec;
+        stage(e, L.sA, leaf, n, n, n);
+        wg_sync();
+        x = e.template matvec<false>(L.sA, e.vload(inst + p.o_xs + (int64_t)(N - 1) * n, n), L.vb[0], n, n) +
+            e.vload(leaf + nn, n);
+        wg_sync();
+    }
+    const S* Pk = inst + p.o_suf + (int64_t)suffix_id(p.rt, 0, k) * p.srec;
+    stage(e, L.sA, Pk, n, n, n);
+    const bool hasu = k < N;
+    if (hasu) stage(e, L.sX, inst + p.o_K + (int64_t)k * m * n, m, n, n);
+    wg_sync();
+    const S* pvec = ADD ? inst + p.o_pp + (int64_t)k * n : Pk + nn;
+    const T lam = e.template matvec<false>(L.sA, x, L.vb[0], n, n) + e.vload(pvec, n);
+    T u = T(0);
+    if (hasu) {
+        const S* kf = ADD ? inst + p.o_kffp + (int64_t)k * m : inst + p.o_kff + (int64_t)k * m;
+        u = e.template matvec<false>(L.sX, x, L.vb[1], n, m) + e.vload(kf, m);
+    }
+    S* xo = out.x + (b * (N + 1) + k) * n;
+    S* lo = out.lam + (b * (N + 1) + k) * n;
+    S* uo = out.u + (b * N + k) * m;
+    bool fin = true;
+    if (e.lg < n) {
+        const T xv = ADD ? T(xo[e.lg]) + x : x;
+        const T lv = ADD ? T(lo[e.lg]) + lam : lam;
+        xo[e.lg] = S(xv);
+        lo[e.lg] = S(lv);
+        fin = finite_(xv) && finite_(lv);
+    }
+    if (hasu && e.lg < m) {
+        const T uv = ADD ? T(uo[e.lg]) + u : u;
+        uo[e.lg] = S(uv);
+        fin = fin && finite_(uv);
+    }
+    if (!wave_all(fin)) set_status(out.status, b, 1);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 KKT residual (stationarity of the Lagrangian of Sec. II-B plus the
+// constraints), one task per (instance, stage):
+//   r_init = x_0 - x0
+//   r_dyn[k+1] = A x_k + B u_k + c - x_{k+1}
+//   r_x[k] = Q x_k + M u_k + q + A' lam_{k+1} - lam_k   (r_x[N] = Q x_N + q - lam_N)
+//   r_u[k] = M' x_k + R u_k + r + B' lam_{k+1}
+// Writes the partial sums of squares (residual, right-hand side) and, when
+// CORR, the correction data c' = r_dyn, q' = r_x, r' = r_u, x0' = -r_init.
+// ---------------------------------------------------------------------------
+template <typename S, class E, bool CORR>
+__global__ __launch_bounds__(64) void k_resid(Plan p, In<S> in, const S* xs_, const S* us_, const S* ls_,
+                                              S* ws, double* dws) {
+    static_assert(sizeof(typename E::T) == 8, "residual runs in FP64");
+    __shared__ double sM[E::MAT];
+    __shared__ double vb[2][E::NP];
+    const E e(threadIdx.x);
+    const int N = p.N, n = p.n, m = p.m;
+    const int64_t b = blockIdx.x / (N + 1);
+    const int k = blockIdx.x % (N + 1);
+    const Ptr<S> P(p, in);
+    const S* xk = xs_ + (b * (N + 1) + k) * n;
+    const S* lk = ls_ + (b * (N + 1) + k) * n;
+    const double x = e.vload(xk, n), lam = e.vload(lk, n);
+    double rr = 0.0, bb = 0.0;
+    S* inst = ws + b * p.stride;
+    // Q x + q - lam (+ M u + A' lam1 for k < N)
+    stage(e, sM, P.Q(b, k), n, n, n);
+    wg_sync();
+    double qv = e.vload(P.q(b, k), n);
+    double rx = e.template matvec<false>(sM, x, vb[0], n, n) + qv - lam;
+    bb += qv * qv;
+    if (k < N) {
+        const double u = e.vload(us_ + (b * N + k) * m, m);
+        const double lam1 = e.vload(lk + n, n);
+        const double x1 = e.vload(xk + n, n);
+        wg_sync();
+        stage(e, sM, P.A(b, k), n, n, n);
+        wg_sync();
+        double rd = e.template matvec<false>(sM, x, vb[0], n, n);
+        rx += e.template matvec<true>(sM, lam1, vb[1], n, n);
+        wg_sync();
+        stage(e, sM, P.B(b, k), n, m, m);
+        wg_sync();
+        rd += e.template matvec<false>(sM, u, vb[0], m, n);
+        double ru = e.template matvec<true>(sM, lam1, vb[1], n, m);
+        wg_sync();
+        stage(e, sM, P.M(b, k), n, m, m);
+        wg_sync();
+        rx += e.template matvec<false>(sM, u, vb[0], m, n);
+        ru += e.template matvec<true>(sM, x, vb[1], n, m);
+        wg_sync();
+        stage(e, sM, P.R(b, k), m, m, m);
+        wg_sync();
+        const double cv = e.vload(P.c(b, k), n), rv = e.vload(P.r(b, k), m);
+        ru += e.template matvec<false>(sM, u, vb[0], m, m) + rv;
+        rd += cv - x1;
+        bb += cv * cv + rv * rv;
+        rr += (e.lg < n ? rd * rd : 0.0) + (e.lg < m ? ru * ru : 0.0);
+        if (CORR) {
+            e.vstore(inst + p.o_cp + (int64_t)k * n, n, rd);
+            e.vstore(inst + p.o_rp + (int64_t)k * m, m, ru);
+        }
+    }
+    rr += e.lg < n ? rx * rx : 0.0;
+    if (CORR) e.vstore(inst + p.o_qp + (int64_t)k * n, n, rx);
+    if (k == 0) {
+        const double x0v = e.vload(P.x0(b), n);
+        const double ri = x - x0v;
+        rr += e.lg < n ? ri * ri : 0.0;
+        bb += x0v * x0v;
+        if (CORR) e.vstore(inst + p.o_x0p, n, -ri);
+    }
+    rr = wave_sum(rr);
+    bb = wave_sum(bb);
+    if (threadIdx.x == 0) {
+        dws[b * p.dstride + 2 * k] = rr;
+        dws[b * p.dstride + 2 * k + 1] = bb;
+    }
+}
+
+template <typename D>
+__global__ void k_resid_reduce(Plan p, const D* dws, D* rel) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= p.batch) return;
+    double rr = 0.0, bb = 0.0;
+    for (int k = 0; k <= p.N; ++k) {
+        rr += dws[b * p.dstride + 2 * k];
+        bb += dws[b * p.dstride + 2 * k + 1];
+    }
+    rel[b] = bb > 0.0 ? __builtin_sqrt(rr) / __builtin_sqrt(bb) : __builtin_sqrt(rr);
+}
+
+// ---------------------------------------------------------------------------
+// Refinement: correction data (x0', c', q', r') solved with the factors of
+// the first solve.  With the policy fixed, the gradient recursion of eq. (lqr)
+// is affine:  p'_k = Abar_k' p'_{k+1} + d_k,
+//   d_k = q'_k + K_k' r'_k + Abar_k' P_{k+1} c'_k,
+// a backward scan whose segment matrices are the transposes of the forward
+// tree's products Abar_e ... Abar_s.
+// ---------------------------------------------------------------------------
+template <typename S, class E>
+__global__ __launch_bounds__(64) void k_ref_d(Plan p, S* ws) {
+    using T = typename E::T;
+    __shared__ Lds<E> L;
+    const E e(threadIdx.x);
+    const int N = p.N, n = p.n, m = p.m;
+    const int64_t b = blockIdx.x / N;
+    const int k = blockIdx.x % N;
+    S* inst = ws + b * p.stride;
+    const S* Pn = inst + p.o_suf + (int64_t)suffix_id(p.rt, 0, k + 1) * p.srec;
+    stage(e, L.sA, Pn, n, n, n);
+    stage(e, L.sX, inst + p.o_ftree + (int64_t)k * p.frec, n, n, n);   // Abar_k
+    wg_sync();
+    const T t = e.template matvec<false>(L.sA, e.vload(inst + p.o_cp + (int64_t)k * n, n), L.vb[0], n, n);
+    wg_sync();
+    T d = e.template matvec<true>(L.sX, t, L.vb[1], n, n);
+    wg_sync();
+    stage(e, L.sA, inst + p.o_K + (int64_t)k * m * n, m, n, n);
+    wg_sync();
+    d += e.template matvec<true>(L.sA, e.vload(inst + p.o_rp + (int64_t)k * m, m), L.vb[0], m, n);
+    d += e.vload(inst + p.o_qp + (int64_t)k * n, n);
+    e.vstore(inst + p.o_w + (int64_t)k * n, n, d);
+}
+
+// backward up-sweep: w(l+1, i) = M(l, 2i)' w(l, 2i+1) + w(l, 2i)
+template <typename S, class E>
+__global__ __launch_bounds__(64) void k_bvec_up(Plan p, S* ws, int lvl) {
+    using T = typename E::T;
+    __shared__ Lds<E> L;
+    const E e(threadIdx.x);
+    const int n = p.n;
+    const int cout = p.ft.cnt[lvl + 1], cin = p.ft.cnt[lvl];
+    const int64_t b = blockIdx.x / cout;
+    const int i = blockIdx.x % cout;
+    S* inst = ws + b * p.stride;
+    const S* wl = inst + p.o_w + (int64_t)(p.ft.off[lvl] + 2 * i) * n;
+    S* wo = inst + p.o_w + (int64_t)(p.ft.off[lvl + 1] + i) * n;
+    if (2 * i + 1 >= cin) {
+        coop_copy(wo, wl, n);
+        return;
+    }
+    stage(e, L.sA, inst + p.o_ftree + (int64_t)(p.ft.off[lvl] + 2 * i) * p.frec, n, n, n);
+    wg_sync();
+    const T w = e.template matvec<true>(L.sA, e.vload(wl + n, n), L.vb[0], n, n) + e.vload(wl, n);
+    e.vstore(wo, n, w);
+}
+
+template <typename S>
+__global__ void k_broot(Plan p, S* ws) {
+    const int64_t b = blockIdx.x;
+    S* inst = ws + b * p.stride;
+    const int root = p.ft.off[p.ft.nlev - 1];
+    coop_copy(inst + p.o_pend + (int64_t)root * p.n, inst + p.o_qp + (int64_t)p.N * p.n, p.n);
+    coop_copy(inst + p.o_pp + (int64_t)p.N * p.n, inst + p.o_qp + (int64_t)p.N * p.n, p.n);
+}
+
+// backward down-sweep: pend = gradient right after the node's last stage.
+//   odd j (right child): pend(parent);  even j: M(l, j+1)' pend(parent) + w(l, j+1)
+template <typename S, class E>
+__global__ __launch_bounds__(64) void k_bvec_down(Plan p, S* ws, int lvl) {
+    using T = typename E::T;
+    __shared__ Lds<E> L;
+    const E e(threadIdx.x);
+    const int n = p.n;
+    const int cnt = p.ft.cnt[lvl];
+    const int64_t b = blockIdx.x / cnt;
+    const int j = blockIdx.x % cnt;
+    S* inst = ws + b * p.stride;
+    const S* par = inst + p.o_pend + (int64_t)(p.ft.off[lvl + 1] + j / 2) * n;
+    S* out = inst + p.o_pend + (int64_t)(p.ft.off[lvl] + j) * n;
+    if ((j & 1) || j + 1 >= cnt) {
+        coop_copy(out, par, n);
+        return;
+    }
+    stage(e, L.sA, inst + p.o_ftree + (int64_t)(p.ft.off[lvl] + j + 1) * p.frec, n, n, n);
+    wg_sync();
+    const T v = e.template matvec<true>(L.sA, e.vload(par, n), L.vb[0], n, n) +
+                e.vload(inst + p.o_w + (int64_t)(p.ft.off[lvl] + j + 1) * n, n);
+    e.vstore(out, n, v);
+}
+
+// kff'_k = -G^{-1} h'_k,  h'_k = B'(p'_{k+1} + P_{k+1} c'_k) + r'_k;
+// p'_k = Abar' p'_{k+1} + d_k;  new forward leaf vector B kff' + c'.
+template <typename S, class E>
+__global__ __launch_bounds__(64) void k_ref_kff(Plan p, In<S> in, S* ws) {
+    using T = typename E::T;
+    __shared__ Lds<E> L;
+    const E e(threadIdx.x);
+    const int N = p.N, n = p.n, m = p.m, nn = n * n;
+    const int64_t b = blockIdx.x / N;
+    const int k = blockIdx.x % N;
+    const Ptr<S> P(p, in);
+    S* inst = ws + b * p.stride;
+    const S* Pn = inst + p.o_suf + (int64_t)suffix_id(p.rt, 0, k + 1) * p.srec;
+    const S* leaf = inst + p.o_ftree + (int64_t)k * p.frec;
+    const T pn = e.vload(inst + p.o_pend + (int64_t)k * n, n);     // p'_{k+1}
+    const T cpv = e.vload(inst + p.o_cp + (int64_t)k * n, n);
+    stage(e, L.sA, Pn, n, n, n);
+    stage(e, L.sX, leaf, n, n, n);
+    wg_sync();
+    const T v = pn + e.template matvec<false>(L.sA, cpv, L.vb[0], n, n);
+    const T pk = e.template matvec<true>(L.sX, pn, L.vb[1], n, n) + e.vload(inst + p.o_w + (int64_t)k * n, n);
+    e.vstore(inst + p.o_pp + (int64_t)k * n, n, pk);
+    wg_sync();
+    stage(e, L.sX, P.B(b, k), n, m, m);                   // B
+    stage(e, L.sA, inst + p.o_LG + (int64_t)k * m * m, m, m, m);
+    wg_sync();
+    fill_dinv<E>(L.sA, L.dA, m);
+    T h[1] = {e.template matvec<true>(L.sX, v, L.vb[0], n, m) + e.vload(inst + p.o_rp + (int64_t)k * m, m)};
+    wg_sync();
+    typename E::Tile none[1];
+    e.template trsm<true, 0, 1>(L.sA, L.dA, m, none, h, L.rb);
+    e.template trsm<false, 0, 1>(L.sA, L.dA, m, none, h, L.rb);
+    const T kf = -h[0];
+    e.vstore(inst + p.o_kffp + (int64_t)k * m, m, kf);
+    const T bb = e.template matvec<false>(L.sX, kf, L.vb[1], m, n) + cpv;
+    e.vstore(inst + p.o_ftree + (int64_t)k * p.frec + nn, n, bb);
+}
+
+// ---------------------------------------------------------------------------
+// Plain baseline: the sequential Riccati recursion of eq. (lqr), forward pass
+// and costates, one group per instance (workspace: P_k, p_k in the suffix
+// area indexed by stage, K_k, k_k).
+// ---------------------------------------------------------------------------
+template <typename S, class E>
+__global__ __launch_bounds__(64) void k_plain(Plan p, In<S> in, Out<S> out, S* ws) {
+    using T = typename E::T;
+    __shared__ Lds3<E> L;
+    const E e(threadIdx.x);
+    const int N = p.N, n = p.n, m = p.m, nn = n * n;
+    const int64_t b = blockIdx.x;
+    const Ptr<S> P(p, in);
+    S* inst = ws + b * p.stride;
+    S* Pst = inst + p.o_suf;                               // P_k, p_k at k * srec
+    typename E::Tile t, tPB, tG, tH, tHc, tPA;
+    e.load(t, P.Q(b, N), n, n, n);
+    to_lds_sym(e, t, L.sP);
+    e.store_sym(t, Pst + (int64_t)N * p.srec, n);
+    T pn = e.vload(P.q(b, N), n);
+    e.vstore(Pst + (int64_t)N * p.srec + nn, n, pn);
+    bool ok = true;
+    for (int k = N - 1; k >= 0; --k) {
+        wg_sync();
+        stage(e, L.sX, P.B(b, k), n, m, m);               // sX = B
+        wg_sync();
+        const T v = e.template matvec<false>(L.sP, e.vload(P.c(b, k), n), L.vb[0], n, n) + pn;
+        e.zero(tPB);
+        e.template gemm<false, false>(tPB, L.sP, L.sX, n); // P'B
+        const T h = e.template matvec<true>(L.sX, v, L.vb[1], n, m) + e.vload(P.r(b, k), m);
+        wg_sync();
+        e.to_lds(tPB, L.sA);                              // sA = P'B
+        wg_sync();
+        e.load(tG, P.R(b, k), m, m, m);
+        e.template gemm<true, false>(tG, L.sA, L.sX, n);   // G
+        wg_sync();
+        stage(e, L.sX, P.A(b, k), n, n, n);               // sX = A
+        wg_sync();
+        e.template load<true>(tH, P.M(b, k), m, n, m);
+        e.template gemm<true, false>(tH, L.sA, L.sX, n);   // H
+        e.zero(tPA);
+        e.template gemm<false, false>(tPA, L.sP, L.sX, n); // P'A
+        const T pa = e.template matvec<true>(L.sX, v, L.vb[0], n, n);   // A'v
+#pragma unroll
+        for (int a = 0; a < E::TS; ++a)
+#pragma unroll
+            for (int c = 0; c < E::TS; ++c) tHc[a][c] = tH[a][c];
+        T dmin, dmax, nov[1];
+        ok = e.template chol<0>(tG, m, L.cb, L.dA, nov, dmin, dmax) && ok;
+        e.to_lds(tG, L.sA);                               // sA = L_G
+        wg_sync();
+        typename E::Tile KK[1];
+#pragma unroll
+        for (int a = 0; a < E::TS; ++a)
+#pragma unroll
+            for (int c = 0; c < E::TS; ++c) KK[0][a][c] = tH[a][c];
+        T hv[1] = {h};
+        e.template trsm<true, 1, 1>(L.sA, L.dA, m, KK, hv, L.rb);
+        e.template trsm<false, 1, 1>(L.sA, L.dA, m, KK, hv, L.rb);
+        negate<E>(KK[0]);
+        hv[0] = -hv[0];
+        e.store(KK[0], inst + p.o_K + (int64_t)k * m * n, m, n, n);
+        e.vstore(inst + p.o_kff + (int64_t)k * m, m, hv[0]);
+        // P_k = Q + A'(P'A) + K'H,  p_k = q + A'v + K'h
+        wg_sync();
+        e.to_lds(tPA, L.sP);                              // sP = P'A
+        wg_sync();
+        e.load(t, P.Q(b, k), n, n, n);
+        e.template gemm<true, false>(t, L.sX, L.sP, n);
+        wg_sync();
+        e.to_lds(KK[0], L.sA);                            // sA = K
+        e.to_lds(tHc, L.sX);                              // sX = H
+        wg_sync();
+        e.template gemm<true, false>(t, L.sA, L.sX, m);
+        pn = e.vload(P.q(b, k), n) + pa + e.template matvec<true>(L.sA, h, L.vb[1], m, n);
+        wg_sync();
+        to_lds_sym(e, t, L.sP);
+        e.store_sym(t, Pst + (int64_t)k * p.srec, n);
+        e.vstore(Pst + (int64_t)k * p.srec + nn, n, pn);
+    }
+    if (!ok) set_status(out.status, b, 2);
+    // forward pass and costates
+    T x = e.vload(P.x0(b), n);
+    bool fin = true;
+    for (int k = 0; k <= N; ++k) {
+        wg_sync();
+        stage(e, L.sP, Pst + (int64_t)k * p.srec, n, n, n);
+        if (k < N) {
+            stage(e, L.sA, inst + p.o_K + (int64_t)k * m * n, m, n, n);
+            stage(e, L.sX, P.A(b, k), n, n, n);
+        }
+        wg_sync();
+        const T lam = e.template matvec<false>(L.sP, x, L.vb[0], n, n) + e.vload(Pst + (int64_t)k * p.srec + nn, n);
+        e.vstore(out.x + (b * (N + 1) + k) * n, n, x);
+        e.vstore(out.lam + (b * (N + 1) + k) * n, n, lam);
+        fin = fin && (e.lg >= n || (finite_(x) && finite_(lam)));
+        if (k == N) break;
+        const T u = e.template matvec<false>(L.sA, x, L.vb[1], n, m) + e.vload(inst + p.o_kff + (int64_t)k * m, m);
+        e.vstore(out.u + (b * N + k) * m, m, u);
+        fin = fin && (e.lg >= m || finite_(u));
+        wg_sync();
+        T xn = e.template matvec<false>(L.sX, x, L.vb[0], n, n) + e.vload(P.c(b, k), n);
+        wg_sync();
+        stage(e, L.sA, P.B(b, k), n, m, m);
+        wg_sync();
+        xn += e.template matvec<false>(L.sA, u, L.vb[1], m, n);
+        x = xn;
+    }
+    if (!wave_all(fin)) set_status(out.status, b, 1);
+}
+
+}  // namespace lqr

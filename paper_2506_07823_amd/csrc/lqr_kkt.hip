@@ -1,0 +1,372 @@
+// lqr_kkt.hip -- host side of the C ABI declared in include/lqr_kkt.h.
+//
+// Builds the launch plan (tree shapes, workspace layout), validates the
+// arguments, and enqueues the kernels of kernels.hpp on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lqr_kkt.h"
+#include "runs.hpp"
+
+using namespace lqr;
+
+thread_local std::string g_err;
+thread_local lqr::Timer* g_timer = nullptr;
+
+lqr::Timer*& lqr::current_timer() { return g_timer; }
+
+int lqr::fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+namespace lqr {
+LQR_DECLARE_RUNS(1)
+LQR_DECLARE_RUNS(2)
+LQR_DECLARE_RUNS(3)
+LQR_DECLARE_RUNS(4)
+LQR_DECLARE_RUNS(5)
+LQR_DECLARE_RUNS(6)
+LQR_DECLARE_RUNS(8)
+}  // namespace lqr
+
+namespace {
+
+Tree make_tree(int leaves) {
+    Tree t;
+    std::memset(&t, 0, sizeof t);
+    t.nlev = 1;
+    t.cnt[0] = leaves;
+    t.off[0] = 0;
+    t.total = leaves;
+    while (t.cnt[t.nlev - 1] > 1) {
+        t.cnt[t.nlev] = (t.cnt[t.nlev - 1] + 1) / 2;
+        t.off[t.nlev] = t.total;
+        t.total += t.cnt[t.nlev];
+        ++t.nlev;
+    }
+    return t;
+}
+
+// padded-order class: TS = ceil(max(n, m) / 8); built classes below
+constexpr int kTS[] = {1, 2, 3, 4, 5, 6, 8};
+int pick_ts(int n, int m) {
+    const int d = n > m ? n : m;
+    for (int ts : kTS)
+        if (8 * ts >= d) return ts;
+    return 0;
+}
+
+int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+Plan make_plan(int64_t batch, int N, int n, int m, size_t esize, const lqr_opts& o) {
+    Plan p;
+    std::memset(&p, 0, sizeof p);
+    p.batch = batch;
+    p.N = N; p.n = n; p.m = m;
+    const int64_t nn = (int64_t)n * n;
+    p.rec = (int)(3 * nn + 2 * n);
+    p.srec = (int)(nn + n);
+    p.frec = (int)(nn + n);
+    p.rt = make_tree(N + 1);
+    p.ft = make_tree(N);
+    int64_t off = 0;
+    auto sec = [&](int64_t count) { int64_t o = off; off = align_up(off + count, 64); return o; };
+    p.o_tree = sec((int64_t)p.rt.total * p.rec);
+    p.o_suf = sec((int64_t)p.rt.total * p.srec);
+    p.o_K = sec((int64_t)N * m * n);
+    p.o_kff = sec((int64_t)N * m);
+    p.o_LG = sec((int64_t)N * m * m);
+    p.o_ftree = sec((int64_t)p.ft.total * p.frec);
+    p.o_xs = sec((int64_t)p.ft.total * n);
+    p.o_w = sec((int64_t)p.ft.total * n);
+    p.o_pend = sec((int64_t)p.ft.total * n);
+    p.o_cp = sec((int64_t)N * n);
+    p.o_qp = sec((int64_t)(N + 1) * n);
+    p.o_rp = sec((int64_t)N * m);
+    p.o_x0p = sec(n);
+    p.o_pp = sec((int64_t)(N + 1) * n);
+    p.o_kffp = sec((int64_t)N * m);
+    p.stride = off;
+    p.dstride = 2 * (N + 1);
+    p.cond_thr = o.cond_threshold;
+    p.fallback = esize == 4 ? o.fallback : 0;   // the FP64 path has nothing to fall back to
+    return p;
+}
+
+struct Layout {
+    size_t main_bytes, int_off, dbl_off, total;
+};
+
+Layout layout(const Plan& p, size_t esize) {
+    Layout l;
+    l.main_bytes = (size_t)align_up((int64_t)(p.batch * p.stride * (int64_t)esize), 256);
+    l.int_off = l.main_bytes;
+    l.dbl_off = l.int_off + (size_t)align_up(queue_layout(p).total * 4, 256);
+    l.total = l.dbl_off + (size_t)align_up(p.batch * p.dstride * 8, 256);
+    return l;
+}
+
+bool aligned(const void* ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
+
+int check_dims(int64_t batch, int N, int n, int m) {
+    if (batch < 1) return fail(LQR_EINVAL, "batch must be >= 1 (got %lld)", (long long)batch);
+    if (N < 1 || n < 1 || m < 1) return fail(LQR_EINVAL, "N, n, m must be >= 1 (got %d, %d, %d)", N, n, m);
+    if (pick_ts(n, m) == 0) return fail(LQR_EUNSUPPORTED, "n=%d m=%d exceed the built shape classes (<= 64)", n, m);
+    if (N + 1 > (1 << (LQR_MAXLEV - 2))) return fail(LQR_EINVAL, "N=%d too large", N);
+    const int64_t tasks = batch * (int64_t)(N + 1);
+    if (tasks > (int64_t)0x7fffffff) return fail(LQR_EINVAL, "batch*(N+1) exceeds the grid limit");
+    return LQR_OK;
+}
+
+template <typename S>
+int dispatch(int ts, int method, const Plan& p, hipStream_t s, const In<S>& in, const Out<S>& out, S* ws,
+             int32_t* iws, double* dws, int refine, double* resid_out) {
+#define LQR_CASE(TSV)                                                                    \
+    case TSV:                                                                            \
+        return method == LQR_METHOD_SCAN                                                 \
+                   ? run_scan<S, TSV>(p, s, in, out, ws, iws, dws, refine, resid_out)    \
+                   : run_plain<S, TSV>(p, s, in, out, ws, iws, dws, resid_out);
+    switch (ts) {
+        LQR_CASE(1) LQR_CASE(2) LQR_CASE(3) LQR_CASE(4) LQR_CASE(5) LQR_CASE(6) LQR_CASE(8)
+        default: return fail(LQR_EUNSUPPORTED, "no shape class for TS=%d", ts);
+    }
+#undef LQR_CASE
+}
+
+template <typename S>
+int dispatch_resid(int ts, const Plan& p, hipStream_t s, const In<S>& in, const S* x, const S* u,
+                   const S* lam, S* ws, double* dws, double* rel) {
+#define LQR_CASE(TSV) \
+    case TSV: return run_resid<S, TSV>(p, s, in, x, u, lam, ws, dws, rel);
+    switch (ts) {
+        LQR_CASE(1) LQR_CASE(2) LQR_CASE(3) LQR_CASE(4) LQR_CASE(5) LQR_CASE(6) LQR_CASE(8)
+        default: return fail(LQR_EUNSUPPORTED, "no shape class for TS=%d", ts);
+    }
+#undef LQR_CASE
+}
+
+}  // namespace
+
+namespace {
+const char* const kFamNames[F_COUNT] = {
+    "clear", "element", "element_fp64", "up", "root", "down", "policy", "policy_fp64", "fwd_up", "fwd_root",
+    "fwd_down", "recover", "residual", "ref_d", "bwd_up", "bwd_root", "bwd_down", "ref_kff", "fwd_up_vec",
+    "recover_add", "reduce", "plain_riccati", "up_fp64", "down_fp64"};
+
+// Per-handle launch timer: two HIP events around every launch, read back by
+// lqr_timing_report.
+struct EventTimer final : lqr::Timer {
+    struct Rec { int fam; hipEvent_t a, b; double flops, bytes; };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t get() {
+        if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    Rec cur{};
+    void before(hipStream_t s, int fam, double flops, double bytes) override {
+        cur = Rec{fam, get(), get(), flops, bytes};
+        if (cur.a) (void)hipEventRecord(cur.a, s);
+    }
+    void after(hipStream_t s) override {
+        if (cur.b) (void)hipEventRecord(cur.b, s);
+        if (cur.a && cur.b) recs.push_back(cur);
+    }
+    ~EventTimer() override {
+        for (auto& r : recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+struct TimerScope {
+    explicit TimerScope(lqr::Timer* t) { g_timer = t; }
+    ~TimerScope() { g_timer = nullptr; }
+};
+}  // namespace
+
+struct lqr_handle_s {
+    int device;
+    bool timing = false;
+    EventTimer timer;
+};
+
+extern "C" {
+
+void lqr_opts_default(lqr_opts* o, int32_t dtype) {
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->dtype = dtype;
+    o->method = LQR_METHOD_SCAN;
+    o->refine_sweeps = dtype == LQR_F32 ? 1 : 0;
+    o->fallback = 1;
+    o->cond_threshold = 1e6;
+    o->resid_out = nullptr;
+}
+
+int lqr_create(lqr_handle_t* h, int device) {
+    if (!h) return fail(LQR_EINVAL, "null handle pointer");
+    int count = 0;
+    HIPCHK(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) return fail(LQR_EINVAL, "device %d out of range (%d devices)", device, count);
+    lqr_handle_s* hh = new lqr_handle_s;
+    hh->device = device;
+    *h = hh;
+    return LQR_OK;
+}
+
+int lqr_destroy(lqr_handle_t h) {
+    delete h;
+    return LQR_OK;
+}
+
+int lqr_max_dim(void) { return 64; }
+
+const char* lqr_last_error(void) { return g_err.c_str(); }
+
+int lqr_workspace_size(lqr_handle_t h, int64_t batch, int N, int n, int m, const lqr_opts* opts,
+                       size_t* bytes) {
+    (void)h;
+    if (!bytes) return fail(LQR_EINVAL, "null output pointer");
+    lqr_opts o;
+    if (opts) o = *opts; else lqr_opts_default(&o, LQR_F32);
+    LCHK(check_dims(batch, N, n, m));
+    if (o.dtype != LQR_F32 && o.dtype != LQR_F64) return fail(LQR_EINVAL, "bad dtype %d", o.dtype);
+    const size_t es = o.dtype == LQR_F32 ? 4 : 8;
+    *bytes = layout(make_plan(batch, N, n, m, es, o), es).total;
+    return LQR_OK;
+}
+
+int lqr_kkt_solve(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int m, const void* A,
+                  const void* B, const void* c, const void* Q, const void* R, const void* M, const void* q,
+                  const void* r, const void* x0, void* x, void* u, void* lam, int32_t* status,
+                  void* workspace, size_t workspace_bytes, const lqr_opts* opts) {
+    if (!h) return fail(LQR_EINVAL, "null handle");
+    lqr_opts o;
+    if (opts) o = *opts; else lqr_opts_default(&o, LQR_F32);
+    LCHK(check_dims(batch, N, n, m));
+    if (o.dtype != LQR_F32 && o.dtype != LQR_F64) return fail(LQR_EINVAL, "bad dtype %d", o.dtype);
+    if (o.method != LQR_METHOD_SCAN && o.method != LQR_METHOD_SEQ_RICCATI)
+        return fail(LQR_EINVAL, "bad method %d", o.method);
+    if (o.refine_sweeps < 0 || o.refine_sweeps > 1) return fail(LQR_EINVAL, "refine_sweeps must be 0 or 1");
+    if (!(o.cond_threshold > 1.0)) return fail(LQR_EINVAL, "cond_threshold must be > 1");
+    const size_t es = o.dtype == LQR_F32 ? 4 : 8;
+    const void* ins[] = {A, B, c, Q, R, M, q, r, x0};
+    const char* names[] = {"A", "B", "c", "Q", "R", "M", "q", "r", "x0"};
+    for (int i = 0; i < 9; ++i) {
+        if (!ins[i]) return fail(LQR_EINVAL, "null input %s", names[i]);
+        if (!aligned(ins[i], es)) return fail(LQR_EINVAL, "input %s not aligned to %zu bytes", names[i], es);
+    }
+    if (!x || !u || !lam || !status || !workspace) return fail(LQR_EINVAL, "null output, status or workspace");
+    if (!aligned(x, es) || !aligned(u, es) || !aligned(lam, es) || !aligned(status, 4))
+        return fail(LQR_EINVAL, "misaligned output");
+    if (!aligned(workspace, 256)) return fail(LQR_EINVAL, "workspace must be 256-byte aligned");
+    if (o.resid_out && !aligned(o.resid_out, 8)) return fail(LQR_EINVAL, "misaligned resid_out");
+    const Plan p = make_plan(batch, N, n, m, es, o);
+    const Layout lay = layout(p, es);
+    if (workspace_bytes < lay.total)
+        return fail(LQR_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", workspace_bytes, lay.total);
+    HIPCHK(hipSetDevice(h->device));
+    hipStream_t s = (hipStream_t)stream;
+    char* wsb = (char*)workspace;
+    int32_t* iws = (int32_t*)(wsb + lay.int_off);
+    double* dws = (double*)(wsb + lay.dbl_off);
+    const int ts = pick_ts(n, m);
+    const int refine = o.method == LQR_METHOD_SCAN ? o.refine_sweeps : 0;
+    TimerScope ts_scope(h->timing ? &h->timer : nullptr);
+    if (o.dtype == LQR_F32) {
+        In<float> in{(const float*)A, (const float*)B, (const float*)c, (const float*)Q, (const float*)R,
+                     (const float*)M, (const float*)q, (const float*)r, (const float*)x0};
+        Out<float> out{(float*)x, (float*)u, (float*)lam, status};
+        return dispatch<float>(ts, o.method, p, s, in, out, (float*)wsb, iws, dws, refine, o.resid_out);
+    }
+    In<double> in{(const double*)A, (const double*)B, (const double*)c, (const double*)Q, (const double*)R,
+                  (const double*)M, (const double*)q, (const double*)r, (const double*)x0};
+    Out<double> out{(double*)x, (double*)u, (double*)lam, status};
+    return dispatch<double>(ts, o.method, p, s, in, out, (double*)wsb, iws, dws, refine, o.resid_out);
+}
+
+int lqr_kkt_residual(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int m, int32_t dtype,
+                     const void* A, const void* B, const void* c, const void* Q, const void* R, const void* M,
+                     const void* q, const void* r, const void* x0, const void* x, const void* u,
+                     const void* lam, double* rel, void* workspace, size_t workspace_bytes) {
+    if (!h) return fail(LQR_EINVAL, "null handle");
+    LCHK(check_dims(batch, N, n, m));
+    if (dtype != LQR_F32 && dtype != LQR_F64) return fail(LQR_EINVAL, "bad dtype %d", dtype);
+    const void* ptrs[] = {A, B, c, Q, R, M, q, r, x0, x, u, lam, rel, workspace};
+    for (const void* ptr : ptrs)
+        if (!ptr) return fail(LQR_EINVAL, "null pointer argument");
+    lqr_opts o;
+    lqr_opts_default(&o, dtype);
+    const size_t es = dtype == LQR_F32 ? 4 : 8;
+    const Plan p = make_plan(batch, N, n, m, es, o);
+    const Layout lay = layout(p, es);
+    if (workspace_bytes < lay.total)
+        return fail(LQR_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", workspace_bytes, lay.total);
+    HIPCHK(hipSetDevice(h->device));
+    hipStream_t s = (hipStream_t)stream;
+    char* wsb = (char*)workspace;
+    double* dws = (double*)(wsb + lay.dbl_off);
+    const int ts = pick_ts(n, m);
+    TimerScope ts_scope(h->timing ? &h->timer : nullptr);
+    if (dtype == LQR_F32) {
+        In<float> in{(const float*)A, (const float*)B, (const float*)c, (const float*)Q, (const float*)R,
+                     (const float*)M, (const float*)q, (const float*)r, (const float*)x0};
+        return dispatch_resid<float>(ts, p, s, in, (const float*)x, (const float*)u, (const float*)lam,
+                                     (float*)wsb, dws, rel);
+    }
+    In<double> in{(const double*)A, (const double*)B, (const double*)c, (const double*)Q, (const double*)R,
+                  (const double*)M, (const double*)q, (const double*)r, (const double*)x0};
+    return dispatch_resid<double>(ts, p, s, in, (const double*)x, (const double*)u, (const double*)lam,
+                                  (double*)wsb, dws, rel);
+}
+
+int lqr_timing_enable(lqr_handle_t h, int enable) {
+    if (!h) return fail(LQR_EINVAL, "null handle");
+    h->timing = enable != 0;
+    return LQR_OK;
+}
+
+int lqr_timing_report(lqr_handle_t h, char* buf, size_t len) {
+    if (!h || !buf || len == 0) return fail(LQR_EINVAL, "null handle or buffer");
+    HIPCHK(hipSetDevice(h->device));
+    struct Acc { int64_t launches = 0; double ms = 0, flops = 0, bytes = 0; } acc[F_COUNT];
+    for (auto& r : h->timer.recs) {
+        HIPCHK(hipEventSynchronize(r.b));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+        Acc& a = acc[r.fam];
+        a.launches += 1;
+        a.ms += ms;
+        a.flops += r.flops;
+        a.bytes += r.bytes;
+        h->timer.pool.push_back(r.a);
+        h->timer.pool.push_back(r.b);
+    }
+    h->timer.recs.clear();
+    std::string out;
+    char line[256];
+    for (int f = 0; f < F_COUNT; ++f) {
+        if (!acc[f].launches) continue;
+        snprintf(line, sizeof line, "%s %lld %.6f %.6e %.6e\n", kFamNames[f], (long long)acc[f].launches, acc[f].ms,
+                 acc[f].flops, acc[f].bytes);
+        out += line;
+    }
+    if (out.size() + 1 > len) return fail(LQR_ENOMEM, "report needs %zu bytes", out.size() + 1);
+    std::memcpy(buf, out.c_str(), out.size() + 1);
+    return LQR_OK;
+}
+
+}  // extern "C"

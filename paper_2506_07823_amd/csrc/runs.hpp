@@ -1,0 +1,255 @@
+// runs.hpp -- launch sequences of the scan, plain and residual paths.
+//
+// Instantiated once per padded-order class (inst.hip with LQR_TS defined) so
+// the classes compile in parallel; lqr_kkt.hip dispatches to them.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "../../include/lqr_kkt.h"
+#include "kernels.hpp"
+
+namespace lqr {
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+
+#define HIPCHK(expr)                                                                  \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess) return fail(LQR_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int WG = 64;
+
+// kernel families (diagnostic timing keys)
+enum Fam {
+    F_CLEAR, F_ELEM, F_ELEM_FB, F_UP, F_ROOT, F_DOWN, F_POLICY, F_POLICY_FB, F_FUP, F_FROOT, F_FDOWN,
+    F_RECOVER, F_RESID, F_REF_D, F_BUP, F_BROOT, F_BDOWN, F_REF_KFF, F_FUPV, F_RECOVER_ADD, F_REDUCE,
+    F_PLAIN, F_UP_FB, F_DOWN_FB, F_COUNT
+};
+
+// Optional per-launch timer (HIP events around each launch on its stream),
+// installed by the ABI layer for the duration of a call.
+struct Timer {
+    virtual ~Timer() {}
+    virtual void before(hipStream_t s, int fam, double flops, double bytes) = 0;
+    virtual void after(hipStream_t s) = 0;
+};
+Timer*& current_timer();
+
+template <typename K, typename... Args>
+int launch(int fam, double flops, double bytes, K kernel, int64_t grid, hipStream_t s, Args... args) {
+    if (grid <= 0) return LQR_OK;
+    Timer* t = current_timer();
+    if (t) t->before(s, fam, flops, bytes);
+    hipLaunchKernelGGL(kernel, dim3((unsigned)grid), dim3(WG), 0, s, args...);
+    if (t) t->after(s);
+    HIPCHK(hipGetLastError());
+    return LQR_OK;
+}
+
+// Layout of the int32 workspace: queue counters, then one id list per
+// (family, level) with room for every task of that launch.
+constexpr int kQElem = 0, kQPolicy = 1, kQUp = 2, kQDown = 2 + LQR_MAXLEV, kQCount = 64;
+struct Queues {
+    int64_t list[kQCount];   // offsets (int32 elements) of each list
+    int64_t total;
+};
+inline Queues queue_layout(const Plan& p) {
+    Queues q;
+    for (int i = 0; i < kQCount; ++i) q.list[i] = 0;
+    int64_t off = kQCount;
+    auto add = [&](int idx, int64_t n) { q.list[idx] = off; off += (n + 63) / 64 * 64; };
+    add(kQElem, p.batch * (p.N + 1));
+    add(kQPolicy, p.batch * p.N);
+    for (int l = 0; l + 1 < p.rt.nlev; ++l) add(kQUp + l, p.batch * p.rt.cnt[l + 1]);
+    for (int l = 0; l + 1 < p.rt.nlev; ++l) add(kQDown + l, p.batch * (p.rt.cnt[l] / 2));
+    q.total = off;
+    return q;
+}
+inline FbQueue fbq(int32_t* iws, const Queues& q, int idx) { return FbQueue{iws + idx, iws + q.list[idx]}; }
+inline int64_t drain_grid(int64_t tasks) { return tasks < 1024 ? tasks : 1024; }
+
+// Algorithmic work per unit (flops counted as 2 per multiply-add, the
+// symmetric and triangular products at their minimal cost; bytes = the
+// records a unit must read and write once).
+struct Work {
+    double n, m, es, rec, srec, frec;
+    explicit Work(const Plan& p, size_t esize)
+        : n(p.n), m(p.m), es((double)esize), rec(p.rec), srec(p.srec), frec(p.frec) {}
+    double elem_f() const { return m * m * m / 3 + 2 * n * m * m + 4 * n * n * m; }
+    double elem_b() const { return es * (2 * n * n + 2 * n * m + m * m + 2 * n + m + rec); }
+    double comb_f() const { return 67.0 / 6.0 * n * n * n; }          // general combine
+    double comb_b() const { return es * 3 * rec; }
+    double cheap_f() const { return 31.0 / 6.0 * n * n * n; }         // combine with a complete suffix
+    double cheap_b() const { return es * (rec + 2 * srec); }
+    double pol_f() const { return 6 * n * n * m + 4 * n * m * m + m * m * m / 3; }
+    double pol_b() const { return es * (n * n + 2 * n * m + m * m + 2 * n + m + srec + n * m + m + m * m + frec); }
+    double fup_f() const { return 2 * n * n * n; }
+    double fup_b() const { return es * 3 * frec; }
+    double vec_f() const { return 2 * n * n; }
+    double vec_b() const { return es * (frec + 2 * n); }
+    double rec_f() const { return 2 * n * n + 2 * n * m; }
+    double rec_b() const { return es * (srec + n * m + 2 * n + m); }
+    double resid_f() const { return 2 * (3 * n * n + 4 * n * m + m * m); }
+    double resid_b() const { return es * (2 * n * n + 2 * n * m + m * m + 6 * n + 2 * m); }
+    double plain_f(int N) const { return N * (4 * n * n * n + 6 * n * n * m + 4 * n * m * m + m * m * m / 3); }
+    double plain_b(int N) const { return es * N * (2 * n * n + 2 * n * m + m * m + 4 * n + m + n * n + n * m); }
+};
+
+#define LCHK(x)                    \
+    do {                           \
+        int rc_ = (x);             \
+        if (rc_ != LQR_OK) return rc_; \
+    } while (0)
+
+// ----------------------------------------------------------------- solve
+template <typename S, int TS>
+int run_scan(const Plan& p, hipStream_t s, const In<S>& in, const Out<S>& out, S* ws, int32_t* iws,
+             double* dws, int refine, double* resid_out) {
+    using E = Eng<S, 8, TS>;
+    using E64 = Eng<double, 8, TS>;
+    const Work w(p, sizeof(S));
+    const double B = (double)p.batch;
+    const int64_t Bi = p.batch;
+    const int N = p.N;
+    const Queues Qs = queue_layout(p);
+    const bool fb = sizeof(S) == 4 && p.fallback;
+    LCHK(launch(F_CLEAR, 0, 4.0 * Bi, k_clear<int32_t>, (Bi + 255) / 256 * 4, s, out.status, Bi, iws,
+                (int64_t)kQCount));
+    // a1: elements (+ FP64 redo of queued stages)
+    {
+        const FbQueue q = fbq(iws, Qs, kQElem);
+        LCHK(launch(F_ELEM, B * N * w.elem_f(), B * N * w.elem_b(), k_element<S, E, false>, Bi * (N + 1), s, p,
+                    in, ws, out.status, q));
+        if (fb)
+            LCHK(launch(F_ELEM_FB, 0, 0, k_element<S, E64, true>, drain_grid(Bi * (N + 1)), s, p, in, ws,
+                        out.status, q));
+    }
+    // a3: reverse scan, up-sweep then down-sweep
+    for (int l = 0; l + 1 < p.rt.nlev; ++l) {
+        const double u = B * (p.rt.cnt[l] / 2);
+        const FbQueue q = fbq(iws, Qs, kQUp + l);
+        LCHK(launch(F_UP, u * w.comb_f(), u * w.comb_b(), k_up<S, E, false>, Bi * p.rt.cnt[l + 1], s, p, ws, l,
+                    out.status, q));
+        if (fb)
+            LCHK(launch(F_UP_FB, 0, 0, k_up<S, E64, true>, drain_grid(Bi * p.rt.cnt[l + 1]), s, p, ws, l,
+                        out.status, q));
+    }
+    LCHK(launch(F_ROOT, 0, 2 * B * w.es * p.srec, k_root<S>, Bi, s, p, ws));
+    for (int l = p.rt.nlev - 2; l >= 0; --l) {
+        const double u = B * (p.rt.cnt[l] / 2);
+        const FbQueue q = fbq(iws, Qs, kQDown + l);
+        LCHK(launch(F_DOWN, u * w.cheap_f(), u * w.cheap_b(), k_down<S, E, false>, Bi * (p.rt.cnt[l] / 2), s, p,
+                    ws, l, out.status, q));
+        if (fb)
+            LCHK(launch(F_DOWN_FB, 0, 0, k_down<S, E64, true>, drain_grid(Bi * (p.rt.cnt[l] / 2)), s, p, ws, l,
+                        out.status, q));
+    }
+    // a4: policy and closed-loop maps
+    {
+        const FbQueue q = fbq(iws, Qs, kQPolicy);
+        LCHK(launch(F_POLICY, B * N * w.pol_f(), B * N * w.pol_b(), k_policy<S, E, false>, Bi * N, s, p, in, ws,
+                    out.status, q));
+        if (fb)
+            LCHK(launch(F_POLICY_FB, 0, 0, k_policy<S, E64, true>, drain_grid(Bi * N), s, p, in, ws, out.status, q));
+    }
+    // a5: forward scan of the closed-loop maps
+    for (int l = 0; l + 1 < p.ft.nlev; ++l) {
+        const double u = B * (p.ft.cnt[l] / 2);
+        LCHK(launch(F_FUP, u * w.fup_f(), u * w.fup_b(), k_fup<S, E, false>, Bi * p.ft.cnt[l + 1], s, p, ws, l));
+    }
+    LCHK(launch(F_FROOT, 0, 2 * B * w.es * p.n, k_froot<S>, Bi, s, p, ws, in.x0, (int64_t)p.n));
+    for (int l = p.ft.nlev - 2; l >= 0; --l) {
+        const double u = B * (p.ft.cnt[l] / 2);
+        LCHK(launch(F_FDOWN, u * w.vec_f(), u * w.vec_b(), k_fdown<S, E>, Bi * p.ft.cnt[l], s, p, ws, l));
+    }
+    // a6: controls and costates
+    LCHK(launch(F_RECOVER, B * (N + 1) * w.rec_f(), B * (N + 1) * w.rec_b(), k_recover<S, E, false>,
+                Bi * (N + 1), s, p, ws, out));
+    // a7: FP64 residual + one refinement sweep
+    if (refine > 0) {
+        LCHK(launch(F_RESID, B * (N + 1) * w.resid_f(), B * (N + 1) * w.resid_b(), k_resid<S, E64, true>,
+                    Bi * (N + 1), s, p, in, (const S*)out.x, (const S*)out.u, (const S*)out.lam, ws, dws));
+        LCHK(launch(F_REF_D, B * N * 3 * w.vec_f(), B * N * 3 * w.vec_b(), k_ref_d<S, E>, Bi * N, s, p, ws));
+        for (int l = 0; l + 1 < p.ft.nlev; ++l) {
+            const double u = B * (p.ft.cnt[l] / 2);
+            LCHK(launch(F_BUP, u * w.vec_f(), u * w.vec_b(), k_bvec_up<S, E>, Bi * p.ft.cnt[l + 1], s, p, ws, l));
+        }
+        LCHK(launch(F_BROOT, 0, 4 * B * w.es * p.n, k_broot<S>, Bi, s, p, ws));
+        for (int l = p.ft.nlev - 2; l >= 0; --l) {
+            const double u = B * (p.ft.cnt[l] / 2);
+            LCHK(launch(F_BDOWN, u * w.vec_f(), u * w.vec_b(), k_bvec_down<S, E>, Bi * p.ft.cnt[l], s, p, ws, l));
+        }
+        LCHK(launch(F_REF_KFF, B * N * 4 * w.vec_f(), B * N * 4 * w.vec_b(), k_ref_kff<S, E>, Bi * N, s, p, in, ws));
+        for (int l = 0; l + 1 < p.ft.nlev; ++l) {
+            const double u = B * (p.ft.cnt[l] / 2);
+            LCHK(launch(F_FUPV, u * w.vec_f(), u * w.vec_b(), k_fup<S, E, true>, Bi * p.ft.cnt[l + 1], s, p, ws, l));
+        }
+        LCHK(launch(F_FROOT, 0, 2 * B * w.es * p.n, k_froot<S>, Bi, s, p, ws, (const S*)(ws + p.o_x0p), p.stride));
+        for (int l = p.ft.nlev - 2; l >= 0; --l) {
+            const double u = B * (p.ft.cnt[l] / 2);
+            LCHK(launch(F_FDOWN, u * w.vec_f(), u * w.vec_b(), k_fdown<S, E>, Bi * p.ft.cnt[l], s, p, ws, l));
+        }
+        LCHK(launch(F_RECOVER_ADD, B * (N + 1) * w.rec_f(), B * (N + 1) * w.rec_b(), k_recover<S, E, true>,
+                    Bi * (N + 1), s, p, ws, out));
+    }
+    if (resid_out) {
+        LCHK(launch(F_RESID, B * (N + 1) * w.resid_f(), B * (N + 1) * w.resid_b(), k_resid<S, E64, false>,
+                    Bi * (N + 1), s, p, in, (const S*)out.x, (const S*)out.u, (const S*)out.lam, ws, dws));
+        LCHK(launch(F_REDUCE, 0, B * 16.0 * (N + 1), k_resid_reduce<double>, (Bi + 63) / 64, s, p,
+                    (const double*)dws, resid_out));
+    }
+    return LQR_OK;
+}
+
+template <typename S, int TS>
+int run_plain(const Plan& p, hipStream_t s, const In<S>& in, const Out<S>& out, S* ws, int32_t* iws,
+              double* dws, double* resid_out) {
+    using E = Eng<S, 8, TS>;
+    using E64 = Eng<double, 8, TS>;
+    const Work w(p, sizeof(S));
+    const double B = (double)p.batch;
+    const int64_t Bi = p.batch;
+    LCHK(launch(F_CLEAR, 0, 4.0 * B, k_clear<int32_t>, (Bi + 255) / 256 * 4, s, out.status, Bi, iws,
+                (int64_t)kQCount));
+    LCHK(launch(F_PLAIN, B * w.plain_f(p.N), B * w.plain_b(p.N), k_plain<S, E>, Bi, s, p, in, out, ws));
+    if (resid_out) {
+        LCHK(launch(F_RESID, B * (p.N + 1) * w.resid_f(), B * (p.N + 1) * w.resid_b(), k_resid<S, E64, false>,
+                    Bi * (p.N + 1), s, p, in, (const S*)out.x, (const S*)out.u, (const S*)out.lam, ws, dws));
+        LCHK(launch(F_REDUCE, 0, B * 16.0 * (p.N + 1), k_resid_reduce<double>, (Bi + 63) / 64, s, p,
+                    (const double*)dws, resid_out));
+    }
+    return LQR_OK;
+}
+
+template <typename S, int TS>
+int run_resid(const Plan& p, hipStream_t s, const In<S>& in, const S* x, const S* u, const S* lam, S* ws,
+              double* dws, double* rel) {
+    using E64 = Eng<double, 8, TS>;
+    const Work w(p, sizeof(S));
+    const double B = (double)p.batch;
+    LCHK(launch(F_RESID, B * (p.N + 1) * w.resid_f(), B * (p.N + 1) * w.resid_b(), k_resid<S, E64, false>,
+                p.batch * (p.N + 1), s, p, in, x, u, lam, ws, dws));
+    LCHK(launch(F_REDUCE, 0, B * 16.0 * (p.N + 1), k_resid_reduce<double>, (p.batch + 63) / 64, s, p,
+                (const double*)dws, rel));
+    return LQR_OK;
+}
+
+#define LQR_RUNS(PREFIX, TSV)                                                                               \
+    PREFIX template int run_scan<float, TSV>(const Plan&, hipStream_t, const In<float>&, const Out<float>&,  \
+                                             float*, int32_t*, double*, int, double*);                      \
+    PREFIX template int run_scan<double, TSV>(const Plan&, hipStream_t, const In<double>&, const Out<double>&,\
+                                              double*, int32_t*, double*, int, double*);                    \
+    PREFIX template int run_plain<float, TSV>(const Plan&, hipStream_t, const In<float>&, const Out<float>&, \
+                                              float*, int32_t*, double*, double*);                          \
+    PREFIX template int run_plain<double, TSV>(const Plan&, hipStream_t, const In<double>&,                  \
+                                               const Out<double>&, double*, int32_t*, double*, double*);     \
+    PREFIX template int run_resid<float, TSV>(const Plan&, hipStream_t, const In<float>&, const float*,      \
+                                              const float*, const float*, float*, double*, double*);        \
+    PREFIX template int run_resid<double, TSV>(const Plan&, hipStream_t, const In<double>&, const double*,   \
+                                               const double*, const double*, double*, double*, double*);
+
+#define LQR_DECLARE_RUNS(TSV) LQR_RUNS(extern, TSV)
+#define LQR_DEFINE_RUNS(TSV) LQR_RUNS(, TSV)
+
+}  // namespace lqr

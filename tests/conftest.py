@@ -18,3 +18,17 @@ def oracle_lib():
     import oracle
     oracle.build(force=False)
     return oracle
+
+
+@pytest.fixture(scope="session", autouse=True)
+def _built_library():
+    """Build the HIP library in-tree if it is missing (the GPU machine gets the
+    prebuilt one with the repository snapshot)."""
+    lib = os.path.join(ROOT, "paper_2506_07823_amd", "liblqr_kkt.so")
+    if not os.path.exists(lib):
+        import importlib.util
+        spec = importlib.util.spec_from_file_location("_lqr_build", os.path.join(ROOT, "paper_2506_07823_amd", "build.py"))
+        mod = importlib.util.module_from_spec(spec)
+        spec.loader.exec_module(mod)
+        mod.build(force=False)
+    yield
