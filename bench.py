@@ -14,7 +14,6 @@ Prints ONE JSON line.  `python bench.py [--steps K] [--warmup W]`.
 from __future__ import annotations
 
 import argparse
-import ctypes
 import json
 import os
 import sys
@@ -40,20 +39,25 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def parse_report(text):
-    fams = {}
-    for line in text.strip().splitlines():
-        name, launches, ms, fl, by = line.split()
-        fams[name] = dict(launches=int(launches), ms=float(ms), flops=float(fl), bytes=float(by))
-    return fams
-
-
-def timed_steps(L, dev, method, dtype_np, steps, warmup, want_timing):
+def timed_steps(L, dev, method, steps, warmup, want_timing, graph=False, refine=None):
+    """Warm up, then time `steps` solves (each bracketed by events on the
+    current stream).  graph=True captures one solve into a HIP graph and
+    times its replays instead of eager launches."""
     import torch
+    ws = L.Workspace()
     out = None
     for _ in range(warmup):
-        out = L.solve(*[dev[k] for k in L.FIELDS], method=method, want_resid=True, out=out)
+        out = L.solve(*[dev[k] for k in L.FIELDS], method=method, want_resid=True, out=out, workspace=ws,
+                          refine=refine)
     torch.cuda.synchronize()
+    g = None
+    if graph:
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            L.solve(*[dev[k] for k in L.FIELDS], method=method, want_resid=True, out=out, workspace=ws,
+                    refine=refine)
+        g.replay()
+        torch.cuda.synchronize()
     if want_timing:
         L.kernel_timing(True)
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
@@ -62,7 +66,11 @@ def timed_steps(L, dev, method, dtype_np, steps, warmup, want_timing):
     t0 = time.perf_counter()
     for i in range(steps):
         starts[i].record()
-        out = L.solve(*[dev[k] for k in L.FIELDS], method=method, want_resid=True, out=out)
+        if g is not None:
+            g.replay()
+        else:
+            out = L.solve(*[dev[k] for k in L.FIELDS], method=method, want_resid=True, out=out, workspace=ws,
+                          refine=refine)
         ends[i].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -100,6 +108,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1024)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--eager", action="store_true", help="time eager launches instead of graph replays")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the batch-sharded multi-GPU form "
@@ -115,18 +124,20 @@ def main():
     dev = {k: torch.from_numpy(v).to("cuda:0") for k, v in host.items()}
     torch.cuda.synchronize()
 
-    log("[bench] FP32 scan: timed steps")
-    wall, lat, _, resid, bad = timed_steps(L, dev, "scan", np.float32, a.steps, a.warmup, False)
-    log("[bench] FP32 scan: kernel timing pass")
-    _, _, fams, _, _ = timed_steps(L, dev, "scan", np.float32, max(3, a.steps // 5), 1, True)
+    log("[bench] FP32 scan: timed graph replays")
+    wall, lat, _, resid, bad = timed_steps(L, dev, "scan", a.steps, a.warmup, False, graph=not a.eager,
+                                           refine=2)
+    log("[bench] FP32 scan: kernel timing pass (eager, HIP events around every launch)")
+    _, _, fams, _, _ = timed_steps(L, dev, "scan", max(3, a.steps // 5), 1, True, refine=2)
     value = BATCH * a.steps / wall
     result = {
         "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": 1e3 * wall / a.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "whole-body-shaped LQR-KKT, n=36 m=12 N=100, batch 4096, FP32 scan + "
-                               "1 FP64-residual refinement sweep",
-                   "batch": BATCH, "N": N_STAGES, "n": NX, "m": NU, "method": "scan"},
+                               "FP64-residual refinement (second sweep only above 1e-5)",
+                   "batch": BATCH, "N": N_STAGES, "n": NX, "m": NU, "method": "scan",
+                   "launch": "eager" if a.eager else "hipGraph replay"},
         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
         "max_rel_kkt_residual": resid, "instances_with_status": bad,
     }
@@ -150,7 +161,7 @@ def main():
         del dev
         torch.cuda.empty_cache()
         pk = max(3, a.steps // 3)
-        pwall, plat, _, presid, pbad = timed_steps(L, dev64, "plain", np.float64, pk, 1, False)
+        pwall, plat, _, presid, pbad = timed_steps(L, dev64, "plain", pk, 1, False, graph=not a.eager)
         result["plain"] = {"value": BATCH * pk / pwall, "unit": "solves/s", "dtype": "f64", "steps": pk,
                            "ms_per_step": 1e3 * pwall / pk, "p50_ms": float(np.percentile(plat, 50)),
                            "p99_ms": float(np.percentile(plat, 99)), "max_rel_kkt_residual": presid,

@@ -38,6 +38,7 @@ class lqr_opts(ctypes.Structure):
         ("refine_sweeps", ctypes.c_int32),
         ("fallback", ctypes.c_int32),
         ("cond_threshold", ctypes.c_double),
+        ("refine_tol", ctypes.c_double),
         ("resid_out", ctypes.c_void_p),
     ]
 
@@ -168,7 +169,8 @@ _default_ws = {}
 
 
 def solve(A, B, c, Q, R, M, q, r, x0, *, method: str = "scan", refine: int | None = None,
-          fallback: bool = True, cond_threshold: float = 1e6, want_resid: bool = False,
+          fallback: bool = True, cond_threshold: float = 1e6, refine_tol: float = 1e-5,
+          want_resid: bool = False,
           workspace: Workspace | None = None, out=None, stream=None):
     """Batched LQR-KKT solve; returns dict x, u, lam, status (+ resid).
 
@@ -187,6 +189,7 @@ def solve(A, B, c, Q, R, M, q, r, x0, *, method: str = "scan", refine: int | Non
         o.refine_sweeps = int(refine)
     o.fallback = 1 if fallback else 0
     o.cond_threshold = float(cond_threshold)
+    o.refine_tol = float(refine_tol)
     if out is None:
         out = {
             "x": torch.empty((batch, N + 1, n), dtype=dtype, device=A.device),

@@ -28,7 +28,16 @@ template <typename T> __device__ __forceinline__ T dsqrt(T x);
 template <> __device__ __forceinline__ float dsqrt<float>(float x) { return __builtin_sqrtf(x); }
 template <> __device__ __forceinline__ double dsqrt<double>(double x) { return __builtin_sqrt(x); }
 
-__device__ __forceinline__ void wg_sync() { __syncthreads(); }
+// Every kernel of this library runs workgroups of exactly one wavefront, so
+// lanes hand data to each other through LDS with a wavefront-scope fence:
+// LDS instructions of one wavefront execute in issue order, and the fence
+// keeps the compiler from moving LDS accesses across the hand-off (a
+// workgroup barrier would also drain every outstanding global load).
+__device__ __forceinline__ void wg_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 template <typename T_, int G_, int TS_>
 struct Eng {
@@ -138,7 +147,9 @@ struct Eng {
 
     // acc (+)= op(X) op(Y) over k < K, X and Y in LDS slots.
     // op(X)(i,k) = TX ? X[k][i] : X[i][k];  op(Y)(k,j) = TY ? Y[j][k] : Y[k][j].
-    template <bool TX, bool TY>
+    // SYM: the product is symmetric and only its lower triangle is needed;
+    // the strictly-upper tile blocks (b > a) are skipped.  SUB: subtract.
+    template <bool TX, bool TY, bool SYM = false, bool SUB = false>
     __device__ __forceinline__ void gemm(Tile& acc, const T* X, const T* Y, int K) const {
 #pragma unroll 2
         for (int k = 0; k < K; ++k) {
@@ -150,24 +161,55 @@ struct Eng {
 #pragma unroll
             for (int a = 0; a < TS; ++a)
 #pragma unroll
-                for (int b = 0; b < TS; ++b) acc[a][b] = __builtin_fma(xa[a], yb[b], acc[a][b]);
+                for (int b = 0; b < TS; ++b)
+                    if (!SYM || b <= a) acc[a][b] = __builtin_fma(SUB ? -xa[a] : xa[a], yb[b], acc[a][b]);
         }
     }
 
-    template <bool TX, bool TY>
+    template <bool TX, bool TY, bool SYM = false>
     __device__ __forceinline__ void gemm_sub(Tile& acc, const T* X, const T* Y, int K) const {
-#pragma unroll 2
-        for (int k = 0; k < K; ++k) {
-            T xa[TS], yb[TS];
-#pragma unroll
-            for (int a = 0; a < TS; ++a) xa[a] = TX ? X[k * LD + row(a)] : X[row(a) * LD + k];
-#pragma unroll
-            for (int b = 0; b < TS; ++b) yb[b] = TY ? Y[col(b) * LD + k] : Y[k * LD + col(b)];
-#pragma unroll
-            for (int a = 0; a < TS; ++a)
-#pragma unroll
-                for (int b = 0; b < TS; ++b) acc[a][b] = __builtin_fma(-xa[a], yb[b], acc[a][b]);
+        gemm<TX, TY, SYM, true>(acc, X, Y, K);
+    }
+
+    // -------------------------------------------- coalesced global <-> LDS
+    // Whole-slot copy of a rows x cols global matrix (leading dim ldg) into an
+    // LDS slot, zero outside: consecutive lanes read consecutive elements.
+    template <typename S>
+    __device__ __forceinline__ void g2s(T* slot, const S* g, int rows, int cols, int ldg) const {
+        for (int idx = lg; idx < NP * NP; idx += GL) {
+            const int i = idx / NP, j = idx - (idx / NP) * NP;
+            slot[i * LD + j] = (i < rows && j < cols) ? T(g[(int64_t)i * ldg + j]) : T(0);
         }
+    }
+    // rows x cols of an LDS slot to global memory (coalesced)
+    template <typename S>
+    __device__ __forceinline__ void s2g(const T* slot, S* g, int rows, int cols, int ldg) const {
+        const float inv = 1.0f / (float)cols;
+        for (int idx = lg; idx < rows * cols; idx += GL) {
+            const int i = (int)(((float)idx + 0.5f) * inv);
+            const int j = idx - i * cols;
+            g[(int64_t)i * ldg + j] = S(slot[i * LD + j]);
+        }
+    }
+    // tile <- slot transposed
+    __device__ __forceinline__ void from_lds_t(Tile& t, const T* s) const {
+#pragma unroll
+        for (int a = 0; a < TS; ++a)
+#pragma unroll
+            for (int b = 0; b < TS; ++b) t[a][b] = s[col(b) * LD + row(a)];
+    }
+    // lower triangle of t mirrored into both triangles of an LDS slot
+    __device__ __forceinline__ void to_lds_sym(const Tile& t, T* s) const {
+#pragma unroll
+        for (int a = 0; a < TS; ++a)
+#pragma unroll
+            for (int b = 0; b <= a; ++b) {
+                const int i = row(a), j = col(b);
+                if (j <= i) {
+                    s[i * LD + j] = t[a][b];
+                    s[j * LD + i] = t[a][b];
+                }
+            }
     }
 
     // ------------------------------------------------------- lane vectors
@@ -199,7 +241,7 @@ struct Eng {
     // factorization continues with a unit pivot so values stay finite).
     // dmin/dmax receive the extreme diagonal entries of L.
     template <int NV>
-    __device__ bool chol(Tile& S, int n, T* cb, T* dinv, T (&gv)[NV > 0 ? NV : 1], T& dmin, T& dmax) const {
+    __device__ __forceinline__ bool chol(Tile& S, int n, T* cb, T* dinv, T (&gv)[NV > 0 ? NV : 1], T& dmin, T& dmax) const {
         bool ok = true;
         dmin = T(0);
         dmax = T(0);
@@ -231,11 +273,12 @@ struct Eng {
 #pragma unroll
                 for (int a = 0; a < TS; ++a) li[a] = c[row(a)] * inv;
 #pragma unroll
-                for (int b = 0; b < TS; ++b) lj[b] = c[col(b)] * inv;
+                for (int b = a0; b < TS; ++b) lj[b] = c[col(b)] * inv;
+                // trailing update of the lower triangle: blocks a >= b >= a0
 #pragma unroll
-                for (int a = 0; a < TS; ++a)
+                for (int a = a0; a < TS; ++a)
 #pragma unroll
-                    for (int b = 0; b < TS; ++b)
+                    for (int b = a0; b <= a; ++b)
                         if (row(a) > k && col(b) > k) S[a][b] = __builtin_fma(-li[a], lj[b], S[a][b]);
                 if (tx == t) {
 #pragma unroll
@@ -266,7 +309,7 @@ struct Eng {
     // reciprocal diagonal dinv.  Solves NT register tiles (their first n rows)
     // and NV lane vectors at once.  rb is LDS scratch of 2*(NT*NP+NV).
     template <bool LOWER, int NT, int NV>
-    __device__ void trsm(const T* sL, const T* dinv, int n, Tile (&X)[NT > 0 ? NT : 1],
+    __device__ __forceinline__ void trsm(const T* sL, const T* dinv, int n, Tile (&X)[NT > 0 ? NT : 1],
                          T (&vv)[NV > 0 ? NV : 1], T* rb) const {
         constexpr int RBS = (NT > 0 ? NT : 0) * NP + (NV > 0 ? NV : 0) + 1;
 #pragma unroll
@@ -291,9 +334,12 @@ struct Eng {
                 for (int v = 0; v < NV; ++v)
                     if (lg == k) r[NT * NP + v] = vv[v] * dk;
                 wg_sync();
+                // row blocks already solved (before a0 going forward, after a0
+                // going backward) are skipped
                 T lik[TS];
 #pragma unroll
                 for (int a = 0; a < TS; ++a) {
+                    if (LOWER ? a < a0 : a > a0) continue;
                     const int i = row(a);
                     const bool act = LOWER ? (i > k && i < n) : (i < k);
                     lik[a] = act ? (LOWER ? sL[i * LD + k] : sL[k * LD + i]) : T(0);
@@ -304,10 +350,12 @@ struct Eng {
 #pragma unroll
                     for (int b = 0; b < TS; ++b) rk[b] = r[it * NP + col(b)];
 #pragma unroll
-                    for (int a = 0; a < TS; ++a)
+                    for (int a = 0; a < TS; ++a) {
+                        if (LOWER ? a < a0 : a > a0) continue;
 #pragma unroll
                         for (int b = 0; b < TS; ++b)
                             X[it][a][b] = (a == a0 && ty == t) ? rk[b] : __builtin_fma(-lik[a], rk[b], X[it][a][b]);
+                    }
                 }
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {

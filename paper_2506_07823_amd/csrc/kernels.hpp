@@ -46,8 +46,15 @@ struct Plan {
     int64_t o_cp, o_qp, o_rp, o_x0p, o_pp, o_kffp;
     int64_t dstride;       // doubles per instance: partial norms 2*(N+1)
     double cond_thr;
+    double refine_tol;
     int fallback;
+    const int32_t* active;   // refinement gating: instances with active[b] == 0 skip (nullptr = all)
 };
+
+#define LQR_GATE(p, b) \
+    do {               \
+        if ((p).active && !(p).active[(b)]) return; \
+    } while (0)
 
 template <typename S>
 struct In {
@@ -111,23 +118,18 @@ __device__ __forceinline__ void coop_zero(D* dst, int count) {
 // load a rows x cols global matrix (optionally transposed) into an LDS slot
 template <class E, bool TR = false, typename S>
 __device__ __forceinline__ void stage(const E& e, typename E::T* slot, const S* g, int rows, int cols, int ldg) {
-    typename E::Tile t;
-    e.template load<TR>(t, g, rows, cols, ldg);
-    e.to_lds(t, slot);
+    if (!TR) {
+        e.g2s(slot, g, rows, cols, ldg);
+    } else {
+        typename E::Tile t;
+        e.template load<TR>(t, g, rows, cols, ldg);
+        e.to_lds(t, slot);
+    }
 }
 
 template <class E>
 __device__ __forceinline__ void to_lds_sym(const E& e, const typename E::Tile& t, typename E::T* s) {
-#pragma unroll
-    for (int a = 0; a < E::TS; ++a)
-#pragma unroll
-        for (int b = 0; b < E::TS; ++b) {
-            const int i = e.row(a), j = e.col(b);
-            if (j <= i) {
-                s[i * E::LD + j] = t[a][b];
-                s[j * E::LD + i] = t[a][b];
-            }
-        }
+    e.to_lds_sym(t, s);
 }
 
 template <class E>
@@ -237,7 +239,7 @@ __global__ void k_clear(I* status, int64_t batch, I* counters, int64_t ncount) {
 // Record layout: A | C | P | b | p.
 // ---------------------------------------------------------------------------
 template <typename S, class E, bool FB>
-__device__ void element_task(Lds<E>& L, const Plan& p, const In<S>& in, S* ws, int32_t* status, FbQueue q,
+__device__ __forceinline__ void element_task(Lds<E>& L, const Plan& p, const In<S>& in, S* ws, int32_t* status, FbQueue q,
                              int64_t task) {
     using T = typename E::T;
     const E e(threadIdx.x);
@@ -274,10 +276,10 @@ __device__ void element_task(Lds<E>& L, const Plan& p, const In<S>& in, S* ws, i
     e.template gemm_sub<true, false>(t, L.sA, L.sX, m);
     e.store(t, rec, n, n, n);                          // At
     e.zero(t);
-    e.template gemm<true, false>(t, L.sA, L.sA, m);
+    e.template gemm<true, false, true>(t, L.sA, L.sA, m);
     e.store_sym(t, rec + nn, n);                       // Ct
     e.load(t, P.Q(b, k), n, n, n);
-    e.template gemm_sub<true, false>(t, L.sX, L.sX, m);
+    e.template gemm_sub<true, false, true>(t, L.sX, L.sX, m);
     e.store_sym(t, rec + 2 * nn, n);                   // Pt
     const T bw = e.template matvec<true>(L.sA, vv[0], L.vb[0], m, n);
     e.vstore(rec + 3 * nn, n, e.vload(P.c(b, k), n) - bw);
@@ -304,35 +306,33 @@ __global__ __launch_bounds__(64) void k_element(Plan p, In<S> in, S* ws, int32_t
 // (A2 = C2 = b2 = 0), only P and p are formed and written to a suffix record.
 // ---------------------------------------------------------------------------
 template <class E, bool CHEAP, typename S>
-__device__ void combine(const E& e, Lds<E>& L, int n, const S* e1, const S* P2, const S* p2v,
-                        const S* e2, S* outA, S* outC, S* outP, S* outb, S* outp, bool& okp,
-                        typename E::T& kappa) {
+__device__ __forceinline__ void combine(const E& e, Lds<E>& L, int n, const S* e1, const S* P2, const S* p2v,
+                                        const S* e2, S* outA, S* outC, S* outP, S* outb, S* outp, bool& okp,
+                                        typename E::T& kappa) {
     using T = typename E::T;
     const int nn = n * n;
     typename E::Tile tS;
     T dmin, dmax;
     // L = chol(P2), g = L^{-1} p2
-    e.load(tS, P2, n, n, n);
+    e.g2s(L.sA, P2, n, n, n);
+    e.g2s(L.sX, e1 + nn, n, n, n);                         // sX = C1
     T g[1] = {e.vload(p2v, n)};
     const T p2l = g[0];
+    wg_sync();
+    e.from_lds(tS, L.sA);
     bool ok = e.template chol<1>(tS, n, L.cb, L.dA, g, dmin, dmax);
     T kap = cond_est(dmin, dmax);
     e.to_lds(tS, L.sA);                                   // sA = L
-    {
-        typename E::Tile tX;
-        e.load(tX, e1 + nn, n, n, n);                      // C1
-        e.to_lds(tX, L.sX);
-    }
     wg_sync();
     T cp = T(0);
     if (!CHEAP) cp = e.template matvec<false>(L.sX, p2l, L.vb[0], n, n);   // C1 p2
     e.zero(tS);
     e.template gemm<false, false>(tS, L.sX, L.sA, n);      // W = C1 L
     wg_sync();
-    e.to_lds(tS, L.sX);
+    e.to_lds(tS, L.sX);                                   // sX = W
     wg_sync();
     e.zero(tS);
-    e.template gemm<true, false>(tS, L.sA, L.sX, n);       // L' W
+    e.template gemm<true, false, true>(tS, L.sA, L.sX, n); // L' W (lower)
     e.add_identity(tS, n);
     T nov[1];
     ok = e.template chol<0>(tS, n, L.cb, L.dB, nov, dmin, dmax) && ok;   // tS = L_S
@@ -343,20 +343,17 @@ __device__ void combine(const E& e, Lds<E>& L, int n, const S* e1, const S* P2, 
     typename E::Tile YZ[2];
     typename E::Tile tC;
     if (!CHEAP) {
+        e.g2s(L.sX, e2, n, n, n);                         // A2
+        wg_sync();
         typename E::Tile Z1[1];
-        e.template load<true>(Z1[0], e2, n, n, n);         // A2'
+        e.from_lds_t(Z1[0], L.sX);                        // A2'
         e.template trsm<true, 1, 0>(L.sA, L.dA, n, Z1, nov, L.rb);   // Z1 = L^{-1} A2'
 #pragma unroll
         for (int a = 0; a < E::TS; ++a)
 #pragma unroll
             for (int bb = 0; bb < E::TS; ++bb) YZ[1][a][bb] = Z1[0][a][bb];
     }
-    {
-        typename E::Tile tX;
-        e.load(tX, e1, n, n, n);                           // A1
-        wg_sync();
-        e.to_lds(tX, L.sX);
-    }
+    e.g2s(L.sX, e1, n, n, n);                             // sX = A1
     wg_sync();
     e.zero(YZ[0]);
     e.template gemm<true, false>(YZ[0], L.sA, L.sX, n);    // L' A1
@@ -370,7 +367,7 @@ __device__ void combine(const E& e, Lds<E>& L, int n, const S* e1, const S* P2, 
         e.to_lds(YZ[1], L.sX);                             // sX = Z1
         wg_sync();
         e.zero(tC);
-        e.template gemm<true, false>(tC, L.sX, L.sX, n);   // Z1' Z1
+        e.template gemm<true, false, true>(tC, L.sX, L.sX, n);   // Z1' Z1 (lower)
     } else {
         vv[1] = T(0);
     }
@@ -394,24 +391,36 @@ __device__ void combine(const E& e, Lds<E>& L, int n, const S* e1, const S* P2, 
         vv[0] = v1[0];
     }
     e.to_lds(YZ[0], L.sX);                                 // sX = Y
+    e.g2s(L.sA, e1 + 2 * nn, n, n, n);                     // sA = P1
     wg_sync();
-    e.load(tS, e1 + 2 * nn, n, n, n);                      // P1
-    e.template gemm<true, false>(tS, L.sX, L.sX, n);       // + Y'Y
-    e.store_sym(tS, outP, n);
+    e.from_lds(tS, L.sA);
+    e.template gemm<true, false, true>(tS, L.sX, L.sX, n); // P1 + Y'Y (lower)
     const T pv = e.template matvec<true>(L.sX, vv[0], L.vb[1], n, n) + e.vload(e1 + 3 * nn + n, n);
     e.vstore(outp, n, pv);
+    wg_sync();
+    e.to_lds_sym(tS, L.sA);                                // sA = P
+    wg_sync();
+    e.s2g(L.sA, outP, n, n, n);
     if (!CHEAP) {
         wg_sync();
         e.to_lds(YZ[1], L.sA);                             // sA = Z
         wg_sync();
         e.zero(tS);
         e.template gemm<true, false>(tS, L.sA, L.sX, n);   // A = Z'Y
-        e.store(tS, outA, n, n, n);
-        e.template gemm_sub<true, false>(tC, L.sA, L.sA, n);   // Z1'Z1 - Z'Z
-        e.add_global(tC, e2 + nn, n, n, n);                // + C2
-        e.store_sym(tC, outC, n);
+        e.template gemm_sub<true, false, true>(tC, L.sA, L.sA, n);   // Z1'Z1 - Z'Z (lower)
         const T bv = e.template matvec<true>(L.sA, vv[1], L.vb[0], n, n) + e.vload(e2 + 3 * nn, n);
         e.vstore(outb, n, bv);
+        wg_sync();
+        e.to_lds(tS, L.sX);                                // sX = A
+        e.to_lds_sym(tC, L.sA);                            // sA = Z1'Z1 - Z'Z
+        wg_sync();
+        e.s2g(L.sX, outA, n, n, n);
+        // C = sA + C2 (coalesced read-add-write)
+        const float invn = 1.0f / (float)n;
+        for (int idx = e.lg; idx < nn; idx += E::GL) {
+            const int i = (int)(((float)idx + 0.5f) * invn), j = idx - i * n;
+            outC[idx] = S(L.sA[i * E::LD + j] + T(e2[nn + idx]));
+        }
     }
     wg_sync();
     okp = ok;
@@ -419,7 +428,7 @@ __device__ void combine(const E& e, Lds<E>& L, int n, const S* e1, const S* P2, 
 }
 
 template <typename S, class E, bool FB>
-__device__ void up_task(Lds<E>& L, const Plan& p, S* ws, int lvl, int32_t* status, FbQueue q, int64_t task) {
+__device__ __forceinline__ void up_task(Lds<E>& L, const Plan& p, S* ws, int lvl, int32_t* status, FbQueue q, int64_t task) {
     const E e(threadIdx.x);
     const int n = p.n, nn = n * n;
     const int cout = p.rt.cnt[lvl + 1], cin = p.rt.cnt[lvl];
@@ -461,7 +470,7 @@ __global__ void k_root(Plan p, S* ws) {
 
 // down-sweep at level lvl: odd node j gets node_j (x) suffix(level lvl+1, (j+1)/2)
 template <typename S, class E, bool FB>
-__device__ void down_task(Lds<E>& L, const Plan& p, S* ws, int lvl, int32_t* status, FbQueue q, int64_t task) {
+__device__ __forceinline__ void down_task(Lds<E>& L, const Plan& p, S* ws, int lvl, int32_t* status, FbQueue q, int64_t task) {
     const E e(threadIdx.x);
     const int n = p.n, nn = n * n;
     const int half = p.rt.cnt[lvl] / 2;
@@ -502,7 +511,7 @@ __global__ __launch_bounds__(64) void k_down(Plan p, S* ws, int lvl, int32_t* st
 // the leaf of the forward tree.  Stores K, k and L_G (reused by refinement).
 // ---------------------------------------------------------------------------
 template <typename S, class E, bool FB>
-__device__ void policy_task(Lds<E>& L, const Plan& p, const In<S>& in, S* ws, int32_t* status, FbQueue q,
+__device__ __forceinline__ void policy_task(Lds<E>& L, const Plan& p, const In<S>& in, S* ws, int32_t* status, FbQueue q,
                             int64_t task) {
     using T = typename E::T;
     const E e(threadIdx.x);
@@ -524,7 +533,7 @@ __device__ void policy_task(Lds<E>& L, const Plan& p, const In<S>& in, S* ws, in
     e.to_lds(t, L.sA);                                    // sA = P'B
     wg_sync();
     e.load(tG, P.R(b, k), m, m, m);
-    e.template gemm<true, false>(tG, L.sA, L.sX, n);       // R + (P'B)'B
+    e.template gemm<true, false, true>(tG, L.sA, L.sX, n); // R + (P'B)'B (lower)
     wg_sync();
     stage(e, L.sX, P.A(b, k), n, n, n);                   // sX = A
     wg_sync();
@@ -581,6 +590,7 @@ __global__ __launch_bounds__(64) void k_fup(Plan p, S* ws, int lvl) {
     const int cout = p.ft.cnt[lvl + 1], cin = p.ft.cnt[lvl];
     const int64_t b = blockIdx.x / cout;
     const int i = blockIdx.x % cout;
+    LQR_GATE(p, b);
     S* base = ws + b * p.stride + p.o_ftree;
     const S* l = base + (int64_t)(p.ft.off[lvl] + 2 * i) * p.frec;
     S* out = base + (int64_t)(p.ft.off[lvl + 1] + i) * p.frec;
@@ -607,6 +617,7 @@ __global__ __launch_bounds__(64) void k_fup(Plan p, S* ws, int lvl) {
 template <typename S>
 __global__ void k_froot(Plan p, S* ws, const S* x0, int64_t x0_stride) {
     const int64_t b = blockIdx.x;
+    LQR_GATE(p, b);
     const int root = p.ft.off[p.ft.nlev - 1];
     coop_copy(ws + b * p.stride + p.o_xs + (int64_t)root * p.n, x0 + b * x0_stride, p.n);
 }
@@ -622,6 +633,7 @@ __global__ __launch_bounds__(64) void k_fdown(Plan p, S* ws, int lvl) {
     const int cnt = p.ft.cnt[lvl];
     const int64_t b = blockIdx.x / cnt;
     const int j = blockIdx.x % cnt;
+    LQR_GATE(p, b);
     S* inst = ws + b * p.stride;
     const S* par = inst + p.o_xs + (int64_t)(p.ft.off[lvl + 1] + j / 2) * n;
     S* out = inst + p.o_xs + (int64_t)(p.ft.off[lvl] + j) * n;
@@ -648,6 +660,7 @@ __global__ __launch_bounds__(64) void k_recover(Plan p, S* ws, Out<S> out) {
     const int N = p.N, n = p.n, m = p.m, nn = n * n;
     const int64_t b = blockIdx.x / (N + 1);
     const int k = blockIdx.x % (N + 1);
+    LQR_GATE(p, b);
     S* inst = ws + b * p.stride;
     T x;
     if (k < N) {
@@ -711,6 +724,7 @@ __global__ __launch_bounds__(64) void k_resid(Plan p, In<S> in, const S* xs_, co
     const int N = p.N, n = p.n, m = p.m;
     const int64_t b = blockIdx.x / (N + 1);
     const int k = blockIdx.x % (N + 1);
+    LQR_GATE(p, b);
     const Ptr<S> P(p, in);
     const S* xk = xs_ + (b * (N + 1) + k) * n;
     const S* lk = ls_ + (b * (N + 1) + k) * n;
@@ -772,16 +786,21 @@ __global__ __launch_bounds__(64) void k_resid(Plan p, In<S> in, const S* xs_, co
     }
 }
 
+// rel[b] = ||r|| / ||(x0, c, q, r)||; with active_out, also mark the
+// instances still above tol for another refinement sweep.
 template <typename D>
-__global__ void k_resid_reduce(Plan p, const D* dws, D* rel) {
+__global__ void k_resid_reduce(Plan p, const D* dws, D* rel, int32_t* active_out, D tol) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= p.batch) return;
-    double rr = 0.0, bb = 0.0;
+    LQR_GATE(p, b);
+    D rr = 0.0, bb = 0.0;
     for (int k = 0; k <= p.N; ++k) {
         rr += dws[b * p.dstride + 2 * k];
         bb += dws[b * p.dstride + 2 * k + 1];
     }
-    rel[b] = bb > 0.0 ? __builtin_sqrt(rr) / __builtin_sqrt(bb) : __builtin_sqrt(rr);
+    const D r = bb > 0.0 ? __builtin_sqrt(rr) / __builtin_sqrt(bb) : __builtin_sqrt(rr);
+    rel[b] = r;
+    if (active_out) active_out[b] = !(r <= tol);
 }
 
 // ---------------------------------------------------------------------------
@@ -800,6 +819,7 @@ __global__ __launch_bounds__(64) void k_ref_d(Plan p, S* ws) {
     const int N = p.N, n = p.n, m = p.m;
     const int64_t b = blockIdx.x / N;
     const int k = blockIdx.x % N;
+    LQR_GATE(p, b);
     S* inst = ws + b * p.stride;
     const S* Pn = inst + p.o_suf + (int64_t)suffix_id(p.rt, 0, k + 1) * p.srec;
     stage(e, L.sA, Pn, n, n, n);
@@ -826,6 +846,7 @@ __global__ __launch_bounds__(64) void k_bvec_up(Plan p, S* ws, int lvl) {
     const int cout = p.ft.cnt[lvl + 1], cin = p.ft.cnt[lvl];
     const int64_t b = blockIdx.x / cout;
     const int i = blockIdx.x % cout;
+    LQR_GATE(p, b);
     S* inst = ws + b * p.stride;
     const S* wl = inst + p.o_w + (int64_t)(p.ft.off[lvl] + 2 * i) * n;
     S* wo = inst + p.o_w + (int64_t)(p.ft.off[lvl + 1] + i) * n;
@@ -842,6 +863,7 @@ __global__ __launch_bounds__(64) void k_bvec_up(Plan p, S* ws, int lvl) {
 template <typename S>
 __global__ void k_broot(Plan p, S* ws) {
     const int64_t b = blockIdx.x;
+    LQR_GATE(p, b);
     S* inst = ws + b * p.stride;
     const int root = p.ft.off[p.ft.nlev - 1];
     coop_copy(inst + p.o_pend + (int64_t)root * p.n, inst + p.o_qp + (int64_t)p.N * p.n, p.n);
@@ -859,6 +881,7 @@ __global__ __launch_bounds__(64) void k_bvec_down(Plan p, S* ws, int lvl) {
     const int cnt = p.ft.cnt[lvl];
     const int64_t b = blockIdx.x / cnt;
     const int j = blockIdx.x % cnt;
+    LQR_GATE(p, b);
     S* inst = ws + b * p.stride;
     const S* par = inst + p.o_pend + (int64_t)(p.ft.off[lvl + 1] + j / 2) * n;
     S* out = inst + p.o_pend + (int64_t)(p.ft.off[lvl] + j) * n;
@@ -883,6 +906,7 @@ __global__ __launch_bounds__(64) void k_ref_kff(Plan p, In<S> in, S* ws) {
     const int N = p.N, n = p.n, m = p.m, nn = n * n;
     const int64_t b = blockIdx.x / N;
     const int k = blockIdx.x % N;
+    LQR_GATE(p, b);
     const Ptr<S> P(p, in);
     S* inst = ws + b * p.stride;
     const S* Pn = inst + p.o_suf + (int64_t)suffix_id(p.rt, 0, k + 1) * p.srec;
@@ -945,7 +969,7 @@ __global__ __launch_bounds__(64) void k_plain(Plan p, In<S> in, Out<S> out, S* w
         e.to_lds(tPB, L.sA);                              // sA = P'B
         wg_sync();
         e.load(tG, P.R(b, k), m, m, m);
-        e.template gemm<true, false>(tG, L.sA, L.sX, n);   // G
+        e.template gemm<true, false, true>(tG, L.sA, L.sX, n);   // G (lower)
         wg_sync();
         stage(e, L.sX, P.A(b, k), n, n, n);               // sX = A
         wg_sync();
@@ -979,12 +1003,12 @@ __global__ __launch_bounds__(64) void k_plain(Plan p, In<S> in, Out<S> out, S* w
         e.to_lds(tPA, L.sP);                              // sP = P'A
         wg_sync();
         e.load(t, P.Q(b, k), n, n, n);
-        e.template gemm<true, false>(t, L.sX, L.sP, n);
+        e.template gemm<true, false, true>(t, L.sX, L.sP, n);   // Q + A'(P'A) (lower)
         wg_sync();
         e.to_lds(KK[0], L.sA);                            // sA = K
         e.to_lds(tHc, L.sX);                              // sX = H
         wg_sync();
-        e.template gemm<true, false>(t, L.sA, L.sX, m);
+        e.template gemm<true, false, true>(t, L.sA, L.sX, m);   // + K'H (lower)
         pn = e.vload(P.q(b, k), n) + pa + e.template matvec<true>(L.sA, h, L.vb[1], m, n);
         wg_sync();
         to_lds_sym(e, t, L.sP);

@@ -100,6 +100,8 @@ Plan make_plan(int64_t batch, int N, int n, int m, size_t esize, const lqr_opts&
     p.stride = off;
     p.dstride = 2 * (N + 1);
     p.cond_thr = o.cond_threshold;
+    p.refine_tol = o.refine_tol;
+    p.active = nullptr;
     p.fallback = esize == 4 ? o.fallback : 0;   // the FP64 path has nothing to fall back to
     return p;
 }
@@ -112,8 +114,8 @@ Layout layout(const Plan& p, size_t esize) {
     Layout l;
     l.main_bytes = (size_t)align_up((int64_t)(p.batch * p.stride * (int64_t)esize), 256);
     l.int_off = l.main_bytes;
-    l.dbl_off = l.int_off + (size_t)align_up(queue_layout(p).total * 4, 256);
-    l.total = l.dbl_off + (size_t)align_up(p.batch * p.dstride * 8, 256);
+    l.dbl_off = l.int_off + (size_t)align_up((queue_layout(p).total + p.batch) * 4, 256);
+    l.total = l.dbl_off + (size_t)align_up((p.batch * p.dstride + p.batch) * 8, 256);
     return l;
 }
 
@@ -213,6 +215,7 @@ void lqr_opts_default(lqr_opts* o, int32_t dtype) {
     o->refine_sweeps = dtype == LQR_F32 ? 1 : 0;
     o->fallback = 1;
     o->cond_threshold = 1e6;
+    o->refine_tol = 1e-5;
     o->resid_out = nullptr;
 }
 
@@ -260,7 +263,8 @@ int lqr_kkt_solve(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int
     if (o.dtype != LQR_F32 && o.dtype != LQR_F64) return fail(LQR_EINVAL, "bad dtype %d", o.dtype);
     if (o.method != LQR_METHOD_SCAN && o.method != LQR_METHOD_SEQ_RICCATI)
         return fail(LQR_EINVAL, "bad method %d", o.method);
-    if (o.refine_sweeps < 0 || o.refine_sweeps > 1) return fail(LQR_EINVAL, "refine_sweeps must be 0 or 1");
+    if (o.refine_sweeps < 0 || o.refine_sweeps > 2) return fail(LQR_EINVAL, "refine_sweeps must be 0, 1 or 2");
+    if (!(o.refine_tol > 0.0)) return fail(LQR_EINVAL, "refine_tol must be > 0");
     if (!(o.cond_threshold > 1.0)) return fail(LQR_EINVAL, "cond_threshold must be > 1");
     const size_t es = o.dtype == LQR_F32 ? 4 : 8;
     const void* ins[] = {A, B, c, Q, R, M, q, r, x0};

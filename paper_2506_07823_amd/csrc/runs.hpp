@@ -166,38 +166,48 @@ int run_scan(const Plan& p, hipStream_t s, const In<S>& in, const Out<S>& out, S
     // a6: controls and costates
     LCHK(launch(F_RECOVER, B * (N + 1) * w.rec_f(), B * (N + 1) * w.rec_b(), k_recover<S, E, false>,
                 Bi * (N + 1), s, p, ws, out));
-    // a7: FP64 residual + one refinement sweep
-    if (refine > 0) {
+    // a7: FP64 residual + refinement sweeps (the second only for instances
+    // whose residual after the first is still above the tolerance)
+    int32_t* active = iws + Qs.total;
+    double* rel = resid_out ? resid_out : dws + Bi * p.dstride;
+    Plan pg = p;
+    for (int sw = 0; sw < refine; ++sw) {
         LCHK(launch(F_RESID, B * (N + 1) * w.resid_f(), B * (N + 1) * w.resid_b(), k_resid<S, E64, true>,
                     Bi * (N + 1), s, p, in, (const S*)out.x, (const S*)out.u, (const S*)out.lam, ws, dws));
-        LCHK(launch(F_REF_D, B * N * 3 * w.vec_f(), B * N * 3 * w.vec_b(), k_ref_d<S, E>, Bi * N, s, p, ws));
+        if (sw > 0) {
+            LCHK(launch(F_REDUCE, 0, B * 16.0 * (N + 1), k_resid_reduce<double>, (Bi + 63) / 64, s, p,
+                        (const double*)dws, rel, active, p.refine_tol));
+            pg.active = active;
+        }
+        LCHK(launch(F_REF_D, B * N * 3 * w.vec_f(), B * N * 3 * w.vec_b(), k_ref_d<S, E>, Bi * N, s, pg, ws));
         for (int l = 0; l + 1 < p.ft.nlev; ++l) {
             const double u = B * (p.ft.cnt[l] / 2);
-            LCHK(launch(F_BUP, u * w.vec_f(), u * w.vec_b(), k_bvec_up<S, E>, Bi * p.ft.cnt[l + 1], s, p, ws, l));
+            LCHK(launch(F_BUP, u * w.vec_f(), u * w.vec_b(), k_bvec_up<S, E>, Bi * p.ft.cnt[l + 1], s, pg, ws, l));
         }
-        LCHK(launch(F_BROOT, 0, 4 * B * w.es * p.n, k_broot<S>, Bi, s, p, ws));
+        LCHK(launch(F_BROOT, 0, 4 * B * w.es * p.n, k_broot<S>, Bi, s, pg, ws));
         for (int l = p.ft.nlev - 2; l >= 0; --l) {
             const double u = B * (p.ft.cnt[l] / 2);
-            LCHK(launch(F_BDOWN, u * w.vec_f(), u * w.vec_b(), k_bvec_down<S, E>, Bi * p.ft.cnt[l], s, p, ws, l));
+            LCHK(launch(F_BDOWN, u * w.vec_f(), u * w.vec_b(), k_bvec_down<S, E>, Bi * p.ft.cnt[l], s, pg, ws, l));
         }
-        LCHK(launch(F_REF_KFF, B * N * 4 * w.vec_f(), B * N * 4 * w.vec_b(), k_ref_kff<S, E>, Bi * N, s, p, in, ws));
+        LCHK(launch(F_REF_KFF, B * N * 4 * w.vec_f(), B * N * 4 * w.vec_b(), k_ref_kff<S, E>, Bi * N, s, pg, in, ws));
         for (int l = 0; l + 1 < p.ft.nlev; ++l) {
             const double u = B * (p.ft.cnt[l] / 2);
-            LCHK(launch(F_FUPV, u * w.vec_f(), u * w.vec_b(), k_fup<S, E, true>, Bi * p.ft.cnt[l + 1], s, p, ws, l));
+            LCHK(launch(F_FUPV, u * w.vec_f(), u * w.vec_b(), k_fup<S, E, true>, Bi * p.ft.cnt[l + 1], s, pg, ws, l));
         }
-        LCHK(launch(F_FROOT, 0, 2 * B * w.es * p.n, k_froot<S>, Bi, s, p, ws, (const S*)(ws + p.o_x0p), p.stride));
+        LCHK(launch(F_FROOT, 0, 2 * B * w.es * p.n, k_froot<S>, Bi, s, pg, ws, (const S*)(ws + p.o_x0p), p.stride));
         for (int l = p.ft.nlev - 2; l >= 0; --l) {
             const double u = B * (p.ft.cnt[l] / 2);
-            LCHK(launch(F_FDOWN, u * w.vec_f(), u * w.vec_b(), k_fdown<S, E>, Bi * p.ft.cnt[l], s, p, ws, l));
+            LCHK(launch(F_FDOWN, u * w.vec_f(), u * w.vec_b(), k_fdown<S, E>, Bi * p.ft.cnt[l], s, pg, ws, l));
         }
         LCHK(launch(F_RECOVER_ADD, B * (N + 1) * w.rec_f(), B * (N + 1) * w.rec_b(), k_recover<S, E, true>,
-                    Bi * (N + 1), s, p, ws, out));
+                    Bi * (N + 1), s, pg, ws, out));
     }
     if (resid_out) {
+        // after an adaptive second sweep only the instances it touched changed
         LCHK(launch(F_RESID, B * (N + 1) * w.resid_f(), B * (N + 1) * w.resid_b(), k_resid<S, E64, false>,
-                    Bi * (N + 1), s, p, in, (const S*)out.x, (const S*)out.u, (const S*)out.lam, ws, dws));
-        LCHK(launch(F_REDUCE, 0, B * 16.0 * (N + 1), k_resid_reduce<double>, (Bi + 63) / 64, s, p,
-                    (const double*)dws, resid_out));
+                    Bi * (N + 1), s, pg, in, (const S*)out.x, (const S*)out.u, (const S*)out.lam, ws, dws));
+        LCHK(launch(F_REDUCE, 0, B * 16.0 * (N + 1), k_resid_reduce<double>, (Bi + 63) / 64, s, pg,
+                    (const double*)dws, resid_out, (int32_t*)nullptr, p.refine_tol));
     }
     return LQR_OK;
 }
@@ -217,7 +227,7 @@ int run_plain(const Plan& p, hipStream_t s, const In<S>& in, const Out<S>& out, 
         LCHK(launch(F_RESID, B * (p.N + 1) * w.resid_f(), B * (p.N + 1) * w.resid_b(), k_resid<S, E64, false>,
                     Bi * (p.N + 1), s, p, in, (const S*)out.x, (const S*)out.u, (const S*)out.lam, ws, dws));
         LCHK(launch(F_REDUCE, 0, B * 16.0 * (p.N + 1), k_resid_reduce<double>, (Bi + 63) / 64, s, p,
-                    (const double*)dws, resid_out));
+                    (const double*)dws, resid_out, (int32_t*)nullptr, p.refine_tol));
     }
     return LQR_OK;
 }
@@ -231,7 +241,7 @@ int run_resid(const Plan& p, hipStream_t s, const In<S>& in, const S* x, const S
     LCHK(launch(F_RESID, B * (p.N + 1) * w.resid_f(), B * (p.N + 1) * w.resid_b(), k_resid<S, E64, false>,
                 p.batch * (p.N + 1), s, p, in, x, u, lam, ws, dws));
     LCHK(launch(F_REDUCE, 0, B * 16.0 * (p.N + 1), k_resid_reduce<double>, (p.batch + 63) / 64, s, p,
-                (const double*)dws, rel));
+                (const double*)dws, rel, (int32_t*)nullptr, p.refine_tol));
     return LQR_OK;
 }
 
