@@ -263,7 +263,7 @@ int lqr_kkt_solve(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int
     if (o.dtype != LQR_F32 && o.dtype != LQR_F64) return fail(LQR_EINVAL, "bad dtype %d", o.dtype);
     if (o.method != LQR_METHOD_SCAN && o.method != LQR_METHOD_SEQ_RICCATI)
         return fail(LQR_EINVAL, "bad method %d", o.method);
-    if (o.refine_sweeps < 0 || o.refine_sweeps > 2) return fail(LQR_EINVAL, "refine_sweeps must be 0, 1 or 2");
+    if (o.refine_sweeps < 0 || o.refine_sweeps > 4) return fail(LQR_EINVAL, "refine_sweeps must be in 0..4");
     if (!(o.refine_tol > 0.0)) return fail(LQR_EINVAL, "refine_tol must be > 0");
     if (!(o.cond_threshold > 1.0)) return fail(LQR_EINVAL, "cond_threshold must be > 1");
     const size_t es = o.dtype == LQR_F32 ? 4 : 8;

@@ -172,10 +172,13 @@ int run_scan(const Plan& p, hipStream_t s, const In<S>& in, const Out<S>& out, S
     double* rel = resid_out ? resid_out : dws + Bi * p.dstride;
     Plan pg = p;
     for (int sw = 0; sw < refine; ++sw) {
+        // sweep 0 and the first decision run over every instance; later
+        // decisions only revisit the instances still active
+        const Plan& pr = sw >= 2 ? pg : p;
         LCHK(launch(F_RESID, B * (N + 1) * w.resid_f(), B * (N + 1) * w.resid_b(), k_resid<S, E64, true>,
-                    Bi * (N + 1), s, p, in, (const S*)out.x, (const S*)out.u, (const S*)out.lam, ws, dws));
+                    Bi * (N + 1), s, pr, in, (const S*)out.x, (const S*)out.u, (const S*)out.lam, ws, dws));
         if (sw > 0) {
-            LCHK(launch(F_REDUCE, 0, B * 16.0 * (N + 1), k_resid_reduce<double>, (Bi + 63) / 64, s, p,
+            LCHK(launch(F_REDUCE, 0, B * 16.0 * (N + 1), k_resid_reduce<double>, (Bi + 63) / 64, s, pr,
                         (const double*)dws, rel, active, p.refine_tol));
             pg.active = active;
         }
