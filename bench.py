@@ -109,6 +109,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of graph replays")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (calibrates the HBM byte "
+                         "counters of a profiler against a known size) and exit")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the batch-sharded multi-GPU form "
@@ -116,6 +119,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if a.copy_calib:
+        nbytes = a.copy_calib << 20
+        src = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calib_bytes": nbytes}), flush=True)
+        return
     import paper_2506_07823_amd as L
     import synth
 

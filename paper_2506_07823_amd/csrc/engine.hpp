@@ -33,6 +33,11 @@ template <> __device__ __forceinline__ double dsqrt<double>(double x) { return _
 // LDS instructions of one wavefront execute in issue order, and the fence
 // keeps the compiler from moving LDS accesses across the hand-off (a
 // workgroup barrier would also drain every outstanding global load).
+// fused multiply-add in the operands' own precision (the unsuffixed builtin
+// is the double one and would promote float operands)
+__device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 __device__ __forceinline__ void wg_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -162,7 +167,7 @@ struct Eng {
             for (int a = 0; a < TS; ++a)
 #pragma unroll
                 for (int b = 0; b < TS; ++b)
-                    if (!SYM || b <= a) acc[a][b] = __builtin_fma(SUB ? -xa[a] : xa[a], yb[b], acc[a][b]);
+                    if (!SYM || b <= a) acc[a][b] = fma_(SUB ? -xa[a] : xa[a], yb[b], acc[a][b]);
         }
     }
 
@@ -227,7 +232,33 @@ struct Eng {
         T s = T(0);
         if (lg < rows) {
             for (int k = 0; k < K; ++k)
-                s = __builtin_fma(TX ? X[k * LD + lg] : X[lg * LD + k], vb[k], s);
+                s = fma_(TX ? X[k * LD + lg] : X[lg * LD + k], vb[k], s);
+        }
+        return s;
+    }
+
+    // y = op(M) x straight from global memory (no staging of M): M is a
+    // rows x cols matrix with leading dim ld; x is a lane vector of length
+    // (TR ? rows : cols) staged through vb.  TR: y = M' x (length cols), lane j
+    // reads column j, coalesced across lanes; else y = M x (length rows), lane
+    // i reads its own row.
+    template <bool TR, typename S>
+    __device__ __forceinline__ T gmv(const S* M, int rows, int cols, int ld, T x, T* vb) const {
+        if (lg < NP) vb[lg] = x;
+        wg_sync();
+        T s = T(0);
+        if (TR) {
+            if (lg < cols) {
+                const S* c = M + lg;
+#pragma unroll 4
+                for (int i = 0; i < rows; ++i) s = fma_(T(c[(int64_t)i * ld]), vb[i], s);
+            }
+        } else {
+            if (lg < rows) {
+                const S* r = M + (int64_t)lg * ld;
+#pragma unroll 4
+                for (int j = 0; j < cols; ++j) s = fma_(T(r[j]), vb[j], s);
+            }
         }
         return s;
     }
@@ -279,7 +310,7 @@ struct Eng {
                 for (int a = a0; a < TS; ++a)
 #pragma unroll
                     for (int b = a0; b <= a; ++b)
-                        if (row(a) > k && col(b) > k) S[a][b] = __builtin_fma(-li[a], lj[b], S[a][b]);
+                        if (row(a) > k && col(b) > k) S[a][b] = fma_(-li[a], lj[b], S[a][b]);
                 if (tx == t) {
 #pragma unroll
                     for (int a = 0; a < TS; ++a)
@@ -295,7 +326,7 @@ struct Eng {
                 for (int v = 0; v < NV; ++v) {
                     const T gk = c[NP + v] * inv;
                     if (lg == k) gv[v] = gk;
-                    else if (lg > k && lg < n) gv[v] = __builtin_fma(-c[lg] * inv, gk, gv[v]);
+                    else if (lg > k && lg < n) gv[v] = fma_(-c[lg] * inv, gk, gv[v]);
                 }
             }
         }
@@ -354,7 +385,7 @@ struct Eng {
                         if (LOWER ? a < a0 : a > a0) continue;
 #pragma unroll
                         for (int b = 0; b < TS; ++b)
-                            X[it][a][b] = (a == a0 && ty == t) ? rk[b] : __builtin_fma(-lik[a], rk[b], X[it][a][b]);
+                            X[it][a][b] = (a == a0 && ty == t) ? rk[b] : fma_(-lik[a], rk[b], X[it][a][b]);
                     }
                 }
 #pragma unroll
@@ -363,7 +394,7 @@ struct Eng {
                     if (lg == k) vv[v] = vk;
                     else {
                         const bool act = LOWER ? (lg > k && lg < n) : (lg < k);
-                        if (act) vv[v] = __builtin_fma(-(LOWER ? sL[lg * LD + k] : sL[k * LD + lg]), vk, vv[v]);
+                        if (act) vv[v] = fma_(-(LOWER ? sL[lg * LD + k] : sL[k * LD + lg]), vk, vv[v]);
                     }
                 }
             }

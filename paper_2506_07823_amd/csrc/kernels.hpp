@@ -49,6 +49,7 @@ struct Plan {
     double refine_tol;
     int fallback;
     const int32_t* active;   // refinement gating: instances with active[b] == 0 skip (nullptr = all)
+    int fused;               // 1: per-instance kernels for the vector-only passes
 };
 
 #define LQR_GATE(p, b) \
@@ -98,6 +99,11 @@ struct Lds {
     T dB[E::NP];
     T rb[2 * (2 * E::NP + 3)];
     T vb[2][E::NP];
+};
+
+template <class E>
+struct ResidLds {
+    double vb[2][E::NP];
 };
 
 template <class E>
@@ -582,14 +588,13 @@ __global__ __launch_bounds__(64) void k_policy(Plan p, In<S> in, S* ws, int32_t*
 // VEC: only the vector part (matrices kept from the first solve).
 // ---------------------------------------------------------------------------
 template <typename S, class E, bool VEC>
-__global__ __launch_bounds__(64) void k_fup(Plan p, S* ws, int lvl) {
+__device__ __forceinline__ void fup_body(Lds<E>& L, Plan p, S* ws, int lvl, int64_t tid) {
     using T = typename E::T;
-    __shared__ Lds<E> L;
     const E e(threadIdx.x);
     const int n = p.n, nn = n * n;
     const int cout = p.ft.cnt[lvl + 1], cin = p.ft.cnt[lvl];
-    const int64_t b = blockIdx.x / cout;
-    const int i = blockIdx.x % cout;
+    const int64_t b = tid / cout;
+    const int i = tid % cout;
     LQR_GATE(p, b);
     S* base = ws + b * p.stride + p.o_ftree;
     const S* l = base + (int64_t)(p.ft.off[lvl] + 2 * i) * p.frec;
@@ -600,8 +605,13 @@ __global__ __launch_bounds__(64) void k_fup(Plan p, S* ws, int lvl) {
         return;
     }
     const S* r = l + p.frec;
+    if (VEC) {
+        const T v = e.template gmv<false>(r, n, n, n, e.vload(l + nn, n), L.vb[0]) + e.vload(r + nn, n);
+        e.vstore(out + nn, n, v);
+        return;
+    }
     stage(e, L.sA, r, n, n, n);                           // M_r
-    if (!VEC) stage(e, L.sX, l, n, n, n);                 // M_l
+    stage(e, L.sX, l, n, n, n);                           // M_l
     wg_sync();
     const T v = e.template matvec<false>(L.sA, e.vload(l + nn, n), L.vb[0], n, n) + e.vload(r + nn, n);
     if (!VEC) {
@@ -613,26 +623,36 @@ __global__ __launch_bounds__(64) void k_fup(Plan p, S* ws, int lvl) {
     e.vstore(out + nn, n, v);
 }
 
+template <typename S, class E, bool VEC>
+__global__ __launch_bounds__(64) void k_fup(Plan p, S* ws, int lvl) {
+    __shared__ Lds<E> L;
+    fup_body<S, E, VEC>(L, p, ws, lvl, (int64_t)blockIdx.x);
+}
+
 // forward tree down-sweep root: start state of the whole horizon
 template <typename S>
-__global__ void k_froot(Plan p, S* ws, const S* x0, int64_t x0_stride) {
-    const int64_t b = blockIdx.x;
+__device__ __forceinline__ void froot_body(Plan p, S* ws, const S* x0, int64_t x0_stride, int64_t tid) {
+    const int64_t b = tid;
     LQR_GATE(p, b);
     const int root = p.ft.off[p.ft.nlev - 1];
     coop_copy(ws + b * p.stride + p.o_xs + (int64_t)root * p.n, x0 + b * x0_stride, p.n);
 }
 
+template <typename S>
+__global__ __launch_bounds__(64) void k_froot(Plan p, S* ws, const S* x0, int64_t x0_stride) {
+    froot_body<S>(p, ws, x0, x0_stride, (int64_t)blockIdx.x);
+}
+
 // node (l, j): even j starts where its parent starts; odd j starts after its
 // left sibling:  xs = M_{j-1} xs(parent) + v_{j-1}
 template <typename S, class E>
-__global__ __launch_bounds__(64) void k_fdown(Plan p, S* ws, int lvl) {
+__device__ __forceinline__ void fdown_body(Lds<E>& L, Plan p, S* ws, int lvl, int64_t tid) {
     using T = typename E::T;
-    __shared__ Lds<E> L;
     const E e(threadIdx.x);
     const int n = p.n, nn = n * n;
     const int cnt = p.ft.cnt[lvl];
-    const int64_t b = blockIdx.x / cnt;
-    const int j = blockIdx.x % cnt;
+    const int64_t b = tid / cnt;
+    const int j = tid % cnt;
     LQR_GATE(p, b);
     S* inst = ws + b * p.stride;
     const S* par = inst + p.o_xs + (int64_t)(p.ft.off[lvl + 1] + j / 2) * n;
@@ -642,10 +662,14 @@ __global__ __launch_bounds__(64) void k_fdown(Plan p, S* ws, int lvl) {
         return;
     }
     const S* sib = inst + p.o_ftree + (int64_t)(p.ft.off[lvl] + j - 1) * p.frec;
-    stage(e, L.sA, sib, n, n, n);
-    wg_sync();
-    const T x = e.template matvec<false>(L.sA, e.vload(par, n), L.vb[0], n, n) + e.vload(sib + nn, n);
+    const T x = e.template gmv<false>(sib, n, n, n, e.vload(par, n), L.vb[0]) + e.vload(sib + nn, n);
     e.vstore(out, n, x);
+}
+
+template <typename S, class E>
+__global__ __launch_bounds__(64) void k_fdown(Plan p, S* ws, int lvl) {
+    __shared__ Lds<E> L;
+    fdown_body<S, E>(L, p, ws, lvl, (int64_t)blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -653,13 +677,12 @@ __global__ __launch_bounds__(64) void k_fdown(Plan p, S* ws, int lvl) {
 // last leaf map.  ADD: the refinement's correction is added to the outputs.
 // ---------------------------------------------------------------------------
 template <typename S, class E, bool ADD>
-__global__ __launch_bounds__(64) void k_recover(Plan p, S* ws, Out<S> out) {
+__device__ __forceinline__ void recover_body(Lds<E>& L, Plan p, S* ws, Out<S> out, int64_t tid) {
     using T = typename E::T;
-    __shared__ Lds<E> L;
     const E e(threadIdx.x);
     const int N = p.N, n = p.n, m = p.m, nn = n * n;
-    const int64_t b = blockIdx.x / (N + 1);
-    const int k = blockIdx.x % (N + 1);
+    const int64_t b = tid / (N + 1);
+    const int k = tid % (N + 1);
     LQR_GATE(p, b);
     S* inst = ws + b * p.stride;
     T x;
@@ -667,23 +690,17 @@ __global__ __launch_bounds__(64) void k_recover(Plan p, S* ws, Out<S> out) {
         x = e.vload(inst + p.o_xs + (int64_t)k * n, n);
     } else {
         const S* leaf = inst + p.o_ftree + (int64_t)(N - 1) * p.frec;
-        stage(e, L.sA, leaf, n, n, n);
-        wg_sync();
-        x = e.template matvec<false>(L.sA, e.vload(inst + p.o_xs + (int64_t)(N - 1) * n, n), L.vb[0], n, n) +
+        x = e.template gmv<false>(leaf, n, n, n, e.vload(inst + p.o_xs + (int64_t)(N - 1) * n, n), L.vb[1]) +
             e.vload(leaf + nn, n);
-        wg_sync();
     }
     const S* Pk = inst + p.o_suf + (int64_t)suffix_id(p.rt, 0, k) * p.srec;
-    stage(e, L.sA, Pk, n, n, n);
     const bool hasu = k < N;
-    if (hasu) stage(e, L.sX, inst + p.o_K + (int64_t)k * m * n, m, n, n);
-    wg_sync();
     const S* pvec = ADD ? inst + p.o_pp + (int64_t)k * n : Pk + nn;
-    const T lam = e.template matvec<false>(L.sA, x, L.vb[0], n, n) + e.vload(pvec, n);
+    const T lam = e.template gmv<false>(Pk, n, n, n, x, L.vb[0]) + e.vload(pvec, n);
     T u = T(0);
     if (hasu) {
         const S* kf = ADD ? inst + p.o_kffp + (int64_t)k * m : inst + p.o_kff + (int64_t)k * m;
-        u = e.template matvec<false>(L.sX, x, L.vb[1], n, m) + e.vload(kf, m);
+        u = e.template gmv<false>(inst + p.o_K + (int64_t)k * m * n, m, n, n, x, L.vb[1]) + e.vload(kf, m);
     }
     S* xo = out.x + (b * (N + 1) + k) * n;
     S* lo = out.lam + (b * (N + 1) + k) * n;
@@ -704,6 +721,12 @@ __global__ __launch_bounds__(64) void k_recover(Plan p, S* ws, Out<S> out) {
     if (!wave_all(fin)) set_status(out.status, b, 1);
 }
 
+template <typename S, class E, bool ADD>
+__global__ __launch_bounds__(64) void k_recover(Plan p, S* ws, Out<S> out) {
+    __shared__ Lds<E> L;
+    recover_body<S, E, ADD>(L, p, ws, out, (int64_t)blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // FP64 KKT residual (stationarity of the Lagrangian of Sec. II-B plus the
 // constraints), one task per (instance, stage):
@@ -715,15 +738,13 @@ __global__ __launch_bounds__(64) void k_recover(Plan p, S* ws, Out<S> out) {
 // CORR, the correction data c' = r_dyn, q' = r_x, r' = r_u, x0' = -r_init.
 // ---------------------------------------------------------------------------
 template <typename S, class E, bool CORR>
-__global__ __launch_bounds__(64) void k_resid(Plan p, In<S> in, const S* xs_, const S* us_, const S* ls_,
-                                              S* ws, double* dws) {
+__device__ __forceinline__ void resid_body(ResidLds<E>& RL, Plan p, In<S> in, const S* xs_, const S* us_, const S* ls_,
+                                              S* ws, double* dws, int64_t tid) {
     static_assert(sizeof(typename E::T) == 8, "residual runs in FP64");
-    __shared__ double sM[E::MAT];
-    __shared__ double vb[2][E::NP];
     const E e(threadIdx.x);
     const int N = p.N, n = p.n, m = p.m;
-    const int64_t b = blockIdx.x / (N + 1);
-    const int k = blockIdx.x % (N + 1);
+    const int64_t b = tid / (N + 1);
+    const int k = tid % (N + 1);
     LQR_GATE(p, b);
     const Ptr<S> P(p, in);
     const S* xk = xs_ + (b * (N + 1) + k) * n;
@@ -731,36 +752,22 @@ __global__ __launch_bounds__(64) void k_resid(Plan p, In<S> in, const S* xs_, co
     const double x = e.vload(xk, n), lam = e.vload(lk, n);
     double rr = 0.0, bb = 0.0;
     S* inst = ws + b * p.stride;
-    // Q x + q - lam (+ M u + A' lam1 for k < N)
-    stage(e, sM, P.Q(b, k), n, n, n);
-    wg_sync();
+    // Q x + q - lam (+ M u + A' lam1 for k < N); products read straight from global memory
     double qv = e.vload(P.q(b, k), n);
-    double rx = e.template matvec<false>(sM, x, vb[0], n, n) + qv - lam;
+    double rx = e.template gmv<false>(P.Q(b, k), n, n, n, x, RL.vb[0]) + qv - lam;
     bb += qv * qv;
     if (k < N) {
         const double u = e.vload(us_ + (b * N + k) * m, m);
         const double lam1 = e.vload(lk + n, n);
         const double x1 = e.vload(xk + n, n);
-        wg_sync();
-        stage(e, sM, P.A(b, k), n, n, n);
-        wg_sync();
-        double rd = e.template matvec<false>(sM, x, vb[0], n, n);
-        rx += e.template matvec<true>(sM, lam1, vb[1], n, n);
-        wg_sync();
-        stage(e, sM, P.B(b, k), n, m, m);
-        wg_sync();
-        rd += e.template matvec<false>(sM, u, vb[0], m, n);
-        double ru = e.template matvec<true>(sM, lam1, vb[1], n, m);
-        wg_sync();
-        stage(e, sM, P.M(b, k), n, m, m);
-        wg_sync();
-        rx += e.template matvec<false>(sM, u, vb[0], m, n);
-        ru += e.template matvec<true>(sM, x, vb[1], n, m);
-        wg_sync();
-        stage(e, sM, P.R(b, k), m, m, m);
-        wg_sync();
+        double rd = e.template gmv<false>(P.A(b, k), n, n, n, x, RL.vb[1]);
+        rx += e.template gmv<true>(P.A(b, k), n, n, n, lam1, RL.vb[0]);
+        rd += e.template gmv<false>(P.B(b, k), n, m, m, u, RL.vb[1]);
+        double ru = e.template gmv<true>(P.B(b, k), n, m, m, lam1, RL.vb[0]);
+        rx += e.template gmv<false>(P.M(b, k), n, m, m, u, RL.vb[1]);
+        ru += e.template gmv<true>(P.M(b, k), n, m, m, x, RL.vb[0]);
         const double cv = e.vload(P.c(b, k), n), rv = e.vload(P.r(b, k), m);
-        ru += e.template matvec<false>(sM, u, vb[0], m, m) + rv;
+        ru += e.template gmv<false>(P.R(b, k), m, m, m, u, RL.vb[1]) + rv;
         rd += cv - x1;
         bb += cv * cv + rv * rv;
         rr += (e.lg < n ? rd * rd : 0.0) + (e.lg < m ? ru * ru : 0.0);
@@ -784,6 +791,13 @@ __global__ __launch_bounds__(64) void k_resid(Plan p, In<S> in, const S* xs_, co
         dws[b * p.dstride + 2 * k] = rr;
         dws[b * p.dstride + 2 * k + 1] = bb;
     }
+}
+
+template <typename S, class E, bool CORR>
+__global__ __launch_bounds__(64) void k_resid(Plan p, In<S> in, const S* xs_, const S* us_, const S* ls_,
+                                              S* ws, double* dws) {
+    __shared__ ResidLds<E> RL;
+    resid_body<S, E, CORR>(RL, p, in, xs_, us_, ls_, ws, dws, (int64_t)blockIdx.x);
 }
 
 // rel[b] = ||r|| / ||(x0, c, q, r)||; with active_out, also mark the
@@ -812,40 +826,38 @@ __global__ void k_resid_reduce(Plan p, const D* dws, D* rel, int32_t* active_out
 // tree's products Abar_e ... Abar_s.
 // ---------------------------------------------------------------------------
 template <typename S, class E>
-__global__ __launch_bounds__(64) void k_ref_d(Plan p, S* ws) {
+__device__ __forceinline__ void ref_d_body(Lds<E>& L, Plan p, S* ws, int64_t tid) {
     using T = typename E::T;
-    __shared__ Lds<E> L;
     const E e(threadIdx.x);
     const int N = p.N, n = p.n, m = p.m;
-    const int64_t b = blockIdx.x / N;
-    const int k = blockIdx.x % N;
+    const int64_t b = tid / N;
+    const int k = tid % N;
     LQR_GATE(p, b);
     S* inst = ws + b * p.stride;
     const S* Pn = inst + p.o_suf + (int64_t)suffix_id(p.rt, 0, k + 1) * p.srec;
-    stage(e, L.sA, Pn, n, n, n);
-    stage(e, L.sX, inst + p.o_ftree + (int64_t)k * p.frec, n, n, n);   // Abar_k
-    wg_sync();
-    const T t = e.template matvec<false>(L.sA, e.vload(inst + p.o_cp + (int64_t)k * n, n), L.vb[0], n, n);
-    wg_sync();
-    T d = e.template matvec<true>(L.sX, t, L.vb[1], n, n);
-    wg_sync();
-    stage(e, L.sA, inst + p.o_K + (int64_t)k * m * n, m, n, n);
-    wg_sync();
-    d += e.template matvec<true>(L.sA, e.vload(inst + p.o_rp + (int64_t)k * m, m), L.vb[0], m, n);
+    const T t = e.template gmv<false>(Pn, n, n, n, e.vload(inst + p.o_cp + (int64_t)k * n, n), L.vb[0]);
+    T d = e.template gmv<true>(inst + p.o_ftree + (int64_t)k * p.frec, n, n, n, t, L.vb[1]);   // Abar_k' t
+    d += e.template gmv<true>(inst + p.o_K + (int64_t)k * m * n, m, n, n,
+                              e.vload(inst + p.o_rp + (int64_t)k * m, m), L.vb[0]);
     d += e.vload(inst + p.o_qp + (int64_t)k * n, n);
     e.vstore(inst + p.o_w + (int64_t)k * n, n, d);
 }
 
+template <typename S, class E>
+__global__ __launch_bounds__(64) void k_ref_d(Plan p, S* ws) {
+    __shared__ Lds<E> L;
+    ref_d_body<S, E>(L, p, ws, (int64_t)blockIdx.x);
+}
+
 // backward up-sweep: w(l+1, i) = M(l, 2i)' w(l, 2i+1) + w(l, 2i)
 template <typename S, class E>
-__global__ __launch_bounds__(64) void k_bvec_up(Plan p, S* ws, int lvl) {
+__device__ __forceinline__ void bvec_up_body(Lds<E>& L, Plan p, S* ws, int lvl, int64_t tid) {
     using T = typename E::T;
-    __shared__ Lds<E> L;
     const E e(threadIdx.x);
     const int n = p.n;
     const int cout = p.ft.cnt[lvl + 1], cin = p.ft.cnt[lvl];
-    const int64_t b = blockIdx.x / cout;
-    const int i = blockIdx.x % cout;
+    const int64_t b = tid / cout;
+    const int i = tid % cout;
     LQR_GATE(p, b);
     S* inst = ws + b * p.stride;
     const S* wl = inst + p.o_w + (int64_t)(p.ft.off[lvl] + 2 * i) * n;
@@ -854,15 +866,20 @@ __global__ __launch_bounds__(64) void k_bvec_up(Plan p, S* ws, int lvl) {
         coop_copy(wo, wl, n);
         return;
     }
-    stage(e, L.sA, inst + p.o_ftree + (int64_t)(p.ft.off[lvl] + 2 * i) * p.frec, n, n, n);
-    wg_sync();
-    const T w = e.template matvec<true>(L.sA, e.vload(wl + n, n), L.vb[0], n, n) + e.vload(wl, n);
+    const T w = e.template gmv<true>(inst + p.o_ftree + (int64_t)(p.ft.off[lvl] + 2 * i) * p.frec, n, n, n,
+                                     e.vload(wl + n, n), L.vb[0]) + e.vload(wl, n);
     e.vstore(wo, n, w);
 }
 
+template <typename S, class E>
+__global__ __launch_bounds__(64) void k_bvec_up(Plan p, S* ws, int lvl) {
+    __shared__ Lds<E> L;
+    bvec_up_body<S, E>(L, p, ws, lvl, (int64_t)blockIdx.x);
+}
+
 template <typename S>
-__global__ void k_broot(Plan p, S* ws) {
-    const int64_t b = blockIdx.x;
+__device__ __forceinline__ void broot_body(Plan p, S* ws, int64_t tid) {
+    const int64_t b = tid;
     LQR_GATE(p, b);
     S* inst = ws + b * p.stride;
     const int root = p.ft.off[p.ft.nlev - 1];
@@ -870,17 +887,21 @@ __global__ void k_broot(Plan p, S* ws) {
     coop_copy(inst + p.o_pp + (int64_t)p.N * p.n, inst + p.o_qp + (int64_t)p.N * p.n, p.n);
 }
 
+template <typename S>
+__global__ __launch_bounds__(64) void k_broot(Plan p, S* ws) {
+    broot_body<S>(p, ws, (int64_t)blockIdx.x);
+}
+
 // backward down-sweep: pend = gradient right after the node's last stage.
 //   odd j (right child): pend(parent);  even j: M(l, j+1)' pend(parent) + w(l, j+1)
 template <typename S, class E>
-__global__ __launch_bounds__(64) void k_bvec_down(Plan p, S* ws, int lvl) {
+__device__ __forceinline__ void bvec_down_body(Lds<E>& L, Plan p, S* ws, int lvl, int64_t tid) {
     using T = typename E::T;
-    __shared__ Lds<E> L;
     const E e(threadIdx.x);
     const int n = p.n;
     const int cnt = p.ft.cnt[lvl];
-    const int64_t b = blockIdx.x / cnt;
-    const int j = blockIdx.x % cnt;
+    const int64_t b = tid / cnt;
+    const int j = tid % cnt;
     LQR_GATE(p, b);
     S* inst = ws + b * p.stride;
     const S* par = inst + p.o_pend + (int64_t)(p.ft.off[lvl + 1] + j / 2) * n;
@@ -889,23 +910,27 @@ __global__ __launch_bounds__(64) void k_bvec_down(Plan p, S* ws, int lvl) {
         coop_copy(out, par, n);
         return;
     }
-    stage(e, L.sA, inst + p.o_ftree + (int64_t)(p.ft.off[lvl] + j + 1) * p.frec, n, n, n);
-    wg_sync();
-    const T v = e.template matvec<true>(L.sA, e.vload(par, n), L.vb[0], n, n) +
+    const T v = e.template gmv<true>(inst + p.o_ftree + (int64_t)(p.ft.off[lvl] + j + 1) * p.frec, n, n, n,
+                                     e.vload(par, n), L.vb[0]) +
                 e.vload(inst + p.o_w + (int64_t)(p.ft.off[lvl] + j + 1) * n, n);
     e.vstore(out, n, v);
+}
+
+template <typename S, class E>
+__global__ __launch_bounds__(64) void k_bvec_down(Plan p, S* ws, int lvl) {
+    __shared__ Lds<E> L;
+    bvec_down_body<S, E>(L, p, ws, lvl, (int64_t)blockIdx.x);
 }
 
 // kff'_k = -G^{-1} h'_k,  h'_k = B'(p'_{k+1} + P_{k+1} c'_k) + r'_k;
 // p'_k = Abar' p'_{k+1} + d_k;  new forward leaf vector B kff' + c'.
 template <typename S, class E>
-__global__ __launch_bounds__(64) void k_ref_kff(Plan p, In<S> in, S* ws) {
+__device__ __forceinline__ void ref_kff_body(Lds<E>& L, Plan p, In<S> in, S* ws, int64_t tid) {
     using T = typename E::T;
-    __shared__ Lds<E> L;
     const E e(threadIdx.x);
     const int N = p.N, n = p.n, m = p.m, nn = n * n;
-    const int64_t b = blockIdx.x / N;
-    const int k = blockIdx.x % N;
+    const int64_t b = tid / N;
+    const int k = tid % N;
     LQR_GATE(p, b);
     const Ptr<S> P(p, in);
     S* inst = ws + b * p.stride;
@@ -913,26 +938,133 @@ __global__ __launch_bounds__(64) void k_ref_kff(Plan p, In<S> in, S* ws) {
     const S* leaf = inst + p.o_ftree + (int64_t)k * p.frec;
     const T pn = e.vload(inst + p.o_pend + (int64_t)k * n, n);     // p'_{k+1}
     const T cpv = e.vload(inst + p.o_cp + (int64_t)k * n, n);
-    stage(e, L.sA, Pn, n, n, n);
-    stage(e, L.sX, leaf, n, n, n);
-    wg_sync();
-    const T v = pn + e.template matvec<false>(L.sA, cpv, L.vb[0], n, n);
-    const T pk = e.template matvec<true>(L.sX, pn, L.vb[1], n, n) + e.vload(inst + p.o_w + (int64_t)k * n, n);
+    const T v = pn + e.template gmv<false>(Pn, n, n, n, cpv, L.vb[0]);
+    const T pk = e.template gmv<true>(leaf, n, n, n, pn, L.vb[1]) + e.vload(inst + p.o_w + (int64_t)k * n, n);
     e.vstore(inst + p.o_pp + (int64_t)k * n, n, pk);
-    wg_sync();
-    stage(e, L.sX, P.B(b, k), n, m, m);                   // B
     stage(e, L.sA, inst + p.o_LG + (int64_t)k * m * m, m, m, m);
+    T h[1] = {e.template gmv<true>(P.B(b, k), n, m, m, v, L.vb[0]) + e.vload(inst + p.o_rp + (int64_t)k * m, m)};
     wg_sync();
     fill_dinv<E>(L.sA, L.dA, m);
-    T h[1] = {e.template matvec<true>(L.sX, v, L.vb[0], n, m) + e.vload(inst + p.o_rp + (int64_t)k * m, m)};
     wg_sync();
     typename E::Tile none[1];
     e.template trsm<true, 0, 1>(L.sA, L.dA, m, none, h, L.rb);
     e.template trsm<false, 0, 1>(L.sA, L.dA, m, none, h, L.rb);
     const T kf = -h[0];
     e.vstore(inst + p.o_kffp + (int64_t)k * m, m, kf);
-    const T bb = e.template matvec<false>(L.sX, kf, L.vb[1], m, n) + cpv;
+    const T bb = e.template gmv<false>(P.B(b, k), n, m, m, kf, L.vb[1]) + cpv;
     e.vstore(inst + p.o_ftree + (int64_t)k * p.frec + nn, n, bb);
+}
+
+template <typename S, class E>
+__global__ __launch_bounds__(64) void k_ref_kff(Plan p, In<S> in, S* ws) {
+    __shared__ Lds<E> L;
+    ref_kff_body<S, E>(L, p, in, ws, (int64_t)blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Per-instance forms of the vector-only passes: one workgroup per instance
+// walks every stage and tree node of its instance in order.  For large
+// batches these replace the level-by-level launches, whose tiny O(n^2)
+// tasks are bound by the workgroup launch rate.  Every vector a task leaves
+// in global memory is read back only by the lane that wrote it (element lg
+// by lane lg: vload/vstore/coop_copy all map element i to lane i for
+// i < 64), so single-thread program order suffices between tasks; the only
+// cross-lane hand-offs are the LDS ones inside the products.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void global_sync() { wg_sync(); }
+
+// forward scan of the closed-loop maps from x0 (UPV: recompute the vector
+// part of the up-sweep first) and u_k, lambda_k (ADD: added to the outputs)
+template <typename S, class E, bool UPV, bool ADD>
+__device__ __forceinline__ void fwd_inst_body(Lds<E>& L, const Plan& p, S* ws, const S* x0, int64_t x0_stride,
+                                              const Out<S>& out, int64_t b) {
+    if (UPV) {
+        for (int l = 0; l + 1 < p.ft.nlev; ++l) {
+            for (int i = 0; i < p.ft.cnt[l + 1]; ++i) {
+                fup_body<S, E, true>(L, p, ws, l, b * p.ft.cnt[l + 1] + i);
+                global_sync();
+            }
+        }
+    }
+    froot_body<S>(p, ws, x0, x0_stride, b);
+    global_sync();
+    for (int l = p.ft.nlev - 2; l >= 0; --l) {
+        for (int j = 0; j < p.ft.cnt[l]; ++j) {
+            fdown_body<S, E>(L, p, ws, l, b * p.ft.cnt[l] + j);
+            global_sync();
+        }
+    }
+    for (int k = 0; k <= p.N; ++k) {
+        recover_body<S, E, ADD>(L, p, ws, out, b * (p.N + 1) + k);
+        wg_sync();
+    }
+}
+
+template <typename S, class E>
+__global__ __launch_bounds__(64) void k_fwd_inst(Plan p, S* ws, const S* x0, int64_t x0_stride, Out<S> out) {
+    __shared__ Lds<E> L;
+    const int64_t b = blockIdx.x;
+    LQR_GATE(p, b);
+    fwd_inst_body<S, E, false, false>(L, p, ws, x0, x0_stride, out, b);
+}
+
+// one whole refinement sweep of one instance (after its residual pass)
+template <typename S, class E>
+__global__ __launch_bounds__(64) void k_refine_inst(Plan p, In<S> in, S* ws, Out<S> out) {
+    __shared__ Lds<E> L;
+    const int64_t b = blockIdx.x;
+    LQR_GATE(p, b);
+    const int N = p.N;
+    for (int k = 0; k < N; ++k) {
+        ref_d_body<S, E>(L, p, ws, b * N + k);
+        wg_sync();
+    }
+    global_sync();
+    for (int l = 0; l + 1 < p.ft.nlev; ++l) {
+        for (int i = 0; i < p.ft.cnt[l + 1]; ++i) {
+            bvec_up_body<S, E>(L, p, ws, l, b * p.ft.cnt[l + 1] + i);
+            global_sync();
+        }
+    }
+    broot_body<S>(p, ws, b);
+    global_sync();
+    for (int l = p.ft.nlev - 2; l >= 0; --l) {
+        for (int j = 0; j < p.ft.cnt[l]; ++j) {
+            bvec_down_body<S, E>(L, p, ws, l, b * p.ft.cnt[l] + j);
+            global_sync();
+        }
+    }
+    for (int k = 0; k < N; ++k) {
+        ref_kff_body<S, E>(L, p, in, ws, b * N + k);
+        wg_sync();
+    }
+    global_sync();
+    fwd_inst_body<S, E, true, true>(L, p, ws, (const S*)(ws + p.o_x0p), p.stride, out, b);
+}
+
+// FP64 residual of one instance, all stages, reduced in place:
+// rel[b] = ||r|| / ||(x0, c, q, r)|| (and active_out[b] = rel > tol)
+template <typename S, class E, bool CORR>
+__global__ __launch_bounds__(64) void k_resid_inst(Plan p, In<S> in, const S* xs_, const S* us_, const S* ls_,
+                                                   S* ws, double* dws, double* rel, int32_t* active_out,
+                                                   double tol) {
+    __shared__ ResidLds<E> RL;
+    const int64_t b = blockIdx.x;
+    LQR_GATE(p, b);
+    for (int k = 0; k <= p.N; ++k) {
+        resid_body<S, E, CORR>(RL, p, in, xs_, us_, ls_, ws, dws, b * (p.N + 1) + k);
+        wg_sync();
+    }
+    if (threadIdx.x == 0) {   // the partial sums were written by this lane
+        double rr = 0.0, bb = 0.0;
+        for (int k = 0; k <= p.N; ++k) {
+            rr += dws[b * p.dstride + 2 * k];
+            bb += dws[b * p.dstride + 2 * k + 1];
+        }
+        const double r = bb > 0.0 ? __builtin_sqrt(rr) / __builtin_sqrt(bb) : __builtin_sqrt(rr);
+        if (rel) rel[b] = r;
+        if (active_out) active_out[b] = !(r <= tol);
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -102,6 +102,9 @@ Plan make_plan(int64_t batch, int N, int n, int m, size_t esize, const lqr_opts&
     p.cond_thr = o.cond_threshold;
     p.refine_tol = o.refine_tol;
     p.active = nullptr;
+    // per-instance vector passes once the batch alone fills the GPU; the
+    // level-parallel launches keep the O(log N) depth for small batches
+    p.fused = batch >= 128 ? 1 : 0;
     p.fallback = esize == 4 ? o.fallback : 0;   // the FP64 path has nothing to fall back to
     return p;
 }
@@ -164,7 +167,7 @@ namespace {
 const char* const kFamNames[F_COUNT] = {
     "clear", "element", "element_fp64", "up", "root", "down", "policy", "policy_fp64", "fwd_up", "fwd_root",
     "fwd_down", "recover", "residual", "ref_d", "bwd_up", "bwd_root", "bwd_down", "ref_kff", "fwd_up_vec",
-    "recover_add", "reduce", "plain_riccati", "up_fp64", "down_fp64"};
+    "recover_add", "reduce", "plain_riccati", "up_fp64", "down_fp64", "fwd_inst", "refine_inst"};
 
 // Per-handle launch timer: two HIP events around every launch, read back by
 // lqr_timing_report.

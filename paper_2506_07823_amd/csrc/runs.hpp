@@ -24,7 +24,7 @@ constexpr int WG = 64;
 enum Fam {
     F_CLEAR, F_ELEM, F_ELEM_FB, F_UP, F_ROOT, F_DOWN, F_POLICY, F_POLICY_FB, F_FUP, F_FROOT, F_FDOWN,
     F_RECOVER, F_RESID, F_REF_D, F_BUP, F_BROOT, F_BDOWN, F_REF_KFF, F_FUPV, F_RECOVER_ADD, F_REDUCE,
-    F_PLAIN, F_UP_FB, F_DOWN_FB, F_COUNT
+    F_PLAIN, F_UP_FB, F_DOWN_FB, F_FWD_INST, F_REFINE_INST, F_COUNT
 };
 
 // Optional per-launch timer (HIP events around each launch on its stream),
@@ -158,23 +158,41 @@ int run_scan(const Plan& p, hipStream_t s, const In<S>& in, const Out<S>& out, S
         const double u = B * (p.ft.cnt[l] / 2);
         LCHK(launch(F_FUP, u * w.fup_f(), u * w.fup_b(), k_fup<S, E, false>, Bi * p.ft.cnt[l + 1], s, p, ws, l));
     }
-    LCHK(launch(F_FROOT, 0, 2 * B * w.es * p.n, k_froot<S>, Bi, s, p, ws, in.x0, (int64_t)p.n));
-    for (int l = p.ft.nlev - 2; l >= 0; --l) {
-        const double u = B * (p.ft.cnt[l] / 2);
-        LCHK(launch(F_FDOWN, u * w.vec_f(), u * w.vec_b(), k_fdown<S, E>, Bi * p.ft.cnt[l], s, p, ws, l));
+    const double fwd_nodes = B * (double)(p.ft.total - p.ft.cnt[p.ft.nlev - 1]);
+    if (p.fused) {
+        // a5 down-sweep + a6 per instance
+        LCHK(launch(F_FWD_INST, fwd_nodes * w.vec_f() + B * (N + 1) * w.rec_f(),
+                    fwd_nodes * w.vec_b() + B * (N + 1) * w.rec_b(), k_fwd_inst<S, E>, Bi, s, p, ws, in.x0,
+                    (int64_t)p.n, out));
+    } else {
+        LCHK(launch(F_FROOT, 0, 2 * B * w.es * p.n, k_froot<S>, Bi, s, p, ws, in.x0, (int64_t)p.n));
+        for (int l = p.ft.nlev - 2; l >= 0; --l) {
+            const double u = B * (p.ft.cnt[l] / 2);
+            LCHK(launch(F_FDOWN, u * w.vec_f(), u * w.vec_b(), k_fdown<S, E>, Bi * p.ft.cnt[l], s, p, ws, l));
+        }
+        // a6: controls and costates
+        LCHK(launch(F_RECOVER, B * (N + 1) * w.rec_f(), B * (N + 1) * w.rec_b(), k_recover<S, E, false>,
+                    Bi * (N + 1), s, p, ws, out));
     }
-    // a6: controls and costates
-    LCHK(launch(F_RECOVER, B * (N + 1) * w.rec_f(), B * (N + 1) * w.rec_b(), k_recover<S, E, false>,
-                Bi * (N + 1), s, p, ws, out));
     // a7: FP64 residual + refinement sweeps (the second only for instances
     // whose residual after the first is still above the tolerance)
     int32_t* active = iws + Qs.total;
     double* rel = resid_out ? resid_out : dws + Bi * p.dstride;
     Plan pg = p;
+    const double ref_f = B * N * 7 * w.vec_f() + 2 * fwd_nodes * w.vec_f() * 2 + B * (N + 1) * w.rec_f();
+    const double ref_b = B * N * 7 * w.vec_b() + 2 * fwd_nodes * w.vec_b() * 2 + B * (N + 1) * w.rec_b();
     for (int sw = 0; sw < refine; ++sw) {
         // sweep 0 and the first decision run over every instance; later
         // decisions only revisit the instances still active
         const Plan& pr = sw >= 2 ? pg : p;
+        if (p.fused) {
+            LCHK(launch(F_RESID, B * (N + 1) * w.resid_f(), B * (N + 1) * w.resid_b(), k_resid_inst<S, E64, true>,
+                        Bi, s, pr, in, (const S*)out.x, (const S*)out.u, (const S*)out.lam, ws, dws,
+                        sw > 0 ? rel : (double*)nullptr, sw > 0 ? active : (int32_t*)nullptr, p.refine_tol));
+            if (sw > 0) pg.active = active;
+            LCHK(launch(F_REFINE_INST, ref_f, ref_b, k_refine_inst<S, E>, Bi, s, pg, in, ws, out));
+            continue;
+        }
         LCHK(launch(F_RESID, B * (N + 1) * w.resid_f(), B * (N + 1) * w.resid_b(), k_resid<S, E64, true>,
                     Bi * (N + 1), s, pr, in, (const S*)out.x, (const S*)out.u, (const S*)out.lam, ws, dws));
         if (sw > 0) {
@@ -206,11 +224,17 @@ int run_scan(const Plan& p, hipStream_t s, const In<S>& in, const Out<S>& out, S
                     Bi * (N + 1), s, pg, ws, out));
     }
     if (resid_out) {
-        // after an adaptive second sweep only the instances it touched changed
-        LCHK(launch(F_RESID, B * (N + 1) * w.resid_f(), B * (N + 1) * w.resid_b(), k_resid<S, E64, false>,
-                    Bi * (N + 1), s, pg, in, (const S*)out.x, (const S*)out.u, (const S*)out.lam, ws, dws));
-        LCHK(launch(F_REDUCE, 0, B * 16.0 * (N + 1), k_resid_reduce<double>, (Bi + 63) / 64, s, pg,
-                    (const double*)dws, resid_out, (int32_t*)nullptr, p.refine_tol));
+        // after an adaptive sweep only the instances it touched changed
+        if (p.fused) {
+            LCHK(launch(F_RESID, B * (N + 1) * w.resid_f(), B * (N + 1) * w.resid_b(), k_resid_inst<S, E64, false>,
+                        Bi, s, pg, in, (const S*)out.x, (const S*)out.u, (const S*)out.lam, ws, dws, resid_out,
+                        (int32_t*)nullptr, p.refine_tol));
+        } else {
+            LCHK(launch(F_RESID, B * (N + 1) * w.resid_f(), B * (N + 1) * w.resid_b(), k_resid<S, E64, false>,
+                        Bi * (N + 1), s, pg, in, (const S*)out.x, (const S*)out.u, (const S*)out.lam, ws, dws));
+            LCHK(launch(F_REDUCE, 0, B * 16.0 * (N + 1), k_resid_reduce<double>, (Bi + 63) / 64, s, pg,
+                        (const double*)dws, resid_out, (int32_t*)nullptr, p.refine_tol));
+        }
     }
     return LQR_OK;
 }
