@@ -21,7 +21,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblqr_kkt.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-TS_CLASSES = (1, 2, 3, 4, 5, 6, 8)
+TS_CLASSES = (1, 2, 3, 4, 5, 6, 8, 32)
 
 HIPFLAGS = [
     "-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17", "-c",
@@ -41,7 +41,7 @@ def torch_lib_dir() -> str:
 
 
 def _sources():
-    deps = [os.path.join(CSRC, f) for f in ("engine.hpp", "kernels.hpp", "runs.hpp")]
+    deps = [os.path.join(CSRC, f) for f in ("engine.hpp", "bigeng.hpp", "kernels.hpp", "kernels_big.hpp", "runs.hpp")]
     deps.append(os.path.join(HERE, "..", "include", "lqr_kkt.h"))
     units = [("lqr_kkt", os.path.join(CSRC, "lqr_kkt.hip"), [])]
     for ts in TS_CLASSES:

@@ -38,6 +38,19 @@ template <> __device__ __forceinline__ double dsqrt<double>(double x) { return _
 __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
+template <typename T>
+__device__ __forceinline__ bool finite_(T v) { return __builtin_isfinite(v); }
+
+__device__ __forceinline__ bool wave_all(bool v) {
+    return __builtin_amdgcn_ballot_w64(!v) == 0;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
 __device__ __forceinline__ void wg_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -55,6 +68,12 @@ struct Eng {
     static constexpr int GL = G * G;         // lanes per group
     static_assert(NP <= GL, "lane-vector layout needs NP <= G*G");
     static_assert(64 % GL == 0, "groups must tile a wavefront");
+    static constexpr bool BIG = false;
+    static constexpr int NT = 64;   // threads per workgroup
+
+    static __device__ __forceinline__ void sync() { wg_sync(); }
+    static __device__ __forceinline__ bool all(bool v) { return wave_all(v); }
+    static __device__ __forceinline__ double sum(double v) { return wave_sum(v); }
 
     int lg, ty, tx;
     __device__ explicit Eng(int lane_in_group)

@@ -24,6 +24,7 @@
 //
 // One 64-lane group (G = 8) owns one task; E::TS selects the padded order.
 #pragma once
+#include "bigeng.hpp"
 #include "engine.hpp"
 
 namespace lqr {
@@ -50,6 +51,9 @@ struct Plan {
     int fallback;
     const int32_t* active;   // refinement gating: instances with active[b] == 0 skip (nullptr = all)
     int fused;               // 1: per-instance kernels for the vector-only passes
+    int64_t o_scr;           // large-block engine: byte offset of the per-workgroup scratch area
+    int64_t scr_elems;       //   its elements per workgroup
+    int big_grid;            //   workgroups of a task launch (scratch slots)
 };
 
 #define LQR_GATE(p, b) \
@@ -101,6 +105,9 @@ struct Lds {
     T vb[2][E::NP];
 };
 
+template <typename T>
+struct Lds<BigEng<T>> : BigLds<T> {};
+
 template <class E>
 struct ResidLds {
     double vb[2][E::NP];
@@ -111,14 +118,15 @@ struct Lds3 : Lds<E> {
     typename E::T sP[E::MAT];
 };
 
-// strided cooperative copy of `count` elements (all 64 lanes)
+// strided cooperative copy of `count` elements (every thread of the
+// workgroup; element i < blockDim.x is handled by thread i)
 template <typename D, typename S>
 __device__ __forceinline__ void coop_copy(D* dst, const S* src, int count) {
-    for (int i = threadIdx.x; i < count; i += 64) dst[i] = D(src[i]);
+    for (int i = threadIdx.x; i < count; i += blockDim.x) dst[i] = D(src[i]);
 }
 template <typename D>
 __device__ __forceinline__ void coop_zero(D* dst, int count) {
-    for (int i = threadIdx.x; i < count; i += 64) dst[i] = D(0);
+    for (int i = threadIdx.x; i < count; i += blockDim.x) dst[i] = D(0);
 }
 
 // load a rows x cols global matrix (optionally transposed) into an LDS slot
@@ -156,18 +164,6 @@ __device__ __forceinline__ void set_status(int32_t* status, int64_t b, int bits)
     if (threadIdx.x == 0) atomicOr(status + b, bits);
 }
 
-template <typename T>
-__device__ __forceinline__ bool finite_(T v) { return __builtin_isfinite(v); }
-
-__device__ __forceinline__ bool wave_all(bool v) {
-    return __builtin_amdgcn_ballot_w64(!v) == 0;
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
 
 // ---------------------------------------------------------------------------
 // FP64 fallback queues.  An FP32 task whose Cholesky factorization fails or
@@ -220,19 +216,32 @@ __global__ void k_clear(I* status, int64_t batch, I* counters, int64_t ncount) {
 }
 
 // Run `body(task)` for every task of the launch (FP32 pass: one task per
-// workgroup) or for every queued task (FP64 pass: grid-stride over the queue).
-#define LQR_TASKS(FB, q, body)                                                    \
+// workgroup, or grid-stride over the per-workgroup scratch slots of the
+// large-block engine) or for every queued task (FP64 pass: grid-stride over
+// the queue).
+#define LQR_TASKS(E, FB, q, ntasks, body)                                         \
     do {                                                                          \
         if (!(FB)) {                                                              \
-            body((int64_t)blockIdx.x);                                            \
+            if (E::BIG) {                                                         \
+                for (int64_t t_ = blockIdx.x; t_ < (ntasks); t_ += gridDim.x) {   \
+                    body(t_);                                                     \
+                    E::sync();                                                    \
+                }                                                                 \
+            } else {                                                              \
+                body((int64_t)blockIdx.x);                                        \
+            }                                                                     \
         } else {                                                                  \
             const int cnt_ = *(q).count;                                          \
             for (int i_ = blockIdx.x; i_ < cnt_; i_ += gridDim.x) {               \
                 body((int64_t)(q).ids[i_]);                                       \
-                wg_sync();                                                        \
+                E::sync();                                                        \
             }                                                                     \
         }                                                                         \
     } while (0)
+
+}  // namespace lqr
+#include "kernels_big.hpp"
+namespace lqr {
 
 // ---------------------------------------------------------------------------
 // Sec. II-D, eq. (initialization): one-stage element with S_k = M_k'.
@@ -294,10 +303,13 @@ __device__ __forceinline__ void element_task(Lds<E>& L, const Plan& p, const In<
 }
 
 template <typename S, class E, bool FB>
-__global__ __launch_bounds__(64) void k_element(Plan p, In<S> in, S* ws, int32_t* status, FbQueue q) {
+__global__ __launch_bounds__(E::NT) void k_element(Plan p, In<S> in, S* ws, int32_t* status, FbQueue q) {
     __shared__ Lds<E> L;
-    auto body = [&](int64_t t) { element_task<S, E, FB>(L, p, in, ws, status, q, t); };
-    LQR_TASKS(FB, q, body);
+    auto body = [&](int64_t t) {
+        if constexpr (E::BIG) big_element_task<S, E, FB>(L, p, in, ws, status, q, t);
+        else element_task<S, E, FB>(L, p, in, ws, status, q, t);
+    };
+    LQR_TASKS(E, FB, q, p.batch * (p.N + 1), body);
 }
 
 // ---------------------------------------------------------------------------
@@ -456,10 +468,13 @@ __device__ __forceinline__ void up_task(Lds<E>& L, const Plan& p, S* ws, int lvl
 }
 
 template <typename S, class E, bool FB>
-__global__ __launch_bounds__(64) void k_up(Plan p, S* ws, int lvl, int32_t* status, FbQueue q) {
+__global__ __launch_bounds__(E::NT) void k_up(Plan p, S* ws, int lvl, int32_t* status, FbQueue q) {
     __shared__ Lds<E> L;
-    auto body = [&](int64_t t) { up_task<S, E, FB>(L, p, ws, lvl, status, q, t); };
-    LQR_TASKS(FB, q, body);
+    auto body = [&](int64_t t) {
+        if constexpr (E::BIG) big_up_task<S, E, FB>(L, p, ws, lvl, status, q, t);
+        else up_task<S, E, FB>(L, p, ws, lvl, status, q, t);
+    };
+    LQR_TASKS(E, FB, q, p.batch * p.rt.cnt[lvl + 1], body);
 }
 
 // root of the reverse tree: its (P, p) is the complete suffix starting at 0
@@ -503,10 +518,13 @@ __device__ __forceinline__ void down_task(Lds<E>& L, const Plan& p, S* ws, int l
 }
 
 template <typename S, class E, bool FB>
-__global__ __launch_bounds__(64) void k_down(Plan p, S* ws, int lvl, int32_t* status, FbQueue q) {
+__global__ __launch_bounds__(E::NT) void k_down(Plan p, S* ws, int lvl, int32_t* status, FbQueue q) {
     __shared__ Lds<E> L;
-    auto body = [&](int64_t t) { down_task<S, E, FB>(L, p, ws, lvl, status, q, t); };
-    LQR_TASKS(FB, q, body);
+    auto body = [&](int64_t t) {
+        if constexpr (E::BIG) big_down_task<S, E, FB>(L, p, ws, lvl, status, q, t);
+        else down_task<S, E, FB>(L, p, ws, lvl, status, q, t);
+    };
+    LQR_TASKS(E, FB, q, p.batch * (p.rt.cnt[lvl] / 2), body);
 }
 
 // ---------------------------------------------------------------------------
@@ -576,10 +594,13 @@ __device__ __forceinline__ void policy_task(Lds<E>& L, const Plan& p, const In<S
 }
 
 template <typename S, class E, bool FB>
-__global__ __launch_bounds__(64) void k_policy(Plan p, In<S> in, S* ws, int32_t* status, FbQueue q) {
+__global__ __launch_bounds__(E::NT) void k_policy(Plan p, In<S> in, S* ws, int32_t* status, FbQueue q) {
     __shared__ Lds<E> L;
-    auto body = [&](int64_t t) { policy_task<S, E, FB>(L, p, in, ws, status, q, t); };
-    LQR_TASKS(FB, q, body);
+    auto body = [&](int64_t t) {
+        if constexpr (E::BIG) big_policy_task<S, E, FB>(L, p, in, ws, status, q, t);
+        else policy_task<S, E, FB>(L, p, in, ws, status, q, t);
+    };
+    LQR_TASKS(E, FB, q, p.batch * p.N, body);
 }
 
 // ---------------------------------------------------------------------------
@@ -605,26 +626,26 @@ __device__ __forceinline__ void fup_body(Lds<E>& L, Plan p, S* ws, int lvl, int6
         return;
     }
     const S* r = l + p.frec;
-    if (VEC) {
+    if constexpr (VEC) {
         const T v = e.template gmv<false>(r, n, n, n, e.vload(l + nn, n), L.vb[0]) + e.vload(r + nn, n);
         e.vstore(out + nn, n, v);
-        return;
-    }
-    stage(e, L.sA, r, n, n, n);                           // M_r
-    stage(e, L.sX, l, n, n, n);                           // M_l
-    wg_sync();
-    const T v = e.template matvec<false>(L.sA, e.vload(l + nn, n), L.vb[0], n, n) + e.vload(r + nn, n);
-    if (!VEC) {
+    } else if constexpr (E::BIG) {
+        big_fup_task<S, E>(L, l, r, out, n);
+    } else {
+        stage(e, L.sA, r, n, n, n);                           // M_r
+        stage(e, L.sX, l, n, n, n);                           // M_l
+        wg_sync();
+        const T v = e.template matvec<false>(L.sA, e.vload(l + nn, n), L.vb[0], n, n) + e.vload(r + nn, n);
         typename E::Tile t;
         e.zero(t);
         e.template gemm<false, false>(t, L.sA, L.sX, n);
         e.store(t, out, n, n, n);
+        e.vstore(out + nn, n, v);
     }
-    e.vstore(out + nn, n, v);
 }
 
 template <typename S, class E, bool VEC>
-__global__ __launch_bounds__(64) void k_fup(Plan p, S* ws, int lvl) {
+__global__ __launch_bounds__(E::NT) void k_fup(Plan p, S* ws, int lvl) {
     __shared__ Lds<E> L;
     fup_body<S, E, VEC>(L, p, ws, lvl, (int64_t)blockIdx.x);
 }
@@ -667,7 +688,7 @@ __device__ __forceinline__ void fdown_body(Lds<E>& L, Plan p, S* ws, int lvl, in
 }
 
 template <typename S, class E>
-__global__ __launch_bounds__(64) void k_fdown(Plan p, S* ws, int lvl) {
+__global__ __launch_bounds__(E::NT) void k_fdown(Plan p, S* ws, int lvl) {
     __shared__ Lds<E> L;
     fdown_body<S, E>(L, p, ws, lvl, (int64_t)blockIdx.x);
 }
@@ -718,11 +739,11 @@ __device__ __forceinline__ void recover_body(Lds<E>& L, Plan p, S* ws, Out<S> ou
         uo[e.lg] = S(uv);
         fin = fin && finite_(uv);
     }
-    if (!wave_all(fin)) set_status(out.status, b, 1);
+    if (!E::all(fin)) set_status(out.status, b, 1);
 }
 
 template <typename S, class E, bool ADD>
-__global__ __launch_bounds__(64) void k_recover(Plan p, S* ws, Out<S> out) {
+__global__ __launch_bounds__(E::NT) void k_recover(Plan p, S* ws, Out<S> out) {
     __shared__ Lds<E> L;
     recover_body<S, E, ADD>(L, p, ws, out, (int64_t)blockIdx.x);
 }
@@ -785,8 +806,8 @@ __device__ __forceinline__ void resid_body(ResidLds<E>& RL, Plan p, In<S> in, co
         bb += x0v * x0v;
         if (CORR) e.vstore(inst + p.o_x0p, n, -ri);
     }
-    rr = wave_sum(rr);
-    bb = wave_sum(bb);
+    rr = E::sum(rr);
+    bb = E::sum(bb);
     if (threadIdx.x == 0) {
         dws[b * p.dstride + 2 * k] = rr;
         dws[b * p.dstride + 2 * k + 1] = bb;
@@ -794,7 +815,7 @@ __device__ __forceinline__ void resid_body(ResidLds<E>& RL, Plan p, In<S> in, co
 }
 
 template <typename S, class E, bool CORR>
-__global__ __launch_bounds__(64) void k_resid(Plan p, In<S> in, const S* xs_, const S* us_, const S* ls_,
+__global__ __launch_bounds__(E::NT) void k_resid(Plan p, In<S> in, const S* xs_, const S* us_, const S* ls_,
                                               S* ws, double* dws) {
     __shared__ ResidLds<E> RL;
     resid_body<S, E, CORR>(RL, p, in, xs_, us_, ls_, ws, dws, (int64_t)blockIdx.x);
@@ -844,7 +865,7 @@ __device__ __forceinline__ void ref_d_body(Lds<E>& L, Plan p, S* ws, int64_t tid
 }
 
 template <typename S, class E>
-__global__ __launch_bounds__(64) void k_ref_d(Plan p, S* ws) {
+__global__ __launch_bounds__(E::NT) void k_ref_d(Plan p, S* ws) {
     __shared__ Lds<E> L;
     ref_d_body<S, E>(L, p, ws, (int64_t)blockIdx.x);
 }
@@ -872,7 +893,7 @@ __device__ __forceinline__ void bvec_up_body(Lds<E>& L, Plan p, S* ws, int lvl, 
 }
 
 template <typename S, class E>
-__global__ __launch_bounds__(64) void k_bvec_up(Plan p, S* ws, int lvl) {
+__global__ __launch_bounds__(E::NT) void k_bvec_up(Plan p, S* ws, int lvl) {
     __shared__ Lds<E> L;
     bvec_up_body<S, E>(L, p, ws, lvl, (int64_t)blockIdx.x);
 }
@@ -917,7 +938,7 @@ __device__ __forceinline__ void bvec_down_body(Lds<E>& L, Plan p, S* ws, int lvl
 }
 
 template <typename S, class E>
-__global__ __launch_bounds__(64) void k_bvec_down(Plan p, S* ws, int lvl) {
+__global__ __launch_bounds__(E::NT) void k_bvec_down(Plan p, S* ws, int lvl) {
     __shared__ Lds<E> L;
     bvec_down_body<S, E>(L, p, ws, lvl, (int64_t)blockIdx.x);
 }
@@ -932,6 +953,10 @@ __device__ __forceinline__ void ref_kff_body(Lds<E>& L, Plan p, In<S> in, S* ws,
     const int64_t b = tid / N;
     const int k = tid % N;
     LQR_GATE(p, b);
+    if constexpr (E::BIG) {
+        big_ref_kff<S, E>(L, p, in, ws, b, k);
+        return;
+    } else {
     const Ptr<S> P(p, in);
     S* inst = ws + b * p.stride;
     const S* Pn = inst + p.o_suf + (int64_t)suffix_id(p.rt, 0, k + 1) * p.srec;
@@ -953,10 +978,11 @@ __device__ __forceinline__ void ref_kff_body(Lds<E>& L, Plan p, In<S> in, S* ws,
     e.vstore(inst + p.o_kffp + (int64_t)k * m, m, kf);
     const T bb = e.template gmv<false>(P.B(b, k), n, m, m, kf, L.vb[1]) + cpv;
     e.vstore(inst + p.o_ftree + (int64_t)k * p.frec + nn, n, bb);
+    }
 }
 
 template <typename S, class E>
-__global__ __launch_bounds__(64) void k_ref_kff(Plan p, In<S> in, S* ws) {
+__global__ __launch_bounds__(E::NT) void k_ref_kff(Plan p, In<S> in, S* ws) {
     __shared__ Lds<E> L;
     ref_kff_body<S, E>(L, p, in, ws, (int64_t)blockIdx.x);
 }
@@ -971,7 +997,6 @@ __global__ __launch_bounds__(64) void k_ref_kff(Plan p, In<S> in, S* ws) {
 // i < 64), so single-thread program order suffices between tasks; the only
 // cross-lane hand-offs are the LDS ones inside the products.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void global_sync() { wg_sync(); }
 
 // forward scan of the closed-loop maps from x0 (UPV: recompute the vector
 // part of the up-sweep first) and u_k, lambda_k (ADD: added to the outputs)
@@ -982,26 +1007,26 @@ __device__ __forceinline__ void fwd_inst_body(Lds<E>& L, const Plan& p, S* ws, c
         for (int l = 0; l + 1 < p.ft.nlev; ++l) {
             for (int i = 0; i < p.ft.cnt[l + 1]; ++i) {
                 fup_body<S, E, true>(L, p, ws, l, b * p.ft.cnt[l + 1] + i);
-                global_sync();
+                E::sync();
             }
         }
     }
     froot_body<S>(p, ws, x0, x0_stride, b);
-    global_sync();
+    E::sync();
     for (int l = p.ft.nlev - 2; l >= 0; --l) {
         for (int j = 0; j < p.ft.cnt[l]; ++j) {
             fdown_body<S, E>(L, p, ws, l, b * p.ft.cnt[l] + j);
-            global_sync();
+            E::sync();
         }
     }
     for (int k = 0; k <= p.N; ++k) {
         recover_body<S, E, ADD>(L, p, ws, out, b * (p.N + 1) + k);
-        wg_sync();
+        E::sync();
     }
 }
 
 template <typename S, class E>
-__global__ __launch_bounds__(64) void k_fwd_inst(Plan p, S* ws, const S* x0, int64_t x0_stride, Out<S> out) {
+__global__ __launch_bounds__(E::NT) void k_fwd_inst(Plan p, S* ws, const S* x0, int64_t x0_stride, Out<S> out) {
     __shared__ Lds<E> L;
     const int64_t b = blockIdx.x;
     LQR_GATE(p, b);
@@ -1010,42 +1035,42 @@ __global__ __launch_bounds__(64) void k_fwd_inst(Plan p, S* ws, const S* x0, int
 
 // one whole refinement sweep of one instance (after its residual pass)
 template <typename S, class E>
-__global__ __launch_bounds__(64) void k_refine_inst(Plan p, In<S> in, S* ws, Out<S> out) {
+__global__ __launch_bounds__(E::NT) void k_refine_inst(Plan p, In<S> in, S* ws, Out<S> out) {
     __shared__ Lds<E> L;
     const int64_t b = blockIdx.x;
     LQR_GATE(p, b);
     const int N = p.N;
     for (int k = 0; k < N; ++k) {
         ref_d_body<S, E>(L, p, ws, b * N + k);
-        wg_sync();
+        E::sync();
     }
-    global_sync();
+    E::sync();
     for (int l = 0; l + 1 < p.ft.nlev; ++l) {
         for (int i = 0; i < p.ft.cnt[l + 1]; ++i) {
             bvec_up_body<S, E>(L, p, ws, l, b * p.ft.cnt[l + 1] + i);
-            global_sync();
+            E::sync();
         }
     }
     broot_body<S>(p, ws, b);
-    global_sync();
+    E::sync();
     for (int l = p.ft.nlev - 2; l >= 0; --l) {
         for (int j = 0; j < p.ft.cnt[l]; ++j) {
             bvec_down_body<S, E>(L, p, ws, l, b * p.ft.cnt[l] + j);
-            global_sync();
+            E::sync();
         }
     }
     for (int k = 0; k < N; ++k) {
         ref_kff_body<S, E>(L, p, in, ws, b * N + k);
-        wg_sync();
+        E::sync();
     }
-    global_sync();
+    E::sync();
     fwd_inst_body<S, E, true, true>(L, p, ws, (const S*)(ws + p.o_x0p), p.stride, out, b);
 }
 
 // FP64 residual of one instance, all stages, reduced in place:
 // rel[b] = ||r|| / ||(x0, c, q, r)|| (and active_out[b] = rel > tol)
 template <typename S, class E, bool CORR>
-__global__ __launch_bounds__(64) void k_resid_inst(Plan p, In<S> in, const S* xs_, const S* us_, const S* ls_,
+__global__ __launch_bounds__(E::NT) void k_resid_inst(Plan p, In<S> in, const S* xs_, const S* us_, const S* ls_,
                                                    S* ws, double* dws, double* rel, int32_t* active_out,
                                                    double tol) {
     __shared__ ResidLds<E> RL;
@@ -1053,7 +1078,7 @@ __global__ __launch_bounds__(64) void k_resid_inst(Plan p, In<S> in, const S* xs
     LQR_GATE(p, b);
     for (int k = 0; k <= p.N; ++k) {
         resid_body<S, E, CORR>(RL, p, in, xs_, us_, ls_, ws, dws, b * (p.N + 1) + k);
-        wg_sync();
+        E::sync();
     }
     if (threadIdx.x == 0) {   // the partial sums were written by this lane
         double rr = 0.0, bb = 0.0;

@@ -38,6 +38,7 @@ LQR_DECLARE_RUNS(4)
 LQR_DECLARE_RUNS(5)
 LQR_DECLARE_RUNS(6)
 LQR_DECLARE_RUNS(8)
+LQR_DECLARE_RUNS(32)
 }  // namespace lqr
 
 namespace {
@@ -58,14 +59,18 @@ Tree make_tree(int leaves) {
     return t;
 }
 
-// padded-order class: TS = ceil(max(n, m) / 8); built classes below
+// padded-order class: TS = ceil(max(n, m) / 8) for the wavefront engine
+// (orders up to 64), the large-block engine (kBigTS) up to kMaxDim
 constexpr int kTS[] = {1, 2, 3, 4, 5, 6, 8};
+constexpr int kMaxDim = 256;
 int pick_ts(int n, int m) {
     const int d = n > m ? n : m;
     for (int ts : kTS)
         if (8 * ts >= d) return ts;
-    return 0;
+    return d <= kMaxDim ? kBigTS : 0;
 }
+// workgroups (= scratch slots) of a large-block task launch
+constexpr int kBigGrid = 512;
 
 int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
@@ -106,19 +111,28 @@ Plan make_plan(int64_t batch, int N, int n, int m, size_t esize, const lqr_opts&
     // level-parallel launches keep the O(log N) depth for small batches
     p.fused = batch >= 128 ? 1 : 0;
     p.fallback = esize == 4 ? o.fallback : 0;   // the FP64 path has nothing to fall back to
+    if (pick_ts(n, m) == kBigTS) {
+        const int64_t d = n > m ? n : m;
+        p.scr_elems = align_up(8 * d * d + 64 * d, 64);
+        const int64_t most = batch * (N + 1);
+        p.big_grid = (int)(most < kBigGrid ? most : kBigGrid);
+    }
     return p;
 }
 
 struct Layout {
-    size_t main_bytes, int_off, dbl_off, total;
+    size_t main_bytes, int_off, dbl_off, scr_off, total;
 };
 
+// per-instance records | int32 queues and flags | FP64 partial sums |
+// large-block scratch (one slot per workgroup, sized for FP64 compute)
 Layout layout(const Plan& p, size_t esize) {
     Layout l;
     l.main_bytes = (size_t)align_up((int64_t)(p.batch * p.stride * (int64_t)esize), 256);
     l.int_off = l.main_bytes;
     l.dbl_off = l.int_off + (size_t)align_up((queue_layout(p).total + p.batch) * 4, 256);
-    l.total = l.dbl_off + (size_t)align_up((p.batch * p.dstride + p.batch) * 8, 256);
+    l.scr_off = l.dbl_off + (size_t)align_up((p.batch * p.dstride + p.batch) * 8, 256);
+    l.total = l.scr_off + (size_t)align_up((int64_t)p.big_grid * p.scr_elems * 8, 256);
     return l;
 }
 
@@ -127,7 +141,8 @@ bool aligned(const void* ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
 int check_dims(int64_t batch, int N, int n, int m) {
     if (batch < 1) return fail(LQR_EINVAL, "batch must be >= 1 (got %lld)", (long long)batch);
     if (N < 1 || n < 1 || m < 1) return fail(LQR_EINVAL, "N, n, m must be >= 1 (got %d, %d, %d)", N, n, m);
-    if (pick_ts(n, m) == 0) return fail(LQR_EUNSUPPORTED, "n=%d m=%d exceed the built shape classes (<= 64)", n, m);
+    if (pick_ts(n, m) == 0)
+        return fail(LQR_EUNSUPPORTED, "n=%d m=%d exceed the built shape classes (<= %d)", n, m, kMaxDim);
     if (N + 1 > (1 << (LQR_MAXLEV - 2))) return fail(LQR_EINVAL, "N=%d too large", N);
     const int64_t tasks = batch * (int64_t)(N + 1);
     if (tasks > (int64_t)0x7fffffff) return fail(LQR_EINVAL, "batch*(N+1) exceeds the grid limit");
@@ -143,7 +158,7 @@ int dispatch(int ts, int method, const Plan& p, hipStream_t s, const In<S>& in, 
                    ? run_scan<S, TSV>(p, s, in, out, ws, iws, dws, refine, resid_out)    \
                    : run_plain<S, TSV>(p, s, in, out, ws, iws, dws, resid_out);
     switch (ts) {
-        LQR_CASE(1) LQR_CASE(2) LQR_CASE(3) LQR_CASE(4) LQR_CASE(5) LQR_CASE(6) LQR_CASE(8)
+        LQR_CASE(1) LQR_CASE(2) LQR_CASE(3) LQR_CASE(4) LQR_CASE(5) LQR_CASE(6) LQR_CASE(8) LQR_CASE(32)
         default: return fail(LQR_EUNSUPPORTED, "no shape class for TS=%d", ts);
     }
 #undef LQR_CASE
@@ -155,7 +170,7 @@ int dispatch_resid(int ts, const Plan& p, hipStream_t s, const In<S>& in, const 
 #define LQR_CASE(TSV) \
     case TSV: return run_resid<S, TSV>(p, s, in, x, u, lam, ws, dws, rel);
     switch (ts) {
-        LQR_CASE(1) LQR_CASE(2) LQR_CASE(3) LQR_CASE(4) LQR_CASE(5) LQR_CASE(6) LQR_CASE(8)
+        LQR_CASE(1) LQR_CASE(2) LQR_CASE(3) LQR_CASE(4) LQR_CASE(5) LQR_CASE(6) LQR_CASE(8) LQR_CASE(32)
         default: return fail(LQR_EUNSUPPORTED, "no shape class for TS=%d", ts);
     }
 #undef LQR_CASE
@@ -238,7 +253,7 @@ int lqr_destroy(lqr_handle_t h) {
     return LQR_OK;
 }
 
-int lqr_max_dim(void) { return 64; }
+int lqr_max_dim(void) { return kMaxDim; }
 
 const char* lqr_last_error(void) { return g_err.c_str(); }
 
@@ -281,10 +296,11 @@ int lqr_kkt_solve(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int
         return fail(LQR_EINVAL, "misaligned output");
     if (!aligned(workspace, 256)) return fail(LQR_EINVAL, "workspace must be 256-byte aligned");
     if (o.resid_out && !aligned(o.resid_out, 8)) return fail(LQR_EINVAL, "misaligned resid_out");
-    const Plan p = make_plan(batch, N, n, m, es, o);
+    Plan p = make_plan(batch, N, n, m, es, o);
     const Layout lay = layout(p, es);
     if (workspace_bytes < lay.total)
         return fail(LQR_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", workspace_bytes, lay.total);
+    p.o_scr = (int64_t)lay.scr_off;
     HIPCHK(hipSetDevice(h->device));
     hipStream_t s = (hipStream_t)stream;
     char* wsb = (char*)workspace;
@@ -318,10 +334,11 @@ int lqr_kkt_residual(lqr_handle_t h, void* stream, int64_t batch, int N, int n, 
     lqr_opts o;
     lqr_opts_default(&o, dtype);
     const size_t es = dtype == LQR_F32 ? 4 : 8;
-    const Plan p = make_plan(batch, N, n, m, es, o);
+    Plan p = make_plan(batch, N, n, m, es, o);
     const Layout lay = layout(p, es);
     if (workspace_bytes < lay.total)
         return fail(LQR_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", workspace_bytes, lay.total);
+    p.o_scr = (int64_t)lay.scr_off;
     HIPCHK(hipSetDevice(h->device));
     hipStream_t s = (hipStream_t)stream;
     char* wsb = (char*)workspace;

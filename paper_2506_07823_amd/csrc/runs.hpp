@@ -5,6 +5,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "../../include/lqr_kkt.h"
 #include "kernels.hpp"
 
@@ -19,6 +21,11 @@ int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
     } while (0)
 
 constexpr int WG = 64;
+// shape class of the large-block engine (orders 65..256)
+constexpr int kBigTS = 32;
+
+template <typename S, int TS>
+using EngOf = typename std::conditional<TS == kBigTS, BigEng<S>, Eng<S, 8, TS>>::type;
 
 // kernel families (diagnostic timing keys)
 enum Fam {
@@ -37,11 +44,11 @@ struct Timer {
 Timer*& current_timer();
 
 template <typename K, typename... Args>
-int launch(int fam, double flops, double bytes, K kernel, int64_t grid, hipStream_t s, Args... args) {
+int launch_nt(int nt, int fam, double flops, double bytes, K kernel, int64_t grid, hipStream_t s, Args... args) {
     if (grid <= 0) return LQR_OK;
     Timer* t = current_timer();
     if (t) t->before(s, fam, flops, bytes);
-    hipLaunchKernelGGL(kernel, dim3((unsigned)grid), dim3(WG), 0, s, args...);
+    hipLaunchKernelGGL(kernel, dim3((unsigned)grid), dim3(nt), 0, s, args...);
     if (t) t->after(s);
     HIPCHK(hipGetLastError());
     return LQR_OK;
@@ -68,6 +75,19 @@ inline Queues queue_layout(const Plan& p) {
 }
 inline FbQueue fbq(int32_t* iws, const Queues& q, int idx) { return FbQueue{iws + idx, iws + q.list[idx]}; }
 inline int64_t drain_grid(int64_t tasks) { return tasks < 1024 ? tasks : 1024; }
+
+// grid of a task launch: one workgroup per task, except for the large-block
+// engine whose workgroups loop over the tasks with one scratch slot each
+template <class E>
+inline int64_t task_grid(const Plan& p, int64_t tasks) {
+    if (!E::BIG) return tasks;
+    return tasks < p.big_grid ? tasks : p.big_grid;
+}
+template <class E>
+inline int64_t fb_grid(const Plan& p, int64_t tasks) {
+    const int64_t g = drain_grid(tasks);
+    return E::BIG && g > p.big_grid ? p.big_grid : g;
+}
 
 // Algorithmic work per unit (flops counted as 2 per multiply-add, the
 // symmetric and triangular products at their minimal cost; bytes = the
@@ -106,72 +126,73 @@ struct Work {
 template <typename S, int TS>
 int run_scan(const Plan& p, hipStream_t s, const In<S>& in, const Out<S>& out, S* ws, int32_t* iws,
              double* dws, int refine, double* resid_out) {
-    using E = Eng<S, 8, TS>;
-    using E64 = Eng<double, 8, TS>;
+    using E = EngOf<S, TS>;
+    using E64 = EngOf<double, TS>;
+    constexpr int NT = E::NT;
     const Work w(p, sizeof(S));
     const double B = (double)p.batch;
     const int64_t Bi = p.batch;
     const int N = p.N;
     const Queues Qs = queue_layout(p);
     const bool fb = sizeof(S) == 4 && p.fallback;
-    LCHK(launch(F_CLEAR, 0, 4.0 * Bi, k_clear<int32_t>, (Bi + 255) / 256 * 4, s, out.status, Bi, iws,
+    LCHK(launch_nt(WG, F_CLEAR, 0, 4.0 * Bi, k_clear<int32_t>, (Bi + 255) / 256 * 4, s, out.status, Bi, iws,
                 (int64_t)kQCount));
     // a1: elements (+ FP64 redo of queued stages)
     {
         const FbQueue q = fbq(iws, Qs, kQElem);
-        LCHK(launch(F_ELEM, B * N * w.elem_f(), B * N * w.elem_b(), k_element<S, E, false>, Bi * (N + 1), s, p,
+        LCHK(launch_nt(NT, F_ELEM, B * N * w.elem_f(), B * N * w.elem_b(), k_element<S, E, false>, task_grid<E>(p, Bi * (N + 1)), s, p,
                     in, ws, out.status, q));
         if (fb)
-            LCHK(launch(F_ELEM_FB, 0, 0, k_element<S, E64, true>, drain_grid(Bi * (N + 1)), s, p, in, ws,
+            LCHK(launch_nt(NT, F_ELEM_FB, 0, 0, k_element<S, E64, true>, fb_grid<E64>(p, Bi * (N + 1)), s, p, in, ws,
                         out.status, q));
     }
     // a3: reverse scan, up-sweep then down-sweep
     for (int l = 0; l + 1 < p.rt.nlev; ++l) {
         const double u = B * (p.rt.cnt[l] / 2);
         const FbQueue q = fbq(iws, Qs, kQUp + l);
-        LCHK(launch(F_UP, u * w.comb_f(), u * w.comb_b(), k_up<S, E, false>, Bi * p.rt.cnt[l + 1], s, p, ws, l,
+        LCHK(launch_nt(NT, F_UP, u * w.comb_f(), u * w.comb_b(), k_up<S, E, false>, task_grid<E>(p, Bi * p.rt.cnt[l + 1]), s, p, ws, l,
                     out.status, q));
         if (fb)
-            LCHK(launch(F_UP_FB, 0, 0, k_up<S, E64, true>, drain_grid(Bi * p.rt.cnt[l + 1]), s, p, ws, l,
+            LCHK(launch_nt(NT, F_UP_FB, 0, 0, k_up<S, E64, true>, fb_grid<E64>(p, Bi * p.rt.cnt[l + 1]), s, p, ws, l,
                         out.status, q));
     }
-    LCHK(launch(F_ROOT, 0, 2 * B * w.es * p.srec, k_root<S>, Bi, s, p, ws));
+    LCHK(launch_nt(WG, F_ROOT, 0, 2 * B * w.es * p.srec, k_root<S>, Bi, s, p, ws));
     for (int l = p.rt.nlev - 2; l >= 0; --l) {
         const double u = B * (p.rt.cnt[l] / 2);
         const FbQueue q = fbq(iws, Qs, kQDown + l);
-        LCHK(launch(F_DOWN, u * w.cheap_f(), u * w.cheap_b(), k_down<S, E, false>, Bi * (p.rt.cnt[l] / 2), s, p,
+        LCHK(launch_nt(NT, F_DOWN, u * w.cheap_f(), u * w.cheap_b(), k_down<S, E, false>, task_grid<E>(p, Bi * (p.rt.cnt[l] / 2)), s, p,
                     ws, l, out.status, q));
         if (fb)
-            LCHK(launch(F_DOWN_FB, 0, 0, k_down<S, E64, true>, drain_grid(Bi * (p.rt.cnt[l] / 2)), s, p, ws, l,
+            LCHK(launch_nt(NT, F_DOWN_FB, 0, 0, k_down<S, E64, true>, fb_grid<E64>(p, Bi * (p.rt.cnt[l] / 2)), s, p, ws, l,
                         out.status, q));
     }
     // a4: policy and closed-loop maps
     {
         const FbQueue q = fbq(iws, Qs, kQPolicy);
-        LCHK(launch(F_POLICY, B * N * w.pol_f(), B * N * w.pol_b(), k_policy<S, E, false>, Bi * N, s, p, in, ws,
+        LCHK(launch_nt(NT, F_POLICY, B * N * w.pol_f(), B * N * w.pol_b(), k_policy<S, E, false>, task_grid<E>(p, Bi * N), s, p, in, ws,
                     out.status, q));
         if (fb)
-            LCHK(launch(F_POLICY_FB, 0, 0, k_policy<S, E64, true>, drain_grid(Bi * N), s, p, in, ws, out.status, q));
+            LCHK(launch_nt(NT, F_POLICY_FB, 0, 0, k_policy<S, E64, true>, fb_grid<E64>(p, Bi * N), s, p, in, ws, out.status, q));
     }
     // a5: forward scan of the closed-loop maps
     for (int l = 0; l + 1 < p.ft.nlev; ++l) {
         const double u = B * (p.ft.cnt[l] / 2);
-        LCHK(launch(F_FUP, u * w.fup_f(), u * w.fup_b(), k_fup<S, E, false>, Bi * p.ft.cnt[l + 1], s, p, ws, l));
+        LCHK(launch_nt(NT, F_FUP, u * w.fup_f(), u * w.fup_b(), k_fup<S, E, false>, Bi * p.ft.cnt[l + 1], s, p, ws, l));
     }
     const double fwd_nodes = B * (double)(p.ft.total - p.ft.cnt[p.ft.nlev - 1]);
     if (p.fused) {
         // a5 down-sweep + a6 per instance
-        LCHK(launch(F_FWD_INST, fwd_nodes * w.vec_f() + B * (N + 1) * w.rec_f(),
+        LCHK(launch_nt(NT, F_FWD_INST, fwd_nodes * w.vec_f() + B * (N + 1) * w.rec_f(),
                     fwd_nodes * w.vec_b() + B * (N + 1) * w.rec_b(), k_fwd_inst<S, E>, Bi, s, p, ws, in.x0,
                     (int64_t)p.n, out));
     } else {
-        LCHK(launch(F_FROOT, 0, 2 * B * w.es * p.n, k_froot<S>, Bi, s, p, ws, in.x0, (int64_t)p.n));
+        LCHK(launch_nt(WG, F_FROOT, 0, 2 * B * w.es * p.n, k_froot<S>, Bi, s, p, ws, in.x0, (int64_t)p.n));
         for (int l = p.ft.nlev - 2; l >= 0; --l) {
             const double u = B * (p.ft.cnt[l] / 2);
-            LCHK(launch(F_FDOWN, u * w.vec_f(), u * w.vec_b(), k_fdown<S, E>, Bi * p.ft.cnt[l], s, p, ws, l));
+            LCHK(launch_nt(NT, F_FDOWN, u * w.vec_f(), u * w.vec_b(), k_fdown<S, E>, Bi * p.ft.cnt[l], s, p, ws, l));
         }
         // a6: controls and costates
-        LCHK(launch(F_RECOVER, B * (N + 1) * w.rec_f(), B * (N + 1) * w.rec_b(), k_recover<S, E, false>,
+        LCHK(launch_nt(NT, F_RECOVER, B * (N + 1) * w.rec_f(), B * (N + 1) * w.rec_b(), k_recover<S, E, false>,
                     Bi * (N + 1), s, p, ws, out));
     }
     // a7: FP64 residual + refinement sweeps (the second only for instances
@@ -186,53 +207,53 @@ int run_scan(const Plan& p, hipStream_t s, const In<S>& in, const Out<S>& out, S
         // decisions only revisit the instances still active
         const Plan& pr = sw >= 2 ? pg : p;
         if (p.fused) {
-            LCHK(launch(F_RESID, B * (N + 1) * w.resid_f(), B * (N + 1) * w.resid_b(), k_resid_inst<S, E64, true>,
+            LCHK(launch_nt(NT, F_RESID, B * (N + 1) * w.resid_f(), B * (N + 1) * w.resid_b(), k_resid_inst<S, E64, true>,
                         Bi, s, pr, in, (const S*)out.x, (const S*)out.u, (const S*)out.lam, ws, dws,
                         sw > 0 ? rel : (double*)nullptr, sw > 0 ? active : (int32_t*)nullptr, p.refine_tol));
             if (sw > 0) pg.active = active;
-            LCHK(launch(F_REFINE_INST, ref_f, ref_b, k_refine_inst<S, E>, Bi, s, pg, in, ws, out));
+            LCHK(launch_nt(NT, F_REFINE_INST, ref_f, ref_b, k_refine_inst<S, E>, Bi, s, pg, in, ws, out));
             continue;
         }
-        LCHK(launch(F_RESID, B * (N + 1) * w.resid_f(), B * (N + 1) * w.resid_b(), k_resid<S, E64, true>,
+        LCHK(launch_nt(NT, F_RESID, B * (N + 1) * w.resid_f(), B * (N + 1) * w.resid_b(), k_resid<S, E64, true>,
                     Bi * (N + 1), s, pr, in, (const S*)out.x, (const S*)out.u, (const S*)out.lam, ws, dws));
         if (sw > 0) {
-            LCHK(launch(F_REDUCE, 0, B * 16.0 * (N + 1), k_resid_reduce<double>, (Bi + 63) / 64, s, pr,
+            LCHK(launch_nt(WG, F_REDUCE, 0, B * 16.0 * (N + 1), k_resid_reduce<double>, (Bi + 63) / 64, s, pr,
                         (const double*)dws, rel, active, p.refine_tol));
             pg.active = active;
         }
-        LCHK(launch(F_REF_D, B * N * 3 * w.vec_f(), B * N * 3 * w.vec_b(), k_ref_d<S, E>, Bi * N, s, pg, ws));
+        LCHK(launch_nt(NT, F_REF_D, B * N * 3 * w.vec_f(), B * N * 3 * w.vec_b(), k_ref_d<S, E>, Bi * N, s, pg, ws));
         for (int l = 0; l + 1 < p.ft.nlev; ++l) {
             const double u = B * (p.ft.cnt[l] / 2);
-            LCHK(launch(F_BUP, u * w.vec_f(), u * w.vec_b(), k_bvec_up<S, E>, Bi * p.ft.cnt[l + 1], s, pg, ws, l));
+            LCHK(launch_nt(NT, F_BUP, u * w.vec_f(), u * w.vec_b(), k_bvec_up<S, E>, Bi * p.ft.cnt[l + 1], s, pg, ws, l));
         }
-        LCHK(launch(F_BROOT, 0, 4 * B * w.es * p.n, k_broot<S>, Bi, s, pg, ws));
+        LCHK(launch_nt(WG, F_BROOT, 0, 4 * B * w.es * p.n, k_broot<S>, Bi, s, pg, ws));
         for (int l = p.ft.nlev - 2; l >= 0; --l) {
             const double u = B * (p.ft.cnt[l] / 2);
-            LCHK(launch(F_BDOWN, u * w.vec_f(), u * w.vec_b(), k_bvec_down<S, E>, Bi * p.ft.cnt[l], s, pg, ws, l));
+            LCHK(launch_nt(NT, F_BDOWN, u * w.vec_f(), u * w.vec_b(), k_bvec_down<S, E>, Bi * p.ft.cnt[l], s, pg, ws, l));
         }
-        LCHK(launch(F_REF_KFF, B * N * 4 * w.vec_f(), B * N * 4 * w.vec_b(), k_ref_kff<S, E>, Bi * N, s, pg, in, ws));
+        LCHK(launch_nt(NT, F_REF_KFF, B * N * 4 * w.vec_f(), B * N * 4 * w.vec_b(), k_ref_kff<S, E>, Bi * N, s, pg, in, ws));
         for (int l = 0; l + 1 < p.ft.nlev; ++l) {
             const double u = B * (p.ft.cnt[l] / 2);
-            LCHK(launch(F_FUPV, u * w.vec_f(), u * w.vec_b(), k_fup<S, E, true>, Bi * p.ft.cnt[l + 1], s, pg, ws, l));
+            LCHK(launch_nt(NT, F_FUPV, u * w.vec_f(), u * w.vec_b(), k_fup<S, E, true>, Bi * p.ft.cnt[l + 1], s, pg, ws, l));
         }
-        LCHK(launch(F_FROOT, 0, 2 * B * w.es * p.n, k_froot<S>, Bi, s, pg, ws, (const S*)(ws + p.o_x0p), p.stride));
+        LCHK(launch_nt(WG, F_FROOT, 0, 2 * B * w.es * p.n, k_froot<S>, Bi, s, pg, ws, (const S*)(ws + p.o_x0p), p.stride));
         for (int l = p.ft.nlev - 2; l >= 0; --l) {
             const double u = B * (p.ft.cnt[l] / 2);
-            LCHK(launch(F_FDOWN, u * w.vec_f(), u * w.vec_b(), k_fdown<S, E>, Bi * p.ft.cnt[l], s, pg, ws, l));
+            LCHK(launch_nt(NT, F_FDOWN, u * w.vec_f(), u * w.vec_b(), k_fdown<S, E>, Bi * p.ft.cnt[l], s, pg, ws, l));
         }
-        LCHK(launch(F_RECOVER_ADD, B * (N + 1) * w.rec_f(), B * (N + 1) * w.rec_b(), k_recover<S, E, true>,
+        LCHK(launch_nt(NT, F_RECOVER_ADD, B * (N + 1) * w.rec_f(), B * (N + 1) * w.rec_b(), k_recover<S, E, true>,
                     Bi * (N + 1), s, pg, ws, out));
     }
     if (resid_out) {
         // after an adaptive sweep only the instances it touched changed
         if (p.fused) {
-            LCHK(launch(F_RESID, B * (N + 1) * w.resid_f(), B * (N + 1) * w.resid_b(), k_resid_inst<S, E64, false>,
+            LCHK(launch_nt(NT, F_RESID, B * (N + 1) * w.resid_f(), B * (N + 1) * w.resid_b(), k_resid_inst<S, E64, false>,
                         Bi, s, pg, in, (const S*)out.x, (const S*)out.u, (const S*)out.lam, ws, dws, resid_out,
                         (int32_t*)nullptr, p.refine_tol));
         } else {
-            LCHK(launch(F_RESID, B * (N + 1) * w.resid_f(), B * (N + 1) * w.resid_b(), k_resid<S, E64, false>,
+            LCHK(launch_nt(NT, F_RESID, B * (N + 1) * w.resid_f(), B * (N + 1) * w.resid_b(), k_resid<S, E64, false>,
                         Bi * (N + 1), s, pg, in, (const S*)out.x, (const S*)out.u, (const S*)out.lam, ws, dws));
-            LCHK(launch(F_REDUCE, 0, B * 16.0 * (N + 1), k_resid_reduce<double>, (Bi + 63) / 64, s, pg,
+            LCHK(launch_nt(WG, F_REDUCE, 0, B * 16.0 * (N + 1), k_resid_reduce<double>, (Bi + 63) / 64, s, pg,
                         (const double*)dws, resid_out, (int32_t*)nullptr, p.refine_tol));
         }
     }
@@ -242,18 +263,23 @@ int run_scan(const Plan& p, hipStream_t s, const In<S>& in, const Out<S>& out, S
 template <typename S, int TS>
 int run_plain(const Plan& p, hipStream_t s, const In<S>& in, const Out<S>& out, S* ws, int32_t* iws,
               double* dws, double* resid_out) {
-    using E = Eng<S, 8, TS>;
-    using E64 = Eng<double, 8, TS>;
+    using E = EngOf<S, TS>;
+    using E64 = EngOf<double, TS>;
+    constexpr int NT = E64::NT;
     const Work w(p, sizeof(S));
     const double B = (double)p.batch;
     const int64_t Bi = p.batch;
-    LCHK(launch(F_CLEAR, 0, 4.0 * B, k_clear<int32_t>, (Bi + 255) / 256 * 4, s, out.status, Bi, iws,
+    LCHK(launch_nt(WG, F_CLEAR, 0, 4.0 * B, k_clear<int32_t>, (Bi + 255) / 256 * 4, s, out.status, Bi, iws,
                 (int64_t)kQCount));
-    LCHK(launch(F_PLAIN, B * w.plain_f(p.N), B * w.plain_b(p.N), k_plain<S, E>, Bi, s, p, in, out, ws));
+    if constexpr (E::BIG)
+        LCHK(launch_nt(NT, F_PLAIN, B * w.plain_f(p.N), B * w.plain_b(p.N), k_plain_big<S, E>, task_grid<E>(p, Bi), s,
+                       p, in, out, ws));
+    else
+        LCHK(launch_nt(NT, F_PLAIN, B * w.plain_f(p.N), B * w.plain_b(p.N), k_plain<S, E>, Bi, s, p, in, out, ws));
     if (resid_out) {
-        LCHK(launch(F_RESID, B * (p.N + 1) * w.resid_f(), B * (p.N + 1) * w.resid_b(), k_resid<S, E64, false>,
+        LCHK(launch_nt(NT, F_RESID, B * (p.N + 1) * w.resid_f(), B * (p.N + 1) * w.resid_b(), k_resid<S, E64, false>,
                     Bi * (p.N + 1), s, p, in, (const S*)out.x, (const S*)out.u, (const S*)out.lam, ws, dws));
-        LCHK(launch(F_REDUCE, 0, B * 16.0 * (p.N + 1), k_resid_reduce<double>, (Bi + 63) / 64, s, p,
+        LCHK(launch_nt(WG, F_REDUCE, 0, B * 16.0 * (p.N + 1), k_resid_reduce<double>, (Bi + 63) / 64, s, p,
                     (const double*)dws, resid_out, (int32_t*)nullptr, p.refine_tol));
     }
     return LQR_OK;
@@ -262,12 +288,13 @@ int run_plain(const Plan& p, hipStream_t s, const In<S>& in, const Out<S>& out, 
 template <typename S, int TS>
 int run_resid(const Plan& p, hipStream_t s, const In<S>& in, const S* x, const S* u, const S* lam, S* ws,
               double* dws, double* rel) {
-    using E64 = Eng<double, 8, TS>;
+    using E64 = EngOf<double, TS>;
+    constexpr int NT = E64::NT;
     const Work w(p, sizeof(S));
     const double B = (double)p.batch;
-    LCHK(launch(F_RESID, B * (p.N + 1) * w.resid_f(), B * (p.N + 1) * w.resid_b(), k_resid<S, E64, false>,
+    LCHK(launch_nt(NT, F_RESID, B * (p.N + 1) * w.resid_f(), B * (p.N + 1) * w.resid_b(), k_resid<S, E64, false>,
                 p.batch * (p.N + 1), s, p, in, x, u, lam, ws, dws));
-    LCHK(launch(F_REDUCE, 0, B * 16.0 * (p.N + 1), k_resid_reduce<double>, (p.batch + 63) / 64, s, p,
+    LCHK(launch_nt(WG, F_REDUCE, 0, B * 16.0 * (p.N + 1), k_resid_reduce<double>, (p.batch + 63) / 64, s, p,
                 (const double*)dws, rel, (int32_t*)nullptr, p.refine_tol));
     return LQR_OK;
 }
