@@ -2,7 +2,12 @@
 
 Workload: whole-body-shaped LQR QPs, n = 36, m = 12, N = 100, a batch of
 4096 independent seeded synthetic instances (inputs resident in HBM before
-the timed region).  One step = one full hot-path pass over the batch: scan
+the timed region).  A second object ("multi_robot") measures the
+centralized multi-robot shape, n = m = 192, N = 50, batch 64, on the
+large-block (matrix-core) engine the same way, and "serving" runs a Poisson
+stream of mixed requests (60 % SRBD-shaped, 30 % whole-body-shaped, 10 %
+multi-robot) through the continuous-batching loop at 70 % of its measured
+capacity (p50/p99 latency from arrival, host-to-device copies included).  One step = one full hot-path pass over the batch: scan
 elements, reverse associative scan (up-sweep + down-sweep), policy, forward
 scan of the closed-loop maps, controls/costates, FP64 KKT residual, one
 refinement sweep, and the FP64 residual of the returned solution (checked
@@ -33,6 +38,9 @@ N_STAGES, NX, NU, BATCH = 100, 36, 12, 4096
 PEAK_FP32_VECTOR_PACKED = 157.3e12
 PEAK_FP32_VECTOR = 256 * 4 * 16 * 2 * 2.4e9
 PEAK_HBM = 8.0e12
+# dense FP32 matrix-core peak (MFMA), the bound of the large-block engine
+PEAK_FP32_MFMA = 157.3e12
+MR_BATCH = 64
 
 
 def log(*a):
@@ -84,20 +92,132 @@ def timed_steps(L, dev, method, steps, warmup, want_timing, graph=False, refine=
     return wall, lat, fams, resid, status
 
 
-def cpu_baseline(sample: int):
+def cpu_baseline(gen, sample: int, batch: int, what: str):
     import oracle
     import synth
     threads = min(os.cpu_count() or 1, 16)
-    probs = synth.gen_batch(synth.gen_c3, sample, np.float32)
+    probs = synth.gen_batch(gen, sample, np.float32)
     probs = {k: v.astype(np.float64) for k, v in probs.items()}
-    oracle.riccati_batch({k: v[:threads] for k, v in probs.items()}, nthreads=threads)  # warm
+    oracle.riccati_batch({k: v[:1] for k, v in probs.items()}, nthreads=1)  # warm
     t0 = time.perf_counter()
     _, _, _, st = oracle.riccati_batch(probs, nthreads=threads)
     dt = time.perf_counter() - t0
     return {"value": sample / dt, "unit": "solves/s", "cores": threads, "kind": "oracle",
-            "sample": f"{sample} of the {BATCH} whole-body instances (FP32-rounded inputs in FP64), "
+            "sample": f"{sample} of the {batch} {what} instances (FP32-rounded inputs in FP64), "
                       f"sequential Riccati in C on {threads} host threads, {dt:.2f} s wall",
             "failed": int((st != 0).sum())}
+
+
+def roofline_of(fams, bound, peak, unit):
+    """Dominant kernel family of a timing pass: algorithmic work / measured time."""
+    dom = max(fams, key=lambda f: fams[f]["ms"])
+    d = fams[dom]
+    achieved = d["flops"] / (d["ms"] * 1e-3)
+    return {"kernel": dom, "bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": unit,
+            "frac": achieved / peak, "traffic": None, "avg_launch_ms": d["ms"] / d["launches"],
+            "launches": d["launches"], "algorithmic_GBps": d["bytes"] / (d["ms"] * 1e-3) / 1e9}
+
+
+def measure(L, gen, batch, steps, warmup, eager, refine, plain, label):
+    """Timed FP32 scan (graph replays) + kernel-timing pass + optional FP64
+    plain comparison on one workload; returns the numbers and the timing
+    families of the scan."""
+    import torch
+    import synth
+    log(f"[bench] {label}: generating inputs")
+    host = synth.gen_batch(gen, batch, np.float32)
+    dev = {k: torch.from_numpy(v).to("cuda:0") for k, v in host.items()}
+    del host
+    torch.cuda.synchronize()
+    log(f"[bench] {label}: FP32 scan, timed {'eager launches' if eager else 'graph replays'}")
+    wall, lat, _, resid, bad = timed_steps(L, dev, "scan", steps, warmup, False, graph=not eager, refine=refine)
+    log(f"[bench] {label}: FP32 scan, kernel timing pass (eager, HIP events around every launch)")
+    _, _, fams, _, _ = timed_steps(L, dev, "scan", max(3, steps // 5), 1, True, refine=refine)
+    r = {"value": batch * steps / wall, "unit": "solves/s", "steps": steps, "ms_per_step": 1e3 * wall / steps,
+         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+         "max_rel_kkt_residual": resid, "instances_with_status": bad}
+    steps_t = fams["clear"]["launches"] if "clear" in fams else 1
+    r["kernel_ms_per_step"] = {f: v["ms"] / steps_t for f, v in fams.items()}
+    if plain:
+        log(f"[bench] {label}: FP64 plain Riccati, timed steps")
+        dev64 = {k: v.double() for k, v in dev.items()}
+        del dev
+        torch.cuda.empty_cache()
+        pk = max(3, steps // 3)
+        pwall, plat, _, presid, pbad = timed_steps(L, dev64, "plain", pk, 1, False, graph=not eager)
+        r["plain"] = {"value": batch * pk / pwall, "unit": "solves/s", "dtype": "f64", "steps": pk,
+                      "ms_per_step": 1e3 * pwall / pk, "p50_ms": float(np.percentile(plat, 50)),
+                      "p99_ms": float(np.percentile(plat, 99)), "max_rel_kkt_residual": presid,
+                      "instances_with_status": pbad}
+        r["scan_over_plain"] = r["value"] / r["plain"]["value"]
+        del dev64
+    else:
+        del dev
+    torch.cuda.empty_cache()
+    return r, fams
+
+
+def serving_leg(L, n_clients: int, warm_requests: int, sat_requests: int, requests: int, load: float):
+    """Serving mix through the continuous-batching loop: a saturated run
+    (every request present at t = 0) gives the capacity; then Poisson
+    arrivals at `load` x capacity give the latency distribution."""
+    import torch
+    import synth
+    from paper_2506_07823_amd.serve import GpuBackend, Request, Server, latency_report
+    log(f"[bench] serving: generating {n_clients} clients")
+    clients = synth.gen_c5_clients(n_clients)
+    # each client writes its QP matrices into pinned host memory once; every
+    # request ships them (and its own x0) to the device
+    pinned = [{k: torch.from_numpy(np.ascontiguousarray(v, np.float32)).pin_memory()
+               for k, v in model.items() if k != "x0"} for model, _ in clients]
+    walks = [synth.x0_walk(model, seed, warm_requests + sat_requests + requests + 1)
+             for model, seed in clients]
+    used = [0] * len(clients)
+    rng = np.random.default_rng([5, 4])
+
+    def make(count, rate, rid0):
+        reqs, t = [], 0.0
+        for j in range(count):
+            c = int(rng.integers(0, len(clients)))
+            if rate:
+                t += rng.exponential(1.0 / rate)
+            data = dict(pinned[c])
+            data["x0"] = torch.from_numpy(walks[c][used[c]].astype(np.float32)).pin_memory()
+            used[c] += 1
+            reqs.append(Request(rid=rid0 + j, client=c, data=data, arrival=t))
+        return reqs
+
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(0.5 * free)
+
+    def phase(count, rate, rid0):
+        be = GpuBackend(nstreams=4, refine=2)
+        srv = Server(be, budget, max_batch=64, warm=True)
+        done = srv.run(make(count, rate, rid0))
+        torch.cuda.synchronize()
+        return done, srv
+
+    log("[bench] serving: warmup")
+    phase(warm_requests, None, 0)
+    log("[bench] serving: saturated run")
+    done, _ = phase(sat_requests, None, warm_requests)
+    cap = latency_report(done)["solves_per_s"]
+    rate = load * cap
+    log(f"[bench] serving: capacity {cap:.0f} solves/s; Poisson arrivals at {rate:.0f}/s")
+    done, srv = phase(requests, rate, warm_requests + sat_requests)
+    rep = latency_report(done)
+    resid = max(float(r.result["resid"]) for r in done)
+    bad = sum(int(r.result["status"] != 0) for r in done)
+    shapes = {}
+    for r in done:
+        key = "N%d_n%d_m%d" % r.shape
+        shapes[key] = shapes.get(key, 0) + 1
+    return {"offered_per_s": rate, "capacity_solves_per_s": cap, "load": load, **rep,
+            "max_rel_kkt_residual": resid, "instances_with_status": bad,
+            "warm_started": sum(r.warm for r in done), "batches": len(srv.launch_log),
+            "mean_batch": float(np.mean([k for _, k in srv.launch_log])), "budget_bytes": budget,
+            "peak_admitted_bytes": srv.peak_used, "clients": n_clients, "mix": shapes,
+            "latency": "arrival to device completion, host->device copies included"}
 
 
 def main():
@@ -108,6 +228,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1024)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-multi-robot", action="store_true", help="skip the n=m=192 multi-robot workload")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-mix workload")
+    ap.add_argument("--serving-requests", type=int, default=1600)
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of graph replays")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (calibrates the HBM byte "
@@ -131,57 +254,37 @@ def main():
     import paper_2506_07823_amd as L
     import synth
 
-    log("[bench] generating inputs")
-    host = synth.gen_batch(synth.gen_c3, BATCH, np.float32)
-    dev = {k: torch.from_numpy(v).to("cuda:0") for k, v in host.items()}
-    torch.cuda.synchronize()
-
-    log("[bench] FP32 scan: timed graph replays")
-    wall, lat, _, resid, bad = timed_steps(L, dev, "scan", a.steps, a.warmup, False, graph=not a.eager,
-                                           refine=2)
-    log("[bench] FP32 scan: kernel timing pass (eager, HIP events around every launch)")
-    _, _, fams, _, _ = timed_steps(L, dev, "scan", max(3, a.steps // 5), 1, True, refine=2)
-    value = BATCH * a.steps / wall
+    wb, fams = measure(L, synth.gen_c3, BATCH, a.steps, a.warmup, a.eager, 2, not a.no_plain, "whole-body")
     result = {
-        "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": a.steps,
-        "warmup": a.warmup, "ms_per_step": 1e3 * wall / a.steps, "higher_is_better": True,
+        "metric": METRIC, "value": wb.pop("value"), "unit": "solves/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": wb.pop("ms_per_step"), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "whole-body-shaped LQR-KKT, n=36 m=12 N=100, batch 4096, FP32 scan + "
                                "FP64-residual refinement (second sweep only above 1e-5)",
                    "batch": BATCH, "N": N_STAGES, "n": NX, "m": NU, "method": "scan",
                    "launch": "eager" if a.eager else "hipGraph replay"},
-        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-        "max_rel_kkt_residual": resid, "instances_with_status": bad,
     }
-    if fams:
-        dom = max(fams, key=lambda f: fams[f]["ms"])
-        d = fams[dom]
-        avg_ms = d["ms"] / d["launches"]
-        achieved = d["flops"] / (d["ms"] * 1e-3)
-        result["roofline"] = {
-            "kernel": dom, "bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
-            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": None,
-            "avg_launch_ms": avg_ms, "launches": d["launches"],
-            "algorithmic_GBps": d["bytes"] / (d["ms"] * 1e-3) / 1e9,
-            "peak_packed_fp32": PEAK_FP32_VECTOR_PACKED / 1e12,
-        }
-        steps_t = fams["clear"]["launches"] if "clear" in fams else 1
-        result["kernel_ms_per_step"] = {f: v["ms"] / steps_t for f, v in fams.items()}
-    if not a.no_plain:
-        log("[bench] FP64 plain Riccati: timed steps")
-        dev64 = {k: v.double() for k, v in dev.items()}
-        del dev
-        torch.cuda.empty_cache()
-        pk = max(3, a.steps // 3)
-        pwall, plat, _, presid, pbad = timed_steps(L, dev64, "plain", pk, 1, False, graph=not a.eager)
-        result["plain"] = {"value": BATCH * pk / pwall, "unit": "solves/s", "dtype": "f64", "steps": pk,
-                           "ms_per_step": 1e3 * pwall / pk, "p50_ms": float(np.percentile(plat, 50)),
-                           "p99_ms": float(np.percentile(plat, 99)), "max_rel_kkt_residual": presid,
-                           "instances_with_status": pbad}
-        result["scan_over_plain"] = value / result["plain"]["value"]
+    wb.pop("steps")
+    result.update(wb)
+    rf = roofline_of(fams, "alu", PEAK_FP32_VECTOR, "TFLOP/s")
+    rf["peak_packed_fp32"] = PEAK_FP32_VECTOR_PACKED / 1e12
+    result["roofline"] = rf
+    if not a.no_multi_robot:
+        mr, mfams = measure(L, synth.gen_c4, MR_BATCH, max(5, a.steps // 3), 1, a.eager, 2, not a.no_plain,
+                            "multi-robot")
+        mr["config"] = {"workload": "centralized multi-robot LQR-KKT, n=m=192 N=50, batch 64, FP32 scan on "
+                                    "matrix cores + FP64-residual refinement", "batch": MR_BATCH, "N": 50,
+                        "n": 192, "m": 192}
+        mr["roofline"] = roofline_of(mfams, "mfma", PEAK_FP32_MFMA, "TFLOP/s")
+        if not a.no_cpu:
+            log("[bench] multi-robot: CPU oracle baseline")
+            mr["cpu_baseline"] = cpu_baseline(synth.gen_c4, 16, MR_BATCH, "multi-robot")
+        result["multi_robot"] = mr
+    if not a.no_serving:
+        result["serving"] = serving_leg(L, 40, 100, max(200, a.serving_requests // 2), a.serving_requests, 0.7)
     if not a.no_cpu:
-        log("[bench] CPU oracle baseline")
-        result["cpu_baseline"] = cpu_baseline(a.cpu_sample)
+        log("[bench] whole-body: CPU oracle baseline")
+        result["cpu_baseline"] = cpu_baseline(synth.gen_c3, a.cpu_sample, BATCH, "whole-body")
     print(json.dumps(result), flush=True)
 
 

@@ -99,6 +99,15 @@ typedef struct {
     double refine_tol;      /* relative KKT residual below which further sweeps are skipped (1e-5) */
     double* resid_out;      /* optional device [batch] FP64: relative KKT residual of the returned
                                solution, ||r(x,u,lam)||_2 / ||(x0, c, q, r)||_2; NULL to skip */
+    /* optional warm start (scan method; all three or none): device arrays in the layout and dtype
+       of x, u, lam holding an initial solution, e.g. a stream's previous solve.  The factors are
+       computed as usual; the returned solution is the warm one plus refinement corrections (at
+       least one sweep), so the FP32 error scales with the distance from the warm start instead of
+       with the solution.  They may be the output arrays themselves (updated in place); otherwise
+       they must not overlap them.  NULL: cold start. */
+    const void* warm_x;
+    const void* warm_u;
+    const void* warm_lam;
 } lqr_opts;
 
 /* Fill *o with the defaults for `dtype` (scan method, refinement as above). */

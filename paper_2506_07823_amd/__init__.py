@@ -40,6 +40,9 @@ class lqr_opts(ctypes.Structure):
         ("cond_threshold", ctypes.c_double),
         ("refine_tol", ctypes.c_double),
         ("resid_out", ctypes.c_void_p),
+        ("warm_x", ctypes.c_void_p),
+        ("warm_u", ctypes.c_void_p),
+        ("warm_lam", ctypes.c_void_p),
     ]
 
 
@@ -170,13 +173,14 @@ _default_ws = {}
 
 def solve(A, B, c, Q, R, M, q, r, x0, *, method: str = "scan", refine: int | None = None,
           fallback: bool = True, cond_threshold: float = 1e6, refine_tol: float = 1e-5,
-          want_resid: bool = False,
+          want_resid: bool = False, warm=None,
           workspace: Workspace | None = None, out=None, stream=None):
     """Batched LQR-KKT solve; returns dict x, u, lam, status (+ resid).
 
     All tensors are device tensors of one dtype (float32 or float64) with a
     leading batch axis; the call is asynchronous on ``stream`` (default: the
-    current torch stream)."""
+    current torch stream).  ``warm`` = (x, u, lam) starts the scan's
+    refinement from that solution (it may be ``out``'s own arrays)."""
     d = dict(A=A, B=B, c=c, Q=Q, R=R, M=M, q=q, r=r, x0=x0)
     dtype = A.dtype
     device = A.device.index
@@ -197,6 +201,13 @@ def solve(A, B, c, Q, R, M, q, r, x0, *, method: str = "scan", refine: int | Non
             "lam": torch.empty((batch, N + 1, n), dtype=dtype, device=A.device),
             "status": torch.empty((batch,), dtype=torch.int32, device=A.device),
         }
+    if warm is not None:
+        wx, wu, wl = warm
+        _validate(dict(warm_x=wx, warm_u=wu, warm_lam=wl), dtype, device)
+        for t, s in ((wx, (batch, N + 1, n)), (wu, (batch, N, m)), (wl, (batch, N + 1, n))):
+            if tuple(t.shape) != s:
+                raise ValueError(f"warm start has shape {tuple(t.shape)}, expected {s}")
+        o.warm_x, o.warm_u, o.warm_lam = wx.data_ptr(), wu.data_ptr(), wl.data_ptr()
     if want_resid:
         if "resid" not in out:
             out["resid"] = torch.empty((batch,), dtype=torch.float64, device=A.device)

@@ -72,6 +72,12 @@ struct Out {
     int32_t* status;
 };
 
+// optional warm start of the scan (null x: cold start)
+template <typename S>
+struct Warm {
+    const S *x, *u, *lam;
+};
+
 // pointer helpers (instance b, stage k)
 template <typename S> struct Ptr {
     const Plan& p;
@@ -213,6 +219,13 @@ __global__ void k_clear(I* status, int64_t batch, I* counters, int64_t ncount) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < batch) status[i] = 0;
     if (i < ncount) counters[i] = 0;
+}
+
+// dst = src, count elements (grid-stride)
+template <typename S>
+__global__ void k_copy(const S* src, S* dst, int64_t count) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
 }
 
 // Run `body(task)` for every task of the launch (FP32 pass: one task per

@@ -151,11 +151,11 @@ int check_dims(int64_t batch, int N, int n, int m) {
 
 template <typename S>
 int dispatch(int ts, int method, const Plan& p, hipStream_t s, const In<S>& in, const Out<S>& out, S* ws,
-             int32_t* iws, double* dws, int refine, double* resid_out) {
-#define LQR_CASE(TSV)                                                                    \
-    case TSV:                                                                            \
-        return method == LQR_METHOD_SCAN                                                 \
-                   ? run_scan<S, TSV>(p, s, in, out, ws, iws, dws, refine, resid_out)    \
+             int32_t* iws, double* dws, int refine, double* resid_out, const Warm<S>& warm) {
+#define LQR_CASE(TSV)                                                                       \
+    case TSV:                                                                               \
+        return method == LQR_METHOD_SCAN                                                    \
+                   ? run_scan<S, TSV>(p, s, in, out, ws, iws, dws, refine, resid_out, warm) \
                    : run_plain<S, TSV>(p, s, in, out, ws, iws, dws, resid_out);
     switch (ts) {
         LQR_CASE(1) LQR_CASE(2) LQR_CASE(3) LQR_CASE(4) LQR_CASE(5) LQR_CASE(6) LQR_CASE(8) LQR_CASE(32)
@@ -182,7 +182,7 @@ namespace {
 const char* const kFamNames[F_COUNT] = {
     "clear", "element", "element_fp64", "up", "root", "down", "policy", "policy_fp64", "fwd_up", "fwd_root",
     "fwd_down", "recover", "residual", "ref_d", "bwd_up", "bwd_root", "bwd_down", "ref_kff", "fwd_up_vec",
-    "recover_add", "reduce", "plain_riccati", "up_fp64", "down_fp64", "fwd_inst", "refine_inst"};
+    "recover_add", "reduce", "plain_riccati", "up_fp64", "down_fp64", "fwd_inst", "refine_inst", "warm_copy"};
 
 // Per-handle launch timer: two HIP events around every launch, read back by
 // lqr_timing_report.
@@ -296,6 +296,12 @@ int lqr_kkt_solve(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int
         return fail(LQR_EINVAL, "misaligned output");
     if (!aligned(workspace, 256)) return fail(LQR_EINVAL, "workspace must be 256-byte aligned");
     if (o.resid_out && !aligned(o.resid_out, 8)) return fail(LQR_EINVAL, "misaligned resid_out");
+    const bool has_warm = o.warm_x || o.warm_u || o.warm_lam;
+    if (has_warm) {
+        if (!o.warm_x || !o.warm_u || !o.warm_lam) return fail(LQR_EINVAL, "warm start needs x, u and lam");
+        if (!aligned(o.warm_x, es) || !aligned(o.warm_u, es) || !aligned(o.warm_lam, es))
+            return fail(LQR_EINVAL, "misaligned warm start");
+    }
     Plan p = make_plan(batch, N, n, m, es, o);
     const Layout lay = layout(p, es);
     if (workspace_bytes < lay.total)
@@ -313,12 +319,14 @@ int lqr_kkt_solve(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int
         In<float> in{(const float*)A, (const float*)B, (const float*)c, (const float*)Q, (const float*)R,
                      (const float*)M, (const float*)q, (const float*)r, (const float*)x0};
         Out<float> out{(float*)x, (float*)u, (float*)lam, status};
-        return dispatch<float>(ts, o.method, p, s, in, out, (float*)wsb, iws, dws, refine, o.resid_out);
+        const Warm<float> warm{(const float*)o.warm_x, (const float*)o.warm_u, (const float*)o.warm_lam};
+        return dispatch<float>(ts, o.method, p, s, in, out, (float*)wsb, iws, dws, refine, o.resid_out, warm);
     }
     In<double> in{(const double*)A, (const double*)B, (const double*)c, (const double*)Q, (const double*)R,
                   (const double*)M, (const double*)q, (const double*)r, (const double*)x0};
     Out<double> out{(double*)x, (double*)u, (double*)lam, status};
-    return dispatch<double>(ts, o.method, p, s, in, out, (double*)wsb, iws, dws, refine, o.resid_out);
+    const Warm<double> warm{(const double*)o.warm_x, (const double*)o.warm_u, (const double*)o.warm_lam};
+    return dispatch<double>(ts, o.method, p, s, in, out, (double*)wsb, iws, dws, refine, o.resid_out, warm);
 }
 
 int lqr_kkt_residual(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int m, int32_t dtype,

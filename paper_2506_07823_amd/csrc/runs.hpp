@@ -31,7 +31,7 @@ using EngOf = typename std::conditional<TS == kBigTS, BigEng<S>, Eng<S, 8, TS>>:
 enum Fam {
     F_CLEAR, F_ELEM, F_ELEM_FB, F_UP, F_ROOT, F_DOWN, F_POLICY, F_POLICY_FB, F_FUP, F_FROOT, F_FDOWN,
     F_RECOVER, F_RESID, F_REF_D, F_BUP, F_BROOT, F_BDOWN, F_REF_KFF, F_FUPV, F_RECOVER_ADD, F_REDUCE,
-    F_PLAIN, F_UP_FB, F_DOWN_FB, F_FWD_INST, F_REFINE_INST, F_COUNT
+    F_PLAIN, F_UP_FB, F_DOWN_FB, F_FWD_INST, F_REFINE_INST, F_WARM, F_COUNT
 };
 
 // Optional per-launch timer (HIP events around each launch on its stream),
@@ -125,7 +125,7 @@ struct Work {
 // ----------------------------------------------------------------- solve
 template <typename S, int TS>
 int run_scan(const Plan& p, hipStream_t s, const In<S>& in, const Out<S>& out, S* ws, int32_t* iws,
-             double* dws, int refine, double* resid_out) {
+             double* dws, int refine, double* resid_out, const Warm<S>& warm) {
     using E = EngOf<S, TS>;
     using E64 = EngOf<double, TS>;
     constexpr int NT = E::NT;
@@ -180,7 +180,21 @@ int run_scan(const Plan& p, hipStream_t s, const In<S>& in, const Out<S>& out, S
         LCHK(launch_nt(NT, F_FUP, u * w.fup_f(), u * w.fup_b(), k_fup<S, E, false>, Bi * p.ft.cnt[l + 1], s, p, ws, l));
     }
     const double fwd_nodes = B * (double)(p.ft.total - p.ft.cnt[p.ft.nlev - 1]);
-    if (p.fused) {
+    if (warm.x) {
+        // warm start: the outputs start at the given solution and the
+        // refinement sweeps below correct it with the factors just computed
+        const int64_t cx = Bi * (N + 1) * p.n, cu = Bi * N * p.m;
+        auto cp = [&](const S* src, S* dst, int64_t count) -> int {
+            if (src == dst) return LQR_OK;
+            const int64_t g = (count + 255) / 256;
+            return launch_nt(256, F_WARM, 0, 2.0 * w.es * count, k_copy<S>, g < 4096 ? g : 4096, s, src, dst,
+                             count);
+        };
+        LCHK(cp(warm.x, out.x, cx));
+        LCHK(cp(warm.u, out.u, cu));
+        LCHK(cp(warm.lam, out.lam, cx));
+        if (refine < 1) refine = 1;
+    } else if (p.fused) {
         // a5 down-sweep + a6 per instance
         LCHK(launch_nt(NT, F_FWD_INST, fwd_nodes * w.vec_f() + B * (N + 1) * w.rec_f(),
                     fwd_nodes * w.vec_b() + B * (N + 1) * w.rec_b(), k_fwd_inst<S, E>, Bi, s, p, ws, in.x0,
@@ -301,9 +315,9 @@ int run_resid(const Plan& p, hipStream_t s, const In<S>& in, const S* x, const S
 
 #define LQR_RUNS(PREFIX, TSV)                                                                               \
     PREFIX template int run_scan<float, TSV>(const Plan&, hipStream_t, const In<float>&, const Out<float>&,  \
-                                             float*, int32_t*, double*, int, double*);                      \
+                                             float*, int32_t*, double*, int, double*, const Warm<float>&);  \
     PREFIX template int run_scan<double, TSV>(const Plan&, hipStream_t, const In<double>&, const Out<double>&,\
-                                              double*, int32_t*, double*, int, double*);                    \
+                                              double*, int32_t*, double*, int, double*, const Warm<double>&);\
     PREFIX template int run_plain<float, TSV>(const Plan&, hipStream_t, const In<float>&, const Out<float>&, \
                                               float*, int32_t*, double*, double*);                          \
     PREFIX template int run_plain<double, TSV>(const Plan&, hipStream_t, const In<double>&,                  \

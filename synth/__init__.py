@@ -12,6 +12,8 @@ distributions of Sec. III / IV stand in for them:
   c3   n=36, m=12, N=100 (whole-body-like), batch of independent instances
   c4   n=m=192 (16 SRBD robots in one centralized problem), N=50
   rand generic well-conditioned problems of any size for tests
+  c5   serving mix: clients (robots) whose requests share the client's
+       matrices while x0 takes a random walk, N(0, 1e-2) per request
 
 Every instance is drawn from ``numpy.random.default_rng([cfg_id, size_idx,
 instance])`` (PCG64) in the fixed order A, B, c, Q, R, M, q, r, x0, each over
@@ -165,6 +167,43 @@ def gen_rand(N: int, n: int, m: int, seed, cross: float = 0.1, dense_q: bool = T
     r = rng.normal(0.0, 1.0, (N, m))
     x0 = rng.normal(0.0, 1.0, n)
     return dict(A=A, B=B, c=c, Q=Q, R=R, M=M, q=q, r=r, x0=x0)
+
+
+def gen_c5_clients(n_clients: int = 40) -> list:
+    """Client population of the serving mix, in the request proportions
+    60 % SRBD-shaped (n = m = 12, N in {25, 50, 100} equally), 30 %
+    whole-body-shaped (n = 36, m = 12, N in {50, 100}) and 10 % multi-robot
+    (n = m = 192, N = 50); every client issues requests at the same rate.
+    Returns a list of (model dict, x0 walk seed)."""
+    kinds = []
+    n_mr = max(1, round(0.1 * n_clients))
+    n_wb = max(1, round(0.3 * n_clients))
+    n_sr = n_clients - n_mr - n_wb
+    for c in range(n_sr):
+        kinds.append(("srbd", (25, 50, 100)[c % 3], c))
+    for c in range(n_wb):
+        kinds.append(("wb", (50, 100)[c % 2], c))
+    for c in range(n_mr):
+        kinds.append(("mr", 50, c))
+    out = []
+    for idx, (kind, N, c) in enumerate(kinds):
+        if kind == "srbd":
+            model = gen_c2(N, 1000 + c)
+        elif kind == "wb":
+            model = gen_c1_like(N, 36, 12, [5, 1, c], dt=0.01)
+        else:
+            model = gen_c4(1000 + c, N=N)
+        out.append((model, [5, 2, idx]))
+    return out
+
+
+def x0_walk(model: dict, seed, steps: int, std: float = 1e-2) -> np.ndarray:
+    """Initial states of a client's consecutive requests: x0 of the model,
+    then x0_{k+1} = x0_k + N(0, std)."""
+    rng = np.random.default_rng(seed)
+    steps_ = rng.normal(0.0, std, (steps, model["x0"].shape[0]))
+    steps_[0] = 0.0
+    return model["x0"][None, :] + np.cumsum(steps_, axis=0)
 
 
 def stack(probs: list) -> dict:
