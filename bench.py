@@ -42,6 +42,21 @@ PEAK_HBM = 8.0e12
 PEAK_FP32_MFMA = 157.3e12
 MR_BATCH = 64
 
+# HBM bytes per launch of the whole-body k_up from rocprofv3 FETCH_SIZE /
+# WRITE_SIZE runs, calibrated against a copy of known size; valid only for
+# the kernel sources they were taken on (hash of engine.hpp + kernels.hpp)
+KUP_TRAFFIC = {"src_hash": "1971c93e2830e294", "bytes_per_launch": 2.911e9,
+               "note": "FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (copy calibration), per launch"}
+
+
+def kernel_src_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("engine.hpp", "kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_2506_07823_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -268,6 +283,9 @@ def main():
     result.update(wb)
     rf = roofline_of(fams, "alu", PEAK_FP32_VECTOR, "TFLOP/s")
     rf["peak_packed_fp32"] = PEAK_FP32_VECTOR_PACKED / 1e12
+    if rf["kernel"] == "up" and kernel_src_hash() == KUP_TRAFFIC["src_hash"]:
+        rf["traffic"] = KUP_TRAFFIC["bytes_per_launch"]
+        rf["traffic_note"] = KUP_TRAFFIC["note"]
     result["roofline"] = rf
     if not a.no_multi_robot:
         mr, mfams = measure(L, synth.gen_c4, MR_BATCH, max(5, a.steps // 3), 1, a.eager, 2, not a.no_plain,
