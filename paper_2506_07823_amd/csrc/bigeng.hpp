@@ -77,7 +77,7 @@ enum : int {
     GM_IDENT = 128  // out += I
 };
 
-constexpr int BG_KC = 16;          // k-chunk staged in LDS
+constexpr int BG_KC = 32;          // k-chunk staged in LDS
 constexpr int BG_LDT = 64 + 16;    // LDS row stride of a staged chunk (bank spread of the 4 lane groups)
 
 template <typename T>
@@ -159,77 +159,137 @@ struct BigEng {
     // one thread after its tile's k-loop, so out may alias add, and may alias
     // A when every output tile reads only its own rows of A.  Ends with a
     // workgroup barrier (the result is visible to the whole workgroup).
+    //
+    // Software pipeline: while the matrix cores consume the k-chunk staged in
+    // LDS, the global loads of the next chunk (of this tile, or the first
+    // chunk of the next tile) are already in flight into registers.
+    template <int F>
+    __device__ __forceinline__ void tile_krange(int ti, int tj, int K, int& kb, int& ke) const {
+        kb = 0;
+        ke = K;
+        if (F & GM_A_LO) ke = min(ke, (ti + 1) * 64);
+        if (F & GM_A_UP) kb = max(kb, ti * 64);
+        if (F & GM_B_LO) kb = max(kb, tj * 64);
+        if (F & GM_B_UP) ke = min(ke, (tj + 1) * 64);
+    }
+
+    // next tile after (ti, tj) in row-major tile order (lower tiles only
+    // with GM_LOWER); false when there is none
+    template <int F>
+    __device__ __forceinline__ bool next_tile(int& ti, int& tj, int nti, int ntj) const {
+        ++tj;
+        if (tj >= ntj || ((F & GM_LOWER) && tj > ti)) {
+            tj = 0;
+            ++ti;
+        }
+        return ti < nti;
+    }
+
+    template <typename PA, typename PB>
+    __device__ __forceinline__ void load_chunk(T (&ra)[BG_KC / 4], T (&rb)[BG_KC / 4], const MV<PA>& A,
+                                               const MV<PB>& B, int M, int N, int i0, int j0, int k0, int ke,
+                                               bool a_kfast, bool b_jfast) const {
+        const int t = lg;
+#pragma unroll
+        for (int r = 0; r < BG_KC / 4; ++r) {
+            int i, kk;
+            if (a_kfast) { kk = t % BG_KC; i = t / BG_KC + (256 / BG_KC) * r; }
+            else { i = t & 63; kk = (t >> 6) + 4 * r; }
+            ra[r] = (i0 + i < M && k0 + kk < ke) ? T(A(i0 + i, k0 + kk)) : T(0);
+            int j, k2;
+            if (b_jfast) { j = t & 63; k2 = (t >> 6) + 4 * r; }
+            else { k2 = t % BG_KC; j = t / BG_KC + (256 / BG_KC) * r; }
+            rb[r] = (j0 + j < N && k0 + k2 < ke) ? T(B(k0 + k2, j0 + j)) : T(0);
+        }
+    }
+
+    __device__ __forceinline__ void store_chunk(BigLds<T>& L, const T (&ra)[BG_KC / 4], const T (&rb)[BG_KC / 4],
+                                                bool a_kfast, bool b_jfast) const {
+        const int t = lg;
+#pragma unroll
+        for (int r = 0; r < BG_KC / 4; ++r) {
+            int i, kk;
+            if (a_kfast) { kk = t % BG_KC; i = t / BG_KC + (256 / BG_KC) * r; }
+            else { i = t & 63; kk = (t >> 6) + 4 * r; }
+            L.As[kk][i] = ra[r];
+            int j, k2;
+            if (b_jfast) { j = t & 63; k2 = (t >> 6) + 4 * r; }
+            else { k2 = t % BG_KC; j = t / BG_KC + (256 / BG_KC) * r; }
+            L.Bs[k2][j] = rb[r];
+        }
+    }
+
     template <int F, typename PA, typename PB, typename PO, typename PC>
-    __device__ __forceinline__ void gemm(BigLds<T>& L, int M, int N, int K, MV<PA> A, MV<PB> B,
+    __device__ __attribute__((noinline)) void gemm(BigLds<T>& L, int M, int N, int K, MV<PA> A, MV<PB> B,
                                                    MV<PO> out, MV<PC> add, T alpha = T(1)) const {
         using Mf = Mfma<T>;
         using V = typename Mf::V;
-        const int t = lg, lane = t & 63, wv = t >> 6;
+        static_assert(BG_KC % 16 == 0 && 64 * BG_KC == 256 * (BG_KC / 4), "chunk mapping");
+        const int lane = lg & 63, wv = lg >> 6;
         const int wr = wv >> 1, wc = wv & 1;
         const int nti = (M + 63) >> 6, ntj = (N + 63) >> 6;
         const bool a_kfast = A.cs == 1, b_jfast = B.cs == 1;
-        for (int ti = 0; ti < nti; ++ti) {
-            for (int tj = 0; tj < ntj; ++tj) {
-                if ((F & GM_LOWER) && tj > ti) continue;
-                int kb = 0, ke = K;
-                if (F & GM_A_LO) ke = min(ke, (ti + 1) * 64);
-                if (F & GM_A_UP) kb = max(kb, ti * 64);
-                if (F & GM_B_LO) kb = max(kb, tj * 64);
-                if (F & GM_B_UP) ke = min(ke, (tj + 1) * 64);
-                V acc[2][2];
+        T ra[BG_KC / 4], rb[BG_KC / 4];
+        bool have = false;   // registers hold the first chunk of the current tile
+        int ti = 0, tj = 0;
+        while (ti < nti) {
+            int kb, ke;
+            tile_krange<F>(ti, tj, K, kb, ke);
+            const int i0 = ti * 64, j0 = tj * 64;
+            if (!have && kb < ke) load_chunk(ra, rb, A, B, M, N, i0, j0, kb, ke, a_kfast, b_jfast);
+            have = false;
+            // the tile after this one (for the prefetch across tiles)
+            int ni = ti, nj = tj;
+            const bool more = next_tile<F>(ni, nj, nti, ntj);
+            int nkb = 0, nke = 0;
+            if (more) tile_krange<F>(ni, nj, K, nkb, nke);
+            V acc[2][2];
 #pragma unroll
-                for (int a = 0; a < 2; ++a)
+            for (int a = 0; a < 2; ++a)
 #pragma unroll
-                    for (int b = 0; b < 2; ++b) acc[a][b] = V{0, 0, 0, 0};
-                const int i0 = ti * 64, j0 = tj * 64;
-                for (int k0 = kb; k0 < ke; k0 += BG_KC) {
-                    __syncthreads();
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        int i, kk;
-                        if (a_kfast) { kk = t & 15; i = (t >> 4) + 16 * r; }
-                        else { i = t & 63; kk = (t >> 6) + 4 * r; }
-                        T v = T(0);
-                        if (i0 + i < M && k0 + kk < ke) v = T(A(i0 + i, k0 + kk));
-                        L.As[kk][i] = v;
-                        int j, k2;
-                        if (b_jfast) { j = t & 63; k2 = (t >> 6) + 4 * r; }
-                        else { k2 = t & 15; j = (t >> 4) + 16 * r; }
-                        T w = T(0);
-                        if (j0 + j < N && k0 + k2 < ke) w = T(B(k0 + k2, j0 + j));
-                        L.Bs[k2][j] = w;
-                    }
-                    __syncthreads();
-#pragma unroll
-                    for (int s = 0; s < BG_KC / 4; ++s) {
-                        const int kr = 4 * s + (lane >> 4);
-                        const T a0 = L.As[kr][wr * 32 + (lane & 15)];
-                        const T a1 = L.As[kr][wr * 32 + 16 + (lane & 15)];
-                        const T b0 = L.Bs[kr][wc * 32 + (lane & 15)];
-                        const T b1 = L.Bs[kr][wc * 32 + 16 + (lane & 15)];
-                        acc[0][0] = Mf::mac(a0, b0, acc[0][0]);
-                        acc[0][1] = Mf::mac(a0, b1, acc[0][1]);
-                        acc[1][0] = Mf::mac(a1, b0, acc[1][0]);
-                        acc[1][1] = Mf::mac(a1, b1, acc[1][1]);
-                    }
+                for (int b = 0; b < 2; ++b) acc[a][b] = V{0, 0, 0, 0};
+            for (int k0 = kb; k0 < ke; k0 += BG_KC) {
+                __syncthreads();
+                store_chunk(L, ra, rb, a_kfast, b_jfast);
+                __syncthreads();
+                if (k0 + BG_KC < ke) {
+                    load_chunk(ra, rb, A, B, M, N, i0, j0, k0 + BG_KC, ke, a_kfast, b_jfast);
+                } else if (more && nkb < nke) {
+                    load_chunk(ra, rb, A, B, M, N, ni * 64, nj * 64, nkb, nke, a_kfast, b_jfast);
+                    have = true;
                 }
 #pragma unroll
-                for (int a = 0; a < 2; ++a)
-#pragma unroll
-                    for (int b = 0; b < 2; ++b)
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const int i = i0 + wr * 32 + a * 16 + Mf::row(lane, r);
-                            const int j = j0 + wc * 32 + b * 16 + (lane & 15);
-                            if (i >= M || j >= N) continue;
-                            if ((F & GM_LOWER) && j > i) continue;
-                            T v = alpha * acc[a][b][r];
-                            if (F & GM_ADD) v += T(add(i, j));
-                            if ((F & GM_IDENT) && i == j) v += T(1);
-                            out(i, j) = (typename std::remove_cv<PO>::type)v;
-                            if ((F & GM_SYM) && j < i) out(j, i) = (typename std::remove_cv<PO>::type)v;
-                        }
+                for (int s = 0; s < BG_KC / 4; ++s) {
+                    const int kr = 4 * s + (lane >> 4);
+                    const T a0 = L.As[kr][wr * 32 + (lane & 15)];
+                    const T a1 = L.As[kr][wr * 32 + 16 + (lane & 15)];
+                    const T b0 = L.Bs[kr][wc * 32 + (lane & 15)];
+                    const T b1 = L.Bs[kr][wc * 32 + 16 + (lane & 15)];
+                    acc[0][0] = Mf::mac(a0, b0, acc[0][0]);
+                    acc[0][1] = Mf::mac(a0, b1, acc[0][1]);
+                    acc[1][0] = Mf::mac(a1, b0, acc[1][0]);
+                    acc[1][1] = Mf::mac(a1, b1, acc[1][1]);
+                }
             }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int i = i0 + wr * 32 + a * 16 + Mf::row(lane, r);
+                        const int j = j0 + wc * 32 + b * 16 + (lane & 15);
+                        if (i >= M || j >= N) continue;
+                        if ((F & GM_LOWER) && j > i) continue;
+                        T v = alpha * acc[a][b][r];
+                        if (F & GM_ADD) v += T(add(i, j));
+                        if ((F & GM_IDENT) && i == j) v += T(1);
+                        out(i, j) = (typename std::remove_cv<PO>::type)v;
+                        if ((F & GM_SYM) && j < i) out(j, i) = (typename std::remove_cv<PO>::type)v;
+                    }
+            ti = ni;
+            tj = nj;
+            if (!more) break;
         }
         __syncthreads();
     }
@@ -258,7 +318,7 @@ struct BigEng {
     // L^{-1}, lower triangular with zeros above.  `tmp` holds 32 x n elements.
     // Returns (uniformly) whether every pivot was positive and finite, and
     // the extreme diagonal entries of L for the condition estimate.
-    __device__ __forceinline__ bool potrf_inv(BigLds<T>& L, T* a, T* li, T* tmp, int n, T& dmin,
+    __device__ __attribute__((noinline)) bool potrf_inv(BigLds<T>& L, T* a, T* li, T* tmp, int n, T& dmin,
                                                         T& dmax) const {
         const int t = lg;
         bool ok = true;

@@ -22,6 +22,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace lqr {
 
 template <typename T> __device__ __forceinline__ T dsqrt(T x);
@@ -173,26 +175,29 @@ struct Eng {
     // op(X)(i,k) = TX ? X[k][i] : X[i][k];  op(Y)(k,j) = TY ? Y[j][k] : Y[k][j].
     // SYM: the product is symmetric and only its lower triangle is needed;
     // the strictly-upper tile blocks (b > a) are skipped.  SUB: subtract.
-    template <bool TX, bool TY, bool SYM = false, bool SUB = false>
+    // RA / CB: only the first RA row blocks and CB column blocks of the tile
+    // are formed (products whose result has fewer than NP rows or columns).
+    template <bool TX, bool TY, bool SYM = false, bool SUB = false, int RA = TS, int CB = TS>
     __device__ __forceinline__ void gemm(Tile& acc, const T* X, const T* Y, int K) const {
+        static_assert(RA <= TS && CB <= TS, "block limits");
 #pragma unroll 2
         for (int k = 0; k < K; ++k) {
-            T xa[TS], yb[TS];
+            T xa[RA], yb[CB];
 #pragma unroll
-            for (int a = 0; a < TS; ++a) xa[a] = TX ? X[k * LD + row(a)] : X[row(a) * LD + k];
+            for (int a = 0; a < RA; ++a) xa[a] = TX ? X[k * LD + row(a)] : X[row(a) * LD + k];
 #pragma unroll
-            for (int b = 0; b < TS; ++b) yb[b] = TY ? Y[col(b) * LD + k] : Y[k * LD + col(b)];
+            for (int b = 0; b < CB; ++b) yb[b] = TY ? Y[col(b) * LD + k] : Y[k * LD + col(b)];
 #pragma unroll
-            for (int a = 0; a < TS; ++a)
+            for (int a = 0; a < RA; ++a)
 #pragma unroll
-                for (int b = 0; b < TS; ++b)
+                for (int b = 0; b < CB; ++b)
                     if (!SYM || b <= a) acc[a][b] = fma_(SUB ? -xa[a] : xa[a], yb[b], acc[a][b]);
         }
     }
 
-    template <bool TX, bool TY, bool SYM = false>
+    template <bool TX, bool TY, bool SYM = false, int RA = TS, int CB = TS>
     __device__ __forceinline__ void gemm_sub(Tile& acc, const T* X, const T* Y, int K) const {
-        gemm<TX, TY, SYM, true>(acc, X, Y, K);
+        gemm<TX, TY, SYM, true, RA, CB>(acc, X, Y, K);
     }
 
     // -------------------------------------------- coalesced global <-> LDS
@@ -272,9 +277,28 @@ struct Eng {
 #pragma unroll 4
                 for (int i = 0; i < rows; ++i) s = fma_(T(c[(int64_t)i * ld]), vb[i], s);
             }
-        } else {
-            if (lg < rows) {
-                const S* r = M + (int64_t)lg * ld;
+        } else if (lg < rows) {
+            const S* r = M + (int64_t)lg * ld;
+            // rows of 16-byte aligned matrices are read 16 bytes at a time
+            // (a lane's row is contiguous; lanes read distinct rows)
+            constexpr int V = 16 / (int)sizeof(S);
+            if ((cols % V) == 0 && (ld % V) == 0 && ((uintptr_t)M & 15) == 0) {
+                using S4 = typename std::conditional<sizeof(S) == 4, float4, double2>::type;
+                const S4* r4 = reinterpret_cast<const S4*>(r);
+#pragma unroll 2
+                for (int j = 0; j < cols / V; ++j) {
+                    const S4 w = r4[j];
+                    if constexpr (sizeof(S) == 4) {
+                        s = fma_(T(w.x), vb[4 * j], s);
+                        s = fma_(T(w.y), vb[4 * j + 1], s);
+                        s = fma_(T(w.z), vb[4 * j + 2], s);
+                        s = fma_(T(w.w), vb[4 * j + 3], s);
+                    } else {
+                        s = fma_(T(w.x), vb[2 * j], s);
+                        s = fma_(T(w.y), vb[2 * j + 1], s);
+                    }
+                }
+            } else {
 #pragma unroll 4
                 for (int j = 0; j < cols; ++j) s = fma_(T(r[j]), vb[j], s);
             }
@@ -290,21 +314,24 @@ struct Eng {
     // 2*(NP+NV) elements.  Returns false if a pivot is not positive (the
     // factorization continues with a unit pivot so values stay finite).
     // dmin/dmax receive the extreme diagonal entries of L.
-    template <int NV>
+    // NB: the matrix occupies the first NB row/column blocks of the tile
+    // (n <= G * NB); the other blocks are left untouched (zero).
+    template <int NV, int NB = TS>
     __device__ __forceinline__ bool chol(Tile& S, int n, T* cb, T* dinv, T (&gv)[NV > 0 ? NV : 1], T& dmin, T& dmax) const {
+        static_assert(NB <= TS, "block limit");
         bool ok = true;
         dmin = T(0);
         dmax = T(0);
         bool first = true;
 #pragma unroll
-        for (int a0 = 0; a0 < TS; ++a0) {
+        for (int a0 = 0; a0 < NB; ++a0) {
             for (int t = 0; t < G; ++t) {
                 const int k = G * a0 + t;
                 if (k >= n) break;
                 T* c = cb + (k & 1) * (NP + (NV > 0 ? NV : 1));
                 if (tx == t) {
 #pragma unroll
-                    for (int a = 0; a < TS; ++a) c[row(a)] = S[a][a0];
+                    for (int a = 0; a < NB; ++a) c[row(a)] = S[a][a0];
                 }
 #pragma unroll
                 for (int v = 0; v < NV; ++v)
@@ -319,25 +346,25 @@ struct Eng {
                 if (first) { dmin = s; dmax = s; first = false; }
                 dmin = s < dmin ? s : dmin;
                 dmax = s > dmax ? s : dmax;
-                T li[TS], lj[TS];
+                T li[NB], lj[NB];
 #pragma unroll
-                for (int a = 0; a < TS; ++a) li[a] = c[row(a)] * inv;
+                for (int a = 0; a < NB; ++a) li[a] = c[row(a)] * inv;
 #pragma unroll
-                for (int b = a0; b < TS; ++b) lj[b] = c[col(b)] * inv;
+                for (int b = a0; b < NB; ++b) lj[b] = c[col(b)] * inv;
                 // trailing update of the lower triangle: blocks a >= b >= a0
 #pragma unroll
-                for (int a = a0; a < TS; ++a)
+                for (int a = a0; a < NB; ++a)
 #pragma unroll
                     for (int b = a0; b <= a; ++b)
                         if (row(a) > k && col(b) > k) S[a][b] = fma_(-li[a], lj[b], S[a][b]);
                 if (tx == t) {
 #pragma unroll
-                    for (int a = 0; a < TS; ++a)
+                    for (int a = 0; a < NB; ++a)
                         S[a][a0] = row(a) > k ? li[a] : (row(a) == k ? s : T(0));
                 }
                 if (ty == t) {
 #pragma unroll
-                    for (int b = 0; b < TS; ++b)
+                    for (int b = 0; b < NB; ++b)
                         if (col(b) > k) S[a0][b] = T(0);
                 }
                 if (lg == 0) dinv[k] = inv;
@@ -358,13 +385,16 @@ struct Eng {
     // backward with the transpose), L (n x n lower) in LDS slot sL with
     // reciprocal diagonal dinv.  Solves NT register tiles (their first n rows)
     // and NV lane vectors at once.  rb is LDS scratch of 2*(NT*NP+NV).
-    template <bool LOWER, int NT, int NV>
+    // NB: the solve order n fits the first NB row blocks (n <= G * NB); the
+    // rows of the right-hand-side tiles beyond them are left untouched.
+    template <bool LOWER, int NT, int NV, int NB = TS>
     __device__ __forceinline__ void trsm(const T* sL, const T* dinv, int n, Tile (&X)[NT > 0 ? NT : 1],
                          T (&vv)[NV > 0 ? NV : 1], T* rb) const {
+        static_assert(NB <= TS, "block limit");
         constexpr int RBS = (NT > 0 ? NT : 0) * NP + (NV > 0 ? NV : 0) + 1;
 #pragma unroll
-        for (int a0s = 0; a0s < TS; ++a0s) {
-            const int a0 = LOWER ? a0s : TS - 1 - a0s;
+        for (int a0s = 0; a0s < NB; ++a0s) {
+            const int a0 = LOWER ? a0s : NB - 1 - a0s;
             for (int ts = 0; ts < G; ++ts) {
                 const int t = LOWER ? ts : G - 1 - ts;
                 const int k = G * a0 + t;
@@ -386,9 +416,9 @@ struct Eng {
                 wg_sync();
                 // row blocks already solved (before a0 going forward, after a0
                 // going backward) are skipped
-                T lik[TS];
+                T lik[NB];
 #pragma unroll
-                for (int a = 0; a < TS; ++a) {
+                for (int a = 0; a < NB; ++a) {
                     if (LOWER ? a < a0 : a > a0) continue;
                     const int i = row(a);
                     const bool act = LOWER ? (i > k && i < n) : (i < k);
@@ -400,7 +430,7 @@ struct Eng {
 #pragma unroll
                     for (int b = 0; b < TS; ++b) rk[b] = r[it * NP + col(b)];
 #pragma unroll
-                    for (int a = 0; a < TS; ++a) {
+                    for (int a = 0; a < NB; ++a) {
                         if (LOWER ? a < a0 : a > a0) continue;
 #pragma unroll
                         for (int b = 0; b < TS; ++b)

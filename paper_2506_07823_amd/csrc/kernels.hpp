@@ -256,6 +256,12 @@ __global__ void k_copy(const S* src, S* dst, int64_t count) {
 #include "kernels_big.hpp"
 namespace lqr {
 
+// MB (kernel template parameter of the element, policy and plain kernels
+// of the wavefront engine): the number of G-row blocks the control
+// dimension m occupies, so the tile products, Cholesky and solves of
+// m-sized operands skip the padding blocks.  The host picks 1, 2 or TS.
+
+
 // ---------------------------------------------------------------------------
 // Sec. II-D, eq. (initialization): one-stage element with S_k = M_k'.
 //   R = L_R L_R',  W_B = L_R^{-1} B',  W_M = L_R^{-1} M',  w_r = L_R^{-1} r
@@ -266,7 +272,7 @@ namespace lqr {
 // threshold, or a non-positive pivot).
 // Record layout: A | C | P | b | p.
 // ---------------------------------------------------------------------------
-template <typename S, class E, bool FB>
+template <typename S, class E, bool FB, int MB>
 __device__ __forceinline__ void element_task(Lds<E>& L, const Plan& p, const In<S>& in, S* ws, int32_t* status, FbQueue q,
                              int64_t task) {
     using T = typename E::T;
@@ -287,7 +293,7 @@ __device__ __forceinline__ void element_task(Lds<E>& L, const Plan& p, const In<
     typename E::Tile tR;
     e.load(tR, P.R(b, k), m, m, m);
     T dmin, dmax, nov[1];
-    const bool ok = e.template chol<0>(tR, m, L.cb, L.dA, nov, dmin, dmax);
+    const bool ok = e.template chol<0, MB>(tR, m, L.cb, L.dA, nov, dmin, dmax);
     fb_decide<FB>(p, ok, cond_est(dmin, dmax), b, task, q, status, 2);
     e.to_lds(tR, L.sA);
     typename E::Tile W[2];
@@ -295,7 +301,7 @@ __device__ __forceinline__ void element_task(Lds<E>& L, const Plan& p, const In<
     e.template load<true>(W[1], P.M(b, k), m, n, m);   // M' (m x n)
     T vv[1] = {e.vload(P.r(b, k), m)};
     wg_sync();
-    e.template trsm<true, 2, 1>(L.sA, L.dA, m, W, vv, L.rb);
+    e.template trsm<true, 2, 1, MB>(L.sA, L.dA, m, W, vv, L.rb);
     e.to_lds(W[0], L.sA);
     e.to_lds(W[1], L.sX);
     wg_sync();
@@ -315,12 +321,12 @@ __device__ __forceinline__ void element_task(Lds<E>& L, const Plan& p, const In<
     e.vstore(rec + 3 * nn + n, n, e.vload(P.q(b, k), n) - pw);
 }
 
-template <typename S, class E, bool FB>
+template <typename S, class E, bool FB, int MB>
 __global__ __launch_bounds__(E::NT) void k_element(Plan p, In<S> in, S* ws, int32_t* status, FbQueue q) {
     __shared__ Lds<E> L;
     auto body = [&](int64_t t) {
         if constexpr (E::BIG) big_element_task<S, E, FB>(L, p, in, ws, status, q, t);
-        else element_task<S, E, FB>(L, p, in, ws, status, q, t);
+        else element_task<S, E, FB, MB>(L, p, in, ws, status, q, t);
     };
     LQR_TASKS(E, FB, q, p.batch * (p.N + 1), body);
 }
@@ -547,7 +553,7 @@ __global__ __launch_bounds__(E::NT) void k_down(Plan p, S* ws, int lvl, int32_t*
 // then eq. (controlled_dynamics): Abar = A + B K, bbar = B k + c, written as
 // the leaf of the forward tree.  Stores K, k and L_G (reused by refinement).
 // ---------------------------------------------------------------------------
-template <typename S, class E, bool FB>
+template <typename S, class E, bool FB, int MB>
 __device__ __forceinline__ void policy_task(Lds<E>& L, const Plan& p, const In<S>& in, S* ws, int32_t* status, FbQueue q,
                             int64_t task) {
     using T = typename E::T;
@@ -564,20 +570,20 @@ __device__ __forceinline__ void policy_task(Lds<E>& L, const Plan& p, const In<S
     wg_sync();
     const T v = e.template matvec<false>(L.sA, e.vload(P.c(b, k), n), L.vb[0], n, n) + e.vload(Pn + nn, n);
     e.zero(t);
-    e.template gemm<false, false>(t, L.sA, L.sX, n);       // P'B
+    e.template gemm<false, false, false, false, E::TS, MB>(t, L.sA, L.sX, n);       // P'B
     const T h = e.template matvec<true>(L.sX, v, L.vb[1], n, m) + e.vload(P.r(b, k), m);
     wg_sync();
     e.to_lds(t, L.sA);                                    // sA = P'B
     wg_sync();
     e.load(tG, P.R(b, k), m, m, m);
-    e.template gemm<true, false, true>(tG, L.sA, L.sX, n); // R + (P'B)'B (lower)
+    e.template gemm<true, false, true, false, MB, MB>(tG, L.sA, L.sX, n); // R + (P'B)'B (lower)
     wg_sync();
     stage(e, L.sX, P.A(b, k), n, n, n);                   // sX = A
     wg_sync();
     e.template load<true>(tH, P.M(b, k), m, n, m);        // M'
-    e.template gemm<true, false>(tH, L.sA, L.sX, n);       // + (P'B)'A
+    e.template gemm<true, false, false, false, MB, E::TS>(tH, L.sA, L.sX, n);       // + (P'B)'A
     T dmin, dmax, nov[1];
-    const bool ok = e.template chol<0>(tG, m, L.cb, L.dA, nov, dmin, dmax);
+    const bool ok = e.template chol<0, MB>(tG, m, L.cb, L.dA, nov, dmin, dmax);
     fb_decide<FB>(p, ok, cond_est(dmin, dmax), b, task, q, status, 2);
     e.to_lds(tG, L.sA);                                   // sA = L_G
     wg_sync();
@@ -587,8 +593,8 @@ __device__ __forceinline__ void policy_task(Lds<E>& L, const Plan& p, const In<S
 #pragma unroll
         for (int c = 0; c < E::TS; ++c) KK[0][a][c] = tH[a][c];
     T hv[1] = {h};
-    e.template trsm<true, 1, 1>(L.sA, L.dA, m, KK, hv, L.rb);
-    e.template trsm<false, 1, 1>(L.sA, L.dA, m, KK, hv, L.rb);
+    e.template trsm<true, 1, 1, MB>(L.sA, L.dA, m, KK, hv, L.rb);
+    e.template trsm<false, 1, 1, MB>(L.sA, L.dA, m, KK, hv, L.rb);
     negate<E>(KK[0]);
     hv[0] = -hv[0];
     e.store(KK[0], inst + p.o_K + (int64_t)k * m * n, m, n, n);
@@ -606,12 +612,12 @@ __device__ __forceinline__ void policy_task(Lds<E>& L, const Plan& p, const In<S
     e.vstore(leaf + nn, n, bb);
 }
 
-template <typename S, class E, bool FB>
+template <typename S, class E, bool FB, int MB>
 __global__ __launch_bounds__(E::NT) void k_policy(Plan p, In<S> in, S* ws, int32_t* status, FbQueue q) {
     __shared__ Lds<E> L;
     auto body = [&](int64_t t) {
         if constexpr (E::BIG) big_policy_task<S, E, FB>(L, p, in, ws, status, q, t);
-        else policy_task<S, E, FB>(L, p, in, ws, status, q, t);
+        else policy_task<S, E, FB, MB>(L, p, in, ws, status, q, t);
     };
     LQR_TASKS(E, FB, q, p.batch * p.N, body);
 }
@@ -1110,10 +1116,9 @@ __global__ __launch_bounds__(E::NT) void k_resid_inst(Plan p, In<S> in, const S*
 // and costates, one group per instance (workspace: P_k, p_k in the suffix
 // area indexed by stage, K_k, k_k).
 // ---------------------------------------------------------------------------
-template <typename S, class E>
-__global__ __launch_bounds__(64) void k_plain(Plan p, In<S> in, Out<S> out, S* ws) {
+template <typename S, class E, int MB>
+__device__ __forceinline__ void plain_body(Lds3<E>& L, const Plan& p, const In<S>& in, const Out<S>& out, S* ws) {
     using T = typename E::T;
-    __shared__ Lds3<E> L;
     const E e(threadIdx.x);
     const int N = p.N, n = p.n, m = p.m, nn = n * n;
     const int64_t b = blockIdx.x;
@@ -1133,18 +1138,18 @@ __global__ __launch_bounds__(64) void k_plain(Plan p, In<S> in, Out<S> out, S* w
         wg_sync();
         const T v = e.template matvec<false>(L.sP, e.vload(P.c(b, k), n), L.vb[0], n, n) + pn;
         e.zero(tPB);
-        e.template gemm<false, false>(tPB, L.sP, L.sX, n); // P'B
+        e.template gemm<false, false, false, false, E::TS, MB>(tPB, L.sP, L.sX, n); // P'B
         const T h = e.template matvec<true>(L.sX, v, L.vb[1], n, m) + e.vload(P.r(b, k), m);
         wg_sync();
         e.to_lds(tPB, L.sA);                              // sA = P'B
         wg_sync();
         e.load(tG, P.R(b, k), m, m, m);
-        e.template gemm<true, false, true>(tG, L.sA, L.sX, n);   // G (lower)
+        e.template gemm<true, false, true, false, MB, MB>(tG, L.sA, L.sX, n);   // G (lower)
         wg_sync();
         stage(e, L.sX, P.A(b, k), n, n, n);               // sX = A
         wg_sync();
         e.template load<true>(tH, P.M(b, k), m, n, m);
-        e.template gemm<true, false>(tH, L.sA, L.sX, n);   // H
+        e.template gemm<true, false, false, false, MB, E::TS>(tH, L.sA, L.sX, n);   // H
         e.zero(tPA);
         e.template gemm<false, false>(tPA, L.sP, L.sX, n); // P'A
         const T pa = e.template matvec<true>(L.sX, v, L.vb[0], n, n);   // A'v
@@ -1153,7 +1158,7 @@ __global__ __launch_bounds__(64) void k_plain(Plan p, In<S> in, Out<S> out, S* w
 #pragma unroll
             for (int c = 0; c < E::TS; ++c) tHc[a][c] = tH[a][c];
         T dmin, dmax, nov[1];
-        ok = e.template chol<0>(tG, m, L.cb, L.dA, nov, dmin, dmax) && ok;
+        ok = e.template chol<0, MB>(tG, m, L.cb, L.dA, nov, dmin, dmax) && ok;
         e.to_lds(tG, L.sA);                               // sA = L_G
         wg_sync();
         typename E::Tile KK[1];
@@ -1162,8 +1167,8 @@ __global__ __launch_bounds__(64) void k_plain(Plan p, In<S> in, Out<S> out, S* w
 #pragma unroll
             for (int c = 0; c < E::TS; ++c) KK[0][a][c] = tH[a][c];
         T hv[1] = {h};
-        e.template trsm<true, 1, 1>(L.sA, L.dA, m, KK, hv, L.rb);
-        e.template trsm<false, 1, 1>(L.sA, L.dA, m, KK, hv, L.rb);
+        e.template trsm<true, 1, 1, MB>(L.sA, L.dA, m, KK, hv, L.rb);
+        e.template trsm<false, 1, 1, MB>(L.sA, L.dA, m, KK, hv, L.rb);
         negate<E>(KK[0]);
         hv[0] = -hv[0];
         e.store(KK[0], inst + p.o_K + (int64_t)k * m * n, m, n, n);
@@ -1214,6 +1219,12 @@ __global__ __launch_bounds__(64) void k_plain(Plan p, In<S> in, Out<S> out, S* w
         x = xn;
     }
     if (!wave_all(fin)) set_status(out.status, b, 1);
+}
+
+template <typename S, class E, int MB>
+__global__ __launch_bounds__(64) void k_plain(Plan p, In<S> in, Out<S> out, S* ws) {
+    __shared__ Lds3<E> L;
+    plain_body<S, E, MB>(L, p, in, out, ws);
 }
 
 }  // namespace lqr

@@ -27,6 +27,25 @@ constexpr int kBigTS = 32;
 template <typename S, int TS>
 using EngOf = typename std::conditional<TS == kBigTS, BigEng<S>, Eng<S, 8, TS>>::type;
 
+// host-side choice of the control-block count MB (see kernels.hpp): calls
+// fn(std::integral_constant<int, MB>) with MB = 1, 2 or TS (0 for the
+// large-block engine, which does not use it)
+template <int TS, typename Fn>
+int with_mb(int m, Fn&& fn) {
+    if constexpr (TS == kBigTS) {
+        return fn(std::integral_constant<int, 0>{});
+    } else {
+        const int mb = (m + 7) / 8;
+        if constexpr (TS > 1) {
+            if (mb <= 1) return fn(std::integral_constant<int, 1>{});
+        }
+        if constexpr (TS > 2) {
+            if (mb <= 2) return fn(std::integral_constant<int, 2>{});
+        }
+        return fn(std::integral_constant<int, TS>{});
+    }
+}
+
 // kernel families (diagnostic timing keys)
 enum Fam {
     F_CLEAR, F_ELEM, F_ELEM_FB, F_UP, F_ROOT, F_DOWN, F_POLICY, F_POLICY_FB, F_FUP, F_FROOT, F_FDOWN,
@@ -140,11 +159,15 @@ int run_scan(const Plan& p, hipStream_t s, const In<S>& in, const Out<S>& out, S
     // a1: elements (+ FP64 redo of queued stages)
     {
         const FbQueue q = fbq(iws, Qs, kQElem);
-        LCHK(launch_nt(NT, F_ELEM, B * N * w.elem_f(), B * N * w.elem_b(), k_element<S, E, false>, task_grid<E>(p, Bi * (N + 1)), s, p,
-                    in, ws, out.status, q));
-        if (fb)
-            LCHK(launch_nt(NT, F_ELEM_FB, 0, 0, k_element<S, E64, true>, fb_grid<E64>(p, Bi * (N + 1)), s, p, in, ws,
-                        out.status, q));
+        LCHK(with_mb<TS>(p.m, [&](auto mb) {
+            constexpr int MB = decltype(mb)::value;
+            LCHK(launch_nt(NT, F_ELEM, B * N * w.elem_f(), B * N * w.elem_b(), k_element<S, E, false, MB>,
+                           task_grid<E>(p, Bi * (N + 1)), s, p, in, ws, out.status, q));
+            if (fb)
+                LCHK(launch_nt(NT, F_ELEM_FB, 0, 0, k_element<S, E64, true, MB>, fb_grid<E64>(p, Bi * (N + 1)), s, p,
+                               in, ws, out.status, q));
+            return LQR_OK;
+        }));
     }
     // a3: reverse scan, up-sweep then down-sweep
     for (int l = 0; l + 1 < p.rt.nlev; ++l) {
@@ -169,10 +192,15 @@ int run_scan(const Plan& p, hipStream_t s, const In<S>& in, const Out<S>& out, S
     // a4: policy and closed-loop maps
     {
         const FbQueue q = fbq(iws, Qs, kQPolicy);
-        LCHK(launch_nt(NT, F_POLICY, B * N * w.pol_f(), B * N * w.pol_b(), k_policy<S, E, false>, task_grid<E>(p, Bi * N), s, p, in, ws,
-                    out.status, q));
-        if (fb)
-            LCHK(launch_nt(NT, F_POLICY_FB, 0, 0, k_policy<S, E64, true>, fb_grid<E64>(p, Bi * N), s, p, in, ws, out.status, q));
+        LCHK(with_mb<TS>(p.m, [&](auto mb) {
+            constexpr int MB = decltype(mb)::value;
+            LCHK(launch_nt(NT, F_POLICY, B * N * w.pol_f(), B * N * w.pol_b(), k_policy<S, E, false, MB>,
+                           task_grid<E>(p, Bi * N), s, p, in, ws, out.status, q));
+            if (fb)
+                LCHK(launch_nt(NT, F_POLICY_FB, 0, 0, k_policy<S, E64, true, MB>, fb_grid<E64>(p, Bi * N), s, p, in,
+                               ws, out.status, q));
+            return LQR_OK;
+        }));
     }
     // a5: forward scan of the closed-loop maps
     for (int l = 0; l + 1 < p.ft.nlev; ++l) {
@@ -289,7 +317,10 @@ int run_plain(const Plan& p, hipStream_t s, const In<S>& in, const Out<S>& out, 
         LCHK(launch_nt(NT, F_PLAIN, B * w.plain_f(p.N), B * w.plain_b(p.N), k_plain_big<S, E>, task_grid<E>(p, Bi), s,
                        p, in, out, ws));
     else
-        LCHK(launch_nt(NT, F_PLAIN, B * w.plain_f(p.N), B * w.plain_b(p.N), k_plain<S, E>, Bi, s, p, in, out, ws));
+        LCHK(with_mb<TS>(p.m, [&](auto mb) {
+            return launch_nt(NT, F_PLAIN, B * w.plain_f(p.N), B * w.plain_b(p.N), k_plain<S, E, decltype(mb)::value>,
+                             Bi, s, p, in, out, ws);
+        }));
     if (resid_out) {
         LCHK(launch_nt(NT, F_RESID, B * (p.N + 1) * w.resid_f(), B * (p.N + 1) * w.resid_b(), k_resid<S, E64, false>,
                     Bi * (p.N + 1), s, p, in, (const S*)out.x, (const S*)out.u, (const S*)out.lam, ws, dws));
