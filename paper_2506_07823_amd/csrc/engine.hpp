@@ -352,11 +352,15 @@ struct Eng {
 #pragma unroll
                 for (int b = a0; b < NB; ++b) lj[b] = c[col(b)] * inv;
                 // trailing update of the lower triangle: blocks a >= b >= a0
+                // (blocks past the pivot block lie entirely below and right
+                // of k: only the pivot block row and column need the test)
 #pragma unroll
                 for (int a = a0; a < NB; ++a)
 #pragma unroll
-                    for (int b = a0; b <= a; ++b)
-                        if (row(a) > k && col(b) > k) S[a][b] = fma_(-li[a], lj[b], S[a][b]);
+                    for (int b = a0; b <= a; ++b) {
+                        if (a > a0 && b > a0) S[a][b] = fma_(-li[a], lj[b], S[a][b]);
+                        else if (row(a) > k && col(b) > k) S[a][b] = fma_(-li[a], lj[b], S[a][b]);
+                    }
                 if (tx == t) {
 #pragma unroll
                     for (int a = 0; a < NB; ++a)
@@ -416,13 +420,19 @@ struct Eng {
                 wg_sync();
                 // row blocks already solved (before a0 going forward, after a0
                 // going backward) are skipped
+                // rows of blocks past the pivot block are all active (the
+                // factor is zero beyond its order n, so no test is needed)
                 T lik[NB];
 #pragma unroll
                 for (int a = 0; a < NB; ++a) {
                     if (LOWER ? a < a0 : a > a0) continue;
                     const int i = row(a);
-                    const bool act = LOWER ? (i > k && i < n) : (i < k);
-                    lik[a] = act ? (LOWER ? sL[i * LD + k] : sL[k * LD + i]) : T(0);
+                    if (a != a0) {
+                        lik[a] = LOWER ? sL[i * LD + k] : sL[k * LD + i];
+                    } else {
+                        const bool act = LOWER ? (i > k && i < n) : (i < k);
+                        lik[a] = act ? (LOWER ? sL[i * LD + k] : sL[k * LD + i]) : T(0);
+                    }
                 }
 #pragma unroll
                 for (int it = 0; it < NT; ++it) {

@@ -114,6 +114,13 @@ struct Lds {
 template <typename T>
 struct Lds<BigEng<T>> : BigLds<T> {};
 
+// LDS of the vector-only passes: two staging vectors (nothing else, so these
+// kernels keep many wavefronts resident to hide their memory latency)
+template <class E>
+struct VecLds {
+    typename E::T vb[2][E::NP];
+};
+
 template <class E>
 struct ResidLds {
     double vb[2][E::NP];
@@ -627,8 +634,8 @@ __global__ __launch_bounds__(E::NT) void k_policy(Plan p, In<S> in, S* ws, int32
 //   M = M_r M_l,  v = M_r v_l + v_r   (apply the earlier map first)
 // VEC: only the vector part (matrices kept from the first solve).
 // ---------------------------------------------------------------------------
-template <typename S, class E, bool VEC>
-__device__ __forceinline__ void fup_body(Lds<E>& L, Plan p, S* ws, int lvl, int64_t tid) {
+template <typename S, class E, bool VEC, class LT>
+__device__ __forceinline__ void fup_body(LT& L, Plan p, S* ws, int lvl, int64_t tid) {
     using T = typename E::T;
     const E e(threadIdx.x);
     const int n = p.n, nn = n * n;
@@ -665,7 +672,7 @@ __device__ __forceinline__ void fup_body(Lds<E>& L, Plan p, S* ws, int lvl, int6
 
 template <typename S, class E, bool VEC>
 __global__ __launch_bounds__(E::NT) void k_fup(Plan p, S* ws, int lvl) {
-    __shared__ Lds<E> L;
+    __shared__ typename std::conditional<VEC, VecLds<E>, Lds<E>>::type L;
     fup_body<S, E, VEC>(L, p, ws, lvl, (int64_t)blockIdx.x);
 }
 
@@ -685,8 +692,8 @@ __global__ __launch_bounds__(64) void k_froot(Plan p, S* ws, const S* x0, int64_
 
 // node (l, j): even j starts where its parent starts; odd j starts after its
 // left sibling:  xs = M_{j-1} xs(parent) + v_{j-1}
-template <typename S, class E>
-__device__ __forceinline__ void fdown_body(Lds<E>& L, Plan p, S* ws, int lvl, int64_t tid) {
+template <typename S, class E, class LT>
+__device__ __forceinline__ void fdown_body(LT& L, Plan p, S* ws, int lvl, int64_t tid) {
     using T = typename E::T;
     const E e(threadIdx.x);
     const int n = p.n, nn = n * n;
@@ -708,7 +715,7 @@ __device__ __forceinline__ void fdown_body(Lds<E>& L, Plan p, S* ws, int lvl, in
 
 template <typename S, class E>
 __global__ __launch_bounds__(E::NT) void k_fdown(Plan p, S* ws, int lvl) {
-    __shared__ Lds<E> L;
+    __shared__ VecLds<E> L;
     fdown_body<S, E>(L, p, ws, lvl, (int64_t)blockIdx.x);
 }
 
@@ -716,8 +723,8 @@ __global__ __launch_bounds__(E::NT) void k_fdown(Plan p, S* ws, int lvl) {
 // u_k = K_k x_k + k_k,  lambda_k = P_k x_k + p_k  (Sec. II-C); x_N from the
 // last leaf map.  ADD: the refinement's correction is added to the outputs.
 // ---------------------------------------------------------------------------
-template <typename S, class E, bool ADD>
-__device__ __forceinline__ void recover_body(Lds<E>& L, Plan p, S* ws, Out<S> out, int64_t tid) {
+template <typename S, class E, bool ADD, class LT>
+__device__ __forceinline__ void recover_body(LT& L, Plan p, S* ws, Out<S> out, int64_t tid) {
     using T = typename E::T;
     const E e(threadIdx.x);
     const int N = p.N, n = p.n, m = p.m, nn = n * n;
@@ -763,7 +770,7 @@ __device__ __forceinline__ void recover_body(Lds<E>& L, Plan p, S* ws, Out<S> ou
 
 template <typename S, class E, bool ADD>
 __global__ __launch_bounds__(E::NT) void k_recover(Plan p, S* ws, Out<S> out) {
-    __shared__ Lds<E> L;
+    __shared__ VecLds<E> L;
     recover_body<S, E, ADD>(L, p, ws, out, (int64_t)blockIdx.x);
 }
 
@@ -865,8 +872,8 @@ __global__ void k_resid_reduce(Plan p, const D* dws, D* rel, int32_t* active_out
 // a backward scan whose segment matrices are the transposes of the forward
 // tree's products Abar_e ... Abar_s.
 // ---------------------------------------------------------------------------
-template <typename S, class E>
-__device__ __forceinline__ void ref_d_body(Lds<E>& L, Plan p, S* ws, int64_t tid) {
+template <typename S, class E, class LT>
+__device__ __forceinline__ void ref_d_body(LT& L, Plan p, S* ws, int64_t tid) {
     using T = typename E::T;
     const E e(threadIdx.x);
     const int N = p.N, n = p.n, m = p.m;
@@ -885,13 +892,13 @@ __device__ __forceinline__ void ref_d_body(Lds<E>& L, Plan p, S* ws, int64_t tid
 
 template <typename S, class E>
 __global__ __launch_bounds__(E::NT) void k_ref_d(Plan p, S* ws) {
-    __shared__ Lds<E> L;
+    __shared__ VecLds<E> L;
     ref_d_body<S, E>(L, p, ws, (int64_t)blockIdx.x);
 }
 
 // backward up-sweep: w(l+1, i) = M(l, 2i)' w(l, 2i+1) + w(l, 2i)
-template <typename S, class E>
-__device__ __forceinline__ void bvec_up_body(Lds<E>& L, Plan p, S* ws, int lvl, int64_t tid) {
+template <typename S, class E, class LT>
+__device__ __forceinline__ void bvec_up_body(LT& L, Plan p, S* ws, int lvl, int64_t tid) {
     using T = typename E::T;
     const E e(threadIdx.x);
     const int n = p.n;
@@ -913,7 +920,7 @@ __device__ __forceinline__ void bvec_up_body(Lds<E>& L, Plan p, S* ws, int lvl, 
 
 template <typename S, class E>
 __global__ __launch_bounds__(E::NT) void k_bvec_up(Plan p, S* ws, int lvl) {
-    __shared__ Lds<E> L;
+    __shared__ VecLds<E> L;
     bvec_up_body<S, E>(L, p, ws, lvl, (int64_t)blockIdx.x);
 }
 
@@ -934,8 +941,8 @@ __global__ __launch_bounds__(64) void k_broot(Plan p, S* ws) {
 
 // backward down-sweep: pend = gradient right after the node's last stage.
 //   odd j (right child): pend(parent);  even j: M(l, j+1)' pend(parent) + w(l, j+1)
-template <typename S, class E>
-__device__ __forceinline__ void bvec_down_body(Lds<E>& L, Plan p, S* ws, int lvl, int64_t tid) {
+template <typename S, class E, class LT>
+__device__ __forceinline__ void bvec_down_body(LT& L, Plan p, S* ws, int lvl, int64_t tid) {
     using T = typename E::T;
     const E e(threadIdx.x);
     const int n = p.n;
@@ -958,14 +965,30 @@ __device__ __forceinline__ void bvec_down_body(Lds<E>& L, Plan p, S* ws, int lvl
 
 template <typename S, class E>
 __global__ __launch_bounds__(E::NT) void k_bvec_down(Plan p, S* ws, int lvl) {
-    __shared__ Lds<E> L;
+    __shared__ VecLds<E> L;
     bvec_down_body<S, E>(L, p, ws, lvl, (int64_t)blockIdx.x);
+}
+
+// v <- L^{-1} v (FWD) or L^{-T} v, L (m x m, lower, row-major) in global
+// memory, v a lane vector: the pivot comes from its lane by a cross-lane
+// read, every other lane updates its element (no LDS)
+template <bool FWD, class E, typename S>
+__device__ __forceinline__ typename E::T lane_trsv(const E& e, const S* Lm, int m, typename E::T v) {
+    using T = typename E::T;
+    for (int s = 0; s < m; ++s) {
+        const int k = FWD ? s : m - 1 - s;
+        const T yk = __shfl(v, k, 64) / T(Lm[k * m + k]);
+        if (e.lg == k) v = yk;
+        else if (FWD ? (e.lg > k && e.lg < m) : (e.lg < k))
+            v = fma_(-T(FWD ? Lm[e.lg * m + k] : Lm[k * m + e.lg]), yk, v);
+    }
+    return v;
 }
 
 // kff'_k = -G^{-1} h'_k,  h'_k = B'(p'_{k+1} + P_{k+1} c'_k) + r'_k;
 // p'_k = Abar' p'_{k+1} + d_k;  new forward leaf vector B kff' + c'.
-template <typename S, class E>
-__device__ __forceinline__ void ref_kff_body(Lds<E>& L, Plan p, In<S> in, S* ws, int64_t tid) {
+template <typename S, class E, class LT>
+__device__ __forceinline__ void ref_kff_body(LT& L, Plan p, In<S> in, S* ws, int64_t tid) {
     using T = typename E::T;
     const E e(threadIdx.x);
     const int N = p.N, n = p.n, m = p.m, nn = n * n;
@@ -985,15 +1008,11 @@ __device__ __forceinline__ void ref_kff_body(Lds<E>& L, Plan p, In<S> in, S* ws,
     const T v = pn + e.template gmv<false>(Pn, n, n, n, cpv, L.vb[0]);
     const T pk = e.template gmv<true>(leaf, n, n, n, pn, L.vb[1]) + e.vload(inst + p.o_w + (int64_t)k * n, n);
     e.vstore(inst + p.o_pp + (int64_t)k * n, n, pk);
-    stage(e, L.sA, inst + p.o_LG + (int64_t)k * m * m, m, m, m);
-    T h[1] = {e.template gmv<true>(P.B(b, k), n, m, m, v, L.vb[0]) + e.vload(inst + p.o_rp + (int64_t)k * m, m)};
-    wg_sync();
-    fill_dinv<E>(L.sA, L.dA, m);
-    wg_sync();
-    typename E::Tile none[1];
-    e.template trsm<true, 0, 1>(L.sA, L.dA, m, none, h, L.rb);
-    e.template trsm<false, 0, 1>(L.sA, L.dA, m, none, h, L.rb);
-    const T kf = -h[0];
+    T h = e.template gmv<true>(P.B(b, k), n, m, m, v, L.vb[0]) + e.vload(inst + p.o_rp + (int64_t)k * m, m);
+    const S* LG = inst + p.o_LG + (int64_t)k * m * m;
+    h = lane_trsv<true>(e, LG, m, h);                      // L_G^{-1} h
+    h = lane_trsv<false>(e, LG, m, h);                     // L_G^{-T} ...
+    const T kf = -h;
     e.vstore(inst + p.o_kffp + (int64_t)k * m, m, kf);
     const T bb = e.template gmv<false>(P.B(b, k), n, m, m, kf, L.vb[1]) + cpv;
     e.vstore(inst + p.o_ftree + (int64_t)k * p.frec + nn, n, bb);
@@ -1002,7 +1021,7 @@ __device__ __forceinline__ void ref_kff_body(Lds<E>& L, Plan p, In<S> in, S* ws,
 
 template <typename S, class E>
 __global__ __launch_bounds__(E::NT) void k_ref_kff(Plan p, In<S> in, S* ws) {
-    __shared__ Lds<E> L;
+    __shared__ VecLds<E> L;
     ref_kff_body<S, E>(L, p, in, ws, (int64_t)blockIdx.x);
 }
 
@@ -1019,8 +1038,8 @@ __global__ __launch_bounds__(E::NT) void k_ref_kff(Plan p, In<S> in, S* ws) {
 
 // forward scan of the closed-loop maps from x0 (UPV: recompute the vector
 // part of the up-sweep first) and u_k, lambda_k (ADD: added to the outputs)
-template <typename S, class E, bool UPV, bool ADD>
-__device__ __forceinline__ void fwd_inst_body(Lds<E>& L, const Plan& p, S* ws, const S* x0, int64_t x0_stride,
+template <typename S, class E, bool UPV, bool ADD, class LT>
+__device__ __forceinline__ void fwd_inst_body(LT& L, const Plan& p, S* ws, const S* x0, int64_t x0_stride,
                                               const Out<S>& out, int64_t b) {
     if (UPV) {
         for (int l = 0; l + 1 < p.ft.nlev; ++l) {
@@ -1046,7 +1065,7 @@ __device__ __forceinline__ void fwd_inst_body(Lds<E>& L, const Plan& p, S* ws, c
 
 template <typename S, class E>
 __global__ __launch_bounds__(E::NT) void k_fwd_inst(Plan p, S* ws, const S* x0, int64_t x0_stride, Out<S> out) {
-    __shared__ Lds<E> L;
+    __shared__ VecLds<E> L;
     const int64_t b = blockIdx.x;
     LQR_GATE(p, b);
     fwd_inst_body<S, E, false, false>(L, p, ws, x0, x0_stride, out, b);
@@ -1055,7 +1074,7 @@ __global__ __launch_bounds__(E::NT) void k_fwd_inst(Plan p, S* ws, const S* x0, 
 // one whole refinement sweep of one instance (after its residual pass)
 template <typename S, class E>
 __global__ __launch_bounds__(E::NT) void k_refine_inst(Plan p, In<S> in, S* ws, Out<S> out) {
-    __shared__ Lds<E> L;
+    __shared__ VecLds<E> L;
     const int64_t b = blockIdx.x;
     LQR_GATE(p, b);
     const int N = p.N;

@@ -248,8 +248,8 @@ __device__ void big_fup_task(BigLds<typename E::T>& L, const S* l, const S* r, S
 }
 
 // refinement, per stage: kff'_k = -G^{-1} h'_k with the stored L_G^{-1}
-template <typename S, class E>
-__device__ void big_ref_kff(BigLds<typename E::T>& L, const Plan& p, const In<S>& in, S* ws, int64_t b, int k) {
+template <typename S, class E, class LT>
+__device__ void big_ref_kff(LT& L, const Plan& p, const In<S>& in, S* ws, int64_t b, int k) {
     using T = typename E::T;
     const E e(threadIdx.x);
     const int n = p.n, m = p.m, nn = n * n;
