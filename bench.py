@@ -144,6 +144,9 @@ def measure(L, gen, batch, steps, warmup, eager, refine, plain, label):
     dev = {k: torch.from_numpy(v).to("cuda:0") for k, v in host.items()}
     del host
     torch.cuda.synchronize()
+    log(f"[bench] {label}: autotuning the mapping")
+    mapping = L.autotune(*[dev[k] for k in L.FIELDS], refine=refine, reps=2)
+    log(f"[bench] {label}: mapping {mapping}")
     log(f"[bench] {label}: FP32 scan, timed {'eager launches' if eager else 'graph replays'}")
     wall, lat, _, resid, bad = timed_steps(L, dev, "scan", steps, warmup, False, graph=not eager, refine=refine)
     log(f"[bench] {label}: FP32 scan, kernel timing pass (eager, HIP events around every launch)")
@@ -153,6 +156,7 @@ def measure(L, gen, batch, steps, warmup, eager, refine, plain, label):
          "max_rel_kkt_residual": resid, "instances_with_status": bad}
     steps_t = fams["clear"]["launches"] if "clear" in fams else 1
     r["kernel_ms_per_step"] = {f: v["ms"] / steps_t for f, v in fams.items()}
+    r["mapping"] = mapping
     if plain:
         log(f"[bench] {label}: FP64 plain Riccati, timed steps")
         dev64 = {k: v.double() for k, v in dev.items()}

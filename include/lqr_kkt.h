@@ -163,6 +163,45 @@ int lqr_timing_enable(lqr_handle_t h, int enable);
  * LQR_ENOMEM if buf is too small. */
 int lqr_timing_report(lqr_handle_t h, char* buf, size_t len);
 
+/* Mapping of a problem shape onto the GPU (for callers that want to pin it):
+ *   engine   0 = default rule, 1 = wavefront tiles (orders <= 64, one 64-lane
+ *            wavefront per task), 2 = matrix-core workgroups (one 256-thread
+ *            workgroup per task, products on MFMA)
+ *   fused    -1 = default (batch >= 128), 0 = level-by-level launches of the
+ *            vector-only passes, 1 = one workgroup per instance
+ *   big_grid 0 = default (512), else the workgroups / scratch slots of a
+ *            matrix-core task launch
+ *   ms       (lqr_autotune output) mean time of one solve with this mapping */
+typedef struct {
+    int32_t engine;
+    int32_t fused;
+    int32_t big_grid;
+    float ms;
+} lqr_tuning;
+
+/* Pin (t != NULL) or clear (t == NULL) the mapping of the shape
+ * (batch, N, n, m, dtype) on this handle; later lqr_workspace_size,
+ * lqr_kkt_solve and lqr_kkt_residual calls of that shape use it.
+ * LQR_EINVAL for an out-of-range field or engine 1 above order 64. */
+int lqr_set_tuning(lqr_handle_t h, int64_t batch, int N, int n, int m, int32_t dtype, const lqr_tuning* t);
+
+/* Autotuner: solves the given problem (same arguments as lqr_kkt_solve)
+ * once per candidate mapping -- each engine that can take the shape, both
+ * forms of the vector-only passes, matrix-core grids of 256 / 512 / 1024
+ * workgroups -- then `reps` more times on the stream, timed with HIP events;
+ * candidates whose status words are not clean (other than the FP64-fallback
+ * bit) or whose workspace does not fit are skipped.  The fastest mapping is
+ * stored on the handle for this shape (as lqr_set_tuning) and written to
+ * *best.  Synchronizes the stream; the outputs hold the last candidate's
+ * solution.  lqr_autotune_workspace_size gives a workspace that fits every
+ * candidate.  Returns LQR_ENOMEM if no candidate fits. */
+int lqr_autotune(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int m,
+                 const void* A, const void* B, const void* c, const void* Q, const void* R,
+                 const void* M, const void* q, const void* r, const void* x0, void* x, void* u,
+                 void* lam, int32_t* status, void* workspace, size_t workspace_bytes,
+                 const lqr_opts* opts, int reps, lqr_tuning* best);
+int lqr_autotune_workspace_size(int64_t batch, int N, int n, int m, const lqr_opts* opts, size_t* bytes);
+
 /* Largest n, m supported by the built shape classes (n, m <= this). */
 int lqr_max_dim(void);
 

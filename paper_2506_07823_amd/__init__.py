@@ -46,6 +46,11 @@ class lqr_opts(ctypes.Structure):
     ]
 
 
+class lqr_tuning(ctypes.Structure):
+    _fields_ = [("engine", ctypes.c_int32), ("fused", ctypes.c_int32), ("big_grid", ctypes.c_int32),
+                ("ms", ctypes.c_float)]
+
+
 class LqrError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"lqr error {code}: {msg}")
@@ -72,6 +77,15 @@ _lib.lqr_kkt_solve.restype = ctypes.c_int
 _lib.lqr_kkt_residual.argtypes = [_vp, _vp, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, _i32] + \
     [_vp] * 9 + [_vp] * 3 + [_vp, _vp, _sz]
 _lib.lqr_kkt_residual.restype = ctypes.c_int
+_lib.lqr_set_tuning.argtypes = [_vp, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, _i32,
+                                ctypes.POINTER(lqr_tuning)]
+_lib.lqr_set_tuning.restype = ctypes.c_int
+_lib.lqr_autotune.argtypes = [_vp, _vp, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int] + [_vp] * 9 + \
+    [_vp, _vp, _vp, _vp, _vp, _sz, ctypes.POINTER(lqr_opts), ctypes.c_int, ctypes.POINTER(lqr_tuning)]
+_lib.lqr_autotune.restype = ctypes.c_int
+_lib.lqr_autotune_workspace_size.argtypes = [_i64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                             ctypes.POINTER(lqr_opts), ctypes.POINTER(_sz)]
+_lib.lqr_autotune_workspace_size.restype = ctypes.c_int
 _lib.lqr_max_dim.argtypes = []
 _lib.lqr_max_dim.restype = ctypes.c_int
 _lib.lqr_last_error.argtypes = []
@@ -246,6 +260,51 @@ def kkt_residual(A, B, c, Q, R, M, q, r, x0, x, u, lam, *, workspace=None, strea
                                  *[d[k].data_ptr() for k in FIELDS + ("x", "u", "lam")],
                                  rel.data_ptr(), wbuf.data_ptr(), wbuf.numel()))
     return rel
+
+
+def autotune(A, B, c, Q, R, M, q, r, x0, *, method: str = "scan", refine: int | None = None, reps: int = 3,
+             stream=None) -> dict:
+    """Time every candidate mapping of this problem shape on these inputs
+    and pin the fastest on the device's handle (later solves of the same
+    shape use it).  Returns the chosen mapping and its mean solve time."""
+    d = dict(A=A, B=B, c=c, Q=Q, R=R, M=M, q=q, r=r, x0=x0)
+    dtype = A.dtype
+    device = A.device.index
+    batch, N, n, m = dims_of(A, B)
+    _validate(d, dtype, device)
+    _expect_shapes(d, batch, N, n, m)
+    o = default_opts(dtype)
+    o.method = LQR_METHOD_SCAN if method == "scan" else LQR_METHOD_SEQ_RICCATI
+    if refine is not None:
+        o.refine_sweeps = int(refine)
+    nbytes = _sz()
+    _check(_lib.lqr_autotune_workspace_size(batch, N, n, m, ctypes.byref(o), ctypes.byref(nbytes)))
+    ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=A.device)
+    out = [torch.empty((batch, N + 1, n), dtype=dtype, device=A.device),
+           torch.empty((batch, N, m), dtype=dtype, device=A.device),
+           torch.empty((batch, N + 1, n), dtype=dtype, device=A.device),
+           torch.empty((batch,), dtype=torch.int32, device=A.device)]
+    best = lqr_tuning()
+    s = (stream or torch.cuda.current_stream(device)).cuda_stream
+    _check(_lib.lqr_autotune(handle(device), s, batch, N, n, m, *[d[k].data_ptr() for k in FIELDS],
+                             *[t.data_ptr() for t in out], ws.data_ptr(), ws.numel(), ctypes.byref(o), int(reps),
+                             ctypes.byref(best)))
+    return {"engine": {1: "wavefront", 2: "matrix-core"}[best.engine], "fused": bool(best.fused),
+            "big_grid": int(best.big_grid), "ms": float(best.ms)}
+
+
+def set_tuning(batch: int, N: int, n: int, m: int, dtype=torch.float32, *, engine: str | None = None,
+               fused: bool | None = None, big_grid: int = 0, device: int = 0, clear: bool = False):
+    """Pin (or clear) the mapping of a problem shape on the device's handle."""
+    dt = LQR_F32 if dtype == torch.float32 else LQR_F64
+    if clear:
+        _check(_lib.lqr_set_tuning(handle(device), batch, N, n, m, dt, None))
+        return
+    t = lqr_tuning()
+    t.engine = {None: 0, "wavefront": 1, "matrix-core": 2}[engine]
+    t.fused = -1 if fused is None else int(bool(fused))
+    t.big_grid = int(big_grid)
+    _check(_lib.lqr_set_tuning(handle(device), batch, N, n, m, dt, ctypes.byref(t)))
 
 
 def kernel_timing(enable: bool, device: int = 0):

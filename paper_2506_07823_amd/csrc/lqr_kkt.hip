@@ -8,6 +8,8 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <map>
+#include <tuple>
 #include <vector>
 
 #include "../../include/lqr_kkt.h"
@@ -69,12 +71,25 @@ int pick_ts(int n, int m) {
         if (8 * ts >= d) return ts;
     return d <= kMaxDim ? kBigTS : 0;
 }
+
+// Mapping choices the autotuner may override (0 / -1: the default rule)
+struct Tuning {
+    int engine = 0;     // 1: wavefront tiles, 2: matrix-core workgroups
+    int fused = -1;     // per-instance vector passes: 0 / 1
+    int big_grid = 0;   // workgroups (scratch slots) of a matrix-core task launch
+};
+
+int pick_ts(int n, int m, const Tuning* t) {
+    const int ts = pick_ts(n, m);
+    if (t && t->engine == 2 && ts != 0) return kBigTS;
+    return ts;
+}
 // workgroups (= scratch slots) of a large-block task launch
 constexpr int kBigGrid = 512;
 
 int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
-Plan make_plan(int64_t batch, int N, int n, int m, size_t esize, const lqr_opts& o) {
+Plan make_plan(int64_t batch, int N, int n, int m, size_t esize, const lqr_opts& o, const Tuning* tun = nullptr) {
     Plan p;
     std::memset(&p, 0, sizeof p);
     p.batch = batch;
@@ -111,11 +126,13 @@ Plan make_plan(int64_t batch, int N, int n, int m, size_t esize, const lqr_opts&
     // level-parallel launches keep the O(log N) depth for small batches
     p.fused = batch >= 128 ? 1 : 0;
     p.fallback = esize == 4 ? o.fallback : 0;   // the FP64 path has nothing to fall back to
-    if (pick_ts(n, m) == kBigTS) {
+    if (tun && tun->fused >= 0) p.fused = tun->fused;
+    if (pick_ts(n, m, tun) == kBigTS) {
         const int64_t d = n > m ? n : m;
         p.scr_elems = align_up(8 * d * d + 64 * d, 64);
         const int64_t most = batch * (N + 1);
-        p.big_grid = (int)(most < kBigGrid ? most : kBigGrid);
+        const int64_t g = tun && tun->big_grid > 0 ? tun->big_grid : kBigGrid;
+        p.big_grid = (int)(most < g ? most : g);
     }
     return p;
 }
@@ -221,6 +238,12 @@ struct lqr_handle_s {
     int device;
     bool timing = false;
     EventTimer timer;
+    // mappings chosen by lqr_autotune / lqr_set_tuning, per (batch, N, n, m, dtype)
+    std::map<std::tuple<int64_t, int, int, int, int>, Tuning> tuned;
+    const Tuning* find(int64_t batch, int N, int n, int m, int dtype) const {
+        auto it = tuned.find(std::make_tuple(batch, N, n, m, dtype));
+        return it == tuned.end() ? nullptr : &it->second;
+    }
 };
 
 extern "C" {
@@ -259,24 +282,24 @@ const char* lqr_last_error(void) { return g_err.c_str(); }
 
 int lqr_workspace_size(lqr_handle_t h, int64_t batch, int N, int n, int m, const lqr_opts* opts,
                        size_t* bytes) {
-    (void)h;
     if (!bytes) return fail(LQR_EINVAL, "null output pointer");
     lqr_opts o;
     if (opts) o = *opts; else lqr_opts_default(&o, LQR_F32);
     LCHK(check_dims(batch, N, n, m));
     if (o.dtype != LQR_F32 && o.dtype != LQR_F64) return fail(LQR_EINVAL, "bad dtype %d", o.dtype);
     const size_t es = o.dtype == LQR_F32 ? 4 : 8;
-    *bytes = layout(make_plan(batch, N, n, m, es, o), es).total;
+    const Tuning* tun = h ? h->find(batch, N, n, m, o.dtype) : nullptr;
+    *bytes = layout(make_plan(batch, N, n, m, es, o, tun), es).total;
     return LQR_OK;
 }
 
-int lqr_kkt_solve(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int m, const void* A,
-                  const void* B, const void* c, const void* Q, const void* R, const void* M, const void* q,
-                  const void* r, const void* x0, void* x, void* u, void* lam, int32_t* status,
-                  void* workspace, size_t workspace_bytes, const lqr_opts* opts) {
-    if (!h) return fail(LQR_EINVAL, "null handle");
-    lqr_opts o;
-    if (opts) o = *opts; else lqr_opts_default(&o, LQR_F32);
+}  // extern "C"
+
+namespace {
+int solve_impl(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int m, const void* A, const void* B,
+               const void* c, const void* Q, const void* R, const void* M, const void* q, const void* r,
+               const void* x0, void* x, void* u, void* lam, int32_t* status, void* workspace,
+               size_t workspace_bytes, const lqr_opts& o, const Tuning* tun) {
     LCHK(check_dims(batch, N, n, m));
     if (o.dtype != LQR_F32 && o.dtype != LQR_F64) return fail(LQR_EINVAL, "bad dtype %d", o.dtype);
     if (o.method != LQR_METHOD_SCAN && o.method != LQR_METHOD_SEQ_RICCATI)
@@ -302,7 +325,7 @@ int lqr_kkt_solve(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int
         if (!aligned(o.warm_x, es) || !aligned(o.warm_u, es) || !aligned(o.warm_lam, es))
             return fail(LQR_EINVAL, "misaligned warm start");
     }
-    Plan p = make_plan(batch, N, n, m, es, o);
+    Plan p = make_plan(batch, N, n, m, es, o, tun);
     const Layout lay = layout(p, es);
     if (workspace_bytes < lay.total)
         return fail(LQR_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", workspace_bytes, lay.total);
@@ -312,7 +335,7 @@ int lqr_kkt_solve(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int
     char* wsb = (char*)workspace;
     int32_t* iws = (int32_t*)(wsb + lay.int_off);
     double* dws = (double*)(wsb + lay.dbl_off);
-    const int ts = pick_ts(n, m);
+    const int ts = pick_ts(n, m, tun);
     const int refine = o.method == LQR_METHOD_SCAN ? o.refine_sweeps : 0;
     TimerScope ts_scope(h->timing ? &h->timer : nullptr);
     if (o.dtype == LQR_F32) {
@@ -328,6 +351,139 @@ int lqr_kkt_solve(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int
     const Warm<double> warm{(const double*)o.warm_x, (const double*)o.warm_u, (const double*)o.warm_lam};
     return dispatch<double>(ts, o.method, p, s, in, out, (double*)wsb, iws, dws, refine, o.resid_out, warm);
 }
+}  // namespace
+
+extern "C" {
+
+int lqr_kkt_solve(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int m, const void* A,
+                  const void* B, const void* c, const void* Q, const void* R, const void* M, const void* q,
+                  const void* r, const void* x0, void* x, void* u, void* lam, int32_t* status,
+                  void* workspace, size_t workspace_bytes, const lqr_opts* opts) {
+    if (!h) return fail(LQR_EINVAL, "null handle");
+    lqr_opts o;
+    if (opts) o = *opts; else lqr_opts_default(&o, LQR_F32);
+    return solve_impl(h, stream, batch, N, n, m, A, B, c, Q, R, M, q, r, x0, x, u, lam, status, workspace,
+                      workspace_bytes, o, h->find(batch, N, n, m, o.dtype));
+}
+
+int lqr_set_tuning(lqr_handle_t h, int64_t batch, int N, int n, int m, int32_t dtype, const lqr_tuning* t) {
+    if (!h) return fail(LQR_EINVAL, "null handle");
+    LCHK(check_dims(batch, N, n, m));
+    const auto key = std::make_tuple(batch, N, n, m, (int)dtype);
+    if (!t) {
+        h->tuned.erase(key);
+        return LQR_OK;
+    }
+    if (t->engine < 0 || t->engine > 2 || t->fused < -1 || t->fused > 1 || t->big_grid < 0)
+        return fail(LQR_EINVAL, "bad tuning (engine %d, fused %d, big_grid %d)", t->engine, t->fused, t->big_grid);
+    if (t->engine == 1 && pick_ts(n, m) == kBigTS)
+        return fail(LQR_EINVAL, "the wavefront engine takes orders up to 64 (n=%d m=%d)", n, m);
+    Tuning tu;
+    tu.engine = t->engine;
+    tu.fused = t->fused;
+    tu.big_grid = t->big_grid;
+    h->tuned[key] = tu;
+    return LQR_OK;
+}
+
+int lqr_autotune(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int m, const void* A, const void* B,
+                 const void* c, const void* Q, const void* R, const void* M, const void* q, const void* r,
+                 const void* x0, void* x, void* u, void* lam, int32_t* status, void* workspace,
+                 size_t workspace_bytes, const lqr_opts* opts, int reps, lqr_tuning* best) {
+    if (!h || !best) return fail(LQR_EINVAL, "null handle or result");
+    if (reps < 1 || reps > 100) return fail(LQR_EINVAL, "reps must be in 1..100");
+    lqr_opts o;
+    if (opts) o = *opts; else lqr_opts_default(&o, LQR_F32);
+    LCHK(check_dims(batch, N, n, m));
+    if (o.dtype != LQR_F32 && o.dtype != LQR_F64) return fail(LQR_EINVAL, "bad dtype %d", o.dtype);
+    const size_t es = o.dtype == LQR_F32 ? 4 : 8;
+    // candidate mappings: engine x vector-pass form x matrix-core grid
+    std::vector<Tuning> cands;
+    const bool small_ok = pick_ts(n, m) != kBigTS;
+    for (int eng : {1, 2}) {
+        if (eng == 1 && !small_ok) continue;
+        for (int fu : {0, 1}) {
+            if (eng == 1) {
+                Tuning t; t.engine = 1; t.fused = fu; cands.push_back(t);
+            } else {
+                for (int g : {256, 512, 1024}) {
+                    Tuning t; t.engine = 2; t.fused = fu; t.big_grid = g; cands.push_back(t);
+                }
+            }
+        }
+    }
+    HIPCHK(hipSetDevice(h->device));
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    std::vector<int32_t> st((size_t)batch);
+    float best_ms = -1.0f;
+    Tuning best_t;
+    int rc = LQR_OK;
+    for (const Tuning& t : cands) {
+        if (layout(make_plan(batch, N, n, m, es, o, &t), es).total > workspace_bytes) continue;
+        auto run = [&]() {
+            return solve_impl(h, stream, batch, N, n, m, A, B, c, Q, R, M, q, r, x0, x, u, lam, status, workspace,
+                              workspace_bytes, o, &t);
+        };
+        if ((rc = run()) != LQR_OK) break;   // warm-up (and the status check below)
+        if (hipMemcpyAsync(st.data(), status, sizeof(int32_t) * (size_t)batch, hipMemcpyDeviceToHost, s) !=
+                hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+            rc = fail(LQR_EDEVICE, "reading the status words failed");
+            break;
+        }
+        bool clean = true;
+        for (int32_t v : st) clean = clean && (v & ~LQR_ST_FP64_FALLBACK) == 0;
+        if (!clean) continue;
+        (void)hipEventRecord(e0, s);
+        for (int i = 0; i < reps && rc == LQR_OK; ++i) rc = run();
+        if (rc != LQR_OK) break;
+        (void)hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) {
+            rc = fail(LQR_EDEVICE, "timing event failed");
+            break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        ms /= (float)reps;
+        if (best_ms < 0.f || ms < best_ms) {
+            best_ms = ms;
+            best_t = t;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != LQR_OK) return rc;
+    if (best_ms < 0.f) return fail(LQR_ENOMEM, "no candidate mapping fits the workspace with a clean status");
+    h->tuned[std::make_tuple(batch, N, n, m, (int)o.dtype)] = best_t;
+    best->engine = best_t.engine;
+    best->fused = best_t.fused;
+    best->big_grid = best_t.big_grid;
+    best->ms = best_ms;
+    return LQR_OK;
+}
+
+int lqr_autotune_workspace_size(int64_t batch, int N, int n, int m, const lqr_opts* opts, size_t* bytes) {
+    if (!bytes) return fail(LQR_EINVAL, "null output pointer");
+    lqr_opts o;
+    if (opts) o = *opts; else lqr_opts_default(&o, LQR_F32);
+    LCHK(check_dims(batch, N, n, m));
+    if (o.dtype != LQR_F32 && o.dtype != LQR_F64) return fail(LQR_EINVAL, "bad dtype %d", o.dtype);
+    const size_t es = o.dtype == LQR_F32 ? 4 : 8;
+    Tuning t;
+    t.engine = 2;
+    t.big_grid = 1024;
+    size_t need = layout(make_plan(batch, N, n, m, es, o, &t), es).total;
+    if (pick_ts(n, m) != kBigTS) {
+        Tuning w;
+        w.engine = 1;
+        const size_t nw = layout(make_plan(batch, N, n, m, es, o, &w), es).total;
+        need = nw > need ? nw : need;
+    }
+    *bytes = need;
+    return LQR_OK;
+}
 
 int lqr_kkt_residual(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int m, int32_t dtype,
                      const void* A, const void* B, const void* c, const void* Q, const void* R, const void* M,
@@ -342,7 +498,8 @@ int lqr_kkt_residual(lqr_handle_t h, void* stream, int64_t batch, int N, int n, 
     lqr_opts o;
     lqr_opts_default(&o, dtype);
     const size_t es = dtype == LQR_F32 ? 4 : 8;
-    Plan p = make_plan(batch, N, n, m, es, o);
+    const Tuning* tun = h->find(batch, N, n, m, dtype);
+    Plan p = make_plan(batch, N, n, m, es, o, tun);
     const Layout lay = layout(p, es);
     if (workspace_bytes < lay.total)
         return fail(LQR_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", workspace_bytes, lay.total);
@@ -351,7 +508,7 @@ int lqr_kkt_residual(lqr_handle_t h, void* stream, int64_t batch, int N, int n, 
     hipStream_t s = (hipStream_t)stream;
     char* wsb = (char*)workspace;
     double* dws = (double*)(wsb + lay.dbl_off);
-    const int ts = pick_ts(n, m);
+    const int ts = pick_ts(n, m, tun);
     TimerScope ts_scope(h->timing ? &h->timer : nullptr);
     if (dtype == LQR_F32) {
         In<float> in{(const float*)A, (const float*)B, (const float*)c, (const float*)Q, (const float*)R,
