@@ -45,7 +45,7 @@ MR_BATCH = 64
 # HBM bytes per launch of the whole-body k_up from rocprofv3 FETCH_SIZE /
 # WRITE_SIZE runs, calibrated against a copy of known size; valid only for
 # the kernel sources they were taken on (hash of engine.hpp + kernels.hpp)
-KUP_TRAFFIC = {"src_hash": "1971c93e2830e294", "bytes_per_launch": 2.911e9,
+KUP_TRAFFIC = {"src_hash": "0d1a30a8e0c38fd2", "bytes_per_launch": 2.907e+09,
                "note": "FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (copy calibration), per launch"}
 
 
@@ -133,7 +133,7 @@ def roofline_of(fams, bound, peak, unit):
             "launches": d["launches"], "algorithmic_GBps": d["bytes"] / (d["ms"] * 1e-3) / 1e9}
 
 
-def measure(L, gen, batch, steps, warmup, eager, refine, plain, label):
+def measure(L, gen, batch, steps, warmup, eager, refine, plain, label, tune=True):
     """Timed FP32 scan (graph replays) + kernel-timing pass + optional FP64
     plain comparison on one workload; returns the numbers and the timing
     families of the scan."""
@@ -144,9 +144,11 @@ def measure(L, gen, batch, steps, warmup, eager, refine, plain, label):
     dev = {k: torch.from_numpy(v).to("cuda:0") for k, v in host.items()}
     del host
     torch.cuda.synchronize()
-    log(f"[bench] {label}: autotuning the mapping")
-    mapping = L.autotune(*[dev[k] for k in L.FIELDS], refine=refine, reps=2)
-    log(f"[bench] {label}: mapping {mapping}")
+    mapping = "default"
+    if tune:
+        log(f"[bench] {label}: autotuning the mapping")
+        mapping = L.autotune(*[dev[k] for k in L.FIELDS], refine=refine, reps=2)
+        log(f"[bench] {label}: mapping {mapping}")
     log(f"[bench] {label}: FP32 scan, timed {'eager launches' if eager else 'graph replays'}")
     wall, lat, _, resid, bad = timed_steps(L, dev, "scan", steps, warmup, False, graph=not eager, refine=refine)
     log(f"[bench] {label}: FP32 scan, kernel timing pass (eager, HIP events around every launch)")
@@ -250,6 +252,7 @@ def main():
     ap.add_argument("--no-multi-robot", action="store_true", help="skip the n=m=192 multi-robot workload")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-mix workload")
     ap.add_argument("--serving-requests", type=int, default=1600)
+    ap.add_argument("--no-tune", action="store_true", help="use the default mapping instead of autotuning it")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of graph replays")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (calibrates the HBM byte "
@@ -273,7 +276,8 @@ def main():
     import paper_2506_07823_amd as L
     import synth
 
-    wb, fams = measure(L, synth.gen_c3, BATCH, a.steps, a.warmup, a.eager, 2, not a.no_plain, "whole-body")
+    wb, fams = measure(L, synth.gen_c3, BATCH, a.steps, a.warmup, a.eager, 2, not a.no_plain, "whole-body",
+                       tune=not a.no_tune)
     result = {
         "metric": METRIC, "value": wb.pop("value"), "unit": "solves/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": wb.pop("ms_per_step"), "higher_is_better": True,
@@ -293,7 +297,7 @@ def main():
     result["roofline"] = rf
     if not a.no_multi_robot:
         mr, mfams = measure(L, synth.gen_c4, MR_BATCH, max(5, a.steps // 3), 1, a.eager, 2, not a.no_plain,
-                            "multi-robot")
+                            "multi-robot", tune=not a.no_tune)
         mr["config"] = {"workload": "centralized multi-robot LQR-KKT, n=m=192 N=50, batch 64, FP32 scan on "
                                     "matrix cores + FP64-residual refinement", "batch": MR_BATCH, "N": 50,
                         "n": 192, "m": 192}
