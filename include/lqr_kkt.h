@@ -202,6 +202,31 @@ int lqr_autotune(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int 
                  const lqr_opts* opts, int reps, lqr_tuning* best);
 int lqr_autotune_workspace_size(int64_t batch, int N, int n, int m, const lqr_opts* opts, size_t* bytes);
 
+/* One problem of a ragged batch: its sizes and the device arrays of one
+ * instance in the layout above (without the batch axis). */
+typedef struct {
+    int32_t N, n, m, reserved;
+    const void *A, *B, *c, *Q, *R, *M, *q, *r, *x0;   /* inputs */
+    void *x, *u, *lam;                                /* outputs */
+} lqr_problem;
+
+/* Ragged batch: `count` independent problems of mixed (N, n, m) in one call
+ * (the equality-constrained LQ subproblem of Sec. II-B for each).  The
+ * host-side descriptor table `probs` is read during the call only.  Problems
+ * of one shape are gathered into a contiguous batch in the workspace
+ * (packing kernels), solved together exactly as lqr_kkt_solve solves a
+ * batch (so each result equals that of solving the problem alone), and
+ * scattered back; shapes run one after another on `stream`.  status
+ * (device [count]) and opts->resid_out (optional device [count]) are in
+ * descriptor order.  Warm starts are not accepted here.  The workspace must
+ * hold lqr_ragged_workspace_size bytes (the largest shape group's packed
+ * arrays and solve workspace).  Errors as lqr_kkt_solve; a bad descriptor
+ * makes the call return LQR_EINVAL before any launch. */
+int lqr_ragged_workspace_size(lqr_handle_t h, int64_t count, const lqr_problem* probs, const lqr_opts* opts,
+                              size_t* bytes);
+int lqr_kkt_solve_ragged(lqr_handle_t h, void* stream, int64_t count, const lqr_problem* probs,
+                         int32_t* status, void* workspace, size_t workspace_bytes, const lqr_opts* opts);
+
 /* Largest n, m supported by the built shape classes (n, m <= this). */
 int lqr_max_dim(void);
 

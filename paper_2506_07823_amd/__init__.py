@@ -51,6 +51,11 @@ class lqr_tuning(ctypes.Structure):
                 ("ms", ctypes.c_float)]
 
 
+class lqr_problem(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("n", ctypes.c_int32), ("m", ctypes.c_int32), ("reserved", ctypes.c_int32)] + \
+        [(f, ctypes.c_void_p) for f in ("A", "B", "c", "Q", "R", "M", "q", "r", "x0", "x", "u", "lam")]
+
+
 class LqrError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"lqr error {code}: {msg}")
@@ -86,6 +91,12 @@ _lib.lqr_autotune.restype = ctypes.c_int
 _lib.lqr_autotune_workspace_size.argtypes = [_i64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                              ctypes.POINTER(lqr_opts), ctypes.POINTER(_sz)]
 _lib.lqr_autotune_workspace_size.restype = ctypes.c_int
+_lib.lqr_ragged_workspace_size.argtypes = [_vp, _i64, ctypes.POINTER(lqr_problem), ctypes.POINTER(lqr_opts),
+                                           ctypes.POINTER(_sz)]
+_lib.lqr_ragged_workspace_size.restype = ctypes.c_int
+_lib.lqr_kkt_solve_ragged.argtypes = [_vp, _vp, _i64, ctypes.POINTER(lqr_problem), _vp, _vp, _sz,
+                                      ctypes.POINTER(lqr_opts)]
+_lib.lqr_kkt_solve_ragged.restype = ctypes.c_int
 _lib.lqr_max_dim.argtypes = []
 _lib.lqr_max_dim.restype = ctypes.c_int
 _lib.lqr_last_error.argtypes = []
@@ -238,6 +249,51 @@ def solve(A, B, c, Q, R, M, q, r, x0, *, method: str = "scan", refine: int | Non
                             out["status"].data_ptr(), wbuf.data_ptr(), wbuf.numel(), ctypes.byref(o))
     _check(rc)
     return out
+
+
+def solve_ragged(problems, *, refine: int | None = None, want_resid: bool = False,
+                 workspace: Workspace | None = None, stream=None):
+    """Ragged batch: a list of problems of mixed (N, n, m), each a dict of
+    single-instance device tensors A..x0 (no batch axis), solved in one call.
+    Returns (list of dicts x, u, lam; status tensor [count]; residual tensor
+    [count] or None), in the order of `problems`."""
+    count = len(problems)
+    first = problems[0]["A"]
+    dtype, device = first.dtype, first.device.index
+    table = (lqr_problem * count)()
+    outs = []
+    for i, pr in enumerate(problems):
+        _validate(pr, dtype, device)
+        N, n, _ = pr["A"].shape
+        m = pr["B"].shape[-1]
+        o = {"x": torch.empty((N + 1, n), dtype=dtype, device=first.device),
+             "u": torch.empty((N, m), dtype=dtype, device=first.device),
+             "lam": torch.empty((N + 1, n), dtype=dtype, device=first.device)}
+        _expect_shapes({k: v.unsqueeze(0) for k, v in pr.items()}, 1, N, n, m)
+        outs.append(o)
+        t = table[i]
+        t.N, t.n, t.m = N, n, m
+        for f in FIELDS:
+            setattr(t, f, pr[f].data_ptr())
+        t.x, t.u, t.lam = o["x"].data_ptr(), o["u"].data_ptr(), o["lam"].data_ptr()
+    op = default_opts(dtype)
+    if refine is not None:
+        op.refine_sweeps = int(refine)
+    status = torch.empty((count,), dtype=torch.int32, device=first.device)
+    resid = None
+    if want_resid:
+        resid = torch.empty((count,), dtype=torch.float64, device=first.device)
+        op.resid_out = resid.data_ptr()
+    h = handle(device)
+    nbytes = _sz()
+    _check(_lib.lqr_ragged_workspace_size(h, count, table, ctypes.byref(op), ctypes.byref(nbytes)))
+    if workspace is None:
+        workspace = _default_ws.setdefault(device, Workspace(device))
+    wbuf = workspace.get(nbytes.value)
+    s = (stream or torch.cuda.current_stream(device)).cuda_stream
+    _check(_lib.lqr_kkt_solve_ragged(h, s, count, table, status.data_ptr(), wbuf.data_ptr(), wbuf.numel(),
+                                     ctypes.byref(op)))
+    return outs, status, resid
 
 
 def kkt_residual(A, B, c, Q, R, M, q, r, x0, x, u, lam, *, workspace=None, stream=None):

@@ -6,6 +6,7 @@
 
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <map>
@@ -13,6 +14,7 @@
 #include <vector>
 
 #include "../../include/lqr_kkt.h"
+#include "pack.hpp"
 #include "runs.hpp"
 
 using namespace lqr;
@@ -199,7 +201,8 @@ namespace {
 const char* const kFamNames[F_COUNT] = {
     "clear", "element", "element_fp64", "up", "root", "down", "policy", "policy_fp64", "fwd_up", "fwd_root",
     "fwd_down", "recover", "residual", "ref_d", "bwd_up", "bwd_root", "bwd_down", "ref_kff", "fwd_up_vec",
-    "recover_add", "reduce", "plain_riccati", "up_fp64", "down_fp64", "fwd_inst", "refine_inst", "warm_copy"};
+    "recover_add", "reduce", "plain_riccati", "up_fp64", "down_fp64", "fwd_inst", "refine_inst", "warm_copy",
+    "ragged_pack"};
 
 // Per-handle launch timer: two HIP events around every launch, read back by
 // lqr_timing_report.
@@ -364,6 +367,199 @@ int lqr_kkt_solve(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int
     if (opts) o = *opts; else lqr_opts_default(&o, LQR_F32);
     return solve_impl(h, stream, batch, N, n, m, A, B, c, Q, R, M, q, r, x0, x, u, lam, status, workspace,
                       workspace_bytes, o, h->find(batch, N, n, m, o.dtype));
+}
+
+}  // extern "C"
+
+namespace {
+// element counts of one instance's arrays, in ABI field order
+void field_elems(int N, int n, int m, int64_t (&in)[9], int64_t (&out)[3]) {
+    const int64_t nn = (int64_t)n * n;
+    in[0] = N * nn;                  // A
+    in[1] = (int64_t)N * n * m;      // B
+    in[2] = (int64_t)N * n;          // c
+    in[3] = (int64_t)(N + 1) * nn;   // Q
+    in[4] = (int64_t)N * m * m;      // R
+    in[5] = (int64_t)N * n * m;      // M
+    in[6] = (int64_t)(N + 1) * n;    // q
+    in[7] = (int64_t)N * m;          // r
+    in[8] = n;                       // x0
+    out[0] = (int64_t)(N + 1) * n;   // x
+    out[1] = (int64_t)N * m;         // u
+    out[2] = (int64_t)(N + 1) * n;   // lam
+}
+
+struct RaggedGroup {
+    int N, n, m;
+    std::vector<int> ids;
+};
+
+int ragged_groups(int64_t count, const lqr_problem* probs, size_t es, std::vector<RaggedGroup>& groups) {
+    if (count < 1) return fail(LQR_EINVAL, "count must be >= 1");
+    if (!probs) return fail(LQR_EINVAL, "null problem table");
+    std::map<std::tuple<int, int, int>, size_t> where;
+    for (int64_t i = 0; i < count; ++i) {
+        const lqr_problem& p = probs[i];
+        LCHK(check_dims(1, p.N, p.n, p.m));
+        const void* ptrs[] = {p.A, p.B, p.c, p.Q, p.R, p.M, p.q, p.r, p.x0, p.x, p.u, p.lam};
+        for (const void* q : ptrs) {
+            if (!q) return fail(LQR_EINVAL, "problem %lld has a null array", (long long)i);
+            if (!aligned(q, es)) return fail(LQR_EINVAL, "problem %lld has a misaligned array", (long long)i);
+        }
+        const auto key = std::make_tuple(p.N, p.n, p.m);
+        auto it = where.find(key);
+        if (it == where.end()) {
+            where[key] = groups.size();
+            groups.push_back(RaggedGroup{p.N, p.n, p.m, {}});
+            it = where.find(key);
+        }
+        groups[it->second].ids.push_back((int)i);
+    }
+    return LQR_OK;
+}
+
+// bytes of one group's packed arrays + its solve workspace
+struct GroupBytes {
+    size_t in, out, st, rel, solve, total;
+};
+GroupBytes group_bytes(const lqr_handle_s* h, const RaggedGroup& g, size_t es, const lqr_opts& o) {
+    int64_t ie[9], oe[3];
+    field_elems(g.N, g.n, g.m, ie, oe);
+    int64_t in = 0, out = 0;
+    for (int64_t v : ie) in += v;
+    for (int64_t v : oe) out += v;
+    const int64_t k = (int64_t)g.ids.size();
+    GroupBytes b;
+    b.in = (size_t)align_up(k * in * (int64_t)es, 256);
+    b.out = (size_t)align_up(k * out * (int64_t)es, 256);
+    b.st = (size_t)align_up(k * 4, 256);
+    b.rel = (size_t)align_up(k * 8, 256);
+    const Tuning* tun = h ? h->find(k, g.N, g.n, g.m, o.dtype) : nullptr;
+    b.solve = layout(make_plan(k, g.N, g.n, g.m, es, o, tun), es).total;
+    b.total = b.in + b.out + b.st + b.rel + b.solve;
+    return b;
+}
+
+int pack_launch(hipStream_t s, bool gather, const std::vector<void*>& ptrs, const std::vector<int>& ids,
+                char* packed, int64_t elems, size_t es) {
+    const int64_t words = elems * (int64_t)es / 4;
+    for (size_t c0 = 0; c0 < ptrs.size(); c0 += kPackTable) {
+        PackTable t;
+        std::memset(&t, 0, sizeof t);
+        t.count = (int)std::min<size_t>(kPackTable, ptrs.size() - c0);
+        for (int j = 0; j < t.count; ++j) {
+            t.p[j] = ptrs[c0 + j];
+            t.idx[j] = ids[c0 + j];
+        }
+        const int64_t gx = std::min<int64_t>((words + 255) / 256, 64);
+        uint32_t* pk = reinterpret_cast<uint32_t*>(packed + c0 * elems * es);
+        Timer* tm = current_timer();
+        if (tm) tm->before(s, F_PACK, 0, 2.0 * words * 4 * t.count);
+        if (gather)
+            hipLaunchKernelGGL(k_pack<true>, dim3((unsigned)gx, (unsigned)t.count), dim3(256), 0, s, t, pk, words);
+        else
+            hipLaunchKernelGGL(k_pack<false>, dim3((unsigned)gx, (unsigned)t.count), dim3(256), 0, s, t, pk, words);
+        if (tm) tm->after(s);
+        HIPCHK(hipGetLastError());
+    }
+    return LQR_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int lqr_ragged_workspace_size(lqr_handle_t h, int64_t count, const lqr_problem* probs, const lqr_opts* opts,
+                              size_t* bytes) {
+    if (!bytes) return fail(LQR_EINVAL, "null output pointer");
+    lqr_opts o;
+    if (opts) o = *opts; else lqr_opts_default(&o, LQR_F32);
+    if (o.dtype != LQR_F32 && o.dtype != LQR_F64) return fail(LQR_EINVAL, "bad dtype %d", o.dtype);
+    const size_t es = o.dtype == LQR_F32 ? 4 : 8;
+    std::vector<RaggedGroup> groups;
+    LCHK(ragged_groups(count, probs, es, groups));
+    size_t most = 0;
+    for (const auto& g : groups) most = std::max(most, group_bytes(h, g, es, o).total);
+    *bytes = most;
+    return LQR_OK;
+}
+
+int lqr_kkt_solve_ragged(lqr_handle_t h, void* stream, int64_t count, const lqr_problem* probs, int32_t* status,
+                         void* workspace, size_t workspace_bytes, const lqr_opts* opts) {
+    if (!h) return fail(LQR_EINVAL, "null handle");
+    lqr_opts o;
+    if (opts) o = *opts; else lqr_opts_default(&o, LQR_F32);
+    if (o.dtype != LQR_F32 && o.dtype != LQR_F64) return fail(LQR_EINVAL, "bad dtype %d", o.dtype);
+    if (o.warm_x || o.warm_u || o.warm_lam) return fail(LQR_EINVAL, "warm starts are per batch, not per ragged call");
+    if (!status || !workspace) return fail(LQR_EINVAL, "null status or workspace");
+    if (!aligned(status, 4) || !aligned(workspace, 256)) return fail(LQR_EINVAL, "misaligned status or workspace");
+    if (count > 0x7fffffff) return fail(LQR_EINVAL, "count too large");
+    const size_t es = o.dtype == LQR_F32 ? 4 : 8;
+    std::vector<RaggedGroup> groups;
+    LCHK(ragged_groups(count, probs, es, groups));
+    for (const auto& g : groups)
+        if (group_bytes(h, g, es, o).total > workspace_bytes)
+            return fail(LQR_ENOMEM, "workspace of %zu bytes is smaller than the %zu a group needs", workspace_bytes,
+                        group_bytes(h, g, es, o).total);
+    HIPCHK(hipSetDevice(h->device));
+    hipStream_t s = (hipStream_t)stream;
+    double* rel_out = o.resid_out;
+    TimerScope ts_scope(h->timing ? &h->timer : nullptr);
+    for (const auto& g : groups) {
+        const GroupBytes gb = group_bytes(h, g, es, o);
+        const int64_t k = (int64_t)g.ids.size();
+        char* base = static_cast<char*>(workspace);
+        char* pin = base;
+        char* pout = pin + gb.in;
+        int32_t* pst = reinterpret_cast<int32_t*>(pout + gb.out);
+        double* prel = reinterpret_cast<double*>(reinterpret_cast<char*>(pst) + gb.st);
+        char* pws = reinterpret_cast<char*>(prel) + gb.rel;
+        int64_t ie[9], oe[3];
+        field_elems(g.N, g.n, g.m, ie, oe);
+        // gather the inputs field by field into batch-major arrays
+        const void* fin[9];
+        char* cur = pin;
+        for (int f = 0; f < 9; ++f) {
+            std::vector<void*> ptrs;
+            for (int id : g.ids) {
+                const lqr_problem& p = probs[id];
+                const void* a[] = {p.A, p.B, p.c, p.Q, p.R, p.M, p.q, p.r, p.x0};
+                ptrs.push_back(const_cast<void*>(a[f]));
+            }
+            LCHK(pack_launch(s, true, ptrs, g.ids, cur, ie[f], es));
+            fin[f] = cur;
+            cur += k * ie[f] * (int64_t)es;
+        }
+        void* fout[3];
+        cur = pout;
+        for (int f = 0; f < 3; ++f) {
+            fout[f] = cur;
+            cur += k * oe[f] * (int64_t)es;
+        }
+        lqr_opts og = o;
+        og.resid_out = rel_out ? prel : nullptr;
+        LCHK(solve_impl(h, stream, k, g.N, g.n, g.m, fin[0], fin[1], fin[2], fin[3], fin[4], fin[5], fin[6],
+                        fin[7], fin[8], fout[0], fout[1], fout[2], pst, pws, gb.solve, og,
+                        h->find(k, g.N, g.n, g.m, o.dtype)));
+        // scatter the solutions and the status words back
+        for (int f = 0; f < 3; ++f) {
+            std::vector<void*> ptrs;
+            for (int id : g.ids) {
+                const lqr_problem& p = probs[id];
+                void* a[] = {p.x, p.u, p.lam};
+                ptrs.push_back(a[f]);
+            }
+            LCHK(pack_launch(s, false, ptrs, g.ids, static_cast<char*>(fout[f]), oe[f], es));
+        }
+        for (size_t c0 = 0; c0 < g.ids.size(); c0 += kPackTable) {
+            PackTable t;
+            std::memset(&t, 0, sizeof t);
+            t.count = (int)std::min<size_t>(kPackTable, g.ids.size() - c0);
+            for (int j = 0; j < t.count; ++j) t.idx[j] = g.ids[c0 + j];
+            hipLaunchKernelGGL(k_unpack_status<double>, dim3(1), dim3(64), 0, s, t, pst + c0, prel + c0, status, rel_out);
+            HIPCHK(hipGetLastError());
+        }
+    }
+    return LQR_OK;
 }
 
 int lqr_set_tuning(lqr_handle_t h, int64_t batch, int N, int n, int m, int32_t dtype, const lqr_tuning* t) {
