@@ -318,7 +318,7 @@ struct BigEng {
     // L^{-1}, lower triangular with zeros above.  `tmp` holds 32 x n elements.
     // Returns (uniformly) whether every pivot was positive and finite, and
     // the extreme diagonal entries of L for the condition estimate.
-    __device__ __attribute__((noinline)) bool potrf_inv(BigLds<T>& L, T* a, T* li, T* tmp, int n, T& dmin,
+    __device__ __forceinline__ bool potrf_inv(BigLds<T>& L, T* a, T* li, T* tmp, int n, T& dmin,
                                                         T& dmax) const {
         const int t = lg;
         bool ok = true;
