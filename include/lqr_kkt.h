@@ -88,15 +88,14 @@ typedef struct lqr_handle_s* lqr_handle_t;
 typedef struct {
     int32_t dtype;          /* lqr_dtype of every array */
     int32_t method;         /* lqr_method */
-    int32_t refine_sweeps;  /* iterative-refinement sweeps (scan method): each computes the FP64 KKT
-                               residual and re-solves the correction system with the factors of the
-                               first solve.  0..4: the first sweep runs for every instance, each
-                               further one only for instances whose relative residual is still
-                               above refine_tol.
-                               Default: 1 for LQR_F32, 0 for LQR_F64. */
+    int32_t refine_sweeps;  /* iterative-refinement sweeps (scan method), 0..4: each computes the
+                               FP64 KKT residual and, for the instances whose relative residual is
+                               above refine_tol, re-solves the correction system with the factors
+                               of the first solve (instances already within the tolerance are left
+                               as they are).  Default: 1 for LQR_F32, 0 for LQR_F64. */
     int32_t fallback;       /* 1 (default): redo ill-conditioned R_k / G_k factorizations in FP64 */
     double cond_threshold;  /* condition estimate above which the FP64 fallback fires (default 1e6) */
-    double refine_tol;      /* relative KKT residual below which further sweeps are skipped (1e-5) */
+    double refine_tol;      /* relative KKT residual at or below which an instance is not refined (1e-5) */
     double* resid_out;      /* optional device [batch] FP64: relative KKT residual of the returned
                                solution, ||r(x,u,lam)||_2 / ||(x0, c, q, r)||_2; NULL to skip */
     /* optional warm start (scan method; all three or none): device arrays in the layout and dtype

@@ -245,24 +245,23 @@ int run_scan(const Plan& p, hipStream_t s, const In<S>& in, const Out<S>& out, S
     const double ref_f = B * N * 7 * w.vec_f() + 2 * fwd_nodes * w.vec_f() * 2 + B * (N + 1) * w.rec_f();
     const double ref_b = B * N * 7 * w.vec_b() + 2 * fwd_nodes * w.vec_b() * 2 + B * (N + 1) * w.rec_b();
     for (int sw = 0; sw < refine; ++sw) {
-        // sweep 0 and the first decision run over every instance; later
-        // decisions only revisit the instances still active
-        const Plan& pr = sw >= 2 ? pg : p;
+        // every sweep runs only for the instances whose residual is above
+        // the tolerance: the first decision covers every instance, later
+        // ones revisit the instances the previous sweep corrected
+        const Plan& pr = sw >= 1 ? pg : p;
         if (p.fused) {
             LCHK(launch_nt(NT, F_RESID, B * (N + 1) * w.resid_f(), B * (N + 1) * w.resid_b(), k_resid_inst<S, E64, true>,
-                        Bi, s, pr, in, (const S*)out.x, (const S*)out.u, (const S*)out.lam, ws, dws,
-                        sw > 0 ? rel : (double*)nullptr, sw > 0 ? active : (int32_t*)nullptr, p.refine_tol));
-            if (sw > 0) pg.active = active;
+                        Bi, s, pr, in, (const S*)out.x, (const S*)out.u, (const S*)out.lam, ws, dws, rel, active,
+                        p.refine_tol));
+            pg.active = active;
             LCHK(launch_nt(NT, F_REFINE_INST, ref_f, ref_b, k_refine_inst<S, E>, Bi, s, pg, in, ws, out));
             continue;
         }
         LCHK(launch_nt(NT, F_RESID, B * (N + 1) * w.resid_f(), B * (N + 1) * w.resid_b(), k_resid<S, E64, true>,
                     Bi * (N + 1), s, pr, in, (const S*)out.x, (const S*)out.u, (const S*)out.lam, ws, dws));
-        if (sw > 0) {
-            LCHK(launch_nt(WG, F_REDUCE, 0, B * 16.0 * (N + 1), k_resid_reduce<double>, (Bi + 63) / 64, s, pr,
-                        (const double*)dws, rel, active, p.refine_tol));
-            pg.active = active;
-        }
+        LCHK(launch_nt(WG, F_REDUCE, 0, B * 16.0 * (N + 1), k_resid_reduce<double>, (Bi + 63) / 64, s, pr,
+                       (const double*)dws, rel, active, p.refine_tol));
+        pg.active = active;
         LCHK(launch_nt(NT, F_REF_D, B * N * 3 * w.vec_f(), B * N * 3 * w.vec_b(), k_ref_d<S, E>, Bi * N, s, pg, ws));
         for (int l = 0; l + 1 < p.ft.nlev; ++l) {
             const double u = B * (p.ft.cnt[l] / 2);
