@@ -36,8 +36,8 @@ METRIC = "LQR-KKT solves/s + p99 latency at rel KKT residual ≤1e-5: batched FP
 N_STAGES, NX, NU, BATCH = 100, 36, 12, 4096
 
 # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2 flops (FMA) x 2.4 GHz.  The vector
-# FP32 peak with packed-FP32 dual issue is twice that; this build compiles with
-# packed FP32 disabled, so 78.6 TFLOP/s is the rate its VALU code can reach.
+# FP32 peak with packed-FP32 dual issue is twice that; the library is compiled
+# with packed FP32 disabled, so 78.6 TFLOP/s is the rate its VALU code can reach.
 PEAK_FP32_VECTOR_PACKED = 157.3e12
 PEAK_FP32_VECTOR = 256 * 4 * 16 * 2 * 2.4e9
 PEAK_HBM = 8.0e12
@@ -262,8 +262,8 @@ def main():
                          "counters of a profiler against a known size) and exit")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the batch-sharded multi-GPU form "
-              "is described in DESIGN.md and not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}): instances are independent and would "
+              "shard across GPUs by batch, but only the single-GPU path is built", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -22,8 +22,8 @@ def oracle_lib():
 
 @pytest.fixture(scope="session", autouse=True)
 def _built_library():
-    """Build the HIP library in-tree if it is missing (the GPU machine gets the
-    prebuilt one with the repository snapshot)."""
+    """Build the HIP library in-tree if it is missing (a machine that
+    receives the repository with the library already built uses it as is)."""
     lib = os.path.join(ROOT, "paper_2506_07823_amd", "liblqr_kkt.so")
     if not os.path.exists(lib):
         import importlib.util
