@@ -117,6 +117,11 @@ lqr_max_dim = _lib.lqr_max_dim
 lqr_last_error = _lib.lqr_last_error
 lqr_timing_enable = _lib.lqr_timing_enable
 lqr_timing_report = _lib.lqr_timing_report
+lqr_set_tuning = _lib.lqr_set_tuning
+lqr_autotune = _lib.lqr_autotune
+lqr_autotune_workspace_size = _lib.lqr_autotune_workspace_size
+lqr_ragged_workspace_size = _lib.lqr_ragged_workspace_size
+lqr_kkt_solve_ragged = _lib.lqr_kkt_solve_ragged
 
 FIELDS = ("A", "B", "c", "Q", "R", "M", "q", "r", "x0")
 
