@@ -310,15 +310,21 @@ struct Eng {
     // In-register right-looking Cholesky of the n x n SPD matrix held in S
     // (lower triangle used).  On return S holds L (lower, zero above), dinv
     // (LDS, >= n) holds 1/L_kk.  NV lane vectors in gv are forward-solved
-    // with L on the way (gv <- L^{-1} gv).  cb is an LDS scratch of
-    // 2*(NP+NV) elements.  Returns false if a pivot is not positive (the
-    // factorization continues with a unit pivot so values stay finite).
-    // dmin/dmax receive the extreme diagonal entries of L.
+    // with L on the way (gv <- L^{-1} gv).  Returns false if a pivot is not
+    // positive (the factorization continues with a unit pivot so values stay
+    // finite).  dmin/dmax receive the extreme diagonal entries of L.
+    //
+    // Step k reads the pivot column straight from the registers of its
+    // owner lanes (tx == k % G) with cross-lane reads: the entry of row
+    // ty + G a sits in lane (ty, t) as S[a][a0], the entry of row tx + G b in
+    // lane (tx, t) as S[b][a0].  No LDS hand-off, no wave barrier per step.
     // NB: the matrix occupies the first NB row/column blocks of the tile
-    // (n <= G * NB); the other blocks are left untouched (zero).
+    // (n <= G * NB); the other blocks are left untouched (zero).  cb is
+    // unused (kept for the call signature).
     template <int NV, int NB = TS>
     __device__ __forceinline__ bool chol(Tile& S, int n, T* cb, T* dinv, T (&gv)[NV > 0 ? NV : 1], T& dmin, T& dmax) const {
         static_assert(NB <= TS, "block limit");
+        (void)cb;
         bool ok = true;
         dmin = T(0);
         dmax = T(0);
@@ -328,16 +334,17 @@ struct Eng {
             for (int t = 0; t < G; ++t) {
                 const int k = G * a0 + t;
                 if (k >= n) break;
-                T* c = cb + (k & 1) * (NP + (NV > 0 ? NV : 1));
-                if (tx == t) {
+                const int src_r = ty * G + t;   // lane (ty, t)
+                const int src_c = tx * G + t;   // lane (tx, t)
+                T cr[NB], cc[NB];
 #pragma unroll
-                    for (int a = 0; a < NB; ++a) c[row(a)] = S[a][a0];
-                }
+                for (int a = 0; a < NB; ++a) cr[a] = __shfl(S[a][a0], src_r, 64);
 #pragma unroll
-                for (int v = 0; v < NV; ++v)
-                    if (lg == k) c[NP + v] = gv[v];
-                wg_sync();
-                T d = c[k];
+                for (int b2 = a0; b2 < NB; ++b2) cc[b2] = __shfl(S[b2][a0], src_c, 64);
+                T d = __shfl(S[a0][a0], t * G + t, 64);
+                T gk0[NV > 0 ? NV : 1];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) gk0[v] = __shfl(gv[v], k, 64);
                 const bool good = d > T(0);
                 ok = ok && good;
                 if (!good) d = T(1);
@@ -348,9 +355,9 @@ struct Eng {
                 dmax = s > dmax ? s : dmax;
                 T li[NB], lj[NB];
 #pragma unroll
-                for (int a = 0; a < NB; ++a) li[a] = c[row(a)] * inv;
+                for (int a = 0; a < NB; ++a) li[a] = cr[a] * inv;
 #pragma unroll
-                for (int b = a0; b < NB; ++b) lj[b] = c[col(b)] * inv;
+                for (int b = a0; b < NB; ++b) lj[b] = cc[b] * inv;
                 // trailing update of the lower triangle: blocks a >= b >= a0
                 // (blocks past the pivot block lie entirely below and right
                 // of k: only the pivot block row and column need the test)
@@ -372,11 +379,18 @@ struct Eng {
                         if (col(b) > k) S[a0][b] = T(0);
                 }
                 if (lg == 0) dinv[k] = inv;
+                if (NV > 0) {
+                    // element lg of column k (row lg = tx + G ty) is cc[ty]
+                    T ck = T(0);
 #pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    const T gk = c[NP + v] * inv;
-                    if (lg == k) gv[v] = gk;
-                    else if (lg > k && lg < n) gv[v] = fma_(-c[lg] * inv, gk, gv[v]);
+                    for (int b = a0; b < NB; ++b)
+                        if (ty == b) ck = cc[b];
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        const T gk = gk0[v] * inv;
+                        if (lg == k) gv[v] = gk;
+                        else if (lg > k && lg < n) gv[v] = fma_(-ck * inv, gk, gv[v]);
+                    }
                 }
             }
         }
@@ -388,14 +402,17 @@ struct Eng {
     // X <- L^{-1} X (LOWER=true, forward) or X <- L^{-T} X (LOWER=false,
     // backward with the transpose), L (n x n lower) in LDS slot sL with
     // reciprocal diagonal dinv.  Solves NT register tiles (their first n rows)
-    // and NV lane vectors at once.  rb is LDS scratch of 2*(NT*NP+NV).
+    // and NV lane vectors at once.  Step k reads the pivot row from the
+    // registers of its owner lanes (ty == k % G; column tx + G b of it sits
+    // in lane (t, tx) as X[a0][b]) with cross-lane reads.  rb is unused (kept
+    // for the call signature).
     // NB: the solve order n fits the first NB row blocks (n <= G * NB); the
     // rows of the right-hand-side tiles beyond them are left untouched.
     template <bool LOWER, int NT, int NV, int NB = TS>
     __device__ __forceinline__ void trsm(const T* sL, const T* dinv, int n, Tile (&X)[NT > 0 ? NT : 1],
                          T (&vv)[NV > 0 ? NV : 1], T* rb) const {
         static_assert(NB <= TS, "block limit");
-        constexpr int RBS = (NT > 0 ? NT : 0) * NP + (NV > 0 ? NV : 0) + 1;
+        (void)rb;
 #pragma unroll
         for (int a0s = 0; a0s < NB; ++a0s) {
             const int a0 = LOWER ? a0s : NB - 1 - a0s;
@@ -406,20 +423,8 @@ struct Eng {
                     if (LOWER) break;
                     continue;
                 }
-                T* r = rb + (k & 1) * RBS;
                 const T dk = dinv[k];
-                if (ty == t) {
-#pragma unroll
-                    for (int it = 0; it < NT; ++it)
-#pragma unroll
-                        for (int b = 0; b < TS; ++b) r[it * NP + col(b)] = X[it][a0][b] * dk;
-                }
-#pragma unroll
-                for (int v = 0; v < NV; ++v)
-                    if (lg == k) r[NT * NP + v] = vv[v] * dk;
-                wg_sync();
-                // row blocks already solved (before a0 going forward, after a0
-                // going backward) are skipped
+                const int src = t * G + tx;   // lane (t, tx)
                 // rows of blocks past the pivot block are all active (the
                 // factor is zero beyond its order n, so no test is needed)
                 T lik[NB];
@@ -438,7 +443,7 @@ struct Eng {
                 for (int it = 0; it < NT; ++it) {
                     T rk[TS];
 #pragma unroll
-                    for (int b = 0; b < TS; ++b) rk[b] = r[it * NP + col(b)];
+                    for (int b = 0; b < TS; ++b) rk[b] = __shfl(X[it][a0][b], src, 64) * dk;
 #pragma unroll
                     for (int a = 0; a < NB; ++a) {
                         if (LOWER ? a < a0 : a > a0) continue;
@@ -449,7 +454,7 @@ struct Eng {
                 }
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
-                    const T vk = r[NT * NP + v];
+                    const T vk = __shfl(vv[v], k, 64) * dk;
                     if (lg == k) vv[v] = vk;
                     else {
                         const bool act = LOWER ? (lg > k && lg < n) : (lg < k);

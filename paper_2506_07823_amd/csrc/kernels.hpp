@@ -104,10 +104,10 @@ struct Lds {
     using T = typename E::T;
     T sA[E::MAT];
     T sX[E::MAT];
-    T cb[2 * (E::NP + 2)];
+    T cb[1];    // (the factorization and solves hand pivots over in registers)
     T dA[E::NP];
     T dB[E::NP];
-    T rb[2 * (2 * E::NP + 3)];
+    T rb[1];
     T vb[2][E::NP];
 };
 
