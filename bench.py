@@ -48,7 +48,7 @@ MR_BATCH = 64
 # HBM bytes per launch of the whole-body k_up from rocprofv3 FETCH_SIZE /
 # WRITE_SIZE runs, calibrated against a copy of known size; valid only for
 # the kernel sources they were taken on (hash of engine.hpp + kernels.hpp)
-KUP_TRAFFIC = {"src_hash": "0d1a30a8e0c38fd2", "bytes_per_launch": 2.907e+09,
+KUP_TRAFFIC = {"src_hash": "b5a9ecfd9904dd74", "bytes_per_launch": 2.908e+09,
                "note": "FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (copy calibration), per launch"}
 
 
