@@ -20,7 +20,8 @@ def _gpu():
         pytest.skip("no GPU")
 
 
-@pytest.mark.parametrize("cfg", ["srbd50_fp32", "wholebody_fp32", "tiny_fp64_plain"])
+@pytest.mark.parametrize("cfg", ["srbd50_fp32", "wholebody_fp32", "tiny_fp64_plain", "matrixcore_fp32",
+                                 "matrixcore_fp64_plain"])
 def test_graph_replay_matches_eager(cfg):
     import torch
     import paper_2506_07823_amd as L
@@ -28,6 +29,12 @@ def test_graph_replay_matches_eager(cfg):
         batch, dt, kw = synth.gen_batch(lambda i: synth.gen_c2(50, i), 4, np.float32), np.float32, {}
     elif cfg == "wholebody_fp32":
         batch, dt, kw = synth.gen_batch(synth.gen_c3, 32, np.float32), np.float32, {}
+    elif cfg == "matrixcore_fp32":
+        batch = synth.gen_batch(lambda i: synth.gen_rand(6, 80, 40, seed=[850, i]), 3, np.float32)
+        dt, kw = np.float32, {}
+    elif cfg == "matrixcore_fp64_plain":
+        batch = synth.gen_batch(lambda i: synth.gen_rand(5, 72, 24, seed=[851, i]), 2, np.float64)
+        dt, kw = np.float64, {"method": "plain"}
     else:
         batch, dt, kw = synth.gen_batch(synth.gen_c1, 3, np.float64), np.float64, {"method": "plain"}
     say(f"[graph replay] {cfg}")

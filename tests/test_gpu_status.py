@@ -60,6 +60,25 @@ def test_ill_conditioned_R_takes_fp64_fallback():
     assert out["resid"][2] <= 1e-5 and res <= 1e-5
 
 
+def test_ill_conditioned_R_fallback_large_blocks():
+    """Same on the matrix-core engine (order 70): the element's FP64 redo
+    runs with FP64 compute on the FP32 records.  The control column with the
+    1e-7 weight also gets a small input matrix column, so the element's C
+    (eigenvalue ~ ||B e_1||^2 / 1e-7) stays within what FP32 records hold
+    (with B ~ N(0, 0.1) at order 70 it would be ~7e6: the unrepresentable
+    case of the next test)."""
+    b = synth.gen_batch(lambda i: synth.gen_c1_like(8, 70, 12, [420, i]), 3, np.float32)
+    b["R"][1, 3] = np.diag([1e-7] + [1.0] * 11)
+    b["B"][1, 3][:, 0] *= 0.03
+    say("[status ill-conditioned R fallback, order 70]")
+    out = run(b, np.float32, want_resid=True, refine=4)
+    assert out["status"][1] == 8, out["status"]
+    assert out["status"][0] == 0 and out["status"][2] == 0
+    errs, res = oracle_check(b, out, 1, as_f32=True)
+    say(f"  fallback instance: rel err {errs}, resid gpu {out['resid'][1]:.2e} oracle {res:.2e}")
+    assert out["resid"][1] <= 1e-5 and res <= 1e-5
+
+
 def test_unrepresentable_scaling_is_reported():
     """With B ~ 0.5 N(0, 1) and a 1e-7 entry in R_k the element's C has
     eigenvalues spread over ~1e7, beyond what FP32 storage of the scan
