@@ -15,7 +15,9 @@ n = m = 192, N = 50, batch 64, on the large-block (matrix-core) engine the
 same way, and "serving" runs a Poisson stream of mixed requests (60 %
 SRBD-shaped, 30 % whole-body-shaped, 10 % multi-robot) through the
 continuous-batching loop at 70 % of its measured capacity (p50/p99 latency
-from arrival, host-to-device copies included).
+from arrival, host-to-device copies included).  "latency" times single
+SRBD-shaped solves (n = m = 12, batch 1, N = 25 .. 200): FP32 scan against
+the FP64 plain Riccati sweep, both as graph replays.
 
 Prints ONE JSON line.  `python bench.py [--steps K] [--warmup W]`.
 """
@@ -181,6 +183,31 @@ def measure(L, gen, batch, steps, warmup, eager, refine, plain, label, tune=True
     return r, fams
 
 
+def latency_leg(L, steps: int = 50):
+    """Single-solve latency of the SRBD-shaped case (n = m = 12, one
+    instance) at every horizon: graph replays of the FP32 scan (with its
+    refinement) against the FP64 plain Riccati sweep, p50/p99 over `steps`
+    replays each.  The scan's O(log N) depth against N dependent steps."""
+    import torch
+    import synth
+    out = {}
+    for N in synth.C2_HORIZONS:
+        host = synth.gen_batch(lambda i: synth.gen_c2(N, i), 1, np.float32)
+        dev = {k: torch.from_numpy(v).to("cuda:0") for k, v in host.items()}
+        _, lat, _, resid, bad = timed_steps(L, dev, "scan", steps, 3, False, graph=True, refine=2)
+        dev64 = {k: v.double() for k, v in dev.items()}
+        _, plat, _, presid, pbad = timed_steps(L, dev64, "plain", steps, 3, False, graph=True)
+        out[f"N{N}"] = {"scan_p50_ms": float(np.percentile(lat, 50)), "scan_p99_ms": float(np.percentile(lat, 99)),
+                        "plain_p50_ms": float(np.percentile(plat, 50)),
+                        "plain_p99_ms": float(np.percentile(plat, 99)),
+                        "scan_rel_kkt_residual": resid, "plain_rel_kkt_residual": presid,
+                        "instances_with_status": bad + pbad}
+        log(f"[bench] latency N={N}: scan p50 {out[f'N{N}']['scan_p50_ms']:.3f} ms, "
+            f"plain p50 {out[f'N{N}']['plain_p50_ms']:.3f} ms")
+    out["workload"] = "SRBD-shaped single solve (n=m=12, batch 1), hipGraph replays, FP32 scan + refinement vs FP64 plain"
+    return out
+
+
 def serving_leg(L, n_clients: int, warm_requests: int, sat_requests: int, requests: int, load: float):
     """Serving mix through the continuous-batching loop: a saturated run
     (every request present at t = 0) gives the capacity; then Poisson
@@ -254,6 +281,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-multi-robot", action="store_true", help="skip the n=m=192 multi-robot workload")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-mix workload")
+    ap.add_argument("--no-latency", action="store_true", help="skip the single-solve latency workload")
     ap.add_argument("--serving-requests", type=int, default=1600)
     ap.add_argument("--no-tune", action="store_true", help="use the default mapping instead of autotuning it")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of graph replays")
@@ -309,6 +337,8 @@ def main():
             log("[bench] multi-robot: CPU oracle baseline")
             mr["cpu_baseline"] = cpu_baseline(synth.gen_c4, 16, MR_BATCH, "multi-robot")
         result["multi_robot"] = mr
+    if not a.no_latency:
+        result["latency"] = latency_leg(L)
     if not a.no_serving:
         result["serving"] = serving_leg(L, 40, 100, max(200, a.serving_requests // 2), a.serving_requests, 0.7)
     if not a.no_cpu:
