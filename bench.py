@@ -17,7 +17,8 @@ SRBD-shaped, 30 % whole-body-shaped, 10 % multi-robot) through the
 continuous-batching loop at 70 % of its measured capacity (p50/p99 latency
 from arrival, host-to-device copies included).  "latency" times single
 SRBD-shaped solves (n = m = 12, batch 1, N = 25 .. 200): FP32 scan against
-the FP64 plain Riccati sweep, both as graph replays.
+the FP64 plain Riccati sweep, both as graph replays; "batch_sweep" runs the
+whole-body workload at batches 16 .. 1024 (scan and plain solves/s).
 
 Prints ONE JSON line.  `python bench.py [--steps K] [--warmup W]`.
 """
@@ -208,6 +209,29 @@ def latency_leg(L, steps: int = 50):
     return out
 
 
+def batch_sweep_leg(L, batches=(16, 64, 256, 1024), steps: int = 10):
+    """Whole-body workload at smaller batches (default mapping, graph
+    replays): solves/s of the FP32 scan and of the FP64 plain sweep, to show
+    where the scan's depth outweighs its extra arithmetic."""
+    import torch
+    import synth
+    host = synth.gen_batch(synth.gen_c3, max(batches), np.float32)
+    rows = {}
+    for B in batches:
+        dev = {k: torch.from_numpy(np.ascontiguousarray(v[:B])).to("cuda:0") for k, v in host.items()}
+        wall, lat, _, resid, bad = timed_steps(L, dev, "scan", steps, 2, False, graph=True, refine=2)
+        dev64 = {k: v.double() for k, v in dev.items()}
+        pwall, plat, _, presid, pbad = timed_steps(L, dev64, "plain", steps, 2, False, graph=True)
+        rows[f"B{B}"] = {"scan_solves_per_s": B * steps / wall, "plain_solves_per_s": B * steps / pwall,
+                         "scan_p50_ms": float(np.percentile(lat, 50)), "plain_p50_ms": float(np.percentile(plat, 50)),
+                         "scan_rel_kkt_residual": resid, "instances_with_status": bad + pbad}
+        log(f"[bench] batch {B}: scan {rows[f'B{B}']['scan_solves_per_s']:.0f}/s, "
+            f"plain {rows[f'B{B}']['plain_solves_per_s']:.0f}/s")
+        del dev, dev64
+    rows["workload"] = "whole-body-shaped (n=36, m=12, N=100), default mapping, hipGraph replays"
+    return rows
+
+
 def serving_leg(L, n_clients: int, warm_requests: int, sat_requests: int, requests: int, load: float):
     """Serving mix through the continuous-batching loop: a saturated run
     (every request present at t = 0) gives the capacity; then Poisson
@@ -282,6 +306,7 @@ def main():
     ap.add_argument("--no-multi-robot", action="store_true", help="skip the n=m=192 multi-robot workload")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-mix workload")
     ap.add_argument("--no-latency", action="store_true", help="skip the single-solve latency workload")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the whole-body batch-size sweep")
     ap.add_argument("--serving-requests", type=int, default=1600)
     ap.add_argument("--no-tune", action="store_true", help="use the default mapping instead of autotuning it")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of graph replays")
@@ -339,6 +364,8 @@ def main():
         result["multi_robot"] = mr
     if not a.no_latency:
         result["latency"] = latency_leg(L)
+    if not a.no_sweep:
+        result["batch_sweep"] = batch_sweep_leg(L)
     if not a.no_serving:
         result["serving"] = serving_leg(L, 40, 100, max(200, a.serving_requests // 2), a.serving_requests, 0.7)
     if not a.no_cpu:

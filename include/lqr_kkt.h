@@ -166,7 +166,7 @@ int lqr_timing_report(lqr_handle_t h, char* buf, size_t len);
  *   engine   0 = default rule, 1 = wavefront tiles (orders <= 64, one 64-lane
  *            wavefront per task), 2 = matrix-core workgroups (one 256-thread
  *            workgroup per task, products on MFMA)
- *   fused    -1 = default (batch >= 128), 0 = level-by-level launches of the
+ *   fused    -1 = default (level by level), 0 = level-by-level launches of the
  *            vector-only passes, 1 = one workgroup per instance
  *   big_grid 0 = default (512), else the workgroups / scratch slots of a
  *            matrix-core task launch

@@ -124,9 +124,10 @@ Plan make_plan(int64_t batch, int N, int n, int m, size_t esize, const lqr_opts&
     p.cond_thr = o.cond_threshold;
     p.refine_tol = o.refine_tol;
     p.active = nullptr;
-    // per-instance vector passes once the batch alone fills the GPU; the
-    // level-parallel launches keep the O(log N) depth for small batches
-    p.fused = batch >= 128 ? 1 : 0;
+    // vector-only passes level by level (one workgroup per tree node or
+    // stage); the per-instance form (one workgroup walks an instance) is a
+    // mapping the autotuner may pick instead
+    p.fused = 0;
     p.fallback = esize == 4 ? o.fallback : 0;   // the FP64 path has nothing to fall back to
     if (tun && tun->fused >= 0) p.fused = tun->fused;
     if (pick_ts(n, m, tun) == kBigTS) {

@@ -95,17 +95,26 @@ def test_big_alone_equals_in_batch():
 
 
 def test_big_per_instance_path():
-    """Batches of >= 128 instances run the vector-only passes one workgroup
-    per instance; same bits as the level-by-level launches."""
+    """The per-instance form of the vector-only passes (pinned for this
+    batch of 130): same bits as the level-by-level launches of an alone
+    solve."""
+    import torch
+    import paper_2506_07823_amd as L
     batch = synth.gen_batch(lambda i: synth.gen_rand(5, 66, 8, seed=[630, i]), 130, np.float64)
     say("[big per-instance path fp64] N=5 n=66 m=8 batch=130")
-    out = run(batch, np.float64, want_resid=True)
+    for dt in (torch.float64, torch.float32):
+        L.set_tuning(130, 5, 66, 8, dt, fused=True)
+    try:
+        out = run(batch, np.float64, want_resid=True)
+        b32 = {k: v.astype(np.float32) for k, v in batch.items()}
+        full = run(b32, np.float32, refine=2, want_resid=True)
+    finally:
+        for dt in (torch.float64, torch.float32):
+            L.set_tuning(130, 5, 66, 8, dt, clear=True)
     assert not out["status"].any()
     for b in (0, 129):
         errs, res = oracle_check(batch, out, b)
         assert max(errs) <= FP64_TOL and res <= 1e-11
-    b32 = {k: v.astype(np.float32) for k, v in batch.items()}
-    full = run(b32, np.float32, refine=2, want_resid=True)
     alone = run({k: v[7:8] for k, v in b32.items()}, np.float32, refine=2, want_resid=True)
     for f in ("x", "u", "lam", "resid"):
         assert np.array_equal(alone[f][0], full[f][7]), f

@@ -137,19 +137,28 @@ def test_deterministic():
 
 
 def test_per_instance_path_fp64_and_matches_level_path():
-    """Batches of >= 128 instances run the vector-only passes one workgroup
-    per instance; they call the same task bodies in the same order as the
-    level-by-level launches used for small batches, so an instance solved in
-    a large batch equals the same instance solved alone, bit for bit."""
+    """The per-instance form of the vector-only passes (one workgroup walks
+    an instance; pinned here as the mapping of a batch of 160) calls the same
+    task bodies in the same order as the level-by-level launches, so an
+    instance solved in that batch equals the same instance solved alone
+    (level by level), bit for bit."""
+    import torch
+    import paper_2506_07823_amd as L
     batch = synth.gen_batch(lambda i: synth.gen_rand(13, 8, 3, seed=[500, i]), 160, np.float64)
     say("[per-instance path fp64] N=13 n=8 m=3 batch=160")
-    out = run(batch, np.float64, want_resid=True)
+    L.set_tuning(160, 13, 8, 3, torch.float64, fused=True)
+    L.set_tuning(160, 13, 8, 3, torch.float32, fused=True)
+    try:
+        out = run(batch, np.float64, want_resid=True)
+        b32 = {k: v.astype(np.float32) for k, v in batch.items()}
+        full = run(b32, np.float32, refine=2, want_resid=True)
+    finally:
+        L.set_tuning(160, 13, 8, 3, torch.float64, clear=True)
+        L.set_tuning(160, 13, 8, 3, torch.float32, clear=True)
     assert not out["status"].any()
     for b in (0, 77, 159):
         errs, res = oracle_check(batch, out, b)
         assert max(errs) <= FP64_TOL and res <= 1e-11
-    b32 = {k: v.astype(np.float32) for k, v in batch.items()}
-    full = run(b32, np.float32, refine=2, want_resid=True)
     for b in (3, 150):
         alone = run({k: v[b:b + 1] for k, v in b32.items()}, np.float32, refine=2, want_resid=True)
         for f in ("x", "u", "lam", "resid"):
