@@ -51,7 +51,7 @@ MR_BATCH = 64
 # HBM bytes per launch of the whole-body k_up from rocprofv3 FETCH_SIZE /
 # WRITE_SIZE runs, calibrated against a copy of known size; valid only for
 # the kernel sources they were taken on (hash of engine.hpp + kernels.hpp)
-KUP_TRAFFIC = {"src_hash": "b5a9ecfd9904dd74", "bytes_per_launch": 2.908e+09,
+KUP_TRAFFIC = {"src_hash": "2badc40252a955a1", "bytes_per_launch": 2.908e+09,
                "note": "FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (copy calibration), per launch"}
 
 
@@ -300,7 +300,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-sample", type=int, default=1024)
+    ap.add_argument("--cpu-sample", type=int, default=4096)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-multi-robot", action="store_true", help="skip the n=m=192 multi-robot workload")

@@ -40,6 +40,16 @@ template <> __device__ __forceinline__ double dsqrt<double>(double x) { return _
 __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
+// Value of v in lane k, k uniform across the wavefront (a scalar read of
+// one lane's register: no LDS traffic).
+__device__ __forceinline__ float lane_at(float v, int k) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+__device__ __forceinline__ double lane_at(double v, int k) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), k),
+                            __builtin_amdgcn_readlane(__double2loint(v), k));
+}
+
 template <typename T>
 __device__ __forceinline__ bool finite_(T v) { return __builtin_isfinite(v); }
 
@@ -248,9 +258,10 @@ struct Eng {
     __device__ __forceinline__ void vstore(S* g, int n, T v) const { if (lg < n) g[lg] = S(v); }
 
     // y = op(X) v over k < K for rows < rows (X in LDS; v staged through vb).
-    // Callers must barrier between successive uses of the same vb.
+    // The workgroup is one wavefront, whose LDS accesses complete in
+    // program order, so successive calls may share one vb.
     template <bool TX>
-    __device__ __forceinline__ T matvec(const T* X, T v, T* vb, int K, int rows) const {
+    __device__ __forceinline__ T matvec(const T* X, T* vb, T v, int K, int rows) const {
         if (lg < NP) vb[lg] = v;
         wg_sync();
         T s = T(0);
@@ -308,8 +319,8 @@ struct Eng {
 
     // --------------------------------------------------------- Cholesky
     // In-register right-looking Cholesky of the n x n SPD matrix held in S
-    // (lower triangle used).  On return S holds L (lower, zero above), dinv
-    // (LDS, >= n) holds 1/L_kk.  NV lane vectors in gv are forward-solved
+    // (lower triangle used).  On return S holds L (lower, zero above) and
+    // lane k's dl holds 1/L_kk (a lane vector).  NV lane vectors in gv are forward-solved
     // with L on the way (gv <- L^{-1} gv).  Returns false if a pivot is not
     // positive (the factorization continues with a unit pivot so values stay
     // finite).  dmin/dmax receive the extreme diagonal entries of L.
@@ -322,9 +333,10 @@ struct Eng {
     // (n <= G * NB); the other blocks are left untouched (zero).  cb is
     // unused (kept for the call signature).
     template <int NV, int NB = TS>
-    __device__ __forceinline__ bool chol(Tile& S, int n, T* cb, T* dinv, T (&gv)[NV > 0 ? NV : 1], T& dmin, T& dmax) const {
+    __device__ __forceinline__ bool chol(Tile& S, int n, T* cb, T& dl, T (&gv)[NV > 0 ? NV : 1], T& dmin, T& dmax) const {
         static_assert(NB <= TS, "block limit");
         (void)cb;
+        dl = T(1);
         bool ok = true;
         dmin = T(0);
         dmax = T(0);
@@ -378,7 +390,7 @@ struct Eng {
                     for (int b = 0; b < NB; ++b)
                         if (col(b) > k) S[a0][b] = T(0);
                 }
-                if (lg == 0) dinv[k] = inv;
+                if (lg == k) dl = inv;
                 if (NV > 0) {
                     // element lg of column k (row lg = tx + G ty) is cc[ty]
                     T ck = T(0);
@@ -400,8 +412,8 @@ struct Eng {
 
     // ------------------------------------------------ triangular solves
     // X <- L^{-1} X (LOWER=true, forward) or X <- L^{-T} X (LOWER=false,
-    // backward with the transpose), L (n x n lower) in LDS slot sL with
-    // reciprocal diagonal dinv.  Solves NT register tiles (their first n rows)
+    // backward with the transpose), L (n x n lower) in LDS slot sL, its
+    // reciprocal diagonal as the lane vector dl (lane k: 1/L_kk).  Solves NT register tiles (their first n rows)
     // and NV lane vectors at once.  Step k reads the pivot row from the
     // registers of its owner lanes (ty == k % G; column tx + G b of it sits
     // in lane (t, tx) as X[a0][b]) with cross-lane reads.  rb is unused (kept
@@ -409,7 +421,7 @@ struct Eng {
     // NB: the solve order n fits the first NB row blocks (n <= G * NB); the
     // rows of the right-hand-side tiles beyond them are left untouched.
     template <bool LOWER, int NT, int NV, int NB = TS>
-    __device__ __forceinline__ void trsm(const T* sL, const T* dinv, int n, Tile (&X)[NT > 0 ? NT : 1],
+    __device__ __forceinline__ void trsm(const T* sL, T dl, int n, Tile (&X)[NT > 0 ? NT : 1],
                          T (&vv)[NV > 0 ? NV : 1], T* rb) const {
         static_assert(NB <= TS, "block limit");
         (void)rb;
@@ -423,7 +435,7 @@ struct Eng {
                     if (LOWER) break;
                     continue;
                 }
-                const T dk = dinv[k];
+                const T dk = lane_at(dl, k);
                 const int src = t * G + tx;   // lane (t, tx)
                 // rows of blocks past the pivot block are all active (the
                 // factor is zero beyond its order n, so no test is needed)

@@ -104,11 +104,9 @@ struct Lds {
     using T = typename E::T;
     T sA[E::MAT];
     T sX[E::MAT];
-    T cb[1];    // (the factorization and solves hand pivots over in registers)
-    T dA[E::NP];
-    T dB[E::NP];
-    T rb[1];
-    T vb[2][E::NP];
+    T vb[E::NP];   // staged vector of the matrix-vector products
+    T cb[1];    // (the factorization and solves hand pivots over
+    T rb[1];    //  in registers)
 };
 
 template <typename T>
@@ -168,10 +166,6 @@ __device__ __forceinline__ void negate(typename E::Tile& t) {
 }
 
 // reciprocal diagonal of a staged lower-triangular factor
-template <class E>
-__device__ __forceinline__ void fill_dinv(const typename E::T* s, typename E::T* d, int n) {
-    for (int i = threadIdx.x; i < n; i += 64) d[i] = typename E::T(1) / s[i * E::LD + i];
-}
 
 __device__ __forceinline__ void set_status(int32_t* status, int64_t b, int bits) {
     if (threadIdx.x == 0) atomicOr(status + b, bits);
@@ -300,7 +294,8 @@ __device__ __forceinline__ void element_task(Lds<E>& L, const Plan& p, const In<
     typename E::Tile tR;
     e.load(tR, P.R(b, k), m, m, m);
     T dmin, dmax, nov[1];
-    const bool ok = e.template chol<0, MB>(tR, m, L.cb, L.dA, nov, dmin, dmax);
+    T dlA;
+    const bool ok = e.template chol<0, MB>(tR, m, L.cb, dlA, nov, dmin, dmax);
     fb_decide<FB>(p, ok, cond_est(dmin, dmax), b, task, q, status, 2);
     e.to_lds(tR, L.sA);
     typename E::Tile W[2];
@@ -308,7 +303,7 @@ __device__ __forceinline__ void element_task(Lds<E>& L, const Plan& p, const In<
     e.template load<true>(W[1], P.M(b, k), m, n, m);   // M' (m x n)
     T vv[1] = {e.vload(P.r(b, k), m)};
     wg_sync();
-    e.template trsm<true, 2, 1, MB>(L.sA, L.dA, m, W, vv, L.rb);
+    e.template trsm<true, 2, 1, MB>(L.sA, dlA, m, W, vv, L.rb);
     e.to_lds(W[0], L.sA);
     e.to_lds(W[1], L.sX);
     wg_sync();
@@ -322,9 +317,9 @@ __device__ __forceinline__ void element_task(Lds<E>& L, const Plan& p, const In<
     e.load(t, P.Q(b, k), n, n, n);
     e.template gemm_sub<true, false, true>(t, L.sX, L.sX, m);
     e.store_sym(t, rec + 2 * nn, n);                   // Pt
-    const T bw = e.template matvec<true>(L.sA, vv[0], L.vb[0], m, n);
+    const T bw = e.template matvec<true>(L.sA, L.vb, vv[0], m, n);
     e.vstore(rec + 3 * nn, n, e.vload(P.c(b, k), n) - bw);
-    const T pw = e.template matvec<true>(L.sX, vv[0], L.vb[1], m, n);
+    const T pw = e.template matvec<true>(L.sX, L.vb, vv[0], m, n);
     e.vstore(rec + 3 * nn + n, n, e.vload(P.q(b, k), n) - pw);
 }
 
@@ -364,12 +359,13 @@ __device__ __forceinline__ void combine(const E& e, Lds<E>& L, int n, const S* e
     const T p2l = g[0];
     wg_sync();
     e.from_lds(tS, L.sA);
-    bool ok = e.template chol<1>(tS, n, L.cb, L.dA, g, dmin, dmax);
+    T dlA, dlB;
+    bool ok = e.template chol<1>(tS, n, L.cb, dlA, g, dmin, dmax);
     T kap = cond_est(dmin, dmax);
     e.to_lds(tS, L.sA);                                   // sA = L
     wg_sync();
     T cp = T(0);
-    if (!CHEAP) cp = e.template matvec<false>(L.sX, p2l, L.vb[0], n, n);   // C1 p2
+    if (!CHEAP) cp = e.template matvec<false>(L.sX, L.vb, p2l, n, n);   // C1 p2
     e.zero(tS);
     e.template gemm<false, false>(tS, L.sX, L.sA, n);      // W = C1 L
     wg_sync();
@@ -379,7 +375,7 @@ __device__ __forceinline__ void combine(const E& e, Lds<E>& L, int n, const S* e
     e.template gemm<true, false, true>(tS, L.sA, L.sX, n); // L' W (lower)
     e.add_identity(tS, n);
     T nov[1];
-    ok = e.template chol<0>(tS, n, L.cb, L.dB, nov, dmin, dmax) && ok;   // tS = L_S
+    ok = e.template chol<0>(tS, n, L.cb, dlB, nov, dmin, dmax) && ok;   // tS = L_S
     {
         const T ks = cond_est(dmin, dmax);
         kap = ks > kap ? ks : kap;
@@ -391,7 +387,7 @@ __device__ __forceinline__ void combine(const E& e, Lds<E>& L, int n, const S* e
         wg_sync();
         typename E::Tile Z1[1];
         e.from_lds_t(Z1[0], L.sX);                        // A2'
-        e.template trsm<true, 1, 0>(L.sA, L.dA, n, Z1, nov, L.rb);   // Z1 = L^{-1} A2'
+        e.template trsm<true, 1, 0>(L.sA, dlA, n, Z1, nov, L.rb);   // Z1 = L^{-1} A2'
 #pragma unroll
         for (int a = 0; a < E::TS; ++a)
 #pragma unroll
@@ -403,10 +399,10 @@ __device__ __forceinline__ void combine(const E& e, Lds<E>& L, int n, const S* e
     e.template gemm<true, false>(YZ[0], L.sA, L.sX, n);    // L' A1
     const T b1 = e.vload(e1 + 3 * nn, n);
     T vv[2];
-    vv[0] = g[0] + e.template matvec<true>(L.sA, b1, L.vb[1], n, n);
+    vv[0] = g[0] + e.template matvec<true>(L.sA, L.vb, b1, n, n);
     wg_sync();
     if (!CHEAP) {
-        vv[1] = e.template matvec<true>(L.sA, b1 - cp, L.vb[0], n, n);
+        vv[1] = e.template matvec<true>(L.sA, L.vb, b1 - cp, n, n);
         wg_sync();
         e.to_lds(YZ[1], L.sX);                             // sX = Z1
         wg_sync();
@@ -419,7 +415,7 @@ __device__ __forceinline__ void combine(const E& e, Lds<E>& L, int n, const S* e
     e.to_lds(tS, L.sA);                                    // sA = L_S
     wg_sync();
     if (!CHEAP) {
-        e.template trsm<true, 2, 2>(L.sA, L.dB, n, YZ, vv, L.rb);
+        e.template trsm<true, 2, 2>(L.sA, dlB, n, YZ, vv, L.rb);
     } else {
         typename E::Tile Y1[1];
 #pragma unroll
@@ -427,7 +423,7 @@ __device__ __forceinline__ void combine(const E& e, Lds<E>& L, int n, const S* e
 #pragma unroll
             for (int bb = 0; bb < E::TS; ++bb) Y1[0][a][bb] = YZ[0][a][bb];
         T v1[1] = {vv[0]};
-        e.template trsm<true, 1, 1>(L.sA, L.dB, n, Y1, v1, L.rb);
+        e.template trsm<true, 1, 1>(L.sA, dlB, n, Y1, v1, L.rb);
 #pragma unroll
         for (int a = 0; a < E::TS; ++a)
 #pragma unroll
@@ -439,7 +435,7 @@ __device__ __forceinline__ void combine(const E& e, Lds<E>& L, int n, const S* e
     wg_sync();
     e.from_lds(tS, L.sA);
     e.template gemm<true, false, true>(tS, L.sX, L.sX, n); // P1 + Y'Y (lower)
-    const T pv = e.template matvec<true>(L.sX, vv[0], L.vb[1], n, n) + e.vload(e1 + 3 * nn + n, n);
+    const T pv = e.template matvec<true>(L.sX, L.vb, vv[0], n, n) + e.vload(e1 + 3 * nn + n, n);
     e.vstore(outp, n, pv);
     wg_sync();
     e.to_lds_sym(tS, L.sA);                                // sA = P
@@ -452,7 +448,7 @@ __device__ __forceinline__ void combine(const E& e, Lds<E>& L, int n, const S* e
         e.zero(tS);
         e.template gemm<true, false>(tS, L.sA, L.sX, n);   // A = Z'Y
         e.template gemm_sub<true, false, true>(tC, L.sA, L.sA, n);   // Z1'Z1 - Z'Z (lower)
-        const T bv = e.template matvec<true>(L.sA, vv[1], L.vb[0], n, n) + e.vload(e2 + 3 * nn, n);
+        const T bv = e.template matvec<true>(L.sA, L.vb, vv[1], n, n) + e.vload(e2 + 3 * nn, n);
         e.vstore(outb, n, bv);
         wg_sync();
         e.to_lds(tS, L.sX);                                // sX = A
@@ -575,10 +571,10 @@ __device__ __forceinline__ void policy_task(Lds<E>& L, const Plan& p, const In<S
     stage(e, L.sA, Pn, n, n, n);                          // sA = P'
     stage(e, L.sX, P.B(b, k), n, m, m);                   // sX = B
     wg_sync();
-    const T v = e.template matvec<false>(L.sA, e.vload(P.c(b, k), n), L.vb[0], n, n) + e.vload(Pn + nn, n);
+    const T v = e.template matvec<false>(L.sA, L.vb, e.vload(P.c(b, k), n), n, n) + e.vload(Pn + nn, n);
     e.zero(t);
     e.template gemm<false, false, false, false, E::TS, MB>(t, L.sA, L.sX, n);       // P'B
-    const T h = e.template matvec<true>(L.sX, v, L.vb[1], n, m) + e.vload(P.r(b, k), m);
+    const T h = e.template matvec<true>(L.sX, L.vb, v, n, m) + e.vload(P.r(b, k), m);
     wg_sync();
     e.to_lds(t, L.sA);                                    // sA = P'B
     wg_sync();
@@ -590,7 +586,8 @@ __device__ __forceinline__ void policy_task(Lds<E>& L, const Plan& p, const In<S
     e.template load<true>(tH, P.M(b, k), m, n, m);        // M'
     e.template gemm<true, false, false, false, MB, E::TS>(tH, L.sA, L.sX, n);       // + (P'B)'A
     T dmin, dmax, nov[1];
-    const bool ok = e.template chol<0, MB>(tG, m, L.cb, L.dA, nov, dmin, dmax);
+    T dlA;
+    const bool ok = e.template chol<0, MB>(tG, m, L.cb, dlA, nov, dmin, dmax);
     fb_decide<FB>(p, ok, cond_est(dmin, dmax), b, task, q, status, 2);
     e.to_lds(tG, L.sA);                                   // sA = L_G
     wg_sync();
@@ -600,8 +597,8 @@ __device__ __forceinline__ void policy_task(Lds<E>& L, const Plan& p, const In<S
 #pragma unroll
         for (int c = 0; c < E::TS; ++c) KK[0][a][c] = tH[a][c];
     T hv[1] = {h};
-    e.template trsm<true, 1, 1, MB>(L.sA, L.dA, m, KK, hv, L.rb);
-    e.template trsm<false, 1, 1, MB>(L.sA, L.dA, m, KK, hv, L.rb);
+    e.template trsm<true, 1, 1, MB>(L.sA, dlA, m, KK, hv, L.rb);
+    e.template trsm<false, 1, 1, MB>(L.sA, dlA, m, KK, hv, L.rb);
     negate<E>(KK[0]);
     hv[0] = -hv[0];
     e.store(KK[0], inst + p.o_K + (int64_t)k * m * n, m, n, n);
@@ -615,7 +612,7 @@ __device__ __forceinline__ void policy_task(Lds<E>& L, const Plan& p, const In<S
     e.template gemm<false, false>(t, L.sX, L.sA, m);
     S* leaf = inst + p.o_ftree + (int64_t)k * p.frec;
     e.store(t, leaf, n, n, n);
-    const T bb = e.template matvec<false>(L.sX, hv[0], L.vb[0], m, n) + e.vload(P.c(b, k), n);
+    const T bb = e.template matvec<false>(L.sX, L.vb, hv[0], m, n) + e.vload(P.c(b, k), n);
     e.vstore(leaf + nn, n, bb);
 }
 
@@ -661,7 +658,7 @@ __device__ __forceinline__ void fup_body(LT& L, Plan p, S* ws, int lvl, int64_t 
         stage(e, L.sA, r, n, n, n);                           // M_r
         stage(e, L.sX, l, n, n, n);                           // M_l
         wg_sync();
-        const T v = e.template matvec<false>(L.sA, e.vload(l + nn, n), L.vb[0], n, n) + e.vload(r + nn, n);
+        const T v = e.template matvec<false>(L.sA, L.vb, e.vload(l + nn, n), n, n) + e.vload(r + nn, n);
         typename E::Tile t;
         e.zero(t);
         e.template gemm<false, false>(t, L.sA, L.sX, n);
@@ -1155,10 +1152,10 @@ __device__ __forceinline__ void plain_body(Lds3<E>& L, const Plan& p, const In<S
         wg_sync();
         stage(e, L.sX, P.B(b, k), n, m, m);               // sX = B
         wg_sync();
-        const T v = e.template matvec<false>(L.sP, e.vload(P.c(b, k), n), L.vb[0], n, n) + pn;
+        const T v = e.template matvec<false>(L.sP, L.vb, e.vload(P.c(b, k), n), n, n) + pn;
         e.zero(tPB);
         e.template gemm<false, false, false, false, E::TS, MB>(tPB, L.sP, L.sX, n); // P'B
-        const T h = e.template matvec<true>(L.sX, v, L.vb[1], n, m) + e.vload(P.r(b, k), m);
+        const T h = e.template matvec<true>(L.sX, L.vb, v, n, m) + e.vload(P.r(b, k), m);
         wg_sync();
         e.to_lds(tPB, L.sA);                              // sA = P'B
         wg_sync();
@@ -1171,13 +1168,14 @@ __device__ __forceinline__ void plain_body(Lds3<E>& L, const Plan& p, const In<S
         e.template gemm<true, false, false, false, MB, E::TS>(tH, L.sA, L.sX, n);   // H
         e.zero(tPA);
         e.template gemm<false, false>(tPA, L.sP, L.sX, n); // P'A
-        const T pa = e.template matvec<true>(L.sX, v, L.vb[0], n, n);   // A'v
+        const T pa = e.template matvec<true>(L.sX, L.vb, v, n, n);   // A'v
 #pragma unroll
         for (int a = 0; a < E::TS; ++a)
 #pragma unroll
             for (int c = 0; c < E::TS; ++c) tHc[a][c] = tH[a][c];
         T dmin, dmax, nov[1];
-        ok = e.template chol<0, MB>(tG, m, L.cb, L.dA, nov, dmin, dmax) && ok;
+        T dlA;
+        ok = e.template chol<0, MB>(tG, m, L.cb, dlA, nov, dmin, dmax) && ok;
         e.to_lds(tG, L.sA);                               // sA = L_G
         wg_sync();
         typename E::Tile KK[1];
@@ -1186,8 +1184,8 @@ __device__ __forceinline__ void plain_body(Lds3<E>& L, const Plan& p, const In<S
 #pragma unroll
             for (int c = 0; c < E::TS; ++c) KK[0][a][c] = tH[a][c];
         T hv[1] = {h};
-        e.template trsm<true, 1, 1, MB>(L.sA, L.dA, m, KK, hv, L.rb);
-        e.template trsm<false, 1, 1, MB>(L.sA, L.dA, m, KK, hv, L.rb);
+        e.template trsm<true, 1, 1, MB>(L.sA, dlA, m, KK, hv, L.rb);
+        e.template trsm<false, 1, 1, MB>(L.sA, dlA, m, KK, hv, L.rb);
         negate<E>(KK[0]);
         hv[0] = -hv[0];
         e.store(KK[0], inst + p.o_K + (int64_t)k * m * n, m, n, n);
@@ -1203,7 +1201,7 @@ __device__ __forceinline__ void plain_body(Lds3<E>& L, const Plan& p, const In<S
         e.to_lds(tHc, L.sX);                              // sX = H
         wg_sync();
         e.template gemm<true, false, true>(t, L.sA, L.sX, m);   // + K'H (lower)
-        pn = e.vload(P.q(b, k), n) + pa + e.template matvec<true>(L.sA, h, L.vb[1], m, n);
+        pn = e.vload(P.q(b, k), n) + pa + e.template matvec<true>(L.sA, L.vb, h, m, n);
         wg_sync();
         to_lds_sym(e, t, L.sP);
         e.store_sym(t, Pst + (int64_t)k * p.srec, n);
@@ -1221,20 +1219,20 @@ __device__ __forceinline__ void plain_body(Lds3<E>& L, const Plan& p, const In<S
             stage(e, L.sX, P.A(b, k), n, n, n);
         }
         wg_sync();
-        const T lam = e.template matvec<false>(L.sP, x, L.vb[0], n, n) + e.vload(Pst + (int64_t)k * p.srec + nn, n);
+        const T lam = e.template matvec<false>(L.sP, L.vb, x, n, n) + e.vload(Pst + (int64_t)k * p.srec + nn, n);
         e.vstore(out.x + (b * (N + 1) + k) * n, n, x);
         e.vstore(out.lam + (b * (N + 1) + k) * n, n, lam);
         fin = fin && (e.lg >= n || (finite_(x) && finite_(lam)));
         if (k == N) break;
-        const T u = e.template matvec<false>(L.sA, x, L.vb[1], n, m) + e.vload(inst + p.o_kff + (int64_t)k * m, m);
+        const T u = e.template matvec<false>(L.sA, L.vb, x, n, m) + e.vload(inst + p.o_kff + (int64_t)k * m, m);
         e.vstore(out.u + (b * N + k) * m, m, u);
         fin = fin && (e.lg >= m || finite_(u));
         wg_sync();
-        T xn = e.template matvec<false>(L.sX, x, L.vb[0], n, n) + e.vload(P.c(b, k), n);
+        T xn = e.template matvec<false>(L.sX, L.vb, x, n, n) + e.vload(P.c(b, k), n);
         wg_sync();
         stage(e, L.sA, P.B(b, k), n, m, m);
         wg_sync();
-        xn += e.template matvec<false>(L.sA, u, L.vb[1], m, n);
+        xn += e.template matvec<false>(L.sA, L.vb, u, m, n);
         x = xn;
     }
     if (!wave_all(fin)) set_status(out.status, b, 1);
