@@ -167,7 +167,12 @@ int lqr_timing_report(lqr_handle_t h, char* buf, size_t len);
  *            wavefront per task), 2 = matrix-core workgroups (one 256-thread
  *            workgroup per task, products on MFMA)
  *   fused    -1 = default (level by level), 0 = level-by-level launches of the
- *            vector-only passes, 1 = one workgroup per instance
+ *            vector-only passes, 1 = one workgroup per instance for them,
+ *            2 = the whole solve (elements, scan, policy, forward scan,
+ *            recovery, residual, refinement) in one launch, one workgroup
+ *            of several wavefronts per instance (wavefront engine only; an
+ *            instance the FP32 pass flags for the FP64 fallback is then
+ *            recomputed whole with FP64 arithmetic by a second launch)
  *   big_grid 0 = default (512), else the workgroups / scratch slots of a
  *            matrix-core task launch
  *   ms       (lqr_autotune output) mean time of one solve with this mapping */
@@ -181,12 +186,14 @@ typedef struct {
 /* Pin (t != NULL) or clear (t == NULL) the mapping of the shape
  * (batch, N, n, m, dtype) on this handle; later lqr_workspace_size,
  * lqr_kkt_solve and lqr_kkt_residual calls of that shape use it.
- * LQR_EINVAL for an out-of-range field or engine 1 above order 64. */
+ * LQR_EINVAL for an out-of-range field, engine 1 above order 64, or fused 2
+ * with the matrix-core engine. */
 int lqr_set_tuning(lqr_handle_t h, int64_t batch, int N, int n, int m, int32_t dtype, const lqr_tuning* t);
 
 /* Autotuner: solves the given problem (same arguments as lqr_kkt_solve)
- * once per candidate mapping -- each engine that can take the shape, both
- * forms of the vector-only passes, matrix-core grids of 256 / 512 / 1024
+ * once per candidate mapping -- each engine that can take the shape, each
+ * form of the passes (fused 0 / 1, and 2 on the wavefront engine),
+ * matrix-core grids of 256 / 512 / 1024
  * workgroups -- then `reps` more times on the stream, timed with HIP events;
  * candidates whose status words are not clean (other than the FP64-fallback
  * bit) or whose workspace does not fit are skipped.  The fastest mapping is

@@ -350,20 +350,24 @@ def autotune(A, B, c, Q, R, M, q, r, x0, *, method: str = "scan", refine: int | 
     _check(_lib.lqr_autotune(handle(device), s, batch, N, n, m, *[d[k].data_ptr() for k in FIELDS],
                              *[t.data_ptr() for t in out], ws.data_ptr(), ws.numel(), ctypes.byref(o), int(reps),
                              ctypes.byref(best)))
-    return {"engine": {1: "wavefront", 2: "matrix-core"}[best.engine], "fused": bool(best.fused),
+    return {"engine": {1: "wavefront", 2: "matrix-core"}[best.engine], "fused": int(best.fused),
             "big_grid": int(best.big_grid), "ms": float(best.ms)}
 
 
 def set_tuning(batch: int, N: int, n: int, m: int, dtype=torch.float32, *, engine: str | None = None,
-               fused: bool | None = None, big_grid: int = 0, device: int = 0, clear: bool = False):
-    """Pin (or clear) the mapping of a problem shape on the device's handle."""
+               fused: bool | int | None = None, big_grid: int = 0, device: int = 0, clear: bool = False):
+    """Pin (or clear) the mapping of a problem shape on the device's handle.
+
+    fused: None = default; 0 / False = vector-only passes level by level;
+    1 / True = one workgroup per instance for them; 2 = the whole solve in
+    one launch (wavefront engine)."""
     dt = LQR_F32 if dtype == torch.float32 else LQR_F64
     if clear:
         _check(_lib.lqr_set_tuning(handle(device), batch, N, n, m, dt, None))
         return
     t = lqr_tuning()
     t.engine = {None: 0, "wavefront": 1, "matrix-core": 2}[engine]
-    t.fused = -1 if fused is None else int(bool(fused))
+    t.fused = -1 if fused is None else int(fused)
     t.big_grid = int(big_grid)
     _check(_lib.lqr_set_tuning(handle(device), batch, N, n, m, dt, ctypes.byref(t)))
 

@@ -129,15 +129,25 @@ struct Lds3 : Lds<E> {
     typename E::T sP[E::MAT];
 };
 
-// strided cooperative copy of `count` elements (every thread of the
-// workgroup; element i < blockDim.x is handled by thread i)
-template <typename D, typename S>
+// Task units.  A task runs on NTU threads (a power of two): one wavefront
+// (64) for the wavefront engine, the whole 256-thread workgroup for the
+// large-block engine.  NTU = 0 means the whole workgroup.  The fused solve
+// runs several wavefront tasks side by side in one workgroup, so the task
+// bodies use the unit-relative thread index.
+template <int NTU>
+__device__ __forceinline__ int unit_tid() { return NTU ? (int)(threadIdx.x & (NTU - 1)) : (int)threadIdx.x; }
+template <int NTU>
+__device__ __forceinline__ int unit_nt() { return NTU ? NTU : (int)blockDim.x; }
+
+// strided cooperative copy of `count` elements (every thread of the task
+// unit; element i < unit size is handled by thread i)
+template <int NTU = 0, typename D, typename S>
 __device__ __forceinline__ void coop_copy(D* dst, const S* src, int count) {
-    for (int i = threadIdx.x; i < count; i += blockDim.x) dst[i] = D(src[i]);
+    for (int i = unit_tid<NTU>(); i < count; i += unit_nt<NTU>()) dst[i] = D(src[i]);
 }
-template <typename D>
+template <int NTU = 0, typename D>
 __device__ __forceinline__ void coop_zero(D* dst, int count) {
-    for (int i = threadIdx.x; i < count; i += blockDim.x) dst[i] = D(0);
+    for (int i = unit_tid<NTU>(); i < count; i += unit_nt<NTU>()) dst[i] = D(0);
 }
 
 // load a rows x cols global matrix (optionally transposed) into an LDS slot
@@ -167,8 +177,9 @@ __device__ __forceinline__ void negate(typename E::Tile& t) {
 
 // reciprocal diagonal of a staged lower-triangular factor
 
+template <int NTU = 0>
 __device__ __forceinline__ void set_status(int32_t* status, int64_t b, int bits) {
-    if (threadIdx.x == 0) atomicOr(status + b, bits);
+    if (unit_tid<NTU>() == 0) atomicOr(status + b, bits);
 }
 
 
@@ -177,35 +188,38 @@ __device__ __forceinline__ void set_status(int32_t* status, int64_t b, int bits)
 // whose condition estimate (max L_ii / min L_ii)^2 exceeds the threshold
 // appends its task id; the FP64 instance of the same kernel then drains the
 // queue with a small grid (no host synchronization, near-free when empty).
+// A queue without an id list (the fused solve) records only the status bit:
+// there the whole instance is redone in FP64.
 // ---------------------------------------------------------------------------
 struct FbQueue {
     int32_t* count;
     int32_t* ids;
 };
 
+template <int NTU = 0>
 __device__ __forceinline__ void fb_push(FbQueue q, int64_t task) {
-    if (threadIdx.x == 0) {
+    if (q.ids && unit_tid<NTU>() == 0) {
         const int slot = atomicAdd(q.count, 1);
         q.ids[slot] = (int32_t)task;
     }
 }
 
 // decide what a finished factorization means for this task
-template <bool FB, typename T>
+template <bool FB, int NTU = 0, typename T>
 __device__ __forceinline__ void fb_decide(const Plan& p, bool ok, T kappa, int64_t b, int64_t task, FbQueue q,
                                           int32_t* status, int failbit) {
     if (!FB) {
         const bool bad = !ok || !(kappa <= T(p.cond_thr));
         if (bad) {
             if (p.fallback) {
-                fb_push(q, task);
-                set_status(status, b, 8);
+                fb_push<NTU>(q, task);
+                set_status<NTU>(status, b, 8);
             } else if (!ok) {
-                set_status(status, b, failbit);
+                set_status<NTU>(status, b, failbit);
             }
         }
     } else if (!ok) {
-        set_status(status, b, failbit);
+        set_status<NTU>(status, b, failbit);
     }
 }
 
@@ -277,7 +291,7 @@ template <typename S, class E, bool FB, int MB>
 __device__ __forceinline__ void element_task(Lds<E>& L, const Plan& p, const In<S>& in, S* ws, int32_t* status, FbQueue q,
                              int64_t task) {
     using T = typename E::T;
-    const E e(threadIdx.x);
+    const E e(unit_tid<E::NT>());
     const int N = p.N, n = p.n, m = p.m, nn = n * n;
     const int64_t b = task / (N + 1);
     const int k = (int)(task % (N + 1));
@@ -285,10 +299,10 @@ __device__ __forceinline__ void element_task(Lds<E>& L, const Plan& p, const In<
     const Ptr<S> P(p, in);
     if (k == N) {
         if (FB) return;
-        coop_zero(rec, 2 * nn);
-        coop_copy(rec + 2 * nn, P.Q(b, N), nn);
-        coop_zero(rec + 3 * nn, n);
-        coop_copy(rec + 3 * nn + n, P.q(b, N), n);
+        coop_zero<E::NT>(rec, 2 * nn);
+        coop_copy<E::NT>(rec + 2 * nn, P.Q(b, N), nn);
+        coop_zero<E::NT>(rec + 3 * nn, n);
+        coop_copy<E::NT>(rec + 3 * nn + n, P.q(b, N), n);
         return;
     }
     typename E::Tile tR;
@@ -296,7 +310,7 @@ __device__ __forceinline__ void element_task(Lds<E>& L, const Plan& p, const In<
     T dmin, dmax, nov[1];
     T dlA;
     const bool ok = e.template chol<0, MB>(tR, m, L.cb, dlA, nov, dmin, dmax);
-    fb_decide<FB>(p, ok, cond_est(dmin, dmax), b, task, q, status, 2);
+    fb_decide<FB, E::NT>(p, ok, cond_est(dmin, dmax), b, task, q, status, 2);
     e.to_lds(tR, L.sA);
     typename E::Tile W[2];
     e.template load<true>(W[0], P.B(b, k), m, n, m);   // B' (m x n)
@@ -469,7 +483,7 @@ __device__ __forceinline__ void combine(const E& e, Lds<E>& L, int n, const S* e
 
 template <typename S, class E, bool FB>
 __device__ __forceinline__ void up_task(Lds<E>& L, const Plan& p, S* ws, int lvl, int32_t* status, FbQueue q, int64_t task) {
-    const E e(threadIdx.x);
+    const E e(unit_tid<E::NT>());
     const int n = p.n, nn = n * n;
     const int cout = p.rt.cnt[lvl + 1], cin = p.rt.cnt[lvl];
     const int64_t b = task / cout;
@@ -478,7 +492,7 @@ __device__ __forceinline__ void up_task(Lds<E>& L, const Plan& p, S* ws, int lvl
     const S* e1 = base + (int64_t)(p.rt.off[lvl] + 2 * i) * p.rec;
     S* out = base + (int64_t)(p.rt.off[lvl + 1] + i) * p.rec;
     if (2 * i + 1 >= cin) {
-        if (!FB) coop_copy(out, e1, p.rec);
+        if (!FB) coop_copy<E::NT>(out, e1, p.rec);
         return;
     }
     const S* e2 = e1 + p.rec;
@@ -486,7 +500,7 @@ __device__ __forceinline__ void up_task(Lds<E>& L, const Plan& p, S* ws, int lvl
     typename E::T kappa;
     combine<E, false>(e, L, n, e1, e2 + 2 * nn, e2 + 3 * nn + n, e2, out, out + nn, out + 2 * nn, out + 3 * nn,
                       out + 3 * nn + n, ok, kappa);
-    fb_decide<FB>(p, ok, kappa, b, task, q, status, 4);
+    fb_decide<FB, E::NT>(p, ok, kappa, b, task, q, status, 4);
 }
 
 template <typename S, class E, bool FB>
@@ -501,20 +515,24 @@ __global__ __launch_bounds__(E::NT) void k_up(Plan p, S* ws, int lvl, int32_t* s
 
 // root of the reverse tree: its (P, p) is the complete suffix starting at 0
 template <typename S>
-__global__ void k_root(Plan p, S* ws) {
-    const int64_t b = blockIdx.x;
+__device__ __forceinline__ void root_body(const Plan& p, S* ws, int64_t b) {
     const int n = p.n, nn = n * n;
     const int root = p.rt.off[p.rt.nlev - 1];
     const S* src = ws + b * p.stride + p.o_tree + (int64_t)root * p.rec;
     S* dst = ws + b * p.stride + p.o_suf + (int64_t)root * p.srec;
-    coop_copy(dst, src + 2 * nn, nn);          // P
-    coop_copy(dst + nn, src + 3 * nn + n, n);  // p (the record stores b between P and p)
+    coop_copy<64>(dst, src + 2 * nn, nn);          // P
+    coop_copy<64>(dst + nn, src + 3 * nn + n, n);  // p (the record stores b between P and p)
+}
+
+template <typename S>
+__global__ void k_root(Plan p, S* ws) {
+    root_body<S>(p, ws, (int64_t)blockIdx.x);
 }
 
 // down-sweep at level lvl: odd node j gets node_j (x) suffix(level lvl+1, (j+1)/2)
 template <typename S, class E, bool FB>
 __device__ __forceinline__ void down_task(Lds<E>& L, const Plan& p, S* ws, int lvl, int32_t* status, FbQueue q, int64_t task) {
-    const E e(threadIdx.x);
+    const E e(unit_tid<E::NT>());
     const int n = p.n, nn = n * n;
     const int half = p.rt.cnt[lvl] / 2;
     const int64_t b = task / half;
@@ -526,8 +544,8 @@ __device__ __forceinline__ void down_task(Lds<E>& L, const Plan& p, S* ws, int l
     const int i1 = (j + 1) / 2;
     if (i1 >= p.rt.cnt[lvl + 1]) {
         if (!FB) {
-            coop_copy(out, node + 2 * nn, nn);
-            coop_copy(out + nn, node + 3 * nn + n, n);
+            coop_copy<E::NT>(out, node + 2 * nn, nn);
+            coop_copy<E::NT>(out + nn, node + 3 * nn + n, n);
         }
         return;
     }
@@ -536,7 +554,7 @@ __device__ __forceinline__ void down_task(Lds<E>& L, const Plan& p, S* ws, int l
     typename E::T kappa;
     combine<E, true>(e, L, n, node, s2, s2 + nn, (const S*)nullptr, (S*)nullptr, (S*)nullptr, out,
                      (S*)nullptr, out + nn, ok, kappa);
-    fb_decide<FB>(p, ok, kappa, b, task, q, status, 4);
+    fb_decide<FB, E::NT>(p, ok, kappa, b, task, q, status, 4);
 }
 
 template <typename S, class E, bool FB>
@@ -560,7 +578,7 @@ template <typename S, class E, bool FB, int MB>
 __device__ __forceinline__ void policy_task(Lds<E>& L, const Plan& p, const In<S>& in, S* ws, int32_t* status, FbQueue q,
                             int64_t task) {
     using T = typename E::T;
-    const E e(threadIdx.x);
+    const E e(unit_tid<E::NT>());
     const int N = p.N, n = p.n, m = p.m, nn = n * n;
     const int64_t b = task / N;
     const int k = (int)(task % N);
@@ -588,7 +606,7 @@ __device__ __forceinline__ void policy_task(Lds<E>& L, const Plan& p, const In<S
     T dmin, dmax, nov[1];
     T dlA;
     const bool ok = e.template chol<0, MB>(tG, m, L.cb, dlA, nov, dmin, dmax);
-    fb_decide<FB>(p, ok, cond_est(dmin, dmax), b, task, q, status, 2);
+    fb_decide<FB, E::NT>(p, ok, cond_est(dmin, dmax), b, task, q, status, 2);
     e.to_lds(tG, L.sA);                                   // sA = L_G
     wg_sync();
     typename E::Tile KK[1];
@@ -634,7 +652,7 @@ __global__ __launch_bounds__(E::NT) void k_policy(Plan p, In<S> in, S* ws, int32
 template <typename S, class E, bool VEC, class LT>
 __device__ __forceinline__ void fup_body(LT& L, Plan p, S* ws, int lvl, int64_t tid) {
     using T = typename E::T;
-    const E e(threadIdx.x);
+    const E e(unit_tid<E::NT>());
     const int n = p.n, nn = n * n;
     const int cout = p.ft.cnt[lvl + 1], cin = p.ft.cnt[lvl];
     const int64_t b = tid / cout;
@@ -644,8 +662,8 @@ __device__ __forceinline__ void fup_body(LT& L, Plan p, S* ws, int lvl, int64_t 
     const S* l = base + (int64_t)(p.ft.off[lvl] + 2 * i) * p.frec;
     S* out = base + (int64_t)(p.ft.off[lvl + 1] + i) * p.frec;
     if (2 * i + 1 >= cin) {
-        if (VEC) coop_copy(out + nn, l + nn, n);
-        else coop_copy(out, l, p.frec);
+        if (VEC) coop_copy<E::NT>(out + nn, l + nn, n);
+        else coop_copy<E::NT>(out, l, p.frec);
         return;
     }
     const S* r = l + p.frec;
@@ -679,7 +697,7 @@ __device__ __forceinline__ void froot_body(Plan p, S* ws, const S* x0, int64_t x
     const int64_t b = tid;
     LQR_GATE(p, b);
     const int root = p.ft.off[p.ft.nlev - 1];
-    coop_copy(ws + b * p.stride + p.o_xs + (int64_t)root * p.n, x0 + b * x0_stride, p.n);
+    coop_copy<64>(ws + b * p.stride + p.o_xs + (int64_t)root * p.n, x0 + b * x0_stride, p.n);
 }
 
 template <typename S>
@@ -692,7 +710,7 @@ __global__ __launch_bounds__(64) void k_froot(Plan p, S* ws, const S* x0, int64_
 template <typename S, class E, class LT>
 __device__ __forceinline__ void fdown_body(LT& L, Plan p, S* ws, int lvl, int64_t tid) {
     using T = typename E::T;
-    const E e(threadIdx.x);
+    const E e(unit_tid<E::NT>());
     const int n = p.n, nn = n * n;
     const int cnt = p.ft.cnt[lvl];
     const int64_t b = tid / cnt;
@@ -702,7 +720,7 @@ __device__ __forceinline__ void fdown_body(LT& L, Plan p, S* ws, int lvl, int64_
     const S* par = inst + p.o_xs + (int64_t)(p.ft.off[lvl + 1] + j / 2) * n;
     S* out = inst + p.o_xs + (int64_t)(p.ft.off[lvl] + j) * n;
     if ((j & 1) == 0) {
-        coop_copy(out, par, n);
+        coop_copy<E::NT>(out, par, n);
         return;
     }
     const S* sib = inst + p.o_ftree + (int64_t)(p.ft.off[lvl] + j - 1) * p.frec;
@@ -723,7 +741,7 @@ __global__ __launch_bounds__(E::NT) void k_fdown(Plan p, S* ws, int lvl) {
 template <typename S, class E, bool ADD, class LT>
 __device__ __forceinline__ void recover_body(LT& L, Plan p, S* ws, Out<S> out, int64_t tid) {
     using T = typename E::T;
-    const E e(threadIdx.x);
+    const E e(unit_tid<E::NT>());
     const int N = p.N, n = p.n, m = p.m, nn = n * n;
     const int64_t b = tid / (N + 1);
     const int k = tid % (N + 1);
@@ -762,7 +780,7 @@ __device__ __forceinline__ void recover_body(LT& L, Plan p, S* ws, Out<S> out, i
         uo[e.lg] = S(uv);
         fin = fin && finite_(uv);
     }
-    if (!E::all(fin)) set_status(out.status, b, 1);
+    if (!E::all(fin)) set_status<E::NT>(out.status, b, 1);
 }
 
 template <typename S, class E, bool ADD>
@@ -785,7 +803,7 @@ template <typename S, class E, bool CORR>
 __device__ __forceinline__ void resid_body(ResidLds<E>& RL, Plan p, In<S> in, const S* xs_, const S* us_, const S* ls_,
                                               S* ws, double* dws, int64_t tid) {
     static_assert(sizeof(typename E::T) == 8, "residual runs in FP64");
-    const E e(threadIdx.x);
+    const E e(unit_tid<E::NT>());
     const int N = p.N, n = p.n, m = p.m;
     const int64_t b = tid / (N + 1);
     const int k = tid % (N + 1);
@@ -831,7 +849,7 @@ __device__ __forceinline__ void resid_body(ResidLds<E>& RL, Plan p, In<S> in, co
     }
     rr = E::sum(rr);
     bb = E::sum(bb);
-    if (threadIdx.x == 0) {
+    if (unit_tid<E::NT>() == 0) {
         dws[b * p.dstride + 2 * k] = rr;
         dws[b * p.dstride + 2 * k + 1] = bb;
     }
@@ -872,7 +890,7 @@ __global__ void k_resid_reduce(Plan p, const D* dws, D* rel, int32_t* active_out
 template <typename S, class E, class LT>
 __device__ __forceinline__ void ref_d_body(LT& L, Plan p, S* ws, int64_t tid) {
     using T = typename E::T;
-    const E e(threadIdx.x);
+    const E e(unit_tid<E::NT>());
     const int N = p.N, n = p.n, m = p.m;
     const int64_t b = tid / N;
     const int k = tid % N;
@@ -897,7 +915,7 @@ __global__ __launch_bounds__(E::NT) void k_ref_d(Plan p, S* ws) {
 template <typename S, class E, class LT>
 __device__ __forceinline__ void bvec_up_body(LT& L, Plan p, S* ws, int lvl, int64_t tid) {
     using T = typename E::T;
-    const E e(threadIdx.x);
+    const E e(unit_tid<E::NT>());
     const int n = p.n;
     const int cout = p.ft.cnt[lvl + 1], cin = p.ft.cnt[lvl];
     const int64_t b = tid / cout;
@@ -907,7 +925,7 @@ __device__ __forceinline__ void bvec_up_body(LT& L, Plan p, S* ws, int lvl, int6
     const S* wl = inst + p.o_w + (int64_t)(p.ft.off[lvl] + 2 * i) * n;
     S* wo = inst + p.o_w + (int64_t)(p.ft.off[lvl + 1] + i) * n;
     if (2 * i + 1 >= cin) {
-        coop_copy(wo, wl, n);
+        coop_copy<E::NT>(wo, wl, n);
         return;
     }
     const T w = e.template gmv<true>(inst + p.o_ftree + (int64_t)(p.ft.off[lvl] + 2 * i) * p.frec, n, n, n,
@@ -927,8 +945,8 @@ __device__ __forceinline__ void broot_body(Plan p, S* ws, int64_t tid) {
     LQR_GATE(p, b);
     S* inst = ws + b * p.stride;
     const int root = p.ft.off[p.ft.nlev - 1];
-    coop_copy(inst + p.o_pend + (int64_t)root * p.n, inst + p.o_qp + (int64_t)p.N * p.n, p.n);
-    coop_copy(inst + p.o_pp + (int64_t)p.N * p.n, inst + p.o_qp + (int64_t)p.N * p.n, p.n);
+    coop_copy<64>(inst + p.o_pend + (int64_t)root * p.n, inst + p.o_qp + (int64_t)p.N * p.n, p.n);
+    coop_copy<64>(inst + p.o_pp + (int64_t)p.N * p.n, inst + p.o_qp + (int64_t)p.N * p.n, p.n);
 }
 
 template <typename S>
@@ -941,7 +959,7 @@ __global__ __launch_bounds__(64) void k_broot(Plan p, S* ws) {
 template <typename S, class E, class LT>
 __device__ __forceinline__ void bvec_down_body(LT& L, Plan p, S* ws, int lvl, int64_t tid) {
     using T = typename E::T;
-    const E e(threadIdx.x);
+    const E e(unit_tid<E::NT>());
     const int n = p.n;
     const int cnt = p.ft.cnt[lvl];
     const int64_t b = tid / cnt;
@@ -951,7 +969,7 @@ __device__ __forceinline__ void bvec_down_body(LT& L, Plan p, S* ws, int lvl, in
     const S* par = inst + p.o_pend + (int64_t)(p.ft.off[lvl + 1] + j / 2) * n;
     S* out = inst + p.o_pend + (int64_t)(p.ft.off[lvl] + j) * n;
     if ((j & 1) || j + 1 >= cnt) {
-        coop_copy(out, par, n);
+        coop_copy<E::NT>(out, par, n);
         return;
     }
     const T v = e.template gmv<true>(inst + p.o_ftree + (int64_t)(p.ft.off[lvl] + j + 1) * p.frec, n, n, n,
@@ -987,7 +1005,7 @@ __device__ __forceinline__ typename E::T lane_trsv(const E& e, const S* Lm, int 
 template <typename S, class E, class LT>
 __device__ __forceinline__ void ref_kff_body(LT& L, Plan p, In<S> in, S* ws, int64_t tid) {
     using T = typename E::T;
-    const E e(threadIdx.x);
+    const E e(unit_tid<E::NT>());
     const int N = p.N, n = p.n, m = p.m, nn = n * n;
     const int64_t b = tid / N;
     const int k = tid % N;
@@ -1020,6 +1038,16 @@ template <typename S, class E>
 __global__ __launch_bounds__(E::NT) void k_ref_kff(Plan p, In<S> in, S* ws) {
     __shared__ VecLds<E> L;
     ref_kff_body<S, E>(L, p, in, ws, (int64_t)blockIdx.x);
+}
+
+// relative KKT residual of instance b from its per-stage partial sums
+__device__ __forceinline__ double resid_of_parts(const Plan& p, const double* dws, int64_t b) {
+    double rr = 0.0, bb = 0.0;
+    for (int k = 0; k <= p.N; ++k) {
+        rr += dws[b * p.dstride + 2 * k];
+        bb += dws[b * p.dstride + 2 * k + 1];
+    }
+    return bb > 0.0 ? __builtin_sqrt(rr) / __builtin_sqrt(bb) : __builtin_sqrt(rr);
 }
 
 // ---------------------------------------------------------------------------
@@ -1069,11 +1097,9 @@ __global__ __launch_bounds__(E::NT) void k_fwd_inst(Plan p, S* ws, const S* x0, 
 }
 
 // one whole refinement sweep of one instance (after its residual pass)
-template <typename S, class E>
-__global__ __launch_bounds__(E::NT) void k_refine_inst(Plan p, In<S> in, S* ws, Out<S> out) {
-    __shared__ VecLds<E> L;
-    const int64_t b = blockIdx.x;
-    LQR_GATE(p, b);
+template <typename S, class E, class LT>
+__device__ __forceinline__ void refine_inst_body(LT& L, const Plan& p, const In<S>& in, S* ws, const Out<S>& out,
+                                                 int64_t b) {
     const int N = p.N;
     for (int k = 0; k < N; ++k) {
         ref_d_body<S, E>(L, p, ws, b * N + k);
@@ -1102,8 +1128,34 @@ __global__ __launch_bounds__(E::NT) void k_refine_inst(Plan p, In<S> in, S* ws, 
     fwd_inst_body<S, E, true, true>(L, p, ws, (const S*)(ws + p.o_x0p), p.stride, out, b);
 }
 
+template <typename S, class E>
+__global__ __launch_bounds__(E::NT) void k_refine_inst(Plan p, In<S> in, S* ws, Out<S> out) {
+    __shared__ VecLds<E> L;
+    const int64_t b = blockIdx.x;
+    LQR_GATE(p, b);
+    refine_inst_body<S, E>(L, p, in, ws, out, b);
+}
+
 // FP64 residual of one instance, all stages, reduced in place:
 // rel[b] = ||r|| / ||(x0, c, q, r)|| (and active_out[b] = rel > tol)
+template <typename S, class E, bool CORR>
+__device__ __forceinline__ double resid_inst_body(ResidLds<E>& RL, const Plan& p, const In<S>& in, const S* xs_,
+                                                  const S* us_, const S* ls_, S* ws, double* dws, double* rel,
+                                                  int32_t* active_out, double tol, int64_t b) {
+    double res = 0.0;   // returned in the task unit's thread 0
+    for (int k = 0; k <= p.N; ++k) {
+        resid_body<S, E, CORR>(RL, p, in, xs_, us_, ls_, ws, dws, b * (p.N + 1) + k);
+        E::sync();
+    }
+    if (unit_tid<E::NT>() == 0) {   // the partial sums were written by this lane
+        const double r = resid_of_parts(p, dws, b);
+        if (rel) rel[b] = r;
+        if (active_out) active_out[b] = !(r <= tol);
+        res = r;
+    }
+    return res;
+}
+
 template <typename S, class E, bool CORR>
 __global__ __launch_bounds__(E::NT) void k_resid_inst(Plan p, In<S> in, const S* xs_, const S* us_, const S* ls_,
                                                    S* ws, double* dws, double* rel, int32_t* active_out,
@@ -1111,20 +1163,7 @@ __global__ __launch_bounds__(E::NT) void k_resid_inst(Plan p, In<S> in, const S*
     __shared__ ResidLds<E> RL;
     const int64_t b = blockIdx.x;
     LQR_GATE(p, b);
-    for (int k = 0; k <= p.N; ++k) {
-        resid_body<S, E, CORR>(RL, p, in, xs_, us_, ls_, ws, dws, b * (p.N + 1) + k);
-        E::sync();
-    }
-    if (threadIdx.x == 0) {   // the partial sums were written by this lane
-        double rr = 0.0, bb = 0.0;
-        for (int k = 0; k <= p.N; ++k) {
-            rr += dws[b * p.dstride + 2 * k];
-            bb += dws[b * p.dstride + 2 * k + 1];
-        }
-        const double r = bb > 0.0 ? __builtin_sqrt(rr) / __builtin_sqrt(bb) : __builtin_sqrt(rr);
-        if (rel) rel[b] = r;
-        if (active_out) active_out[b] = !(r <= tol);
-    }
+    resid_inst_body<S, E, CORR>(RL, p, in, xs_, us_, ls_, ws, dws, rel, active_out, tol, b);
 }
 
 // ---------------------------------------------------------------------------
@@ -1135,7 +1174,7 @@ __global__ __launch_bounds__(E::NT) void k_resid_inst(Plan p, In<S> in, const S*
 template <typename S, class E, int MB>
 __device__ __forceinline__ void plain_body(Lds3<E>& L, const Plan& p, const In<S>& in, const Out<S>& out, S* ws) {
     using T = typename E::T;
-    const E e(threadIdx.x);
+    const E e(unit_tid<E::NT>());
     const int N = p.N, n = p.n, m = p.m, nn = n * n;
     const int64_t b = blockIdx.x;
     const Ptr<S> P(p, in);
@@ -1207,7 +1246,7 @@ __device__ __forceinline__ void plain_body(Lds3<E>& L, const Plan& p, const In<S
         e.store_sym(t, Pst + (int64_t)k * p.srec, n);
         e.vstore(Pst + (int64_t)k * p.srec + nn, n, pn);
     }
-    if (!ok) set_status(out.status, b, 2);
+    if (!ok) set_status<E::NT>(out.status, b, 2);
     // forward pass and costates
     T x = e.vload(P.x0(b), n);
     bool fin = true;
@@ -1235,13 +1274,157 @@ __device__ __forceinline__ void plain_body(Lds3<E>& L, const Plan& p, const In<S
         xn += e.template matvec<false>(L.sA, L.vb, u, m, n);
         x = xn;
     }
-    if (!wave_all(fin)) set_status(out.status, b, 1);
+    if (!wave_all(fin)) set_status<E::NT>(out.status, b, 1);
 }
 
 template <typename S, class E, int MB>
 __global__ __launch_bounds__(64) void k_plain(Plan p, In<S> in, Out<S> out, S* ws) {
     __shared__ Lds3<E> L;
     plain_body<S, E, MB>(L, p, in, out, ws);
+}
+
+// ---------------------------------------------------------------------------
+// Fused solve (wavefront engine): one workgroup of W wavefronts runs one
+// instance from its elements to its last refinement sweep (Sec. II-D
+// elements, reverse scan, policy, forward scan, recovery; FP64 residual and
+// refinement) in a single launch.  Each phase of the launch sequence (the
+// stages of a per-stage pass, the nodes of one tree level) becomes a loop
+// whose tasks are spread over the wavefronts, each wavefront with LDS slots
+// of its own, and a workgroup barrier separates dependent phases.  Every
+// task body is the one the launch sequence uses, in the same phase order,
+// so an instance gets the bits of the launched form.
+// REDO: the pass over the instances the FP32 pass flagged for the FP64
+// fallback (status bit 8): the whole instance is recomputed with the FP64
+// engine (plan with fallback off, so a failure there sets the failure bits).
+// ---------------------------------------------------------------------------
+template <class E, class E64>
+struct FusedLds {
+    Lds<E> m;          // matrix tasks
+    VecLds<E> v;       // vector-only tasks
+    ResidLds<E64> r;   // FP64 residual
+};
+
+template <class E>
+constexpr int fused_waves() {
+    using F = FusedLds<E, Eng<double, E::G, E::TS>>;
+    constexpr int lim = E::TS <= 2 ? 8 : 4;
+    constexpr int w = (int)(65536 / sizeof(F));
+    return w < 1 ? 1 : (w > lim ? lim : w);
+}
+
+template <typename S, class E, class E64, int MB, bool REDO>
+__global__ __launch_bounds__(64 * fused_waves<E>()) void k_solve_fused(Plan p, In<S> in, Out<S> out, S* ws,
+                                                                      double* dws, double* rel_out, Warm<S> warm,
+                                                                      int refine) {
+    static_assert(!E::BIG && E::NT == 64, "wavefront engine only");
+    constexpr int W = fused_waves<E>();
+    __shared__ FusedLds<E, E64> F[W];
+    __shared__ double sh_rel;
+    const int wv = (int)(threadIdx.x >> 6);
+    const int64_t b = blockIdx.x;
+    const int N = p.N, n = p.n;
+    const FbQueue nq{nullptr, nullptr};
+    auto& Lm = F[wv].m;
+    auto& Lv = F[wv].v;
+    auto& Lr = F[wv].r;
+    // one phase: tasks t = wv, wv + W, ... < count, then the workgroup barrier
+    auto phase = [&](int count, auto&& body) {
+        for (int t = wv; t < count; t += W) {
+            body(t);
+            E::sync();
+        }
+        __syncthreads();
+    };
+    if (REDO) {
+        // bit 8 is only ever added, so every thread sees the same decision
+        if (!(out.status[b] & 8)) return;
+    } else if (threadIdx.x == 0) {
+        out.status[b] = 0;
+    }
+    __syncthreads();
+    // elements; reverse scan (up-sweep, root, down-sweep); policy and
+    // closed-loop maps; up-sweep of the forward tree
+    phase(N + 1, [&](int k) { element_task<S, E, false, MB>(Lm, p, in, ws, out.status, nq, b * (N + 1) + k); });
+    for (int l = 0; l + 1 < p.rt.nlev; ++l) {
+        const int c = p.rt.cnt[l + 1];
+        phase(c, [&](int i) { up_task<S, E, false>(Lm, p, ws, l, out.status, nq, b * c + i); });
+    }
+    phase(1, [&](int) { root_body<S>(p, ws, b); });
+    for (int l = p.rt.nlev - 2; l >= 0; --l) {
+        const int c = p.rt.cnt[l] / 2;
+        phase(c, [&](int j) { down_task<S, E, false>(Lm, p, ws, l, out.status, nq, b * c + j); });
+    }
+    phase(N, [&](int k) { policy_task<S, E, false, MB>(Lm, p, in, ws, out.status, nq, b * N + k); });
+    for (int l = 0; l + 1 < p.ft.nlev; ++l) {
+        const int c = p.ft.cnt[l + 1];
+        phase(c, [&](int i) { fup_body<S, E, false>(Lm, p, ws, l, b * c + i); });
+    }
+    // forward down-sweep from a start state, then u_k, lambda_k (ADD: the
+    // refinement's correction is added to the outputs)
+    auto forward = [&](const S* x0, int64_t x0_stride, auto add) {
+        constexpr bool ADD = decltype(add)::value;
+        phase(1, [&](int) { froot_body<S>(p, ws, x0, x0_stride, b); });
+        for (int l = p.ft.nlev - 2; l >= 0; --l) {
+            const int c = p.ft.cnt[l];
+            phase(c, [&](int j) { fdown_body<S, E>(Lv, p, ws, l, b * c + j); });
+        }
+        phase(N + 1, [&](int k) { recover_body<S, E, ADD>(Lv, p, ws, out, b * (N + 1) + k); });
+    };
+    // FP64 residual of the current outputs (CORR: also the right-hand sides
+    // of the correction); the same value in every thread
+    auto residual = [&](auto corr) -> double {
+        constexpr bool CORR = decltype(corr)::value;
+        phase(N + 1, [&](int k) {
+            resid_body<S, E64, CORR>(Lr, p, in, (const S*)out.x, (const S*)out.u, (const S*)out.lam, ws, dws,
+                                     b * (N + 1) + k);
+        });
+        if (threadIdx.x == 0) {
+            const double r = resid_of_parts(p, dws, b);
+            sh_rel = r;
+            if (rel_out) rel_out[b] = r;
+        }
+        __syncthreads();
+        return sh_rel;
+    };
+    int sweeps = refine;
+    if (warm.x) {
+        const int cx = (N + 1) * n, cu = N * p.m;
+        for (int i = (int)threadIdx.x; i < cx; i += 64 * W) {
+            if (warm.x != out.x) out.x[b * cx + i] = warm.x[b * cx + i];
+            if (warm.lam != out.lam) out.lam[b * cx + i] = warm.lam[b * cx + i];
+        }
+        for (int i = (int)threadIdx.x; i < cu; i += 64 * W)
+            if (warm.u != out.u) out.u[b * cu + i] = warm.u[b * cu + i];
+        __syncthreads();
+        if (sweeps < 1) sweeps = 1;
+    } else {
+        forward(in.x0, (int64_t)n, std::false_type{});
+    }
+    // refinement sweeps while the residual is above the tolerance
+    bool changed = true;   // outputs changed since the last residual
+    for (int sw = 0; sw < sweeps; ++sw) {
+        const double r = residual(std::true_type{});
+        changed = false;
+        if (r <= p.refine_tol) break;
+        phase(N, [&](int k) { ref_d_body<S, E>(Lv, p, ws, b * N + k); });
+        for (int l = 0; l + 1 < p.ft.nlev; ++l) {
+            const int c = p.ft.cnt[l + 1];
+            phase(c, [&](int i) { bvec_up_body<S, E>(Lv, p, ws, l, b * c + i); });
+        }
+        phase(1, [&](int) { broot_body<S>(p, ws, b); });
+        for (int l = p.ft.nlev - 2; l >= 0; --l) {
+            const int c = p.ft.cnt[l];
+            phase(c, [&](int j) { bvec_down_body<S, E>(Lv, p, ws, l, b * c + j); });
+        }
+        phase(N, [&](int k) { ref_kff_body<S, E>(Lv, p, in, ws, b * N + k); });
+        for (int l = 0; l + 1 < p.ft.nlev; ++l) {
+            const int c = p.ft.cnt[l + 1];
+            phase(c, [&](int i) { fup_body<S, E, true>(Lv, p, ws, l, b * c + i); });
+        }
+        forward((const S*)(ws + p.o_x0p), p.stride, std::true_type{});
+        changed = true;
+    }
+    if (rel_out && changed) residual(std::false_type{});
 }
 
 }  // namespace lqr

@@ -77,7 +77,7 @@ int pick_ts(int n, int m) {
 // Mapping choices the autotuner may override (0 / -1: the default rule)
 struct Tuning {
     int engine = 0;     // 1: wavefront tiles, 2: matrix-core workgroups
-    int fused = -1;     // per-instance vector passes: 0 / 1
+    int fused = -1;     // vector passes level by level 0, per instance 1; 2: whole solve in one launch
     int big_grid = 0;   // workgroups (scratch slots) of a matrix-core task launch
 };
 
@@ -131,6 +131,7 @@ Plan make_plan(int64_t batch, int N, int n, int m, size_t esize, const lqr_opts&
     p.fallback = esize == 4 ? o.fallback : 0;   // the FP64 path has nothing to fall back to
     if (tun && tun->fused >= 0) p.fused = tun->fused;
     if (pick_ts(n, m, tun) == kBigTS) {
+        if (p.fused == 2) p.fused = 1;   // the one-launch solve is a wavefront-engine form
         const int64_t d = n > m ? n : m;
         p.scr_elems = align_up(8 * d * d + 64 * d, 64);
         const int64_t most = batch * (N + 1);
@@ -203,7 +204,7 @@ const char* const kFamNames[F_COUNT] = {
     "clear", "element", "element_fp64", "up", "root", "down", "policy", "policy_fp64", "fwd_up", "fwd_root",
     "fwd_down", "recover", "residual", "ref_d", "bwd_up", "bwd_root", "bwd_down", "ref_kff", "fwd_up_vec",
     "recover_add", "reduce", "plain_riccati", "up_fp64", "down_fp64", "fwd_inst", "refine_inst", "warm_copy",
-    "ragged_pack"};
+    "ragged_pack", "fused_solve", "fused_solve_fp64"};
 
 // Per-handle launch timer: two HIP events around every launch, read back by
 // lqr_timing_report.
@@ -571,10 +572,12 @@ int lqr_set_tuning(lqr_handle_t h, int64_t batch, int N, int n, int m, int32_t d
         h->tuned.erase(key);
         return LQR_OK;
     }
-    if (t->engine < 0 || t->engine > 2 || t->fused < -1 || t->fused > 1 || t->big_grid < 0)
+    if (t->engine < 0 || t->engine > 2 || t->fused < -1 || t->fused > 2 || t->big_grid < 0)
         return fail(LQR_EINVAL, "bad tuning (engine %d, fused %d, big_grid %d)", t->engine, t->fused, t->big_grid);
     if (t->engine == 1 && pick_ts(n, m) == kBigTS)
         return fail(LQR_EINVAL, "the wavefront engine takes orders up to 64 (n=%d m=%d)", n, m);
+    if (t->fused == 2 && (t->engine == 2 || pick_ts(n, m) == kBigTS))
+        return fail(LQR_EINVAL, "the one-launch solve runs on the wavefront engine (orders up to 64)");
     Tuning tu;
     tu.engine = t->engine;
     tu.fused = t->fused;
@@ -599,7 +602,8 @@ int lqr_autotune(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int 
     const bool small_ok = pick_ts(n, m) != kBigTS;
     for (int eng : {1, 2}) {
         if (eng == 1 && !small_ok) continue;
-        for (int fu : {0, 1}) {
+        for (int fu : {0, 1, 2}) {
+            if (eng == 2 && fu == 2) continue;
             if (eng == 1) {
                 Tuning t; t.engine = 1; t.fused = fu; cands.push_back(t);
             } else {

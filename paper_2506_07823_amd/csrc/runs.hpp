@@ -50,7 +50,7 @@ int with_mb(int m, Fn&& fn) {
 enum Fam {
     F_CLEAR, F_ELEM, F_ELEM_FB, F_UP, F_ROOT, F_DOWN, F_POLICY, F_POLICY_FB, F_FUP, F_FROOT, F_FDOWN,
     F_RECOVER, F_RESID, F_REF_D, F_BUP, F_BROOT, F_BDOWN, F_REF_KFF, F_FUPV, F_RECOVER_ADD, F_REDUCE,
-    F_PLAIN, F_UP_FB, F_DOWN_FB, F_FWD_INST, F_REFINE_INST, F_WARM, F_PACK, F_COUNT
+    F_PLAIN, F_UP_FB, F_DOWN_FB, F_FWD_INST, F_REFINE_INST, F_WARM, F_PACK, F_FUSED, F_FUSED_FB, F_COUNT
 };
 
 // Optional per-launch timer (HIP events around each launch on its stream),
@@ -142,12 +142,50 @@ struct Work {
     } while (0)
 
 // ----------------------------------------------------------------- solve
+// The whole scan solve in one launch per instance batch (wavefront engine;
+// plan.fused == 2), plus the FP64 redo launch over flagged instances.  The
+// flop and byte figures are those of the launch sequence it replaces.
+template <typename S, int TS>
+int run_fused(const Plan& p, hipStream_t s, const In<S>& in, const Out<S>& out, S* ws, double* dws, int refine,
+              double* resid_out, const Warm<S>& warm) {
+    using E = EngOf<S, TS>;
+    using E64 = EngOf<double, TS>;
+    static_assert(!E::BIG, "wavefront engine only");
+    const Work w(p, sizeof(S));
+    const double B = (double)p.batch;
+    const int N = p.N;
+    double u_up = 0, u_down = 0, u_fup = 0;
+    for (int l = 0; l + 1 < p.rt.nlev; ++l) u_up += p.rt.cnt[l] / 2, u_down += p.rt.cnt[l] / 2;
+    for (int l = 0; l + 1 < p.ft.nlev; ++l) u_fup += p.ft.cnt[l] / 2;
+    const double flops = B * (N * w.elem_f() + u_up * w.comb_f() + u_down * w.cheap_f() + N * w.pol_f() +
+                              u_fup * w.fup_f());
+    const double bytes = B * (N * w.elem_b() + u_up * w.comb_b() + u_down * w.cheap_b() + N * w.pol_b() +
+                              u_fup * w.fup_b());
+    return with_mb<TS>(p.m, [&](auto mb) {
+        constexpr int MB = decltype(mb)::value;
+        LCHK(launch_nt(64 * fused_waves<E>(), F_FUSED, flops, bytes, k_solve_fused<S, E, E64, MB, false>, p.batch,
+                       s, p, in, out, ws, dws, resid_out, warm, refine));
+        if constexpr (sizeof(S) == 4) {
+            if (p.fallback) {
+                Plan pf = p;
+                pf.fallback = 0;
+                LCHK(launch_nt(64 * fused_waves<E64>(), F_FUSED_FB, 0, 0, k_solve_fused<S, E64, E64, MB, true>,
+                               p.batch, s, pf, in, out, ws, dws, resid_out, warm, refine));
+            }
+        }
+        return LQR_OK;
+    });
+}
+
 template <typename S, int TS>
 int run_scan(const Plan& p, hipStream_t s, const In<S>& in, const Out<S>& out, S* ws, int32_t* iws,
              double* dws, int refine, double* resid_out, const Warm<S>& warm) {
     using E = EngOf<S, TS>;
     using E64 = EngOf<double, TS>;
     constexpr int NT = E::NT;
+    if constexpr (!E::BIG) {
+        if (p.fused == 2) return run_fused<S, TS>(p, s, in, out, ws, dws, refine, resid_out, warm);
+    }
     const Work w(p, sizeof(S));
     const double B = (double)p.batch;
     const int64_t Bi = p.batch;

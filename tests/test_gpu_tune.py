@@ -27,7 +27,7 @@ def _batch(count, dtype):
     return synth.gen_batch(lambda i: synth.gen_rand(N, n, m, seed=[800, i]), count, dtype)
 
 
-@pytest.mark.parametrize("engine,fused,grid", [("wavefront", False, 0), ("wavefront", True, 0),
+@pytest.mark.parametrize("engine,fused,grid", [("wavefront", False, 0), ("wavefront", True, 0), ("wavefront", 2, 0),
                                                ("matrix-core", False, 256), ("matrix-core", True, 512)])
 def test_every_mapping_meets_the_bar(engine, fused, grid):
     import torch
@@ -52,12 +52,13 @@ def test_vector_pass_forms_bitwise_equal():
     N, n, m = SHAPE
     b = _batch(4, np.float32)
     outs = []
-    for fused in (False, True):
+    for fused in (0, 1, 2):
         L.set_tuning(4, N, n, m, torch.float32, engine="wavefront", fused=fused)
         outs.append(run(b, np.float32, refine=2, want_resid=True))
     L.set_tuning(4, N, n, m, torch.float32, clear=True)
-    for f in ("x", "u", "lam", "resid"):
-        assert np.array_equal(outs[0][f], outs[1][f]), f
+    for o in outs[1:]:
+        for f in ("x", "u", "lam", "resid"):
+            assert np.array_equal(outs[0][f], o[f]), f
 
 
 def test_autotune_picks_and_pins_a_mapping():
@@ -82,3 +83,9 @@ def test_set_tuning_rejects_bad_mappings():
         L.set_tuning(1, 10, 100, 10, engine="wavefront")   # order 100 has no wavefront class
     with pytest.raises(L.LqrError):
         L.set_tuning(1, 10, 10, 10, engine="matrix-core", big_grid=-1)
+    with pytest.raises(L.LqrError):
+        L.set_tuning(1, 10, 10, 10, engine="matrix-core", fused=2)   # one-launch form: wavefront engine only
+    with pytest.raises(L.LqrError):
+        L.set_tuning(1, 10, 100, 10, fused=2)
+    with pytest.raises(L.LqrError):
+        L.set_tuning(1, 10, 10, 10, fused=3)
