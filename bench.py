@@ -51,7 +51,7 @@ MR_BATCH = 64
 # HBM bytes per launch of the whole-body k_up from rocprofv3 FETCH_SIZE /
 # WRITE_SIZE runs, calibrated against a copy of known size; valid only for
 # the kernel sources they were taken on (hash of engine.hpp + kernels.hpp)
-KUP_TRAFFIC = {"src_hash": "2badc40252a955a1", "bytes_per_launch": 2.908e+09,
+KUP_TRAFFIC = {"src_hash": "b211c56977598ee1", "bytes_per_launch": 2.720e+09,
                "note": "FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (copy calibration), per launch"}
 
 
@@ -184,6 +184,18 @@ def measure(L, gen, batch, steps, warmup, eager, refine, plain, label, tune=True
     return r, fams
 
 
+def fused_steps(L, dev, N, n, m, batch, steps):
+    """timed_steps of the FP32 scan with the one-launch mapping pinned for
+    this shape (wavefront engine, the whole solve in one kernel per
+    instance), then the pin cleared."""
+    import torch
+    L.set_tuning(batch, N, n, m, torch.float32, engine="wavefront", fused=2)
+    try:
+        return timed_steps(L, dev, "scan", steps, 2, False, graph=True, refine=2)
+    finally:
+        L.set_tuning(batch, N, n, m, torch.float32, clear=True)
+
+
 def latency_leg(L, steps: int = 50):
     """Single-solve latency of the SRBD-shaped case (n = m = 12, one
     instance) at every horizon: graph replays of the FP32 scan (with its
@@ -196,16 +208,21 @@ def latency_leg(L, steps: int = 50):
         host = synth.gen_batch(lambda i: synth.gen_c2(N, i), 1, np.float32)
         dev = {k: torch.from_numpy(v).to("cuda:0") for k, v in host.items()}
         _, lat, _, resid, bad = timed_steps(L, dev, "scan", steps, 3, False, graph=True, refine=2)
+        _, flat, _, fresid, fbad = fused_steps(L, dev, N, 12, 12, 1, steps)
         dev64 = {k: v.double() for k, v in dev.items()}
         _, plat, _, presid, pbad = timed_steps(L, dev64, "plain", steps, 3, False, graph=True)
         out[f"N{N}"] = {"scan_p50_ms": float(np.percentile(lat, 50)), "scan_p99_ms": float(np.percentile(lat, 99)),
+                        "one_launch_p50_ms": float(np.percentile(flat, 50)),
+                        "one_launch_p99_ms": float(np.percentile(flat, 99)),
                         "plain_p50_ms": float(np.percentile(plat, 50)),
                         "plain_p99_ms": float(np.percentile(plat, 99)),
-                        "scan_rel_kkt_residual": resid, "plain_rel_kkt_residual": presid,
-                        "instances_with_status": bad + pbad}
+                        "scan_rel_kkt_residual": max(resid, fresid), "plain_rel_kkt_residual": presid,
+                        "instances_with_status": bad + fbad + pbad}
         log(f"[bench] latency N={N}: scan p50 {out[f'N{N}']['scan_p50_ms']:.3f} ms, "
+            f"one launch p50 {out[f'N{N}']['one_launch_p50_ms']:.3f} ms, "
             f"plain p50 {out[f'N{N}']['plain_p50_ms']:.3f} ms")
-    out["workload"] = "SRBD-shaped single solve (n=m=12, batch 1), hipGraph replays, FP32 scan + refinement vs FP64 plain"
+    out["workload"] = ("SRBD-shaped single solve (n=m=12, batch 1), hipGraph replays, FP32 scan + refinement "
+                       "(level-by-level launches, and the one-launch form) vs FP64 plain")
     return out
 
 
@@ -220,15 +237,20 @@ def batch_sweep_leg(L, batches=(16, 64, 256, 1024), steps: int = 10):
     for B in batches:
         dev = {k: torch.from_numpy(np.ascontiguousarray(v[:B])).to("cuda:0") for k, v in host.items()}
         wall, lat, _, resid, bad = timed_steps(L, dev, "scan", steps, 2, False, graph=True, refine=2)
+        fwall, flat, _, fresid, fbad = fused_steps(L, dev, 100, 36, 12, B, steps)
         dev64 = {k: v.double() for k, v in dev.items()}
         pwall, plat, _, presid, pbad = timed_steps(L, dev64, "plain", steps, 2, False, graph=True)
-        rows[f"B{B}"] = {"scan_solves_per_s": B * steps / wall, "plain_solves_per_s": B * steps / pwall,
-                         "scan_p50_ms": float(np.percentile(lat, 50)), "plain_p50_ms": float(np.percentile(plat, 50)),
-                         "scan_rel_kkt_residual": resid, "instances_with_status": bad + pbad}
+        rows[f"B{B}"] = {"scan_solves_per_s": B * steps / wall, "one_launch_solves_per_s": B * steps / fwall,
+                         "plain_solves_per_s": B * steps / pwall,
+                         "scan_p50_ms": float(np.percentile(lat, 50)), "one_launch_p50_ms": float(np.percentile(flat, 50)),
+                         "plain_p50_ms": float(np.percentile(plat, 50)),
+                         "scan_rel_kkt_residual": max(resid, fresid), "instances_with_status": bad + fbad + pbad}
         log(f"[bench] batch {B}: scan {rows[f'B{B}']['scan_solves_per_s']:.0f}/s, "
+            f"one launch {rows[f'B{B}']['one_launch_solves_per_s']:.0f}/s, "
             f"plain {rows[f'B{B}']['plain_solves_per_s']:.0f}/s")
         del dev, dev64
-    rows["workload"] = "whole-body-shaped (n=36, m=12, N=100), default mapping, hipGraph replays"
+    rows["workload"] = ("whole-body-shaped (n=36, m=12, N=100), hipGraph replays: default mapping (level-by-level "
+                        "launches), the one-launch form, and the FP64 plain sweep")
     return rows
 
 
