@@ -51,7 +51,7 @@ MR_BATCH = 64
 # HBM bytes per launch of the whole-body k_up from rocprofv3 FETCH_SIZE /
 # WRITE_SIZE runs, calibrated against a copy of known size; valid only for
 # the kernel sources they were taken on (hash of engine.hpp + kernels.hpp)
-KUP_TRAFFIC = {"src_hash": "b211c56977598ee1", "bytes_per_launch": 2.720e+09,
+KUP_TRAFFIC = {"src_hash": "b211c56977598ee1", "bytes_per_launch": 2.909e+09,
                "note": "FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (copy calibration), per launch"}
 
 
@@ -184,12 +184,13 @@ def measure(L, gen, batch, steps, warmup, eager, refine, plain, label, tune=True
     return r, fams
 
 
-def fused_steps(L, dev, N, n, m, batch, steps):
-    """timed_steps of the FP32 scan with the one-launch mapping pinned for
-    this shape (wavefront engine, the whole solve in one kernel per
-    instance), then the pin cleared."""
+def fused_steps(L, dev, N, n, m, batch, steps, **mapping):
+    """timed_steps of the FP32 scan with a wavefront-engine mapping pinned
+    for this shape (default: the one-launch form, the whole solve in one
+    kernel per instance), then the pin cleared."""
     import torch
-    L.set_tuning(batch, N, n, m, torch.float32, engine="wavefront", fused=2)
+    mapping = mapping or {"fused": 2}
+    L.set_tuning(batch, N, n, m, torch.float32, engine="wavefront", **mapping)
     try:
         return timed_steps(L, dev, "scan", steps, 2, False, graph=True, refine=2)
     finally:
@@ -238,19 +239,23 @@ def batch_sweep_leg(L, batches=(16, 64, 256, 1024), steps: int = 10):
         dev = {k: torch.from_numpy(np.ascontiguousarray(v[:B])).to("cuda:0") for k, v in host.items()}
         wall, lat, _, resid, bad = timed_steps(L, dev, "scan", steps, 2, False, graph=True, refine=2)
         fwall, flat, _, fresid, fbad = fused_steps(L, dev, 100, 36, 12, B, steps)
+        swall, slat, _, sresid, sbad = fused_steps(L, dev, 100, 36, 12, B, steps, fused=0, split=True)
         dev64 = {k: v.double() for k, v in dev.items()}
         pwall, plat, _, presid, pbad = timed_steps(L, dev64, "plain", steps, 2, False, graph=True)
         rows[f"B{B}"] = {"scan_solves_per_s": B * steps / wall, "one_launch_solves_per_s": B * steps / fwall,
-                         "plain_solves_per_s": B * steps / pwall,
+                         "split_solves_per_s": B * steps / swall, "plain_solves_per_s": B * steps / pwall,
                          "scan_p50_ms": float(np.percentile(lat, 50)), "one_launch_p50_ms": float(np.percentile(flat, 50)),
-                         "plain_p50_ms": float(np.percentile(plat, 50)),
-                         "scan_rel_kkt_residual": max(resid, fresid), "instances_with_status": bad + fbad + pbad}
+                         "split_p50_ms": float(np.percentile(slat, 50)), "plain_p50_ms": float(np.percentile(plat, 50)),
+                         "scan_rel_kkt_residual": max(resid, fresid, sresid),
+                         "instances_with_status": bad + fbad + sbad + pbad}
         log(f"[bench] batch {B}: scan {rows[f'B{B}']['scan_solves_per_s']:.0f}/s, "
             f"one launch {rows[f'B{B}']['one_launch_solves_per_s']:.0f}/s, "
+            f"split {rows[f'B{B}']['split_solves_per_s']:.0f}/s, "
             f"plain {rows[f'B{B}']['plain_solves_per_s']:.0f}/s")
         del dev, dev64
     rows["workload"] = ("whole-body-shaped (n=36, m=12, N=100), hipGraph replays: default mapping (level-by-level "
-                        "launches), the one-launch form, and the FP64 plain sweep")
+                        "launches, balanced tree), the one-launch form, the split schedule (tree over 64 elements, "
+                        "sequential sweep over 37), and the FP64 plain sweep")
     return rows
 
 

@@ -175,24 +175,34 @@ int lqr_timing_report(lqr_handle_t h, char* buf, size_t len);
  *            recomputed whole with FP64 arithmetic by a second launch)
  *   big_grid 0 = default (512), else the workgroups / scratch slots of a
  *            matrix-core task launch
- *   ms       (lqr_autotune output) mean time of one solve with this mapping */
+ *   ms       (lqr_autotune output) mean time of one solve with this mapping
+ *   split    0 = balanced tree over all N+1 scan elements (default), 1 = split
+ *            schedule (wavefront engine, fused 0 or 1): the tree over the
+ *            first 2^k elements (the largest power of two below N+1), the
+ *            suffixes of the others by a sequential sweep of combines with
+ *            the complete suffix to their right (Sec. II-D combination rule;
+ *            the same value functions, fewer general combines, more
+ *            dependent steps) */
 typedef struct {
     int32_t engine;
     int32_t fused;
     int32_t big_grid;
     float ms;
+    int32_t split;
 } lqr_tuning;
 
 /* Pin (t != NULL) or clear (t == NULL) the mapping of the shape
  * (batch, N, n, m, dtype) on this handle; later lqr_workspace_size,
  * lqr_kkt_solve and lqr_kkt_residual calls of that shape use it.
- * LQR_EINVAL for an out-of-range field, engine 1 above order 64, or fused 2
- * with the matrix-core engine. */
+ * LQR_EINVAL for an out-of-range field, engine 1 above order 64, fused 2
+ * with the matrix-core engine, or split 1 with the matrix-core engine or
+ * fused 2. */
 int lqr_set_tuning(lqr_handle_t h, int64_t batch, int N, int n, int m, int32_t dtype, const lqr_tuning* t);
 
 /* Autotuner: solves the given problem (same arguments as lqr_kkt_solve)
  * once per candidate mapping -- each engine that can take the shape, each
- * form of the passes (fused 0 / 1, and 2 on the wavefront engine),
+ * form of the passes (fused 0 / 1, and 2 on the wavefront engine), both
+ * reverse-scan schedules on the wavefront engine (split 0 / 1),
  * matrix-core grids of 256 / 512 / 1024
  * workgroups -- then `reps` more times on the stream, timed with HIP events;
  * candidates whose status words are not clean (other than the FP64-fallback

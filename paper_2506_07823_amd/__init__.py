@@ -48,7 +48,7 @@ class lqr_opts(ctypes.Structure):
 
 class lqr_tuning(ctypes.Structure):
     _fields_ = [("engine", ctypes.c_int32), ("fused", ctypes.c_int32), ("big_grid", ctypes.c_int32),
-                ("ms", ctypes.c_float)]
+                ("ms", ctypes.c_float), ("split", ctypes.c_int32)]
 
 
 class lqr_problem(ctypes.Structure):
@@ -351,16 +351,19 @@ def autotune(A, B, c, Q, R, M, q, r, x0, *, method: str = "scan", refine: int | 
                              *[t.data_ptr() for t in out], ws.data_ptr(), ws.numel(), ctypes.byref(o), int(reps),
                              ctypes.byref(best)))
     return {"engine": {1: "wavefront", 2: "matrix-core"}[best.engine], "fused": int(best.fused),
-            "big_grid": int(best.big_grid), "ms": float(best.ms)}
+            "big_grid": int(best.big_grid), "split": int(best.split), "ms": float(best.ms)}
 
 
 def set_tuning(batch: int, N: int, n: int, m: int, dtype=torch.float32, *, engine: str | None = None,
-               fused: bool | int | None = None, big_grid: int = 0, device: int = 0, clear: bool = False):
+               fused: bool | int | None = None, big_grid: int = 0, split: bool = False, device: int = 0,
+               clear: bool = False):
     """Pin (or clear) the mapping of a problem shape on the device's handle.
 
     fused: None = default; 0 / False = vector-only passes level by level;
     1 / True = one workgroup per instance for them; 2 = the whole solve in
-    one launch (wavefront engine)."""
+    one launch (wavefront engine).  split: the split schedule of the reverse
+    scan (tree over the first 2^k elements, a sequential sweep over the
+    rest; wavefront engine, fused 0 or 1)."""
     dt = LQR_F32 if dtype == torch.float32 else LQR_F64
     if clear:
         _check(_lib.lqr_set_tuning(handle(device), batch, N, n, m, dt, None))
@@ -369,6 +372,7 @@ def set_tuning(batch: int, N: int, n: int, m: int, dtype=torch.float32, *, engin
     t.engine = {None: 0, "wavefront": 1, "matrix-core": 2}[engine]
     t.fused = -1 if fused is None else int(fused)
     t.big_grid = int(big_grid)
+    t.split = 1 if split else 0
     _check(_lib.lqr_set_tuning(handle(device), batch, N, n, m, dt, ctypes.byref(t)))
 
 

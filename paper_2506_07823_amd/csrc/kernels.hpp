@@ -51,6 +51,8 @@ struct Plan {
     int fallback;
     const int32_t* active;   // refinement gating: instances with active[b] == 0 skip (nullptr = all)
     int fused;               // 1: per-instance kernels for the vector-only passes
+    int tail;                // split schedule: the tree covers leaves [0, tail) (a power of two), a
+                             // sequential sweep the rest; 0 = balanced tree over all N+1 leaves
     int64_t o_scr;           // large-block engine: byte offset of the per-workgroup scratch area
     int64_t scr_elems;       //   its elements per workgroup
     int big_grid;            //   workgroups of a task launch (scratch slots)
@@ -97,6 +99,17 @@ template <typename S> struct Ptr {
 __device__ __forceinline__ int suffix_id(const Tree& t, int l, int j) {
     while (l < t.nlev - 1 && (j & 1) == 0) { j >>= 1; ++l; }
     return t.off[l] + j;
+}
+
+// Tasks of a reverse-tree launch.  Under the split schedule only the nodes
+// whose leaves all lie in [0, tail) are combined (tail is a power of two, so
+// no node straddles the boundary); the suffixes of leaves >= tail come from
+// the sequential sweep.
+__host__ __device__ __forceinline__ int up_count(const Plan& p, int lvl) {
+    return p.tail ? (p.tail >> (lvl + 1)) : p.rt.cnt[lvl + 1];
+}
+__host__ __device__ __forceinline__ int down_half(const Plan& p, int lvl) {
+    return p.tail ? (p.tail >> lvl) / 2 : p.rt.cnt[lvl] / 2;
 }
 
 template <class E>
@@ -485,7 +498,7 @@ template <typename S, class E, bool FB>
 __device__ __forceinline__ void up_task(Lds<E>& L, const Plan& p, S* ws, int lvl, int32_t* status, FbQueue q, int64_t task) {
     const E e(unit_tid<E::NT>());
     const int n = p.n, nn = n * n;
-    const int cout = p.rt.cnt[lvl + 1], cin = p.rt.cnt[lvl];
+    const int cout = up_count(p, lvl), cin = p.rt.cnt[lvl];
     const int64_t b = task / cout;
     const int i = (int)(task % cout);
     S* base = ws + b * p.stride + p.o_tree;
@@ -510,7 +523,7 @@ __global__ __launch_bounds__(E::NT) void k_up(Plan p, S* ws, int lvl, int32_t* s
         if constexpr (E::BIG) big_up_task<S, E, FB>(L, p, ws, lvl, status, q, t);
         else up_task<S, E, FB>(L, p, ws, lvl, status, q, t);
     };
-    LQR_TASKS(E, FB, q, p.batch * p.rt.cnt[lvl + 1], body);
+    LQR_TASKS(E, FB, q, p.batch * up_count(p, lvl), body);
 }
 
 // root of the reverse tree: its (P, p) is the complete suffix starting at 0
@@ -534,7 +547,7 @@ template <typename S, class E, bool FB>
 __device__ __forceinline__ void down_task(Lds<E>& L, const Plan& p, S* ws, int lvl, int32_t* status, FbQueue q, int64_t task) {
     const E e(unit_tid<E::NT>());
     const int n = p.n, nn = n * n;
-    const int half = p.rt.cnt[lvl] / 2;
+    const int half = down_half(p, lvl);
     const int64_t b = task / half;
     const int j = 2 * (int)(task % half) + 1;
     S* tree = ws + b * p.stride + p.o_tree;
@@ -564,7 +577,87 @@ __global__ __launch_bounds__(E::NT) void k_down(Plan p, S* ws, int lvl, int32_t*
         if constexpr (E::BIG) big_down_task<S, E, FB>(L, p, ws, lvl, status, q, t);
         else down_task<S, E, FB>(L, p, ws, lvl, status, q, t);
     };
-    LQR_TASKS(E, FB, q, p.batch * (p.rt.cnt[lvl] / 2), body);
+    LQR_TASKS(E, FB, q, p.batch * down_half(p, lvl), body);
+}
+
+// ---------------------------------------------------------------------------
+// Split schedule (wavefront engine).  The suffixes of the leaves >= tail are
+// computed one after the other from the terminal element backwards, each as
+// the combine of leaf k with the complete suffix starting at k+1 (the cheap
+// form: a complete suffix has A = C = b = 0), i.e. the information form of
+// the Riccati recursion of eq. (lqr).  Each is stored where the balanced
+// tree would store the suffix of leaf k.  Meanwhile nothing of the tree
+// depends on these leaves: the tree over [0, tail) needs only the suffix of
+// leaf `tail`, taken by the root task below.  One wavefront per instance;
+// the wave barrier with its fences orders each step's stores before the
+// next step's loads (all lanes of the wave share one CU's caches).  Any
+// flagged step sends the whole instance's sweep to the FP64 redo (queue id
+// = instance), which recomputes it from the same records.
+// ---------------------------------------------------------------------------
+template <typename S, class E, bool FB>
+__device__ __forceinline__ void tail_task(Lds<E>& L, const Plan& p, S* ws, int32_t* status, FbQueue q, int64_t b) {
+    static_assert(!E::BIG, "wavefront engine only");
+    const E e(unit_tid<E::NT>());
+    const int N = p.N, n = p.n, nn = n * n;
+    S* tree = ws + b * p.stride + p.o_tree;
+    S* suf = ws + b * p.stride + p.o_suf;
+    {
+        const S* leaf = tree + (int64_t)(p.rt.off[0] + N) * p.rec;   // terminal element (0, 0, 0, Q_N, q_N)
+        S* out = suf + (int64_t)suffix_id(p.rt, 0, N) * p.srec;
+        coop_copy<E::NT>(out, leaf + 2 * nn, nn);
+        coop_copy<E::NT>(out + nn, leaf + 3 * nn + n, n);
+    }
+    E::sync();
+    bool ok_all = true;
+    typename E::T kmax = 0;
+    for (int k = N - 1; k >= p.tail; --k) {
+        const S* node = tree + (int64_t)(p.rt.off[0] + k) * p.rec;
+        const S* s2 = suf + (int64_t)suffix_id(p.rt, 0, k + 1) * p.srec;
+        S* out = suf + (int64_t)suffix_id(p.rt, 0, k) * p.srec;
+        bool ok;
+        typename E::T kappa;
+        combine<E, true>(e, L, n, node, s2, s2 + nn, (const S*)nullptr, (S*)nullptr, (S*)nullptr, out,
+                         (S*)nullptr, out + nn, ok, kappa);
+        ok_all = ok_all && ok;
+        if (!(kappa <= kmax)) kmax = kappa;   // NaN propagates
+        E::sync();
+    }
+    fb_decide<FB, E::NT>(p, ok_all, kmax, b, b, q, status, 4);
+}
+
+template <typename S, class E, bool FB>
+__global__ __launch_bounds__(E::NT) void k_tail(Plan p, S* ws, int32_t* status, FbQueue q) {
+    __shared__ Lds<E> L;
+    auto body = [&](int64_t t) { tail_task<S, E, FB>(L, p, ws, status, q, t); };
+    LQR_TASKS(E, FB, q, p.batch, body);
+}
+
+// Root under the split schedule: the complete suffix from leaf 0 is the
+// aggregate of the head, node (nlev-2, 0), after the suffix of leaf `tail`.
+template <typename S, class E, bool FB>
+__device__ __forceinline__ void tail_root_task(Lds<E>& L, const Plan& p, S* ws, int32_t* status, FbQueue q,
+                                               int64_t b) {
+    static_assert(!E::BIG, "wavefront engine only");
+    const E e(unit_tid<E::NT>());
+    const int n = p.n, nn = n * n;
+    const int top = p.rt.nlev - 2;
+    S* tree = ws + b * p.stride + p.o_tree;
+    S* suf = ws + b * p.stride + p.o_suf;
+    const S* node = tree + (int64_t)p.rt.off[top] * p.rec;
+    const S* s2 = suf + (int64_t)suffix_id(p.rt, 0, p.tail) * p.srec;
+    S* out = suf + (int64_t)p.rt.off[p.rt.nlev - 1] * p.srec;
+    bool ok;
+    typename E::T kappa;
+    combine<E, true>(e, L, n, node, s2, s2 + nn, (const S*)nullptr, (S*)nullptr, (S*)nullptr, out, (S*)nullptr,
+                     out + nn, ok, kappa);
+    fb_decide<FB, E::NT>(p, ok, kappa, b, b, q, status, 4);
+}
+
+template <typename S, class E, bool FB>
+__global__ __launch_bounds__(E::NT) void k_tail_root(Plan p, S* ws, int32_t* status, FbQueue q) {
+    __shared__ Lds<E> L;
+    auto body = [&](int64_t t) { tail_root_task<S, E, FB>(L, p, ws, status, q, t); };
+    LQR_TASKS(E, FB, q, p.batch, body);
 }
 
 // ---------------------------------------------------------------------------

@@ -79,6 +79,7 @@ struct Tuning {
     int engine = 0;     // 1: wavefront tiles, 2: matrix-core workgroups
     int fused = -1;     // vector passes level by level 0, per instance 1; 2: whole solve in one launch
     int big_grid = 0;   // workgroups (scratch slots) of a matrix-core task launch
+    int split = 0;      // 1: split schedule of the reverse scan (wavefront engine, level-by-level forms)
 };
 
 int pick_ts(int n, int m, const Tuning* t) {
@@ -130,6 +131,11 @@ Plan make_plan(int64_t batch, int N, int n, int m, size_t esize, const lqr_opts&
     p.fused = 0;
     p.fallback = esize == 4 ? o.fallback : 0;   // the FP64 path has nothing to fall back to
     if (tun && tun->fused >= 0) p.fused = tun->fused;
+    // split schedule: the tree over the largest power of two of leaves below
+    // N + 1 (every tree level above the leaves has a node past it), the rest
+    // by the sequential sweep
+    p.tail = 0;
+    if (tun && tun->split && p.fused != 2 && pick_ts(n, m, tun) != kBigTS) p.tail = 1 << (p.rt.nlev - 2);
     if (pick_ts(n, m, tun) == kBigTS) {
         if (p.fused == 2) p.fused = 1;   // the one-launch solve is a wavefront-engine form
         const int64_t d = n > m ? n : m;
@@ -204,7 +210,8 @@ const char* const kFamNames[F_COUNT] = {
     "clear", "element", "element_fp64", "up", "root", "down", "policy", "policy_fp64", "fwd_up", "fwd_root",
     "fwd_down", "recover", "residual", "ref_d", "bwd_up", "bwd_root", "bwd_down", "ref_kff", "fwd_up_vec",
     "recover_add", "reduce", "plain_riccati", "up_fp64", "down_fp64", "fwd_inst", "refine_inst", "warm_copy",
-    "ragged_pack", "fused_solve", "fused_solve_fp64"};
+    "ragged_pack", "fused_solve", "fused_solve_fp64", "tail_sweep", "tail_sweep_fp64", "tail_root",
+    "tail_root_fp64"};
 
 // Per-handle launch timer: two HIP events around every launch, read back by
 // lqr_timing_report.
@@ -572,8 +579,12 @@ int lqr_set_tuning(lqr_handle_t h, int64_t batch, int N, int n, int m, int32_t d
         h->tuned.erase(key);
         return LQR_OK;
     }
-    if (t->engine < 0 || t->engine > 2 || t->fused < -1 || t->fused > 2 || t->big_grid < 0)
-        return fail(LQR_EINVAL, "bad tuning (engine %d, fused %d, big_grid %d)", t->engine, t->fused, t->big_grid);
+    if (t->engine < 0 || t->engine > 2 || t->fused < -1 || t->fused > 2 || t->big_grid < 0 || t->split < 0 ||
+        t->split > 1)
+        return fail(LQR_EINVAL, "bad tuning (engine %d, fused %d, big_grid %d, split %d)", t->engine, t->fused,
+                    t->big_grid, t->split);
+    if (t->split && (t->engine == 2 || pick_ts(n, m) == kBigTS || t->fused == 2))
+        return fail(LQR_EINVAL, "the split schedule runs on the wavefront engine with level-by-level launches");
     if (t->engine == 1 && pick_ts(n, m) == kBigTS)
         return fail(LQR_EINVAL, "the wavefront engine takes orders up to 64 (n=%d m=%d)", n, m);
     if (t->fused == 2 && (t->engine == 2 || pick_ts(n, m) == kBigTS))
@@ -582,6 +593,7 @@ int lqr_set_tuning(lqr_handle_t h, int64_t batch, int N, int n, int m, int32_t d
     tu.engine = t->engine;
     tu.fused = t->fused;
     tu.big_grid = t->big_grid;
+    tu.split = t->split;
     h->tuned[key] = tu;
     return LQR_OK;
 }
@@ -606,6 +618,9 @@ int lqr_autotune(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int 
             if (eng == 2 && fu == 2) continue;
             if (eng == 1) {
                 Tuning t; t.engine = 1; t.fused = fu; cands.push_back(t);
+                if (fu != 2) {
+                    Tuning ts = t; ts.split = 1; cands.push_back(ts);
+                }
             } else {
                 for (int g : {256, 512, 1024}) {
                     Tuning t; t.engine = 2; t.fused = fu; t.big_grid = g; cands.push_back(t);
@@ -661,6 +676,7 @@ int lqr_autotune(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int 
     best->engine = best_t.engine;
     best->fused = best_t.fused;
     best->big_grid = best_t.big_grid;
+    best->split = best_t.split;
     best->ms = best_ms;
     return LQR_OK;
 }

@@ -50,7 +50,8 @@ int with_mb(int m, Fn&& fn) {
 enum Fam {
     F_CLEAR, F_ELEM, F_ELEM_FB, F_UP, F_ROOT, F_DOWN, F_POLICY, F_POLICY_FB, F_FUP, F_FROOT, F_FDOWN,
     F_RECOVER, F_RESID, F_REF_D, F_BUP, F_BROOT, F_BDOWN, F_REF_KFF, F_FUPV, F_RECOVER_ADD, F_REDUCE,
-    F_PLAIN, F_UP_FB, F_DOWN_FB, F_FWD_INST, F_REFINE_INST, F_WARM, F_PACK, F_FUSED, F_FUSED_FB, F_COUNT
+    F_PLAIN, F_UP_FB, F_DOWN_FB, F_FWD_INST, F_REFINE_INST, F_WARM, F_PACK, F_FUSED, F_FUSED_FB, F_TAIL, F_TAIL_FB,
+    F_TROOT, F_TROOT_FB, F_COUNT
 };
 
 // Optional per-launch timer (HIP events around each launch on its stream),
@@ -75,7 +76,9 @@ int launch_nt(int nt, int fam, double flops, double bytes, K kernel, int64_t gri
 
 // Layout of the int32 workspace: queue counters, then one id list per
 // (family, level) with room for every task of that launch.
-constexpr int kQElem = 0, kQPolicy = 1, kQUp = 2, kQDown = 2 + LQR_MAXLEV, kQCount = 64;
+constexpr int kQElem = 0, kQPolicy = 1, kQUp = 2, kQDown = 2 + LQR_MAXLEV, kQTail = 2 + 2 * LQR_MAXLEV,
+              kQTailRoot = kQTail + 1, kQCount = 64;
+static_assert(kQTailRoot < kQCount, "queue counters");
 struct Queues {
     int64_t list[kQCount];   // offsets (int32 elements) of each list
     int64_t total;
@@ -89,6 +92,8 @@ inline Queues queue_layout(const Plan& p) {
     add(kQPolicy, p.batch * p.N);
     for (int l = 0; l + 1 < p.rt.nlev; ++l) add(kQUp + l, p.batch * p.rt.cnt[l + 1]);
     for (int l = 0; l + 1 < p.rt.nlev; ++l) add(kQDown + l, p.batch * (p.rt.cnt[l] / 2));
+    add(kQTail, p.batch);
+    add(kQTailRoot, p.batch);
     q.total = off;
     return q;
 }
@@ -207,24 +212,48 @@ int run_scan(const Plan& p, hipStream_t s, const In<S>& in, const Out<S>& out, S
             return LQR_OK;
         }));
     }
-    // a3: reverse scan, up-sweep then down-sweep
+    // a3: reverse scan, up-sweep then down-sweep (split schedule: the
+    // sequential sweep of the tail leaves first, the tree over the head)
+    if constexpr (!E::BIG) {
+        if (p.tail) {
+            const double u = B * (N - p.tail);
+            const FbQueue q = fbq(iws, Qs, kQTail);
+            LCHK(launch_nt(NT, F_TAIL, u * w.cheap_f(), u * w.cheap_b(), k_tail<S, E, false>, Bi, s, p, ws,
+                           out.status, q));
+            if (fb)
+                LCHK(launch_nt(NT, F_TAIL_FB, 0, 0, k_tail<S, E64, true>, fb_grid<E64>(p, Bi), s, p, ws, out.status, q));
+        }
+    }
     for (int l = 0; l + 1 < p.rt.nlev; ++l) {
-        const double u = B * (p.rt.cnt[l] / 2);
+        const int c = up_count(p, l);
+        if (c == 0) continue;
+        const double u = B * (p.tail ? c : p.rt.cnt[l] / 2);
         const FbQueue q = fbq(iws, Qs, kQUp + l);
-        LCHK(launch_nt(NT, F_UP, u * w.comb_f(), u * w.comb_b(), k_up<S, E, false>, task_grid<E>(p, Bi * p.rt.cnt[l + 1]), s, p, ws, l,
+        LCHK(launch_nt(NT, F_UP, u * w.comb_f(), u * w.comb_b(), k_up<S, E, false>, task_grid<E>(p, Bi * c), s, p, ws, l,
                     out.status, q));
         if (fb)
-            LCHK(launch_nt(NT, F_UP_FB, 0, 0, k_up<S, E64, true>, fb_grid<E64>(p, Bi * p.rt.cnt[l + 1]), s, p, ws, l,
+            LCHK(launch_nt(NT, F_UP_FB, 0, 0, k_up<S, E64, true>, fb_grid<E64>(p, Bi * c), s, p, ws, l,
                         out.status, q));
     }
-    LCHK(launch_nt(WG, F_ROOT, 0, 2 * B * w.es * p.srec, k_root<S>, Bi, s, p, ws));
+    if (!p.tail) {
+        LCHK(launch_nt(WG, F_ROOT, 0, 2 * B * w.es * p.srec, k_root<S>, Bi, s, p, ws));
+    } else if constexpr (!E::BIG) {
+        const FbQueue q = fbq(iws, Qs, kQTailRoot);
+        LCHK(launch_nt(NT, F_TROOT, B * w.cheap_f(), B * w.cheap_b(), k_tail_root<S, E, false>, Bi, s, p, ws,
+                       out.status, q));
+        if (fb)
+            LCHK(launch_nt(NT, F_TROOT_FB, 0, 0, k_tail_root<S, E64, true>, fb_grid<E64>(p, Bi), s, p, ws, out.status,
+                           q));
+    }
     for (int l = p.rt.nlev - 2; l >= 0; --l) {
-        const double u = B * (p.rt.cnt[l] / 2);
+        const int h = down_half(p, l);
+        if (h == 0) continue;
+        const double u = B * h;
         const FbQueue q = fbq(iws, Qs, kQDown + l);
-        LCHK(launch_nt(NT, F_DOWN, u * w.cheap_f(), u * w.cheap_b(), k_down<S, E, false>, task_grid<E>(p, Bi * (p.rt.cnt[l] / 2)), s, p,
+        LCHK(launch_nt(NT, F_DOWN, u * w.cheap_f(), u * w.cheap_b(), k_down<S, E, false>, task_grid<E>(p, Bi * h), s, p,
                     ws, l, out.status, q));
         if (fb)
-            LCHK(launch_nt(NT, F_DOWN_FB, 0, 0, k_down<S, E64, true>, fb_grid<E64>(p, Bi * (p.rt.cnt[l] / 2)), s, p, ws, l,
+            LCHK(launch_nt(NT, F_DOWN_FB, 0, 0, k_down<S, E64, true>, fb_grid<E64>(p, Bi * h), s, p, ws, l,
                         out.status, q));
     }
     // a4: policy and closed-loop maps
