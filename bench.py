@@ -48,10 +48,11 @@ PEAK_HBM = 8.0e12
 PEAK_FP32_MFMA = 157.3e12
 MR_BATCH = 64
 
-# HBM bytes per launch of the whole-body k_up from rocprofv3 FETCH_SIZE /
+# HBM bytes per launch of the whole-body dominant kernel (the tail sweeps
+# with the first up-sweep level, split schedule) from rocprofv3 FETCH_SIZE /
 # WRITE_SIZE runs, calibrated against a copy of known size; valid only for
 # the kernel sources they were taken on (hash of engine.hpp + kernels.hpp)
-KUP_TRAFFIC = {"src_hash": "b211c56977598ee1", "bytes_per_launch": 2.909e+09,
+KUP_TRAFFIC = {"kernel": "tail_sweep_up0", "src_hash": "b293bd66cef3394e", "bytes_per_launch": 1.0088e+10,
                "note": "FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (copy calibration), per launch"}
 
 
@@ -139,7 +140,7 @@ def roofline_of(fams, bound, peak, unit):
             "launches": d["launches"], "algorithmic_GBps": d["bytes"] / (d["ms"] * 1e-3) / 1e9}
 
 
-def measure(L, gen, batch, steps, warmup, eager, refine, plain, label, tune=True):
+def measure(L, gen, batch, steps, warmup, eager, refine, plain, label, tune=True, pin=None):
     """Timed FP32 scan (graph replays) + kernel-timing pass + optional FP64
     plain comparison on one workload; returns the numbers and the timing
     families of the scan."""
@@ -151,7 +152,11 @@ def measure(L, gen, batch, steps, warmup, eager, refine, plain, label, tune=True
     del host
     torch.cuda.synchronize()
     mapping = "default"
-    if tune:
+    if pin:
+        N_, n_, m_ = dev["B"].shape[1:]
+        L.set_tuning(batch, N_, n_, m_, torch.float32, **pin)
+        mapping = dict(pin)
+    elif tune:
         log(f"[bench] {label}: autotuning the mapping")
         mapping = L.autotune(*[dev[k] for k in L.FIELDS], refine=refine, reps=2)
         log(f"[bench] {label}: mapping {mapping}")
@@ -336,6 +341,8 @@ def main():
     ap.add_argument("--no-sweep", action="store_true", help="skip the whole-body batch-size sweep")
     ap.add_argument("--serving-requests", type=int, default=1600)
     ap.add_argument("--no-tune", action="store_true", help="use the default mapping instead of autotuning it")
+    ap.add_argument("--split", action="store_true",
+                    help="pin the split schedule (wavefront engine) for the whole-body workload instead of autotuning")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of graph replays")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (calibrates the HBM byte "
@@ -360,7 +367,8 @@ def main():
     import synth
 
     wb, fams = measure(L, synth.gen_c3, BATCH, a.steps, a.warmup, a.eager, 2, not a.no_plain, "whole-body",
-                       tune=not a.no_tune)
+                       tune=not a.no_tune, pin=({"engine": "wavefront", "fused": 0, "split": True}
+                                                if a.split else None))
     result = {
         "metric": METRIC, "value": wb.pop("value"), "unit": "solves/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": wb.pop("ms_per_step"), "higher_is_better": True,
@@ -374,7 +382,7 @@ def main():
     result.update(wb)
     rf = roofline_of(fams, "alu", PEAK_FP32_VECTOR, "TFLOP/s")
     rf["peak_packed_fp32"] = PEAK_FP32_VECTOR_PACKED / 1e12
-    if rf["kernel"] == "up" and kernel_src_hash() == KUP_TRAFFIC["src_hash"]:
+    if rf["kernel"] == KUP_TRAFFIC["kernel"] and kernel_src_hash() == KUP_TRAFFIC["src_hash"]:
         rf["traffic"] = KUP_TRAFFIC["bytes_per_launch"]
         rf["traffic_note"] = KUP_TRAFFIC["note"]
     result["roofline"] = rf

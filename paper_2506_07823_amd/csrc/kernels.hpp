@@ -632,6 +632,19 @@ __global__ __launch_bounds__(E::NT) void k_tail(Plan p, S* ws, int32_t* status, 
     LQR_TASKS(E, FB, q, p.batch, body);
 }
 
+// The sweeps and the first up-sweep level in one launch (they are
+// independent): workgroups 0 .. batch-1 sweep the tails (dispatched first,
+// they are the long ones), the others combine leaf pairs of the heads, so
+// the combines fill the CUs while the sweeps run their dependent steps.
+template <typename S, class E>
+__global__ __launch_bounds__(E::NT) void k_tail_up0(Plan p, S* ws, int32_t* status, FbQueue q_tail, FbQueue q_up) {
+    static_assert(!E::BIG, "wavefront engine only");
+    __shared__ Lds<E> L;
+    const int64_t t = blockIdx.x;
+    if (t < p.batch) tail_task<S, E, false>(L, p, ws, status, q_tail, t);
+    else up_task<S, E, false>(L, p, ws, 0, status, q_up, t - p.batch);
+}
+
 // Root under the split schedule: the complete suffix from leaf 0 is the
 // aggregate of the head, node (nlev-2, 0), after the suffix of leaf `tail`.
 template <typename S, class E, bool FB>

@@ -211,7 +211,7 @@ const char* const kFamNames[F_COUNT] = {
     "fwd_down", "recover", "residual", "ref_d", "bwd_up", "bwd_root", "bwd_down", "ref_kff", "fwd_up_vec",
     "recover_add", "reduce", "plain_riccati", "up_fp64", "down_fp64", "fwd_inst", "refine_inst", "warm_copy",
     "ragged_pack", "fused_solve", "fused_solve_fp64", "tail_sweep", "tail_sweep_fp64", "tail_root",
-    "tail_root_fp64"};
+    "tail_root_fp64", "tail_sweep_up0"};
 
 // Per-handle launch timer: two HIP events around every launch, read back by
 // lqr_timing_report.

@@ -51,7 +51,7 @@ enum Fam {
     F_CLEAR, F_ELEM, F_ELEM_FB, F_UP, F_ROOT, F_DOWN, F_POLICY, F_POLICY_FB, F_FUP, F_FROOT, F_FDOWN,
     F_RECOVER, F_RESID, F_REF_D, F_BUP, F_BROOT, F_BDOWN, F_REF_KFF, F_FUPV, F_RECOVER_ADD, F_REDUCE,
     F_PLAIN, F_UP_FB, F_DOWN_FB, F_FWD_INST, F_REFINE_INST, F_WARM, F_PACK, F_FUSED, F_FUSED_FB, F_TAIL, F_TAIL_FB,
-    F_TROOT, F_TROOT_FB, F_COUNT
+    F_TROOT, F_TROOT_FB, F_TAIL_UP0, F_COUNT
 };
 
 // Optional per-launch timer (HIP events around each launch on its stream),
@@ -214,17 +214,35 @@ int run_scan(const Plan& p, hipStream_t s, const In<S>& in, const Out<S>& out, S
     }
     // a3: reverse scan, up-sweep then down-sweep (split schedule: the
     // sequential sweep of the tail leaves first, the tree over the head)
+    int l_first = 0;   // first up-sweep level launched by the loop below
     if constexpr (!E::BIG) {
         if (p.tail) {
             const double u = B * (N - p.tail);
             const FbQueue q = fbq(iws, Qs, kQTail);
-            LCHK(launch_nt(NT, F_TAIL, u * w.cheap_f(), u * w.cheap_b(), k_tail<S, E, false>, Bi, s, p, ws,
-                           out.status, q));
-            if (fb)
-                LCHK(launch_nt(NT, F_TAIL_FB, 0, 0, k_tail<S, E64, true>, fb_grid<E64>(p, Bi), s, p, ws, out.status, q));
+            const int c0 = up_count(p, 0);
+            if (c0 > 0) {
+                // the sweeps and the first up-sweep level side by side
+                const double u0 = B * c0;
+                const FbQueue q0 = fbq(iws, Qs, kQUp);
+                LCHK(launch_nt(NT, F_TAIL_UP0, u * w.cheap_f() + u0 * w.comb_f(), u * w.cheap_b() + u0 * w.comb_b(),
+                               k_tail_up0<S, E>, Bi + Bi * c0, s, p, ws, out.status, q, q0));
+                if (fb) {
+                    LCHK(launch_nt(NT, F_TAIL_FB, 0, 0, k_tail<S, E64, true>, fb_grid<E64>(p, Bi), s, p, ws,
+                                   out.status, q));
+                    LCHK(launch_nt(NT, F_UP_FB, 0, 0, k_up<S, E64, true>, fb_grid<E64>(p, Bi * c0), s, p, ws, 0,
+                                   out.status, q0));
+                }
+                l_first = 1;
+            } else {
+                LCHK(launch_nt(NT, F_TAIL, u * w.cheap_f(), u * w.cheap_b(), k_tail<S, E, false>, Bi, s, p, ws,
+                               out.status, q));
+                if (fb)
+                    LCHK(launch_nt(NT, F_TAIL_FB, 0, 0, k_tail<S, E64, true>, fb_grid<E64>(p, Bi), s, p, ws,
+                                   out.status, q));
+            }
         }
     }
-    for (int l = 0; l + 1 < p.rt.nlev; ++l) {
+    for (int l = l_first; l + 1 < p.rt.nlev; ++l) {
         const int c = up_count(p, l);
         if (c == 0) continue;
         const double u = B * (p.tail ? c : p.rt.cnt[l] / 2);
