@@ -320,15 +320,17 @@ __device__ __forceinline__ void element_task(Lds<E>& L, const Plan& p, const In<
     }
     typename E::Tile tR;
     e.load(tR, P.R(b, k), m, m, m);
+    // loaded before the factorization (its wave barrier keeps later loads
+    // from moving up), so their latency overlaps it
+    typename E::Tile W[2];
+    e.template load<true>(W[0], P.B(b, k), m, n, m);   // B' (m x n)
+    e.template load<true>(W[1], P.M(b, k), m, n, m);   // M' (m x n)
+    T vv[1] = {e.vload(P.r(b, k), m)};
     T dmin, dmax, nov[1];
     T dlA;
     const bool ok = e.template chol<0, MB>(tR, m, L.cb, dlA, nov, dmin, dmax);
     fb_decide<FB, E::NT>(p, ok, cond_est(dmin, dmax), b, task, q, status, 2);
     e.to_lds(tR, L.sA);
-    typename E::Tile W[2];
-    e.template load<true>(W[0], P.B(b, k), m, n, m);   // B' (m x n)
-    e.template load<true>(W[1], P.M(b, k), m, n, m);   // M' (m x n)
-    T vv[1] = {e.vload(P.r(b, k), m)};
     wg_sync();
     e.template trsm<true, 2, 1, MB>(L.sA, dlA, m, W, vv, L.rb);
     e.to_lds(W[0], L.sA);
@@ -691,7 +693,12 @@ __device__ __forceinline__ void policy_task(Lds<E>& L, const Plan& p, const In<S
     const Ptr<S> P(p, in);
     S* inst = ws + b * p.stride;
     const S* Pn = inst + p.o_suf + (int64_t)suffix_id(p.rt, 0, k + 1) * p.srec;
-    typename E::Tile t, tG, tH;
+    typename E::Tile t, tG, tH, tA;
+    // the stage inputs go to registers first: their global latency overlaps
+    // the products below (the wave barriers keep later loads from moving up)
+    e.load(tA, P.A(b, k), n, n, n);
+    e.load(tG, P.R(b, k), m, m, m);
+    e.template load<true>(tH, P.M(b, k), m, n, m);        // M'
     stage(e, L.sA, Pn, n, n, n);                          // sA = P'
     stage(e, L.sX, P.B(b, k), n, m, m);                   // sX = B
     wg_sync();
@@ -702,13 +709,11 @@ __device__ __forceinline__ void policy_task(Lds<E>& L, const Plan& p, const In<S
     wg_sync();
     e.to_lds(t, L.sA);                                    // sA = P'B
     wg_sync();
-    e.load(tG, P.R(b, k), m, m, m);
     e.template gemm<true, false, true, false, MB, MB>(tG, L.sA, L.sX, n); // R + (P'B)'B (lower)
     wg_sync();
-    stage(e, L.sX, P.A(b, k), n, n, n);                   // sX = A
+    e.to_lds(tA, L.sX);                                   // sX = A
     wg_sync();
-    e.template load<true>(tH, P.M(b, k), m, n, m);        // M'
-    e.template gemm<true, false, false, false, MB, E::TS>(tH, L.sA, L.sX, n);       // + (P'B)'A
+    e.template gemm<true, false, false, false, MB, E::TS>(tH, L.sA, L.sX, n);       // M' + (P'B)'A
     T dmin, dmax, nov[1];
     T dlA;
     const bool ok = e.template chol<0, MB>(tG, m, L.cb, dlA, nov, dmin, dmax);
@@ -732,10 +737,9 @@ __device__ __forceinline__ void policy_task(Lds<E>& L, const Plan& p, const In<S
     e.to_lds(KK[0], L.sA);                                // sA = K (m x n)
     stage(e, L.sX, P.B(b, k), n, m, m);                   // sX = B
     wg_sync();
-    e.load(t, P.A(b, k), n, n, n);
-    e.template gemm<false, false>(t, L.sX, L.sA, m);
+    e.template gemm<false, false>(tA, L.sX, L.sA, m);     // A + B K
     S* leaf = inst + p.o_ftree + (int64_t)k * p.frec;
-    e.store(t, leaf, n, n, n);
+    e.store(tA, leaf, n, n, n);
     const T bb = e.template matvec<false>(L.sX, L.vb, hv[0], m, n) + e.vload(P.c(b, k), n);
     e.vstore(leaf + nn, n, bb);
 }
