@@ -52,7 +52,7 @@ MR_BATCH = 64
 # with the first up-sweep level, split schedule) from rocprofv3 FETCH_SIZE /
 # WRITE_SIZE runs, calibrated against a copy of known size; valid only for
 # the kernel sources they were taken on (hash of engine.hpp + kernels.hpp)
-KUP_TRAFFIC = {"kernel": "tail_sweep_up0", "src_hash": "ae5fd5ac9bf3b5a6", "bytes_per_launch": 1.0087e+10,
+KUP_TRAFFIC = {"kernel": "tail_sweep_up0", "src_hash": "bafff0af5dac88d2", "bytes_per_launch": 1.0284e+10,
                "note": "FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (copy calibration), per launch"}
 
 

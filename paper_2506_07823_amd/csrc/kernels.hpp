@@ -381,6 +381,19 @@ __device__ __forceinline__ void combine(const E& e, Lds<E>& L, int n, const S* e
     const int nn = n * n;
     typename E::Tile tS;
     T dmin, dmax;
+    // Cheap form: A1, P1, b1, p1 go to registers up front, so their global
+    // latency overlaps the two factorizations (the wave barriers keep loads
+    // written at their point of use from moving up).  The general form
+    // keeps them at their point of use: 50 more VGPRs there would cost a
+    // wavefront per SIMD.
+    typename E::Tile tA1, tP1;
+    T b1pre = T(0), p1pre = T(0);
+    if constexpr (CHEAP) {
+        e.load(tA1, e1, n, n, n);
+        e.load(tP1, e1 + 2 * nn, n, n, n);
+        b1pre = e.vload(e1 + 3 * nn, n);
+        p1pre = e.vload(e1 + 3 * nn + n, n);
+    }
     // L = chol(P2), g = L^{-1} p2
     e.g2s(L.sA, P2, n, n, n);
     e.g2s(L.sX, e1 + nn, n, n, n);                         // sX = C1
@@ -422,11 +435,12 @@ __device__ __forceinline__ void combine(const E& e, Lds<E>& L, int n, const S* e
 #pragma unroll
             for (int bb = 0; bb < E::TS; ++bb) YZ[1][a][bb] = Z1[0][a][bb];
     }
-    e.g2s(L.sX, e1, n, n, n);                             // sX = A1
+    if constexpr (CHEAP) e.to_lds(tA1, L.sX);             // sX = A1
+    else e.g2s(L.sX, e1, n, n, n);
     wg_sync();
     e.zero(YZ[0]);
     e.template gemm<true, false>(YZ[0], L.sA, L.sX, n);    // L' A1
-    const T b1 = e.vload(e1 + 3 * nn, n);
+    const T b1 = CHEAP ? b1pre : e.vload(e1 + 3 * nn, n);
     T vv[2];
     vv[0] = g[0] + e.template matvec<true>(L.sA, L.vb, b1, n, n);
     wg_sync();
@@ -460,11 +474,19 @@ __device__ __forceinline__ void combine(const E& e, Lds<E>& L, int n, const S* e
         vv[0] = v1[0];
     }
     e.to_lds(YZ[0], L.sX);                                 // sX = Y
-    e.g2s(L.sA, e1 + 2 * nn, n, n, n);                     // sA = P1
-    wg_sync();
-    e.from_lds(tS, L.sA);
+    if constexpr (CHEAP) {
+        wg_sync();
+#pragma unroll
+        for (int a = 0; a < E::TS; ++a)
+#pragma unroll
+            for (int bb = 0; bb < E::TS; ++bb) tS[a][bb] = tP1[a][bb];   // P1
+    } else {
+        e.g2s(L.sA, e1 + 2 * nn, n, n, n);                 // sA = P1
+        wg_sync();
+        e.from_lds(tS, L.sA);
+    }
     e.template gemm<true, false, true>(tS, L.sX, L.sX, n); // P1 + Y'Y (lower)
-    const T pv = e.template matvec<true>(L.sX, L.vb, vv[0], n, n) + e.vload(e1 + 3 * nn + n, n);
+    const T pv = e.template matvec<true>(L.sX, L.vb, vv[0], n, n) + (CHEAP ? p1pre : e.vload(e1 + 3 * nn + n, n));
     e.vstore(outp, n, pv);
     wg_sync();
     e.to_lds_sym(tS, L.sA);                                // sA = P
