@@ -53,9 +53,19 @@
  *
  * Errors: functions return LQR_OK (0) or a negative code; nothing is launched
  * when argument checking fails.  Per-instance numerical problems are
- * reported in `status` (bit flags below) and make lqr_kkt_solve return
- * LQR_OK: the status array is written on the device, so the host learns of
- * them only after synchronizing and reading it.
+ * reported in `status` (bit flags below).  The call is asynchronous, so by
+ * default it returns LQR_OK and the host learns of them after synchronizing
+ * and reading `status`; with opts.sync_status set the call waits for the
+ * stream, reads the status words and returns LQR_ENUMERIC if an instance
+ * failed even after the FP64 fallback.
+ *
+ * FP64 fallback (FP32 calls, opts.fallback = 1): a Cholesky factorization of
+ * the scan (R_k in the element, G_k in the policy, the value matrix and the
+ * inner matrix of a combine) with a non-positive pivot or a condition
+ * estimate (max L_ii / min L_ii)^2 above opts.cond_threshold marks its
+ * instance; after the FP32 solve every marked instance is solved again whole
+ * with FP64 arithmetic and FP64 intermediates (the sequential recursion of
+ * eq. (lqr)), its FP32 outputs are overwritten, and its status carries bit 8.
  */
 #ifndef LQR_KKT_H
 #define LQR_KKT_H
@@ -71,6 +81,7 @@ extern "C" {
 #define LQR_OK 0
 #define LQR_EINVAL (-1)   /* bad size, null or misaligned pointer, bad option */
 #define LQR_ENOMEM (-2)   /* workspace smaller than lqr_workspace_size reports */
+#define LQR_ENUMERIC (-3) /* (opts.sync_status only) an instance failed even after the FP64 fallback */
 #define LQR_EDEVICE (-4)  /* a HIP runtime call failed (see lqr_last_error) */
 #define LQR_EUNSUPPORTED (-5) /* shape class not built into this library */
 
@@ -78,7 +89,7 @@ extern "C" {
 #define LQR_ST_NONFINITE 1    /* a non-finite value reached the output */
 #define LQR_ST_NOT_SPD 2      /* R_k or G_k = R_k + B_k'P_{k+1}B_k not positive definite, even in FP64 */
 #define LQR_ST_P_NOT_SPD 4    /* a scan value matrix lost positive definiteness */
-#define LQR_ST_FP64_FALLBACK 8 /* an R_k / G_k factorization was redone in FP64 (informational) */
+#define LQR_ST_FP64_FALLBACK 8 /* the instance was solved again whole in FP64 (informational) */
 
 typedef enum { LQR_F32 = 0, LQR_F64 = 1 } lqr_dtype;
 typedef enum { LQR_METHOD_SCAN = 0, LQR_METHOD_SEQ_RICCATI = 1 } lqr_method;
@@ -93,9 +104,12 @@ typedef struct {
                                above refine_tol, re-solves the correction system with the factors
                                of the first solve (instances already within the tolerance are left
                                as they are).  Default: 1 for LQR_F32, 0 for LQR_F64. */
-    int32_t fallback;       /* 1 (default): redo ill-conditioned R_k / G_k factorizations in FP64 */
+    int32_t fallback;       /* 1 (default): solve an instance again whole in FP64 when one of its FP32
+                               factorizations fails or is ill-conditioned (see above) */
     double cond_threshold;  /* condition estimate above which the FP64 fallback fires (default 1e6) */
-    double refine_tol;      /* relative KKT residual at or below which an instance is not refined (1e-5) */
+    double refine_tol;      /* relative KKT residual at or below which an instance is not refined
+                               (default 1e-6: a tenth of the 1e-5 the FP32 path promises, so that an
+                               instance is returned unrefined only well inside that tolerance) */
     double* resid_out;      /* optional device [batch] FP64: relative KKT residual of the returned
                                solution, ||r(x,u,lam)||_2 / ||(x0, c, q, r)||_2; NULL to skip */
     /* optional warm start (scan method; all three or none): device arrays in the layout and dtype
@@ -107,6 +121,9 @@ typedef struct {
     const void* warm_x;
     const void* warm_u;
     const void* warm_lam;
+    int32_t sync_status;    /* 1: wait for the stream after the solve, read the status words and return
+                               LQR_ENUMERIC if an instance has a failure bit (anything but bit 8);
+                               not for use under stream capture.  Default 0 (asynchronous). */
 } lqr_opts;
 
 /* Fill *o with the defaults for `dtype` (scan method, refinement as above). */
@@ -148,6 +165,17 @@ int lqr_kkt_residual(lqr_handle_t h, void* stream, int64_t batch, int N, int n, 
                      const void* lam, double* rel, void* workspace,
                      size_t workspace_bytes);
 
+/* Diagnostics: the value function and policy of Sec. II-C that the last
+ * LQR_METHOD_SCAN solve of this shape (same handle mapping, same workspace)
+ * left in `workspace`: P [batch][N+1][n][n] and p [batch][N+1][n] (the
+ * complete-suffix value functions P_k, p_k of the reverse scan), K
+ * [batch][N][m][n] and kff [batch][N][m] (the policy of eq. (lqr)), device
+ * arrays of the call's dtype.  Asynchronous on `stream`.  For an instance
+ * that was solved again by the FP64 fallback (status bit 8) these are the
+ * FP32 pass's values, not those of its returned solution. */
+int lqr_kkt_factors(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int m, int32_t dtype,
+                    const void* workspace, size_t workspace_bytes, void* P, void* p, void* K, void* kff);
+
 /* Diagnostics: while enabled, every kernel launch of lqr_kkt_solve /
  * lqr_kkt_residual on this handle is bracketed by two HIP events recorded on
  * the call's stream (adds two event records per launch).  Not for use under
@@ -170,40 +198,55 @@ int lqr_timing_report(lqr_handle_t h, char* buf, size_t len);
  *            vector-only passes, 1 = one workgroup per instance for them,
  *            2 = the whole solve (elements, scan, policy, forward scan,
  *            recovery, residual, refinement) in one launch, one workgroup
- *            of several wavefronts per instance (wavefront engine only; an
- *            instance the FP32 pass flags for the FP64 fallback is then
- *            recomputed whole with FP64 arithmetic by a second launch)
+ *            of several wavefronts per instance (wavefront engine only)
  *   big_grid 0 = default (512), else the workgroups / scratch slots of a
  *            matrix-core task launch
  *   ms       (lqr_autotune output) mean time of one solve with this mapping
- *   split    0 = balanced tree over all N+1 scan elements (default), 1 = split
- *            schedule (wavefront engine, fused 0 or 1): the tree over the
+ *   split    schedule of the reverse scan (Sec. II-D; every schedule gives the
+ *            same value functions, they differ in depth and work):
+ *            0 = balanced tree over all N+1 scan elements (default);
+ *            1 = split (wavefront engine, fused 0 or 1): the tree over the
  *            first 2^k elements (the largest power of two below N+1), the
  *            suffixes of the others by a sequential sweep of combines with
- *            the complete suffix to their right (Sec. II-D combination rule;
- *            the same value functions, fewer general combines, more
- *            dependent steps) */
+ *            the complete suffix to their right;
+ *            2 = chunked (wavefront engine, fused 0 or 1): the last `sweep`
+ *            elements by the sequential sweep, the others in chunks of
+ *            `chunk` elements -- each chunk's aggregate by sequential
+ *            combines, the complete suffixes at the chunk starts by a
+ *            sequential pass over the aggregates, then the other suffixes
+ *            of every chunk (chunk 1, or sweep N+1: the sequential
+ *            information-form recursion)
+ *   chunk    chunk length for split 2 (>= 1)
+ *   sweep    elements of the sequential sweep for split 2 (1..N+1; the
+ *            terminal element is always in it)
+ *   fwd_seq  1 = forward scan, control/costate recovery and refinement
+ *            vector passes as sequential sweeps over the stages (one task
+ *            unit per instance, no forward-tree map products); fused 0 or 1 */
 typedef struct {
     int32_t engine;
     int32_t fused;
     int32_t big_grid;
     float ms;
     int32_t split;
+    int32_t chunk;
+    int32_t sweep;
+    int32_t fwd_seq;
 } lqr_tuning;
 
 /* Pin (t != NULL) or clear (t == NULL) the mapping of the shape
  * (batch, N, n, m, dtype) on this handle; later lqr_workspace_size,
  * lqr_kkt_solve and lqr_kkt_residual calls of that shape use it.
  * LQR_EINVAL for an out-of-range field, engine 1 above order 64, fused 2
- * with the matrix-core engine, or split 1 with the matrix-core engine or
- * fused 2. */
+ * with the matrix-core engine, split 1 or 2 with the matrix-core engine or
+ * fused 2, or fwd_seq with fused 2. */
 int lqr_set_tuning(lqr_handle_t h, int64_t batch, int N, int n, int m, int32_t dtype, const lqr_tuning* t);
 
 /* Autotuner: solves the given problem (same arguments as lqr_kkt_solve)
  * once per candidate mapping -- each engine that can take the shape, each
- * form of the passes (fused 0 / 1, and 2 on the wavefront engine), both
- * reverse-scan schedules on the wavefront engine (split 0 / 1),
- * matrix-core grids of 256 / 512 / 1024
+ * form of the passes (fused 0 / 1, fwd_seq 0 / 1, and the one-launch solve on
+ * the wavefront engine), the reverse-scan schedules of the wavefront engine
+ * (balanced tree, split, chunked with chunk 1 / 4 / 8 / 16 / 32 and a
+ * one-element sweep), matrix-core grids of 256 / 512 / 1024
  * workgroups -- then `reps` more times on the stream, timed with HIP events;
  * candidates whose status words are not clean (other than the FP64-fallback
  * bit) or whose workspace does not fit are skipped.  The fastest mapping is
@@ -217,6 +260,17 @@ int lqr_autotune(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int 
                  void* lam, int32_t* status, void* workspace, size_t workspace_bytes,
                  const lqr_opts* opts, int reps, lqr_tuning* best);
 int lqr_autotune_workspace_size(int64_t batch, int N, int n, int m, const lqr_opts* opts, size_t* bytes);
+
+/* Tuning cache.  lqr_autotune also records its choice per shape bucket
+ * (dtype, n, m, N and batch rounded up to powers of two), and a solve of a
+ * shape with no exact mapping pinned uses its bucket's.  lqr_tuning_save
+ * writes the buckets of this handle to a text file at `path` (replacing the
+ * entries of this device's architecture, keeping those of others);
+ * lqr_tuning_load reads the entries of this device's architecture into the
+ * handle and returns how many it loaded (>= 0), or LQR_EINVAL if the file
+ * cannot be read. */
+int lqr_tuning_save(lqr_handle_t h, const char* path);
+int lqr_tuning_load(lqr_handle_t h, const char* path);
 
 /* One problem of a ragged batch: its sizes and the device arrays of one
  * instance in the layout above (without the batch axis). */

@@ -45,6 +45,15 @@ def build(force: bool = True) -> str:
     return _LIB
 
 
+def build_native(path: str) -> str:
+    """Compile the same source for the host it runs on (-march=native) into
+    ``path`` (the CPU baseline's timing build; the default build above stays
+    portable because the built library travels to other hosts)."""
+    flags = [f for f in CFLAGS if not f.startswith("-march=")] + ["-march=native"]
+    subprocess.check_call(["gcc", *flags, "-o", path, _SRC, "-lm"])
+    return path
+
+
 def _bind(lib):
     dp = ctypes.POINTER(ctypes.c_double)
     ip = ctypes.POINTER(ctypes.c_int32)

@@ -25,7 +25,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblqr_kkt.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "lqr_kkt.h")
 
-LQR_OK, LQR_EINVAL, LQR_ENOMEM, LQR_EDEVICE, LQR_EUNSUPPORTED = 0, -1, -2, -4, -5
+LQR_OK, LQR_EINVAL, LQR_ENOMEM, LQR_ENUMERIC, LQR_EDEVICE, LQR_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 LQR_F32, LQR_F64 = 0, 1
 LQR_METHOD_SCAN, LQR_METHOD_SEQ_RICCATI = 0, 1
 ST_NONFINITE, ST_NOT_SPD, ST_P_NOT_SPD, ST_FP64_FALLBACK = 1, 2, 4, 8
@@ -43,12 +43,14 @@ class lqr_opts(ctypes.Structure):
         ("warm_x", ctypes.c_void_p),
         ("warm_u", ctypes.c_void_p),
         ("warm_lam", ctypes.c_void_p),
+        ("sync_status", ctypes.c_int32),
     ]
 
 
 class lqr_tuning(ctypes.Structure):
     _fields_ = [("engine", ctypes.c_int32), ("fused", ctypes.c_int32), ("big_grid", ctypes.c_int32),
-                ("ms", ctypes.c_float), ("split", ctypes.c_int32)]
+                ("ms", ctypes.c_float), ("split", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("sweep", ctypes.c_int32), ("fwd_seq", ctypes.c_int32)]
 
 
 class lqr_problem(ctypes.Structure):
@@ -105,6 +107,13 @@ _lib.lqr_timing_enable.argtypes = [_vp, ctypes.c_int]
 _lib.lqr_timing_enable.restype = ctypes.c_int
 _lib.lqr_timing_report.argtypes = [_vp, ctypes.c_char_p, _sz]
 _lib.lqr_timing_report.restype = ctypes.c_int
+_lib.lqr_kkt_factors.argtypes = [_vp, _vp, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, _i32, _vp, _sz,
+                                 _vp, _vp, _vp, _vp]
+_lib.lqr_kkt_factors.restype = ctypes.c_int
+_lib.lqr_tuning_save.argtypes = [_vp, ctypes.c_char_p]
+_lib.lqr_tuning_save.restype = ctypes.c_int
+_lib.lqr_tuning_load.argtypes = [_vp, ctypes.c_char_p]
+_lib.lqr_tuning_load.restype = ctypes.c_int
 
 # the C entry points under their own names
 lqr_opts_default = _lib.lqr_opts_default
@@ -122,6 +131,9 @@ lqr_autotune = _lib.lqr_autotune
 lqr_autotune_workspace_size = _lib.lqr_autotune_workspace_size
 lqr_ragged_workspace_size = _lib.lqr_ragged_workspace_size
 lqr_kkt_solve_ragged = _lib.lqr_kkt_solve_ragged
+lqr_tuning_save = _lib.lqr_tuning_save
+lqr_kkt_factors = _lib.lqr_kkt_factors
+lqr_tuning_load = _lib.lqr_tuning_load
 
 FIELDS = ("A", "B", "c", "Q", "R", "M", "q", "r", "x0")
 
@@ -202,15 +214,17 @@ _default_ws = {}
 
 
 def solve(A, B, c, Q, R, M, q, r, x0, *, method: str = "scan", refine: int | None = None,
-          fallback: bool = True, cond_threshold: float = 1e6, refine_tol: float = 1e-5,
-          want_resid: bool = False, warm=None,
+          fallback: bool = True, cond_threshold: float = 1e6, refine_tol: float | None = None,
+          want_resid: bool = False, warm=None, sync_status: bool = False,
           workspace: Workspace | None = None, out=None, stream=None):
     """Batched LQR-KKT solve; returns dict x, u, lam, status (+ resid).
 
     All tensors are device tensors of one dtype (float32 or float64) with a
     leading batch axis; the call is asynchronous on ``stream`` (default: the
     current torch stream).  ``warm`` = (x, u, lam) starts the scan's
-    refinement from that solution (it may be ``out``'s own arrays)."""
+    refinement from that solution (it may be ``out``'s own arrays).
+    ``sync_status``: wait for the solve and raise LqrError (LQR_ENUMERIC) if
+    an instance failed even after the FP64 fallback."""
     d = dict(A=A, B=B, c=c, Q=Q, R=R, M=M, q=q, r=r, x0=x0)
     dtype = A.dtype
     device = A.device.index
@@ -223,7 +237,9 @@ def solve(A, B, c, Q, R, M, q, r, x0, *, method: str = "scan", refine: int | Non
         o.refine_sweeps = int(refine)
     o.fallback = 1 if fallback else 0
     o.cond_threshold = float(cond_threshold)
-    o.refine_tol = float(refine_tol)
+    if refine_tol is not None:
+        o.refine_tol = float(refine_tol)
+    o.sync_status = 1 if sync_status else 0
     if out is None:
         out = {
             "x": torch.empty((batch, N + 1, n), dtype=dtype, device=A.device),
@@ -351,19 +367,23 @@ def autotune(A, B, c, Q, R, M, q, r, x0, *, method: str = "scan", refine: int | 
                              *[t.data_ptr() for t in out], ws.data_ptr(), ws.numel(), ctypes.byref(o), int(reps),
                              ctypes.byref(best)))
     return {"engine": {1: "wavefront", 2: "matrix-core"}[best.engine], "fused": int(best.fused),
-            "big_grid": int(best.big_grid), "split": int(best.split), "ms": float(best.ms)}
+            "big_grid": int(best.big_grid), "split": int(best.split), "chunk": int(best.chunk),
+            "sweep": int(best.sweep), "fwd_seq": int(best.fwd_seq), "ms": float(best.ms)}
 
 
 def set_tuning(batch: int, N: int, n: int, m: int, dtype=torch.float32, *, engine: str | None = None,
-               fused: bool | int | None = None, big_grid: int = 0, split: bool = False, device: int = 0,
-               clear: bool = False):
+               fused: bool | int | None = None, big_grid: int = 0, split: bool | int = False, chunk: int = 0,
+               sweep: int = 0, fwd_seq: bool = False, device: int = 0, clear: bool = False):
     """Pin (or clear) the mapping of a problem shape on the device's handle.
 
     fused: None = default; 0 / False = vector-only passes level by level;
     1 / True = one workgroup per instance for them; 2 = the whole solve in
-    one launch (wavefront engine).  split: the split schedule of the reverse
-    scan (tree over the first 2^k elements, a sequential sweep over the
-    rest; wavefront engine, fused 0 or 1)."""
+    one launch (wavefront engine).  split: schedule of the reverse scan,
+    0 / False = balanced tree, 1 / True = split (tree over the first 2^k
+    elements, a sequential sweep over the rest), 2 = chunked (`sweep`
+    elements swept sequentially, chunks of `chunk` elements over the rest);
+    wavefront engine, fused 0 or 1.  fwd_seq: sequential forward and
+    refinement vector passes (no forward-tree products)."""
     dt = LQR_F32 if dtype == torch.float32 else LQR_F64
     if clear:
         _check(_lib.lqr_set_tuning(handle(device), batch, N, n, m, dt, None))
@@ -372,8 +392,41 @@ def set_tuning(batch: int, N: int, n: int, m: int, dtype=torch.float32, *, engin
     t.engine = {None: 0, "wavefront": 1, "matrix-core": 2}[engine]
     t.fused = -1 if fused is None else int(fused)
     t.big_grid = int(big_grid)
-    t.split = 1 if split else 0
+    t.split = int(split)
+    t.chunk = int(chunk)
+    t.sweep = int(sweep)
+    t.fwd_seq = 1 if fwd_seq else 0
     _check(_lib.lqr_set_tuning(handle(device), batch, N, n, m, dt, ctypes.byref(t)))
+
+
+def save_tuning(path: str, device: int = 0):
+    """Write the autotuned mappings (per shape bucket) of the device's handle to `path`."""
+    _check(_lib.lqr_tuning_save(handle(device), os.fsencode(path)))
+
+
+def load_tuning(path: str, device: int = 0) -> int:
+    """Load the mappings of this device's architecture from `path`; returns how many."""
+    rc = _lib.lqr_tuning_load(handle(device), os.fsencode(path))
+    if rc < 0:
+        _check(rc)
+    return rc
+
+
+def factors(batch, N, n, m, dtype, workspace: Workspace, stream=None) -> dict:
+    """P_k, p_k, K_k, kff_k of the last scan solve of this shape that used
+    `workspace` (diagnostics: the records the reverse scan and the policy
+    left there)."""
+    device = workspace.device
+    dev = f"cuda:{device}"
+    out = {"P": torch.empty((batch, N + 1, n, n), dtype=dtype, device=dev),
+           "p": torch.empty((batch, N + 1, n), dtype=dtype, device=dev),
+           "K": torch.empty((batch, N, m, n), dtype=dtype, device=dev),
+           "kff": torch.empty((batch, N, m), dtype=dtype, device=dev)}
+    s = (stream or torch.cuda.current_stream(device)).cuda_stream
+    _check(_lib.lqr_kkt_factors(handle(device), s, batch, N, n, m, LQR_F32 if dtype == torch.float32 else LQR_F64,
+                                workspace.buf.data_ptr(), workspace.buf.numel(), out["P"].data_ptr(),
+                                out["p"].data_ptr(), out["K"].data_ptr(), out["kff"].data_ptr()))
+    return out
 
 
 def kernel_timing(enable: bool, device: int = 0):
@@ -382,12 +435,15 @@ def kernel_timing(enable: bool, device: int = 0):
 
 
 def kernel_report(device: int = 0) -> dict:
-    """Per kernel family: launches, total ms, algorithmic flops and bytes of
-    the launches timed since the last report (waits for them)."""
+    """Per kernel family: launches, total ms, algorithmic flops (the method's
+    per-unit cost model) and bytes, and the flops with the combines counted
+    at the minimal cost of their Cholesky form, of the launches timed since
+    the last report (waits for them)."""
     buf = ctypes.create_string_buffer(1 << 16)
     _check(_lib.lqr_timing_report(handle(device), buf, len(buf)))
     fams = {}
     for line in buf.value.decode().strip().splitlines():
-        name, launches, ms, fl, by = line.split()
-        fams[name] = dict(launches=int(launches), ms=float(ms), flops=float(fl), bytes=float(by))
+        name, launches, ms, fl, by, flm = line.split()
+        fams[name] = dict(launches=int(launches), ms=float(ms), flops=float(fl), bytes=float(by),
+                          flops_min=float(flm))
     return fams

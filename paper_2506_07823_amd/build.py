@@ -1,6 +1,6 @@
 """Build liblqr_kkt.so (the HIP/gfx950 C-ABI library) in-tree.
 
-Each padded-order class is a separate translation unit, compiled in parallel
+Each (padded-order class, storage type) pair is a separate translation unit, compiled in parallel
 with hipcc; the objects are linked against the HIP runtime that PyTorch-ROCm
 loads (``torch/lib/libamdhip64.so``), so that a Python process holding both
 torch and this library runs a single HIP runtime.
@@ -44,8 +44,10 @@ def _sources():
     deps = [os.path.join(CSRC, f) for f in ("engine.hpp", "bigeng.hpp", "kernels.hpp", "kernels_big.hpp", "runs.hpp", "pack.hpp")]
     deps.append(os.path.join(HERE, "..", "include", "lqr_kkt.h"))
     units = [("lqr_kkt", os.path.join(CSRC, "lqr_kkt.hip"), [])]
-    for ts in TS_CLASSES:
-        units.append((f"inst_ts{ts}", os.path.join(CSRC, "inst.hip"), [f"-DLQR_TS={ts}"]))
+    # the slowest units first, so the parallel build ends sooner
+    for ts in sorted(TS_CLASSES, key=lambda t: -t if t != 32 else 0):
+        for sv in ("float", "double"):
+            units.append((f"inst_ts{ts}_{sv}", os.path.join(CSRC, "inst.hip"), [f"-DLQR_TS={ts}", f"-DLQR_S={sv}"]))
     return units, deps
 
 

@@ -5,7 +5,6 @@
 //
 // Kernels of the scan path, in launch order:
 //   k_element   one-stage conditional value function, eq. (initialization)
-//               (+ FP64 redo of ill-conditioned R_k factorizations)
 //   k_up        up-sweep of the reverse scan: node = left (x) right, with the
 //               combine of eq. (combination_rule) in Cholesky form
 //   k_root/k_down  down-sweep: complete suffixes e_k (x) ... (x) e_N, whose
@@ -51,8 +50,14 @@ struct Plan {
     int fallback;
     const int32_t* active;   // refinement gating: instances with active[b] == 0 skip (nullptr = all)
     int fused;               // 1: per-instance kernels for the vector-only passes
-    int tail;                // split schedule: the tree covers leaves [0, tail) (a power of two), a
-                             // sequential sweep the rest; 0 = balanced tree over all N+1 leaves
+    int sched;               // reverse scan: 0 balanced tree over all N+1 leaves; 1 split (tree over
+                             // [0, tail), tail a power of two); 2 chunked (chunks of `chunk` leaves
+                             // over [0, tail)); in 1 and 2 a sequential sweep covers [tail, N]
+    int tail;                // first leaf of the sequential sweep (schedules 1 and 2)
+    int chunk;               // chunk length (schedule 2)
+    int nchunk;              // chunks over [0, tail) (schedule 2)
+    int fwdseq;              // 1: forward scan and refinement vector passes as sequential sweeps
+                             // over the stages, one task unit per instance
     int64_t o_scr;           // large-block engine: byte offset of the per-workgroup scratch area
     int64_t scr_elems;       //   its elements per workgroup
     int big_grid;            //   workgroups of a task launch (scratch slots)
@@ -106,10 +111,10 @@ __device__ __forceinline__ int suffix_id(const Tree& t, int l, int j) {
 // no node straddles the boundary); the suffixes of leaves >= tail come from
 // the sequential sweep.
 __host__ __device__ __forceinline__ int up_count(const Plan& p, int lvl) {
-    return p.tail ? (p.tail >> (lvl + 1)) : p.rt.cnt[lvl + 1];
+    return p.sched == 1 ? (p.tail >> (lvl + 1)) : p.rt.cnt[lvl + 1];
 }
 __host__ __device__ __forceinline__ int down_half(const Plan& p, int lvl) {
-    return p.tail ? (p.tail >> lvl) / 2 : p.rt.cnt[lvl] / 2;
+    return p.sched == 1 ? (p.tail >> lvl) / 2 : p.rt.cnt[lvl] / 2;
 }
 
 template <class E>
@@ -197,43 +202,21 @@ __device__ __forceinline__ void set_status(int32_t* status, int64_t b, int bits)
 
 
 // ---------------------------------------------------------------------------
-// FP64 fallback queues.  An FP32 task whose Cholesky factorization fails or
-// whose condition estimate (max L_ii / min L_ii)^2 exceeds the threshold
-// appends its task id; the FP64 instance of the same kernel then drains the
-// queue with a small grid (no host synchronization, near-free when empty).
-// A queue without an id list (the fused solve) records only the status bit:
-// there the whole instance is redone in FP64.
+// FP64 fallback.  An FP32 task whose Cholesky factorization fails or whose
+// condition estimate (max L_ii / min L_ii)^2 exceeds the threshold marks its
+// instance (status bit 8).  Once the FP32 launch sequence has finished, the
+// marked instances are solved again whole with FP64 arithmetic and FP64
+// intermediates (k_redo): FP32 records of such an instance (the element of
+// an ill-conditioned R_k has eigenvalues spread over the square of its
+// condition number) cannot be repaired by redoing one factorization.
+// Without the fallback a failed factorization sets `failbit` instead.
 // ---------------------------------------------------------------------------
-struct FbQueue {
-    int32_t* count;
-    int32_t* ids;
-};
-
-template <int NTU = 0>
-__device__ __forceinline__ void fb_push(FbQueue q, int64_t task) {
-    if (q.ids && unit_tid<NTU>() == 0) {
-        const int slot = atomicAdd(q.count, 1);
-        q.ids[slot] = (int32_t)task;
-    }
-}
-
-// decide what a finished factorization means for this task
-template <bool FB, int NTU = 0, typename T>
-__device__ __forceinline__ void fb_decide(const Plan& p, bool ok, T kappa, int64_t b, int64_t task, FbQueue q,
-                                          int32_t* status, int failbit) {
-    if (!FB) {
-        const bool bad = !ok || !(kappa <= T(p.cond_thr));
-        if (bad) {
-            if (p.fallback) {
-                fb_push<NTU>(q, task);
-                set_status<NTU>(status, b, 8);
-            } else if (!ok) {
-                set_status<NTU>(status, b, failbit);
-            }
-        }
-    } else if (!ok) {
-        set_status<NTU>(status, b, failbit);
-    }
+template <int NTU = 0, typename T>
+__device__ __forceinline__ void fb_flag(const Plan& p, bool ok, T kappa, int64_t b, int32_t* status, int failbit) {
+    const bool bad = !ok || !(kappa <= T(p.cond_thr));
+    if (!bad) return;
+    if (p.fallback) set_status<NTU>(status, b, 8);
+    else if (!ok) set_status<NTU>(status, b, failbit);
 }
 
 template <typename T>
@@ -241,12 +224,31 @@ __device__ __forceinline__ T cond_est(T dmin, T dmax) {
     return dmin > T(0) ? (dmax / dmin) * (dmax / dmin) : T(3.0e38);
 }
 
-// clear the status words and the fallback queue counters (graph-safe fill)
+// clear the status words (a fill kernel, safe under graph capture)
 template <typename I>
-__global__ void k_clear(I* status, int64_t batch, I* counters, int64_t ncount) {
+__global__ void k_clear(I* status, int64_t batch) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < batch) status[i] = 0;
-    if (i < ncount) counters[i] = 0;
+}
+
+// Value function and policy of the last scan solve, read back from the
+// records of the workspace (one workgroup per instance and stage):
+// P [b][k] (n x n), p [b][k] (n) for k = 0..N; K [b][k] (m x n), kff [b][k]
+// (m) for k < N.
+template <typename S>
+__global__ void k_factors(Plan p, const S* ws, S* P, S* pv, S* K, S* kff) {
+    const int N = p.N, n = p.n, m = p.m, nn = n * n;
+    const int64_t b = blockIdx.x / (N + 1);
+    const int k = (int)(blockIdx.x % (N + 1));
+    const S* inst = ws + b * p.stride;
+    const S* rec = inst + p.o_suf + (int64_t)suffix_id(p.rt, 0, k) * p.srec;
+    const int64_t bk = b * (N + 1) + k;
+    for (int i = threadIdx.x; i < nn; i += blockDim.x) P[bk * nn + i] = rec[i];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) pv[bk * n + i] = rec[nn + i];
+    if (k == N) return;
+    const int64_t bq = b * N + k;
+    for (int i = threadIdx.x; i < m * n; i += blockDim.x) K[bq * m * n + i] = inst[p.o_K + (int64_t)k * m * n + i];
+    for (int i = threadIdx.x; i < m; i += blockDim.x) kff[bq * m + i] = inst[p.o_kff + (int64_t)k * m + i];
 }
 
 // dst = src, count elements (grid-stride)
@@ -256,28 +258,18 @@ __global__ void k_copy(const S* src, S* dst, int64_t count) {
         dst[i] = src[i];
 }
 
-// Run `body(task)` for every task of the launch (FP32 pass: one task per
-// workgroup, or grid-stride over the per-workgroup scratch slots of the
-// large-block engine) or for every queued task (FP64 pass: grid-stride over
-// the queue).
-#define LQR_TASKS(E, FB, q, ntasks, body)                                         \
-    do {                                                                          \
-        if (!(FB)) {                                                              \
-            if (E::BIG) {                                                         \
-                for (int64_t t_ = blockIdx.x; t_ < (ntasks); t_ += gridDim.x) {   \
-                    body(t_);                                                     \
-                    E::sync();                                                    \
-                }                                                                 \
-            } else {                                                              \
-                body((int64_t)blockIdx.x);                                        \
-            }                                                                     \
-        } else {                                                                  \
-            const int cnt_ = *(q).count;                                          \
-            for (int i_ = blockIdx.x; i_ < cnt_; i_ += gridDim.x) {               \
-                body((int64_t)(q).ids[i_]);                                       \
-                E::sync();                                                        \
-            }                                                                     \
-        }                                                                         \
+// Run `body(task)` for every task of the launch: one task per workgroup, or
+// grid-stride over the per-workgroup scratch slots of the large-block engine.
+#define LQR_TASKS(E, ntasks, body)                                            \
+    do {                                                                      \
+        if (E::BIG) {                                                         \
+            for (int64_t t_ = blockIdx.x; t_ < (ntasks); t_ += gridDim.x) {   \
+                body(t_);                                                     \
+                E::sync();                                                    \
+            }                                                                 \
+        } else {                                                              \
+            body((int64_t)blockIdx.x);                                        \
+        }                                                                     \
     } while (0)
 
 }  // namespace lqr
@@ -295,13 +287,13 @@ namespace lqr {
 //   R = L_R L_R',  W_B = L_R^{-1} B',  W_M = L_R^{-1} M',  w_r = L_R^{-1} r
 //   At = A - W_B' W_M,  Ct = W_B' W_B,  Pt = Q - W_M' W_M,
 //   bt = c - W_B' w_r,  pt = q - W_M' w_r.
-// The terminal element (k = N) is (0, 0, 0, Q_N, q_N).  FB: the FP64 redo
-// of stages flagged by the FP32 pass (condition estimate of L_R above the
-// threshold, or a non-positive pivot).
+// The terminal element (k = N) is (0, 0, 0, Q_N, q_N).  A factorization of
+// R_k with a non-positive pivot or a condition estimate above the threshold
+// marks the instance for the FP64 redo.
 // Record layout: A | C | P | b | p.
 // ---------------------------------------------------------------------------
-template <typename S, class E, bool FB, int MB>
-__device__ __forceinline__ void element_task(Lds<E>& L, const Plan& p, const In<S>& in, S* ws, int32_t* status, FbQueue q,
+template <typename S, class E, int MB>
+__device__ __forceinline__ void element_task(Lds<E>& L, const Plan& p, const In<S>& in, S* ws, int32_t* status,
                              int64_t task) {
     using T = typename E::T;
     const E e(unit_tid<E::NT>());
@@ -311,7 +303,6 @@ __device__ __forceinline__ void element_task(Lds<E>& L, const Plan& p, const In<
     S* rec = ws + b * p.stride + p.o_tree + (int64_t)k * p.rec;
     const Ptr<S> P(p, in);
     if (k == N) {
-        if (FB) return;
         coop_zero<E::NT>(rec, 2 * nn);
         coop_copy<E::NT>(rec + 2 * nn, P.Q(b, N), nn);
         coop_zero<E::NT>(rec + 3 * nn, n);
@@ -329,7 +320,7 @@ __device__ __forceinline__ void element_task(Lds<E>& L, const Plan& p, const In<
     T dmin, dmax, nov[1];
     T dlA;
     const bool ok = e.template chol<0, MB>(tR, m, L.cb, dlA, nov, dmin, dmax);
-    fb_decide<FB, E::NT>(p, ok, cond_est(dmin, dmax), b, task, q, status, 2);
+    fb_flag<E::NT>(p, ok, cond_est(dmin, dmax), b, status, 2);
     e.to_lds(tR, L.sA);
     wg_sync();
     e.template trsm<true, 2, 1, MB>(L.sA, dlA, m, W, vv, L.rb);
@@ -352,14 +343,14 @@ __device__ __forceinline__ void element_task(Lds<E>& L, const Plan& p, const In<
     e.vstore(rec + 3 * nn + n, n, e.vload(P.q(b, k), n) - pw);
 }
 
-template <typename S, class E, bool FB, int MB>
-__global__ __launch_bounds__(E::NT) void k_element(Plan p, In<S> in, S* ws, int32_t* status, FbQueue q) {
+template <typename S, class E, int MB>
+__global__ __launch_bounds__(E::NT) void k_element(Plan p, In<S> in, S* ws, int32_t* status) {
     __shared__ Lds<E> L;
     auto body = [&](int64_t t) {
-        if constexpr (E::BIG) big_element_task<S, E, FB>(L, p, in, ws, status, q, t);
-        else element_task<S, E, FB, MB>(L, p, in, ws, status, q, t);
+        if constexpr (E::BIG) big_element_task<S, E>(L, p, in, ws, status, t);
+        else element_task<S, E, MB>(L, p, in, ws, status, t);
     };
-    LQR_TASKS(E, FB, q, p.batch * (p.N + 1), body);
+    LQR_TASKS(E, p.batch * (p.N + 1), body);
 }
 
 // ---------------------------------------------------------------------------
@@ -518,8 +509,8 @@ __device__ __forceinline__ void combine(const E& e, Lds<E>& L, int n, const S* e
     kappa = kap;
 }
 
-template <typename S, class E, bool FB>
-__device__ __forceinline__ void up_task(Lds<E>& L, const Plan& p, S* ws, int lvl, int32_t* status, FbQueue q, int64_t task) {
+template <typename S, class E>
+__device__ __forceinline__ void up_task(Lds<E>& L, const Plan& p, S* ws, int lvl, int32_t* status, int64_t task) {
     const E e(unit_tid<E::NT>());
     const int n = p.n, nn = n * n;
     const int cout = up_count(p, lvl), cin = p.rt.cnt[lvl];
@@ -529,7 +520,7 @@ __device__ __forceinline__ void up_task(Lds<E>& L, const Plan& p, S* ws, int lvl
     const S* e1 = base + (int64_t)(p.rt.off[lvl] + 2 * i) * p.rec;
     S* out = base + (int64_t)(p.rt.off[lvl + 1] + i) * p.rec;
     if (2 * i + 1 >= cin) {
-        if (!FB) coop_copy<E::NT>(out, e1, p.rec);
+        coop_copy<E::NT>(out, e1, p.rec);
         return;
     }
     const S* e2 = e1 + p.rec;
@@ -537,17 +528,17 @@ __device__ __forceinline__ void up_task(Lds<E>& L, const Plan& p, S* ws, int lvl
     typename E::T kappa;
     combine<E, false>(e, L, n, e1, e2 + 2 * nn, e2 + 3 * nn + n, e2, out, out + nn, out + 2 * nn, out + 3 * nn,
                       out + 3 * nn + n, ok, kappa);
-    fb_decide<FB, E::NT>(p, ok, kappa, b, task, q, status, 4);
+    fb_flag<E::NT>(p, ok, kappa, b, status, 4);
 }
 
-template <typename S, class E, bool FB>
-__global__ __launch_bounds__(E::NT) void k_up(Plan p, S* ws, int lvl, int32_t* status, FbQueue q) {
+template <typename S, class E>
+__global__ __launch_bounds__(E::NT) void k_up(Plan p, S* ws, int lvl, int32_t* status) {
     __shared__ Lds<E> L;
     auto body = [&](int64_t t) {
-        if constexpr (E::BIG) big_up_task<S, E, FB>(L, p, ws, lvl, status, q, t);
-        else up_task<S, E, FB>(L, p, ws, lvl, status, q, t);
+        if constexpr (E::BIG) big_up_task<S, E>(L, p, ws, lvl, status, t);
+        else up_task<S, E>(L, p, ws, lvl, status, t);
     };
-    LQR_TASKS(E, FB, q, p.batch * up_count(p, lvl), body);
+    LQR_TASKS(E, p.batch * up_count(p, lvl), body);
 }
 
 // root of the reverse tree: its (P, p) is the complete suffix starting at 0
@@ -567,8 +558,8 @@ __global__ void k_root(Plan p, S* ws) {
 }
 
 // down-sweep at level lvl: odd node j gets node_j (x) suffix(level lvl+1, (j+1)/2)
-template <typename S, class E, bool FB>
-__device__ __forceinline__ void down_task(Lds<E>& L, const Plan& p, S* ws, int lvl, int32_t* status, FbQueue q, int64_t task) {
+template <typename S, class E>
+__device__ __forceinline__ void down_task(Lds<E>& L, const Plan& p, S* ws, int lvl, int32_t* status, int64_t task) {
     const E e(unit_tid<E::NT>());
     const int n = p.n, nn = n * n;
     const int half = down_half(p, lvl);
@@ -580,10 +571,8 @@ __device__ __forceinline__ void down_task(Lds<E>& L, const Plan& p, S* ws, int l
     S* out = suf + (int64_t)(p.rt.off[lvl] + j) * p.srec;
     const int i1 = (j + 1) / 2;
     if (i1 >= p.rt.cnt[lvl + 1]) {
-        if (!FB) {
-            coop_copy<E::NT>(out, node + 2 * nn, nn);
-            coop_copy<E::NT>(out + nn, node + 3 * nn + n, n);
-        }
+        coop_copy<E::NT>(out, node + 2 * nn, nn);
+        coop_copy<E::NT>(out + nn, node + 3 * nn + n, n);
         return;
     }
     const S* s2 = suf + (int64_t)suffix_id(p.rt, lvl + 1, i1) * p.srec;
@@ -591,17 +580,17 @@ __device__ __forceinline__ void down_task(Lds<E>& L, const Plan& p, S* ws, int l
     typename E::T kappa;
     combine<E, true>(e, L, n, node, s2, s2 + nn, (const S*)nullptr, (S*)nullptr, (S*)nullptr, out,
                      (S*)nullptr, out + nn, ok, kappa);
-    fb_decide<FB, E::NT>(p, ok, kappa, b, task, q, status, 4);
+    fb_flag<E::NT>(p, ok, kappa, b, status, 4);
 }
 
-template <typename S, class E, bool FB>
-__global__ __launch_bounds__(E::NT) void k_down(Plan p, S* ws, int lvl, int32_t* status, FbQueue q) {
+template <typename S, class E>
+__global__ __launch_bounds__(E::NT) void k_down(Plan p, S* ws, int lvl, int32_t* status) {
     __shared__ Lds<E> L;
     auto body = [&](int64_t t) {
-        if constexpr (E::BIG) big_down_task<S, E, FB>(L, p, ws, lvl, status, q, t);
-        else down_task<S, E, FB>(L, p, ws, lvl, status, q, t);
+        if constexpr (E::BIG) big_down_task<S, E>(L, p, ws, lvl, status, t);
+        else down_task<S, E>(L, p, ws, lvl, status, t);
     };
-    LQR_TASKS(E, FB, q, p.batch * down_half(p, lvl), body);
+    LQR_TASKS(E, p.batch * down_half(p, lvl), body);
 }
 
 // ---------------------------------------------------------------------------
@@ -614,12 +603,11 @@ __global__ __launch_bounds__(E::NT) void k_down(Plan p, S* ws, int lvl, int32_t*
 // depends on these leaves: the tree over [0, tail) needs only the suffix of
 // leaf `tail`, taken by the root task below.  One wavefront per instance;
 // the wave barrier with its fences orders each step's stores before the
-// next step's loads (all lanes of the wave share one CU's caches).  Any
-// flagged step sends the whole instance's sweep to the FP64 redo (queue id
-// = instance), which recomputes it from the same records.
+// next step's loads (all lanes of the wave share one CU's caches).  A
+// flagged step marks the instance for the FP64 redo.
 // ---------------------------------------------------------------------------
-template <typename S, class E, bool FB>
-__device__ __forceinline__ void tail_task(Lds<E>& L, const Plan& p, S* ws, int32_t* status, FbQueue q, int64_t b) {
+template <typename S, class E>
+__device__ __forceinline__ void tail_task(Lds<E>& L, const Plan& p, S* ws, int32_t* status, int64_t b) {
     static_assert(!E::BIG, "wavefront engine only");
     const E e(unit_tid<E::NT>());
     const int N = p.N, n = p.n, nn = n * n;
@@ -646,14 +634,14 @@ __device__ __forceinline__ void tail_task(Lds<E>& L, const Plan& p, S* ws, int32
         if (!(kappa <= kmax)) kmax = kappa;   // NaN propagates
         E::sync();
     }
-    fb_decide<FB, E::NT>(p, ok_all, kmax, b, b, q, status, 4);
+    fb_flag<E::NT>(p, ok_all, kmax, b, status, 4);
 }
 
-template <typename S, class E, bool FB>
-__global__ __launch_bounds__(E::NT) void k_tail(Plan p, S* ws, int32_t* status, FbQueue q) {
+template <typename S, class E>
+__global__ __launch_bounds__(E::NT) void k_tail(Plan p, S* ws, int32_t* status) {
     __shared__ Lds<E> L;
-    auto body = [&](int64_t t) { tail_task<S, E, FB>(L, p, ws, status, q, t); };
-    LQR_TASKS(E, FB, q, p.batch, body);
+    auto body = [&](int64_t t) { tail_task<S, E>(L, p, ws, status, t); };
+    LQR_TASKS(E, p.batch, body);
 }
 
 // The sweeps and the first up-sweep level in one launch (they are
@@ -661,18 +649,18 @@ __global__ __launch_bounds__(E::NT) void k_tail(Plan p, S* ws, int32_t* status, 
 // they are the long ones), the others combine leaf pairs of the heads, so
 // the combines fill the CUs while the sweeps run their dependent steps.
 template <typename S, class E>
-__global__ __launch_bounds__(E::NT) void k_tail_up0(Plan p, S* ws, int32_t* status, FbQueue q_tail, FbQueue q_up) {
+__global__ __launch_bounds__(E::NT) void k_tail_up0(Plan p, S* ws, int32_t* status) {
     static_assert(!E::BIG, "wavefront engine only");
     __shared__ Lds<E> L;
     const int64_t t = blockIdx.x;
-    if (t < p.batch) tail_task<S, E, false>(L, p, ws, status, q_tail, t);
-    else up_task<S, E, false>(L, p, ws, 0, status, q_up, t - p.batch);
+    if (t < p.batch) tail_task<S, E>(L, p, ws, status, t);
+    else up_task<S, E>(L, p, ws, 0, status, t - p.batch);
 }
 
 // Root under the split schedule: the complete suffix from leaf 0 is the
 // aggregate of the head, node (nlev-2, 0), after the suffix of leaf `tail`.
-template <typename S, class E, bool FB>
-__device__ __forceinline__ void tail_root_task(Lds<E>& L, const Plan& p, S* ws, int32_t* status, FbQueue q,
+template <typename S, class E>
+__device__ __forceinline__ void tail_root_task(Lds<E>& L, const Plan& p, S* ws, int32_t* status,
                                                int64_t b) {
     static_assert(!E::BIG, "wavefront engine only");
     const E e(unit_tid<E::NT>());
@@ -687,14 +675,140 @@ __device__ __forceinline__ void tail_root_task(Lds<E>& L, const Plan& p, S* ws, 
     typename E::T kappa;
     combine<E, true>(e, L, n, node, s2, s2 + nn, (const S*)nullptr, (S*)nullptr, (S*)nullptr, out, (S*)nullptr,
                      out + nn, ok, kappa);
-    fb_decide<FB, E::NT>(p, ok, kappa, b, b, q, status, 4);
+    fb_flag<E::NT>(p, ok, kappa, b, status, 4);
 }
 
-template <typename S, class E, bool FB>
-__global__ __launch_bounds__(E::NT) void k_tail_root(Plan p, S* ws, int32_t* status, FbQueue q) {
+template <typename S, class E>
+__global__ __launch_bounds__(E::NT) void k_tail_root(Plan p, S* ws, int32_t* status) {
     __shared__ Lds<E> L;
-    auto body = [&](int64_t t) { tail_root_task<S, E, FB>(L, p, ws, status, q, t); };
-    LQR_TASKS(E, FB, q, p.batch, body);
+    auto body = [&](int64_t t) { tail_root_task<S, E>(L, p, ws, status, t); };
+    LQR_TASKS(E, p.batch, body);
+}
+
+// ---------------------------------------------------------------------------
+// Chunked schedule of the reverse scan (wavefront engine).  The leaves
+// [0, tail) form `nchunk` chunks of `chunk` consecutive leaves (the last may
+// be shorter); the leaves [tail, N] are swept sequentially from the terminal
+// element as in the split schedule (tail_task).  Three phases:
+//   1. the aggregate e_c0 (x) ... (x) e_c1-1 of every chunk, by general
+//      combines from its right end (one task unit per chunk, ping-pong
+//      between two records of the otherwise unused tree levels), side by
+//      side with the tail sweep;
+//   2. per instance, the complete suffixes at the chunk starts, from the
+//      last chunk back: S_c0 = aggregate (x) S_c1, a cheap combine each;
+//   3. per chunk, the complete suffixes of its other leaves from its right
+//      end: S_k = e_k (x) S_k+1 (cheap).
+// A chunk length of 1 over the whole horizon (tail = N) is the sequential
+// information-form recursion; the balanced tree is the other extreme.  Any
+// flagged step marks the instance for the FP64 redo.
+// ---------------------------------------------------------------------------
+__host__ __device__ __forceinline__ int chunk_end(const Plan& p, int c) {
+    const int e = (c + 1) * p.chunk;
+    return e < p.tail ? e : p.tail;
+}
+
+// record holding the aggregate of chunk c (its leaf when it has one leaf)
+template <typename S>
+__device__ __forceinline__ const S* chunk_agg(const Plan& p, const S* tree, int c) {
+    const int c0 = c * p.chunk, len = chunk_end(p, c) - c0;
+    if (len == 1) return tree + (int64_t)(p.rt.off[0] + c0) * p.rec;
+    return tree + (int64_t)(p.rt.off[1] + 2 * c + ((len & 1) ? 1 : 0)) * p.rec;
+}
+
+template <typename S, class E>
+__device__ __forceinline__ void chunk_agg_task(Lds<E>& L, const Plan& p, S* ws, int32_t* status, int64_t b, int c) {
+    const E e(unit_tid<E::NT>());
+    const int n = p.n, nn = n * n;
+    S* tree = ws + b * p.stride + p.o_tree;
+    const int c0 = c * p.chunk, c1 = chunk_end(p, c);
+    S* X = tree + (int64_t)(p.rt.off[1] + 2 * c) * p.rec;
+    S* Y = X + p.rec;
+    const S* cur = tree + (int64_t)(p.rt.off[0] + c1 - 1) * p.rec;
+    bool ok_all = true;
+    typename E::T kmax = 0;
+    for (int k = c1 - 2, j = 0; k >= c0; --k, ++j) {
+        S* out = (j & 1) ? Y : X;
+        const S* e1 = tree + (int64_t)(p.rt.off[0] + k) * p.rec;
+        bool ok;
+        typename E::T kappa;
+        combine<E, false>(e, L, n, e1, cur + 2 * nn, cur + 3 * nn + n, cur, out, out + nn, out + 2 * nn,
+                          out + 3 * nn, out + 3 * nn + n, ok, kappa);
+        ok_all = ok_all && ok;
+        if (!(kappa <= kmax)) kmax = kappa;
+        cur = out;
+        E::sync();
+    }
+    fb_flag<E::NT>(p, ok_all, kmax, b, status, 4);
+}
+
+// phase 1: workgroups 0 .. batch-1 sweep the tails, the others aggregate chunks
+template <typename S, class E>
+__global__ __launch_bounds__(E::NT) void k_chunk_up(Plan p, S* ws, int32_t* status) {
+    static_assert(!E::BIG, "wavefront engine only");
+    __shared__ Lds<E> L;
+    const int64_t t = blockIdx.x;
+    if (t < p.batch) {
+        tail_task<S, E>(L, p, ws, status, t);
+    } else {
+        const int64_t u = t - p.batch;
+        chunk_agg_task<S, E>(L, p, ws, status, u / p.nchunk, (int)(u % p.nchunk));
+    }
+}
+
+// phase 2: complete suffixes at the chunk starts, one task unit per instance
+template <typename S, class E>
+__global__ __launch_bounds__(E::NT) void k_chunk_mid(Plan p, S* ws, int32_t* status) {
+    static_assert(!E::BIG, "wavefront engine only");
+    __shared__ Lds<E> L;
+    const int64_t b = blockIdx.x;
+    const E e(unit_tid<E::NT>());
+    const int n = p.n, nn = n * n;
+    const S* tree = ws + b * p.stride + p.o_tree;
+    S* suf = ws + b * p.stride + p.o_suf;
+    bool ok_all = true;
+    typename E::T kmax = 0;
+    for (int c = p.nchunk - 1; c >= 0; --c) {
+        const S* node = chunk_agg(p, tree, c);
+        const S* s2 = suf + (int64_t)suffix_id(p.rt, 0, chunk_end(p, c)) * p.srec;
+        S* out = suf + (int64_t)suffix_id(p.rt, 0, c * p.chunk) * p.srec;
+        bool ok;
+        typename E::T kappa;
+        combine<E, true>(e, L, n, node, s2, s2 + nn, (const S*)nullptr, (S*)nullptr, (S*)nullptr, out,
+                         (S*)nullptr, out + nn, ok, kappa);
+        ok_all = ok_all && ok;
+        if (!(kappa <= kmax)) kmax = kappa;
+        E::sync();
+    }
+    fb_flag<E::NT>(p, ok_all, kmax, b, status, 4);
+}
+
+// phase 3: the other leaves of every chunk, one task unit per chunk
+template <typename S, class E>
+__global__ __launch_bounds__(E::NT) void k_chunk_down(Plan p, S* ws, int32_t* status) {
+    static_assert(!E::BIG, "wavefront engine only");
+    __shared__ Lds<E> L;
+    const int64_t b = blockIdx.x / p.nchunk;
+    const int c = (int)(blockIdx.x % p.nchunk);
+    const E e(unit_tid<E::NT>());
+    const int n = p.n, nn = n * n;
+    const S* tree = ws + b * p.stride + p.o_tree;
+    S* suf = ws + b * p.stride + p.o_suf;
+    const int c0 = c * p.chunk, c1 = chunk_end(p, c);
+    bool ok_all = true;
+    typename E::T kmax = 0;
+    for (int k = c1 - 1; k > c0; --k) {
+        const S* node = tree + (int64_t)(p.rt.off[0] + k) * p.rec;
+        const S* s2 = suf + (int64_t)suffix_id(p.rt, 0, k + 1) * p.srec;
+        S* out = suf + (int64_t)suffix_id(p.rt, 0, k) * p.srec;
+        bool ok;
+        typename E::T kappa;
+        combine<E, true>(e, L, n, node, s2, s2 + nn, (const S*)nullptr, (S*)nullptr, (S*)nullptr, out,
+                         (S*)nullptr, out + nn, ok, kappa);
+        ok_all = ok_all && ok;
+        if (!(kappa <= kmax)) kmax = kappa;
+        E::sync();
+    }
+    fb_flag<E::NT>(p, ok_all, kmax, b, status, 4);
 }
 
 // ---------------------------------------------------------------------------
@@ -704,8 +818,8 @@ __global__ __launch_bounds__(E::NT) void k_tail_root(Plan p, S* ws, int32_t* sta
 // then eq. (controlled_dynamics): Abar = A + B K, bbar = B k + c, written as
 // the leaf of the forward tree.  Stores K, k and L_G (reused by refinement).
 // ---------------------------------------------------------------------------
-template <typename S, class E, bool FB, int MB>
-__device__ __forceinline__ void policy_task(Lds<E>& L, const Plan& p, const In<S>& in, S* ws, int32_t* status, FbQueue q,
+template <typename S, class E, int MB>
+__device__ __forceinline__ void policy_task(Lds<E>& L, const Plan& p, const In<S>& in, S* ws, int32_t* status,
                             int64_t task) {
     using T = typename E::T;
     const E e(unit_tid<E::NT>());
@@ -739,7 +853,7 @@ __device__ __forceinline__ void policy_task(Lds<E>& L, const Plan& p, const In<S
     T dmin, dmax, nov[1];
     T dlA;
     const bool ok = e.template chol<0, MB>(tG, m, L.cb, dlA, nov, dmin, dmax);
-    fb_decide<FB, E::NT>(p, ok, cond_est(dmin, dmax), b, task, q, status, 2);
+    fb_flag<E::NT>(p, ok, cond_est(dmin, dmax), b, status, 2);
     e.to_lds(tG, L.sA);                                   // sA = L_G
     wg_sync();
     typename E::Tile KK[1];
@@ -766,14 +880,14 @@ __device__ __forceinline__ void policy_task(Lds<E>& L, const Plan& p, const In<S
     e.vstore(leaf + nn, n, bb);
 }
 
-template <typename S, class E, bool FB, int MB>
-__global__ __launch_bounds__(E::NT) void k_policy(Plan p, In<S> in, S* ws, int32_t* status, FbQueue q) {
+template <typename S, class E, int MB>
+__global__ __launch_bounds__(E::NT) void k_policy(Plan p, In<S> in, S* ws, int32_t* status) {
     __shared__ Lds<E> L;
     auto body = [&](int64_t t) {
-        if constexpr (E::BIG) big_policy_task<S, E, FB>(L, p, in, ws, status, q, t);
-        else policy_task<S, E, FB, MB>(L, p, in, ws, status, q, t);
+        if constexpr (E::BIG) big_policy_task<S, E>(L, p, in, ws, status, t);
+        else policy_task<S, E, MB>(L, p, in, ws, status, t);
     };
-    LQR_TASKS(E, FB, q, p.batch * p.N, body);
+    LQR_TASKS(E, p.batch * p.N, body);
 }
 
 // ---------------------------------------------------------------------------
@@ -995,9 +1109,10 @@ __global__ __launch_bounds__(E::NT) void k_resid(Plan p, In<S> in, const S* xs_,
 }
 
 // rel[b] = ||r|| / ||(x0, c, q, r)||; with active_out, also mark the
-// instances still above tol for another refinement sweep.
+// instances still above tol for another refinement sweep (never one marked
+// for the FP64 redo: its FP32 factors are not usable).
 template <typename D>
-__global__ void k_resid_reduce(Plan p, const D* dws, D* rel, int32_t* active_out, D tol) {
+__global__ void k_resid_reduce(Plan p, const D* dws, D* rel, int32_t* active_out, D tol, const int32_t* status) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= p.batch) return;
     LQR_GATE(p, b);
@@ -1008,7 +1123,15 @@ __global__ void k_resid_reduce(Plan p, const D* dws, D* rel, int32_t* active_out
     }
     const D r = bb > 0.0 ? __builtin_sqrt(rr) / __builtin_sqrt(bb) : __builtin_sqrt(rr);
     rel[b] = r;
-    if (active_out) active_out[b] = !(r <= tol);
+    if (active_out) active_out[b] = !(r <= tol) && !(status[b] & 8);
+}
+
+// active[b] = status bit BIT of instance b is set (bit 8: marked for the
+// FP64 redo; gates the residual pass that follows the redo)
+template <int BIT>
+__global__ void k_mark_status(const int32_t* status, int32_t* active, int64_t batch) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < batch) active[b] = (status[b] & BIT) != 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1172,6 +1295,119 @@ __global__ __launch_bounds__(E::NT) void k_ref_kff(Plan p, In<S> in, S* ws) {
     ref_kff_body<S, E>(L, p, in, ws, (int64_t)blockIdx.x);
 }
 
+// ---------------------------------------------------------------------------
+// Sequential vector passes (plan.fwdseq): one task unit per instance walks
+// the stages in order and needs only the closed-loop leaf maps, so the
+// forward tree's map products (2n^3 per node) are never formed.  For a batch
+// that fills the GPU this trades the O(log N) depth of the forward scan for
+// O(N n^2) work; the autotuner weighs the two.
+// ---------------------------------------------------------------------------
+
+// v <- G_k^{-1} v with the stored policy factor (L_G, or L_G^{-1} in the
+// large-block engine)
+template <class E, typename S>
+__device__ __forceinline__ typename E::T g_solve(const E& e, const S* LG, int m, typename E::T v,
+                                                 typename E::T* vb0, typename E::T* vb1) {
+    if constexpr (E::BIG) {
+        const typename E::T t = e.template gmv<false>(LG, m, m, m, v, vb0);
+        return e.template gmv<true>(LG, m, m, m, t, vb1);
+    } else {
+        v = lane_trsv<true>(e, LG, m, v);
+        return lane_trsv<false>(e, LG, m, v);
+    }
+}
+
+// x_0 = x0, x_{k+1} = Abar_k x_k + bbar_k (eq. (controlled_dynamics)),
+// u_k = K_k x_k + k_k, lambda_k = P_k x_k + p_k.  ADD: the refinement's
+// correction (p' and k' from the backward sweep) is added to the outputs.
+template <typename S, class E, bool ADD, class LT>
+__device__ __forceinline__ void fwd_seq_body(LT& L, const Plan& p, S* ws, const S* x0, const Out<S>& out, int64_t b) {
+    using T = typename E::T;
+    const E e(unit_tid<E::NT>());
+    const int N = p.N, n = p.n, m = p.m, nn = n * n;
+    S* inst = ws + b * p.stride;
+    T x = e.vload(x0, n);
+    bool fin = true;
+    for (int k = 0; k <= N; ++k) {
+        const S* Pk = inst + p.o_suf + (int64_t)suffix_id(p.rt, 0, k) * p.srec;
+        const S* pv = ADD ? inst + p.o_pp + (int64_t)k * n : Pk + nn;
+        const T lam = e.template gmv<false>(Pk, n, n, n, x, L.vb[0]) + e.vload(pv, n);
+        S* xo = out.x + (b * (N + 1) + k) * n;
+        S* lo = out.lam + (b * (N + 1) + k) * n;
+        if (e.lg < n) {
+            const T xv = ADD ? T(xo[e.lg]) + x : x;
+            const T lv = ADD ? T(lo[e.lg]) + lam : lam;
+            xo[e.lg] = S(xv);
+            lo[e.lg] = S(lv);
+            fin = fin && finite_(xv) && finite_(lv);
+        }
+        if (k == N) break;
+        const S* kf = inst + (ADD ? p.o_kffp : p.o_kff) + (int64_t)k * m;
+        const T u = e.template gmv<false>(inst + p.o_K + (int64_t)k * m * n, m, n, n, x, L.vb[1]) + e.vload(kf, m);
+        S* uo = out.u + (b * N + k) * m;
+        if (e.lg < m) {
+            const T uv = ADD ? T(uo[e.lg]) + u : u;
+            uo[e.lg] = S(uv);
+            fin = fin && finite_(uv);
+        }
+        const S* leaf = inst + p.o_ftree + (int64_t)k * p.frec;
+        x = e.template gmv<false>(leaf, n, n, n, x, L.vb[0]) + e.vload(leaf + nn, n);
+    }
+    if (!E::all(fin)) set_status<E::NT>(out.status, b, 1);
+}
+
+template <typename S, class E>
+__global__ __launch_bounds__(E::NT) void k_fwd_seq(Plan p, S* ws, const S* x0, Out<S> out) {
+    __shared__ VecLds<E> L;
+    const int64_t b = blockIdx.x;
+    fwd_seq_body<S, E, false>(L, p, ws, x0 + b * p.n, out, b);
+}
+
+// One refinement sweep of instance b with the factors of the first solve
+// (after the FP64 residual pass wrote c', q', r', x0'): the gradient
+// recursion of eq. (lqr) with the policy fixed, backward,
+//   v = p'_{k+1} + P_{k+1} c'_k,  k'_k = -G_k^{-1}(B_k' v + r'_k),
+//   p'_k = Abar_k' v + K_k' r'_k + q'_k,
+// the correction's closed-loop offsets B_k k'_k + c'_k written over the leaf
+// vectors, then the forward sweep of the correction, added to the outputs.
+template <typename S, class E, class LT>
+__device__ __forceinline__ void refine_seq_body(LT& L, const Plan& p, const In<S>& in, S* ws, const Out<S>& out,
+                                                int64_t b) {
+    using T = typename E::T;
+    const E e(unit_tid<E::NT>());
+    const int N = p.N, n = p.n, m = p.m, nn = n * n;
+    const Ptr<S> P(p, in);
+    S* inst = ws + b * p.stride;
+    T pn = e.vload(inst + p.o_qp + (int64_t)N * n, n);
+    e.vstore(inst + p.o_pp + (int64_t)N * n, n, pn);
+    for (int k = N - 1; k >= 0; --k) {
+        const S* Pn = inst + p.o_suf + (int64_t)suffix_id(p.rt, 0, k + 1) * p.srec;
+        S* leaf = inst + p.o_ftree + (int64_t)k * p.frec;
+        const T cpv = e.vload(inst + p.o_cp + (int64_t)k * n, n);
+        const T rpv = e.vload(inst + p.o_rp + (int64_t)k * m, m);
+        const T v = pn + e.template gmv<false>(Pn, n, n, n, cpv, L.vb[0]);
+        const T h = e.template gmv<true>(P.B(b, k), n, m, m, v, L.vb[1]) + rpv;
+        pn = e.template gmv<true>(leaf, n, n, n, v, L.vb[0]) +
+             e.template gmv<true>(inst + p.o_K + (int64_t)k * m * n, m, n, n, rpv, L.vb[1]) +
+             e.vload(inst + p.o_qp + (int64_t)k * n, n);
+        e.vstore(inst + p.o_pp + (int64_t)k * n, n, pn);
+        const T kf = -g_solve(e, inst + p.o_LG + (int64_t)k * m * m, m, h, L.vb[0], L.vb[1]);
+        e.vstore(inst + p.o_kffp + (int64_t)k * m, m, kf);
+        const T bb = e.template gmv<false>(P.B(b, k), n, m, m, kf, L.vb[1]) + cpv;
+        e.vstore(leaf + nn, n, bb);
+        E::sync();
+    }
+    fwd_seq_body<S, E, true>(L, p, ws, (const S*)(inst + p.o_x0p), out, b);
+}
+
+template <typename S, class E>
+__global__ __launch_bounds__(E::NT) void k_refine_seq(Plan p, In<S> in, S* ws, Out<S> out) {
+    __shared__ VecLds<E> L;
+    const int64_t b = blockIdx.x;
+    LQR_GATE(p, b);
+    refine_seq_body<S, E>(L, p, in, ws, out, b);
+}
+
 // relative KKT residual of instance b from its per-stage partial sums
 __device__ __forceinline__ double resid_of_parts(const Plan& p, const double* dws, int64_t b) {
     double rr = 0.0, bb = 0.0;
@@ -1269,11 +1505,12 @@ __global__ __launch_bounds__(E::NT) void k_refine_inst(Plan p, In<S> in, S* ws, 
 }
 
 // FP64 residual of one instance, all stages, reduced in place:
-// rel[b] = ||r|| / ||(x0, c, q, r)|| (and active_out[b] = rel > tol)
+// rel[b] = ||r|| / ||(x0, c, q, r)|| (and active_out[b] = rel > tol for an
+// instance not marked for the FP64 redo)
 template <typename S, class E, bool CORR>
 __device__ __forceinline__ double resid_inst_body(ResidLds<E>& RL, const Plan& p, const In<S>& in, const S* xs_,
                                                   const S* us_, const S* ls_, S* ws, double* dws, double* rel,
-                                                  int32_t* active_out, double tol, int64_t b) {
+                                                  int32_t* active_out, double tol, const int32_t* status, int64_t b) {
     double res = 0.0;   // returned in the task unit's thread 0
     for (int k = 0; k <= p.N; ++k) {
         resid_body<S, E, CORR>(RL, p, in, xs_, us_, ls_, ws, dws, b * (p.N + 1) + k);
@@ -1282,7 +1519,7 @@ __device__ __forceinline__ double resid_inst_body(ResidLds<E>& RL, const Plan& p
     if (unit_tid<E::NT>() == 0) {   // the partial sums were written by this lane
         const double r = resid_of_parts(p, dws, b);
         if (rel) rel[b] = r;
-        if (active_out) active_out[b] = !(r <= tol);
+        if (active_out) active_out[b] = !(r <= tol) && !(status[b] & 8);
         res = r;
     }
     return res;
@@ -1291,27 +1528,28 @@ __device__ __forceinline__ double resid_inst_body(ResidLds<E>& RL, const Plan& p
 template <typename S, class E, bool CORR>
 __global__ __launch_bounds__(E::NT) void k_resid_inst(Plan p, In<S> in, const S* xs_, const S* us_, const S* ls_,
                                                    S* ws, double* dws, double* rel, int32_t* active_out,
-                                                   double tol) {
+                                                   double tol, const int32_t* status) {
     __shared__ ResidLds<E> RL;
     const int64_t b = blockIdx.x;
     LQR_GATE(p, b);
-    resid_inst_body<S, E, CORR>(RL, p, in, xs_, us_, ls_, ws, dws, rel, active_out, tol, b);
+    resid_inst_body<S, E, CORR>(RL, p, in, xs_, us_, ls_, ws, dws, rel, active_out, tol, status, b);
 }
 
 // ---------------------------------------------------------------------------
 // Plain baseline: the sequential Riccati recursion of eq. (lqr), forward pass
-// and costates, one group per instance (workspace: P_k, p_k in the suffix
-// area indexed by stage, K_k, k_k).
+// and costates, one group per instance.  Inputs and outputs are of type S;
+// the intermediates (P_k, p_k in the suffix area indexed by stage, K_k, k_k)
+// live in `inst` of type W (W = S for the baseline, double for the FP64
+// redo of an FP32 instance).
 // ---------------------------------------------------------------------------
-template <typename S, class E, int MB>
-__device__ __forceinline__ void plain_body(Lds3<E>& L, const Plan& p, const In<S>& in, const Out<S>& out, S* ws) {
+template <typename S, typename W, class E, int MB>
+__device__ __forceinline__ void plain_body(Lds3<E>& L, const Plan& p, const In<S>& in, const Out<S>& out, W* inst,
+                                           int64_t b) {
     using T = typename E::T;
     const E e(unit_tid<E::NT>());
     const int N = p.N, n = p.n, m = p.m, nn = n * n;
-    const int64_t b = blockIdx.x;
     const Ptr<S> P(p, in);
-    S* inst = ws + b * p.stride;
-    S* Pst = inst + p.o_suf;                               // P_k, p_k at k * srec
+    W* Pst = inst + p.o_suf;                               // P_k, p_k at k * srec
     typename E::Tile t, tPB, tG, tH, tHc, tPA;
     e.load(t, P.Q(b, N), n, n, n);
     to_lds_sym(e, t, L.sP);
@@ -1412,7 +1650,25 @@ __device__ __forceinline__ void plain_body(Lds3<E>& L, const Plan& p, const In<S
 template <typename S, class E, int MB>
 __global__ __launch_bounds__(64) void k_plain(Plan p, In<S> in, Out<S> out, S* ws) {
     __shared__ Lds3<E> L;
-    plain_body<S, E, MB>(L, p, in, out, ws);
+    const int64_t b = blockIdx.x;
+    plain_body<S, S, E, MB>(L, p, in, out, ws + b * p.stride, b);
+}
+
+// FP64 redo of the instances an FP32 solve marked (status bit 8): each is
+// solved again whole by the sequential Riccati recursion of eq. (lqr) with
+// FP64 arithmetic and FP64 intermediates (one FP64 slot of `rp.stride`
+// doubles per workgroup), and its FP32 outputs are overwritten.  The status
+// word keeps bit 8 and gets the failure bits of this solve.  `rp` is the
+// plan of the redo slots (batch = the instance count of the call).
+template <typename S, class E64, int MB>
+__global__ __launch_bounds__(64) void k_redo(Plan rp, In<S> in, Out<S> out, double* ws64) {
+    __shared__ Lds3<E64> L;
+    for (int64_t b = blockIdx.x; b < rp.batch; b += gridDim.x) {
+        if (!(out.status[b] & 8)) continue;   // uniform: one status word per workgroup iteration
+        wg_sync();
+        if (threadIdx.x == 0) out.status[b] = 8;
+        plain_body<S, double, E64, MB>(L, rp, in, out, ws64 + (int64_t)blockIdx.x * rp.stride, b);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1425,9 +1681,8 @@ __global__ __launch_bounds__(64) void k_plain(Plan p, In<S> in, Out<S> out, S* w
 // of its own, and a workgroup barrier separates dependent phases.  Every
 // task body is the one the launch sequence uses, in the same phase order,
 // so an instance gets the bits of the launched form.
-// REDO: the pass over the instances the FP32 pass flagged for the FP64
-// fallback (status bit 8): the whole instance is recomputed with the FP64
-// engine (plan with fallback off, so a failure there sets the failure bits).
+// An instance a factorization marks (status bit 8) is solved again whole by
+// the FP64 redo launch that follows (k_redo).
 // ---------------------------------------------------------------------------
 template <class E, class E64>
 struct FusedLds {
@@ -1444,7 +1699,7 @@ constexpr int fused_waves() {
     return w < 1 ? 1 : (w > lim ? lim : w);
 }
 
-template <typename S, class E, class E64, int MB, bool REDO>
+template <typename S, class E, class E64, int MB>
 __global__ __launch_bounds__(64 * fused_waves<E>()) void k_solve_fused(Plan p, In<S> in, Out<S> out, S* ws,
                                                                       double* dws, double* rel_out, Warm<S> warm,
                                                                       int refine) {
@@ -1455,7 +1710,6 @@ __global__ __launch_bounds__(64 * fused_waves<E>()) void k_solve_fused(Plan p, I
     const int wv = (int)(threadIdx.x >> 6);
     const int64_t b = blockIdx.x;
     const int N = p.N, n = p.n;
-    const FbQueue nq{nullptr, nullptr};
     auto& Lm = F[wv].m;
     auto& Lv = F[wv].v;
     auto& Lr = F[wv].r;
@@ -1467,26 +1721,21 @@ __global__ __launch_bounds__(64 * fused_waves<E>()) void k_solve_fused(Plan p, I
         }
         __syncthreads();
     };
-    if (REDO) {
-        // bit 8 is only ever added, so every thread sees the same decision
-        if (!(out.status[b] & 8)) return;
-    } else if (threadIdx.x == 0) {
-        out.status[b] = 0;
-    }
+    if (threadIdx.x == 0) out.status[b] = 0;
     __syncthreads();
     // elements; reverse scan (up-sweep, root, down-sweep); policy and
     // closed-loop maps; up-sweep of the forward tree
-    phase(N + 1, [&](int k) { element_task<S, E, false, MB>(Lm, p, in, ws, out.status, nq, b * (N + 1) + k); });
+    phase(N + 1, [&](int k) { element_task<S, E, MB>(Lm, p, in, ws, out.status, b * (N + 1) + k); });
     for (int l = 0; l + 1 < p.rt.nlev; ++l) {
         const int c = p.rt.cnt[l + 1];
-        phase(c, [&](int i) { up_task<S, E, false>(Lm, p, ws, l, out.status, nq, b * c + i); });
+        phase(c, [&](int i) { up_task<S, E>(Lm, p, ws, l, out.status, b * c + i); });
     }
     phase(1, [&](int) { root_body<S>(p, ws, b); });
     for (int l = p.rt.nlev - 2; l >= 0; --l) {
         const int c = p.rt.cnt[l] / 2;
-        phase(c, [&](int j) { down_task<S, E, false>(Lm, p, ws, l, out.status, nq, b * c + j); });
+        phase(c, [&](int j) { down_task<S, E>(Lm, p, ws, l, out.status, b * c + j); });
     }
-    phase(N, [&](int k) { policy_task<S, E, false, MB>(Lm, p, in, ws, out.status, nq, b * N + k); });
+    phase(N, [&](int k) { policy_task<S, E, MB>(Lm, p, in, ws, out.status, b * N + k); });
     for (int l = 0; l + 1 < p.ft.nlev; ++l) {
         const int c = p.ft.cnt[l + 1];
         phase(c, [&](int i) { fup_body<S, E, false>(Lm, p, ws, l, b * c + i); });

@@ -26,9 +26,8 @@ template <typename P> __device__ __forceinline__ MV<const P> ctr(const P* p, int
 //   At = A - W_B' W_M,  Ct = W_B' W_B,  Pt = Q - W_M' W_M,
 //   bt = c - W_B' w_r,  pt = q - W_M' w_r.
 // ---------------------------------------------------------------------------
-template <typename S, class E, bool FB>
-__device__ void big_element_task(BigLds<typename E::T>& L, const Plan& p, const In<S>& in, S* ws, int32_t* status,
-                                 FbQueue q, int64_t task) {
+template <typename S, class E>
+__device__ void big_element_task(BigLds<typename E::T>& L, const Plan& p, const In<S>& in, S* ws, int32_t* status, int64_t task) {
     using T = typename E::T;
     const E e(threadIdx.x);
     const int N = p.N, n = p.n, m = p.m, nn = n * n;
@@ -37,7 +36,6 @@ __device__ void big_element_task(BigLds<typename E::T>& L, const Plan& p, const 
     S* rec = ws + b * p.stride + p.o_tree + (int64_t)k * p.rec;
     const Ptr<S> P(p, in);
     if (k == N) {
-        if (FB) return;
         coop_zero(rec, 2 * nn);
         coop_copy(rec + 2 * nn, P.Q(b, N), nn);
         coop_zero(rec + 3 * nn, n);
@@ -53,7 +51,7 @@ __device__ void big_element_task(BigLds<typename E::T>& L, const Plan& p, const 
     e.copy(Lr, m, P.R(b, k), m, m, m);
     T dmin, dmax;
     const bool ok = e.potrf_inv(L, Lr, Lri, tmp, m, dmin, dmax);
-    fb_decide<FB>(p, ok, cond_est(dmin, dmax), b, task, q, status, 2);
+    fb_flag(p, ok, cond_est(dmin, dmax), b, status, 2);
     e.template gemm<GM_A_LO>(L, m, n, m, crm(Lri, m), ctr(P.B(b, k), m), rowm(WB, n));
     e.template gemm<GM_A_LO>(L, m, n, m, crm(Lri, m), ctr(P.M(b, k), m), rowm(WM, n));
     const T wr = e.template gmv<false>(Lri, m, m, m, e.vload(P.r(b, k), m), L.vb[0]);
@@ -136,8 +134,8 @@ __device__ void big_combine(const E& e, BigLds<typename E::T>& L, typename E::T*
     kappa = kap;
 }
 
-template <typename S, class E, bool FB>
-__device__ void big_up_task(BigLds<typename E::T>& L, const Plan& p, S* ws, int lvl, int32_t* status, FbQueue q,
+template <typename S, class E>
+__device__ void big_up_task(BigLds<typename E::T>& L, const Plan& p, S* ws, int lvl, int32_t* status,
                             int64_t task) {
     using T = typename E::T;
     const E e(threadIdx.x);
@@ -149,7 +147,7 @@ __device__ void big_up_task(BigLds<typename E::T>& L, const Plan& p, S* ws, int 
     const S* e1 = base + (int64_t)(p.rt.off[lvl] + 2 * i) * p.rec;
     S* out = base + (int64_t)(p.rt.off[lvl + 1] + i) * p.rec;
     if (2 * i + 1 >= cin) {
-        if (!FB) coop_copy(out, e1, p.rec);
+        coop_copy(out, e1, p.rec);
         E::sync();
         return;
     }
@@ -158,11 +156,11 @@ __device__ void big_up_task(BigLds<typename E::T>& L, const Plan& p, S* ws, int 
     T kappa;
     big_combine<E, false>(e, L, big_scratch<T>(p, ws), n, e1, e2 + 2 * nn, e2 + 3 * nn + n, e2, out, out + nn,
                           out + 2 * nn, out + 3 * nn, out + 3 * nn + n, ok, kappa);
-    fb_decide<FB>(p, ok, kappa, b, task, q, status, 4);
+    fb_flag(p, ok, kappa, b, status, 4);
 }
 
-template <typename S, class E, bool FB>
-__device__ void big_down_task(BigLds<typename E::T>& L, const Plan& p, S* ws, int lvl, int32_t* status, FbQueue q,
+template <typename S, class E>
+__device__ void big_down_task(BigLds<typename E::T>& L, const Plan& p, S* ws, int lvl, int32_t* status,
                               int64_t task) {
     using T = typename E::T;
     const E e(threadIdx.x);
@@ -176,10 +174,8 @@ __device__ void big_down_task(BigLds<typename E::T>& L, const Plan& p, S* ws, in
     S* out = suf + (int64_t)(p.rt.off[lvl] + j) * p.srec;
     const int i1 = (j + 1) / 2;
     if (i1 >= p.rt.cnt[lvl + 1]) {
-        if (!FB) {
-            coop_copy(out, node + 2 * nn, nn);
-            coop_copy(out + nn, node + 3 * nn + n, n);
-        }
+        coop_copy(out, node + 2 * nn, nn);
+        coop_copy(out + nn, node + 3 * nn + n, n);
         E::sync();
         return;
     }
@@ -188,16 +184,15 @@ __device__ void big_down_task(BigLds<typename E::T>& L, const Plan& p, S* ws, in
     T kappa;
     big_combine<E, true>(e, L, big_scratch<T>(p, ws), n, node, s2, s2 + nn, (const S*)nullptr, (S*)nullptr,
                          (S*)nullptr, out, (S*)nullptr, out + nn, ok, kappa);
-    fb_decide<FB>(p, ok, kappa, b, task, q, status, 4);
+    fb_flag(p, ok, kappa, b, status, 4);
 }
 
 // ---------------------------------------------------------------------------
 // eq. (lqr) per stage and eq. (controlled_dynamics), as policy_task.  The
 // refinement needs G^{-1} = L_G^{-T} L_G^{-1}: the record keeps L_G^{-1}.
 // ---------------------------------------------------------------------------
-template <typename S, class E, bool FB>
-__device__ void big_policy_task(BigLds<typename E::T>& L, const Plan& p, const In<S>& in, S* ws, int32_t* status,
-                                FbQueue q, int64_t task) {
+template <typename S, class E>
+__device__ void big_policy_task(BigLds<typename E::T>& L, const Plan& p, const In<S>& in, S* ws, int32_t* status, int64_t task) {
     using T = typename E::T;
     const E e(threadIdx.x);
     const int N = p.N, n = p.n, m = p.m, nn = n * n;
@@ -220,7 +215,7 @@ __device__ void big_policy_task(BigLds<typename E::T>& L, const Plan& p, const I
     const T h = e.template gmv<true>(P.B(b, k), n, m, m, v, L.vb[1]) + e.vload(P.r(b, k), m);
     T dmin, dmax;
     const bool ok = e.potrf_inv(L, G, Gi, tmp, m, dmin, dmax);
-    fb_decide<FB>(p, ok, cond_est(dmin, dmax), b, task, q, status, 2);
+    fb_flag(p, ok, cond_est(dmin, dmax), b, status, 2);
     e.template gemm<GM_A_LO>(L, m, n, m, crm(Gi, m), crm(H, n), rowm(H2, n));                   // L_G^{-1} H
     e.template gemm<GM_A_UP>(L, m, n, m, ctr(Gi, m), crm(H2, n), rowm(KT, n), T(-1));            // K = -G^{-1} H
     const T t = e.template gmv<false>(Gi, m, m, m, h, L.vb[0]);
@@ -274,16 +269,17 @@ __device__ void big_ref_kff(LT& L, const Plan& p, const In<S>& in, S* ws, int64_
 
 // ---------------------------------------------------------------------------
 // Plain baseline for large blocks: the sequential Riccati recursion of
-// eq. (lqr), one workgroup per instance (grid-stride over instances).
+// eq. (lqr) for instance b.  Inputs and outputs of type S; P_k, p_k, K_k, k_k
+// in `inst` of type W, the intermediates of one step in `scr` (compute type).
 // ---------------------------------------------------------------------------
-template <typename S, class E>
-__global__ __launch_bounds__(256) void k_plain_big(Plan p, In<S> in, Out<S> out, S* ws) {
+template <typename S, typename W, class E>
+__device__ void big_plain_body(BigLds<typename E::T>& L, const Plan& p, const In<S>& in, const Out<S>& out, W* inst,
+                               typename E::T* scr, int64_t b) {
     using T = typename E::T;
-    __shared__ BigLds<T> L;
     const E e(threadIdx.x);
     const int N = p.N, n = p.n, m = p.m, nn = n * n;
     const Ptr<S> P(p, in);
-    T* Pc = big_scratch<T>(p, ws);
+    T* Pc = scr;
     T* PA = Pc + nn;
     T* T1 = PA + nn;
     T* G = T1 + n * m;
@@ -292,60 +288,81 @@ __global__ __launch_bounds__(256) void k_plain_big(Plan p, In<S> in, Out<S> out,
     T* H2 = H + m * n;
     T* KT = H2 + m * n;
     T* tmp = KT + m * n;
-    for (int64_t b = blockIdx.x; b < p.batch; b += gridDim.x) {
-        S* inst = ws + b * p.stride;
-        S* Pst = inst + p.o_suf;
-        e.copy(Pc, n, P.Q(b, N), n, n, n);
-        e.copy(Pst + (int64_t)N * p.srec, n, Pc, n, n, n);
-        T pn = e.vload(P.q(b, N), n);
-        e.vstore(Pst + (int64_t)N * p.srec + nn, n, pn);
-        bool ok = true;
-        for (int k = N - 1; k >= 0; --k) {
-            e.template gemm<0>(L, n, m, n, crm(Pc, n), crm(P.B(b, k), m), rowm(T1, m));
-            e.template gemm<GM_LOWER | GM_ADD>(L, m, m, n, ctr(P.B(b, k), m), crm(T1, m), rowm(G, m),
-                                               crm(P.R(b, k), m));
-            e.template gemm<GM_ADD>(L, m, n, n, ctr(T1, m), crm(P.A(b, k), n), rowm(H, n), ctr(P.M(b, k), m));
-            e.template gemm<0>(L, n, n, n, crm(Pc, n), crm(P.A(b, k), n), rowm(PA, n));
-            const T v = e.template gmv<false>(Pc, n, n, n, e.vload(P.c(b, k), n), L.vb[0]) + pn;
-            const T h = e.template gmv<true>(P.B(b, k), n, m, m, v, L.vb[1]) + e.vload(P.r(b, k), m);
-            const T pa = e.template gmv<true>(P.A(b, k), n, n, n, v, L.vb[0]);
-            T dmin, dmax;
-            ok = e.potrf_inv(L, G, Gi, tmp, m, dmin, dmax) && ok;
-            e.template gemm<GM_A_LO>(L, m, n, m, crm(Gi, m), crm(H, n), rowm(H2, n));
-            e.template gemm<GM_A_UP>(L, m, n, m, ctr(Gi, m), crm(H2, n), rowm(KT, n), T(-1));
-            const T t = e.template gmv<false>(Gi, m, m, m, h, L.vb[1]);
-            const T kf = -e.template gmv<true>(Gi, m, m, m, t, L.vb[0]);
-            e.copy(inst + p.o_K + (int64_t)k * m * n, n, KT, n, m, n);
-            e.vstore(inst + p.o_kff + (int64_t)k * m, m, kf);
-            // P_k = Q + A'(P'A) + K'H,  p_k = q + A'v + K'h
-            e.template gemm<GM_LOWER | GM_SYM | GM_ADD>(L, n, n, n, ctr(P.A(b, k), n), crm(PA, n), rowm(Pc, n),
-                                                        crm(P.Q(b, k), n));
-            e.template gemm<GM_LOWER | GM_SYM | GM_ADD>(L, n, n, m, ctr(KT, n), crm(H, n), rowm(Pc, n), crm(Pc, n));
-            pn = e.vload(P.q(b, k), n) + pa + e.template gmv<true>(KT, m, n, n, h, L.vb[1]);
-            e.copy(Pst + (int64_t)k * p.srec, n, Pc, n, n, n);
-            e.vstore(Pst + (int64_t)k * p.srec + nn, n, pn);
-        }
-        if (!ok) set_status(out.status, b, 2);
-        // forward pass and costates
-        T x = e.vload(P.x0(b), n);
-        bool fin = true;
-        for (int k = 0; k <= N; ++k) {
-            const S* Pk = Pst + (int64_t)k * p.srec;
-            const T lam = e.template gmv<false>(Pk, n, n, n, x, L.vb[0]) + e.vload(Pk + nn, n);
-            e.vstore(out.x + (b * (N + 1) + k) * n, n, x);
-            e.vstore(out.lam + (b * (N + 1) + k) * n, n, lam);
-            fin = fin && (e.lg >= n || (finite_(x) && finite_(lam)));
-            if (k == N) break;
-            const T u = e.template gmv<false>(inst + p.o_K + (int64_t)k * m * n, m, n, n, x, L.vb[1]) +
-                        e.vload(inst + p.o_kff + (int64_t)k * m, m);
-            e.vstore(out.u + (b * N + k) * m, m, u);
-            fin = fin && (e.lg >= m || finite_(u));
-            const T xa = e.template gmv<false>(P.A(b, k), n, n, n, x, L.vb[0]);
-            const T xb = e.template gmv<false>(P.B(b, k), n, m, m, u, L.vb[1]);
-            x = xa + xb + e.vload(P.c(b, k), n);
-        }
-        if (!E::all(fin)) set_status(out.status, b, 1);
-        E::sync();
+    W* Pst = inst + p.o_suf;
+    e.copy(Pc, n, P.Q(b, N), n, n, n);
+    e.copy(Pst + (int64_t)N * p.srec, n, Pc, n, n, n);
+    T pn = e.vload(P.q(b, N), n);
+    e.vstore(Pst + (int64_t)N * p.srec + nn, n, pn);
+    bool ok = true;
+    for (int k = N - 1; k >= 0; --k) {
+        e.template gemm<0>(L, n, m, n, crm(Pc, n), crm(P.B(b, k), m), rowm(T1, m));
+        e.template gemm<GM_LOWER | GM_ADD>(L, m, m, n, ctr(P.B(b, k), m), crm(T1, m), rowm(G, m),
+                                           crm(P.R(b, k), m));
+        e.template gemm<GM_ADD>(L, m, n, n, ctr(T1, m), crm(P.A(b, k), n), rowm(H, n), ctr(P.M(b, k), m));
+        e.template gemm<0>(L, n, n, n, crm(Pc, n), crm(P.A(b, k), n), rowm(PA, n));
+        const T v = e.template gmv<false>(Pc, n, n, n, e.vload(P.c(b, k), n), L.vb[0]) + pn;
+        const T h = e.template gmv<true>(P.B(b, k), n, m, m, v, L.vb[1]) + e.vload(P.r(b, k), m);
+        const T pa = e.template gmv<true>(P.A(b, k), n, n, n, v, L.vb[0]);
+        T dmin, dmax;
+        ok = e.potrf_inv(L, G, Gi, tmp, m, dmin, dmax) && ok;
+        e.template gemm<GM_A_LO>(L, m, n, m, crm(Gi, m), crm(H, n), rowm(H2, n));
+        e.template gemm<GM_A_UP>(L, m, n, m, ctr(Gi, m), crm(H2, n), rowm(KT, n), T(-1));
+        const T t = e.template gmv<false>(Gi, m, m, m, h, L.vb[1]);
+        const T kf = -e.template gmv<true>(Gi, m, m, m, t, L.vb[0]);
+        e.copy(inst + p.o_K + (int64_t)k * m * n, n, KT, n, m, n);
+        e.vstore(inst + p.o_kff + (int64_t)k * m, m, kf);
+        // P_k = Q + A'(P'A) + K'H,  p_k = q + A'v + K'h
+        e.template gemm<GM_LOWER | GM_SYM | GM_ADD>(L, n, n, n, ctr(P.A(b, k), n), crm(PA, n), rowm(Pc, n),
+                                                    crm(P.Q(b, k), n));
+        e.template gemm<GM_LOWER | GM_SYM | GM_ADD>(L, n, n, m, ctr(KT, n), crm(H, n), rowm(Pc, n), crm(Pc, n));
+        pn = e.vload(P.q(b, k), n) + pa + e.template gmv<true>(KT, m, n, n, h, L.vb[1]);
+        e.copy(Pst + (int64_t)k * p.srec, n, Pc, n, n, n);
+        e.vstore(Pst + (int64_t)k * p.srec + nn, n, pn);
+    }
+    if (!ok) set_status(out.status, b, 2);
+    // forward pass and costates
+    T x = e.vload(P.x0(b), n);
+    bool fin = true;
+    for (int k = 0; k <= N; ++k) {
+        const W* Pk = Pst + (int64_t)k * p.srec;
+        const T lam = e.template gmv<false>(Pk, n, n, n, x, L.vb[0]) + e.vload(Pk + nn, n);
+        e.vstore(out.x + (b * (N + 1) + k) * n, n, x);
+        e.vstore(out.lam + (b * (N + 1) + k) * n, n, lam);
+        fin = fin && (e.lg >= n || (finite_(x) && finite_(lam)));
+        if (k == N) break;
+        const T u = e.template gmv<false>(inst + p.o_K + (int64_t)k * m * n, m, n, n, x, L.vb[1]) +
+                    e.vload(inst + p.o_kff + (int64_t)k * m, m);
+        e.vstore(out.u + (b * N + k) * m, m, u);
+        fin = fin && (e.lg >= m || finite_(u));
+        const T xa = e.template gmv<false>(P.A(b, k), n, n, n, x, L.vb[0]);
+        const T xb = e.template gmv<false>(P.B(b, k), n, m, m, u, L.vb[1]);
+        x = xa + xb + e.vload(P.c(b, k), n);
+    }
+    if (!E::all(fin)) set_status(out.status, b, 1);
+    E::sync();
+}
+
+// one workgroup per instance (grid-stride over the instances)
+template <typename S, class E>
+__global__ __launch_bounds__(256) void k_plain_big(Plan p, In<S> in, Out<S> out, S* ws) {
+    using T = typename E::T;
+    __shared__ BigLds<T> L;
+    for (int64_t b = blockIdx.x; b < p.batch; b += gridDim.x)
+        big_plain_body<S, S, E>(L, p, in, out, ws + b * p.stride, big_scratch<T>(p, ws), b);
+}
+
+// FP64 redo of marked instances (as k_redo), large blocks: FP64 slot and
+// FP64 scratch of the calling workgroup
+template <typename S, class E64>
+__global__ __launch_bounds__(256) void k_redo_big(Plan rp, In<S> in, Out<S> out, double* ws64) {
+    __shared__ BigLds<double> L;
+    for (int64_t b = blockIdx.x; b < rp.batch; b += gridDim.x) {
+        if (!(out.status[b] & 8)) continue;   // uniform across the workgroup
+        __syncthreads();
+        if (threadIdx.x == 0) out.status[b] = 8;
+        __syncthreads();
+        big_plain_body<S, double, E64>(L, rp, in, out, ws64 + (int64_t)blockIdx.x * rp.stride,
+                                       big_scratch<double>(rp, ws64), b);
     }
 }
 

@@ -79,7 +79,10 @@ struct Tuning {
     int engine = 0;     // 1: wavefront tiles, 2: matrix-core workgroups
     int fused = -1;     // vector passes level by level 0, per instance 1; 2: whole solve in one launch
     int big_grid = 0;   // workgroups (scratch slots) of a matrix-core task launch
-    int split = 0;      // 1: split schedule of the reverse scan (wavefront engine, level-by-level forms)
+    int split = 0;      // reverse scan: 0 balanced tree, 1 split, 2 chunked (wavefront engine)
+    int chunk = 0;      // chunked schedule: chunk length (>= 1)
+    int sweep = 0;      // chunked schedule: leaves of the sequential sweep (>= 1, the terminal included)
+    int fwd_seq = 0;    // 1: sequential forward and refinement vector passes
 };
 
 int pick_ts(int n, int m, const Tuning* t) {
@@ -89,6 +92,8 @@ int pick_ts(int n, int m, const Tuning* t) {
 }
 // workgroups (= scratch slots) of a large-block task launch
 constexpr int kBigGrid = 512;
+// slots of the FP64 redo of marked instances
+constexpr int kRedoSlots = 128;
 
 int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
@@ -131,12 +136,27 @@ Plan make_plan(int64_t batch, int N, int n, int m, size_t esize, const lqr_opts&
     p.fused = 0;
     p.fallback = esize == 4 ? o.fallback : 0;   // the FP64 path has nothing to fall back to
     if (tun && tun->fused >= 0) p.fused = tun->fused;
-    // split schedule: the tree over the largest power of two of leaves below
-    // N + 1 (every tree level above the leaves has a node past it), the rest
-    // by the sequential sweep
-    p.tail = 0;
-    if (tun && tun->split && p.fused != 2 && pick_ts(n, m, tun) != kBigTS) p.tail = 1 << (p.rt.nlev - 2);
-    if (pick_ts(n, m, tun) == kBigTS) {
+    const bool big = pick_ts(n, m, tun) == kBigTS;
+    p.sched = 0;
+    if (tun && tun->split && p.fused != 2 && !big) {
+        if (tun->split == 1) {
+            // split: the tree over the largest power of two of leaves below
+            // N + 1 (every tree level above the leaves has a node past it),
+            // the rest by the sequential sweep
+            p.sched = 1;
+            p.tail = 1 << (p.rt.nlev - 2);
+        } else {
+            // chunked: `sweep` leaves swept sequentially, chunks of `chunk`
+            // leaves over the rest
+            p.sched = 2;
+            const int sweep = std::min(std::max(tun->sweep, 1), N + 1);
+            p.tail = N + 1 - sweep;
+            p.chunk = std::max(tun->chunk, 1);
+            p.nchunk = (p.tail + p.chunk - 1) / p.chunk;
+        }
+    }
+    p.fwdseq = tun && tun->fwd_seq && p.fused != 2 ? 1 : 0;
+    if (big) {
         if (p.fused == 2) p.fused = 1;   // the one-launch solve is a wavefront-engine form
         const int64_t d = n > m ? n : m;
         p.scr_elems = align_up(8 * d * d + 64 * d, 64);
@@ -147,19 +167,49 @@ Plan make_plan(int64_t batch, int N, int n, int m, size_t esize, const lqr_opts&
     return p;
 }
 
+// Plan of the FP64 redo slots: per slot P_k, p_k (suffix area by stage), K_k,
+// k_k in FP64 (plus, for the large-block engine, an FP64 scratch area of one
+// element block per slot after all slots)
+Plan make_redo_plan(const Plan& p, bool big, int64_t& slots, size_t& bytes) {
+    Plan r = p;
+    r.active = nullptr;
+    int64_t off = 0;
+    auto sec = [&](int64_t count) { int64_t o = off; off = align_up(off + count, 64); return o; };
+    r.o_suf = sec((int64_t)(p.N + 1) * p.srec);
+    r.o_K = sec((int64_t)p.N * p.m * p.n);
+    r.o_kff = sec((int64_t)p.N * p.m);
+    r.stride = off;
+    slots = std::min<int64_t>(p.batch, kRedoSlots);
+    r.big_grid = (int)slots;
+    bytes = (size_t)(slots * r.stride * 8);
+    if (big) {
+        r.o_scr = (int64_t)align_up((int64_t)bytes, 256);
+        bytes = (size_t)r.o_scr + (size_t)(slots * p.scr_elems * 8);
+    }
+    bytes = (size_t)align_up((int64_t)bytes, 256);
+    return r;
+}
+
 struct Layout {
-    size_t main_bytes, int_off, dbl_off, scr_off, total;
+    size_t main_bytes, int_off, dbl_off, scr_off, redo_off, total;
 };
 
-// per-instance records | int32 queues and flags | FP64 partial sums |
-// large-block scratch (one slot per workgroup, sized for FP64 compute)
+// per-instance records | int32 refinement flags | FP64 partial sums |
+// large-block scratch (one slot per workgroup) | FP64 redo slots
 Layout layout(const Plan& p, size_t esize) {
     Layout l;
     l.main_bytes = (size_t)align_up((int64_t)(p.batch * p.stride * (int64_t)esize), 256);
     l.int_off = l.main_bytes;
-    l.dbl_off = l.int_off + (size_t)align_up((queue_layout(p).total + p.batch) * 4, 256);
+    l.dbl_off = l.int_off + (size_t)align_up(p.batch * 4, 256);
     l.scr_off = l.dbl_off + (size_t)align_up((p.batch * p.dstride + p.batch) * 8, 256);
-    l.total = l.scr_off + (size_t)align_up((int64_t)p.big_grid * p.scr_elems * 8, 256);
+    l.redo_off = l.scr_off + (size_t)align_up((int64_t)p.big_grid * p.scr_elems * (int64_t)esize, 256);
+    l.total = l.redo_off;
+    if (p.fallback) {
+        int64_t slots;
+        size_t rb;
+        make_redo_plan(p, p.big_grid > 0, slots, rb);
+        l.total += rb;
+    }
     return l;
 }
 
@@ -176,14 +226,25 @@ int check_dims(int64_t batch, int N, int n, int m) {
     return LQR_OK;
 }
 
+// the chunked schedule keeps its aggregates in records of the tree levels
+// above the leaves (two per chunk of two or more leaves): they must exist
+bool sched_fits(const Plan& p) {
+    if (p.sched != 2) return true;
+    for (int c = 0; c < p.nchunk; ++c) {
+        const int c0 = c * p.chunk, len = std::min(c0 + p.chunk, p.tail) - c0;
+        if (len >= 2 && p.rt.off[1] + 2 * c + (len >= 3 ? 1 : 0) >= p.rt.total) return false;
+    }
+    return true;
+}
+
 template <typename S>
 int dispatch(int ts, int method, const Plan& p, hipStream_t s, const In<S>& in, const Out<S>& out, S* ws,
-             int32_t* iws, double* dws, int refine, double* resid_out, const Warm<S>& warm) {
-#define LQR_CASE(TSV)                                                                       \
-    case TSV:                                                                               \
-        return method == LQR_METHOD_SCAN                                                    \
-                   ? run_scan<S, TSV>(p, s, in, out, ws, iws, dws, refine, resid_out, warm) \
-                   : run_plain<S, TSV>(p, s, in, out, ws, iws, dws, resid_out);
+             const Ctx& cx, int refine, double* resid_out, const Warm<S>& warm) {
+#define LQR_CASE(TSV)                                                                    \
+    case TSV:                                                                            \
+        return method == LQR_METHOD_SCAN                                                 \
+                   ? run_scan<S, TSV>(p, s, in, out, ws, cx, refine, resid_out, warm)    \
+                   : run_plain<S, TSV>(p, s, in, out, ws, cx, resid_out);
     switch (ts) {
         LQR_CASE(1) LQR_CASE(2) LQR_CASE(3) LQR_CASE(4) LQR_CASE(5) LQR_CASE(6) LQR_CASE(8) LQR_CASE(32)
         default: return fail(LQR_EUNSUPPORTED, "no shape class for TS=%d", ts);
@@ -207,16 +268,15 @@ int dispatch_resid(int ts, const Plan& p, hipStream_t s, const In<S>& in, const 
 
 namespace {
 const char* const kFamNames[F_COUNT] = {
-    "clear", "element", "element_fp64", "up", "root", "down", "policy", "policy_fp64", "fwd_up", "fwd_root",
-    "fwd_down", "recover", "residual", "ref_d", "bwd_up", "bwd_root", "bwd_down", "ref_kff", "fwd_up_vec",
-    "recover_add", "reduce", "plain_riccati", "up_fp64", "down_fp64", "fwd_inst", "refine_inst", "warm_copy",
-    "ragged_pack", "fused_solve", "fused_solve_fp64", "tail_sweep", "tail_sweep_fp64", "tail_root",
-    "tail_root_fp64", "tail_sweep_up0"};
+    "clear", "element", "up", "root", "down", "policy", "fwd_up", "fwd_root", "fwd_down", "recover", "residual",
+    "ref_d", "bwd_up", "bwd_root", "bwd_down", "ref_kff", "fwd_up_vec", "recover_add", "reduce", "plain_riccati",
+    "fwd_inst", "refine_inst", "warm_copy", "ragged_pack", "fused_solve", "tail_sweep", "tail_root",
+    "tail_sweep_up0", "chunk_up", "chunk_mid", "chunk_down", "fwd_seq", "refine_seq", "fp64_redo", "mark_redo"};
 
 // Per-handle launch timer: two HIP events around every launch, read back by
 // lqr_timing_report.
 struct EventTimer final : lqr::Timer {
-    struct Rec { int fam; hipEvent_t a, b; double flops, bytes; };
+    struct Rec { int fam; hipEvent_t a, b; double flops, bytes, flops_min; };
     std::vector<Rec> recs;
     std::vector<hipEvent_t> pool;
     hipEvent_t get() {
@@ -226,8 +286,8 @@ struct EventTimer final : lqr::Timer {
         return e;
     }
     Rec cur{};
-    void before(hipStream_t s, int fam, double flops, double bytes) override {
-        cur = Rec{fam, get(), get(), flops, bytes};
+    void before(hipStream_t s, int fam, double flops, double bytes, double flops_min) override {
+        cur = Rec{fam, get(), get(), flops, bytes, flops_min};
         if (cur.a) (void)hipEventRecord(cur.a, s);
     }
     void after(hipStream_t s) override {
@@ -250,12 +310,11 @@ struct lqr_handle_s {
     int device;
     bool timing = false;
     EventTimer timer;
-    // mappings chosen by lqr_autotune / lqr_set_tuning, per (batch, N, n, m, dtype)
-    std::map<std::tuple<int64_t, int, int, int, int>, Tuning> tuned;
-    const Tuning* find(int64_t batch, int N, int n, int m, int dtype) const {
-        auto it = tuned.find(std::make_tuple(batch, N, n, m, dtype));
-        return it == tuned.end() ? nullptr : &it->second;
-    }
+    // mappings chosen by lqr_autotune / lqr_set_tuning, per (batch, N, n, m,
+    // dtype), and per shape bucket (batch and N rounded up to powers of two:
+    // what the tuning cache file holds)
+    std::map<std::tuple<int64_t, int, int, int, int>, Tuning> tuned, cached;
+    const Tuning* find(int64_t batch, int N, int n, int m, int dtype) const;
 };
 
 extern "C" {
@@ -268,8 +327,9 @@ void lqr_opts_default(lqr_opts* o, int32_t dtype) {
     o->refine_sweeps = dtype == LQR_F32 ? 1 : 0;
     o->fallback = 1;
     o->cond_threshold = 1e6;
-    o->refine_tol = 1e-5;
+    o->refine_tol = 1e-6;
     o->resid_out = nullptr;
+    o->sync_status = 0;
 }
 
 int lqr_create(lqr_handle_t* h, int device) {
@@ -308,6 +368,42 @@ int lqr_workspace_size(lqr_handle_t h, int64_t batch, int N, int n, int m, const
 }  // extern "C"
 
 namespace {
+// the buffers of a call beside the records, carved from the workspace
+Ctx make_ctx(const Plan& p, const Layout& lay, char* wsb, bool big) {
+    Ctx cx;
+    cx.active = (int32_t*)(wsb + lay.int_off);
+    cx.dws = (double*)(wsb + lay.dbl_off);
+    cx.ws64 = nullptr;
+    cx.redo_grid = 0;
+    std::memset(&cx.rp, 0, sizeof cx.rp);
+    if (p.fallback) {
+        int64_t slots;
+        size_t rb;
+        cx.rp = make_redo_plan(p, big, slots, rb);
+        cx.ws64 = (double*)(wsb + lay.redo_off);
+        cx.redo_grid = (int)slots;
+    }
+    return cx;
+}
+
+// LQR_ENUMERIC check of a call with opts.sync_status: wait for the stream
+// and read the status words back
+int sync_status_check(hipStream_t s, const int32_t* status, int64_t batch) {
+    std::vector<int32_t> st((size_t)batch);
+    HIPCHK(hipMemcpyAsync(st.data(), status, sizeof(int32_t) * (size_t)batch, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    int64_t bad = 0, first = -1;
+    for (int64_t b = 0; b < batch; ++b)
+        if (st[(size_t)b] & ~LQR_ST_FP64_FALLBACK) {
+            if (first < 0) first = b;
+            ++bad;
+        }
+    if (bad)
+        return fail(LQR_ENUMERIC, "%lld instance(s) failed (first: instance %lld, status %d)", (long long)bad,
+                    (long long)first, st[(size_t)first]);
+    return LQR_OK;
+}
+
 int solve_impl(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int m, const void* A, const void* B,
                const void* c, const void* Q, const void* R, const void* M, const void* q, const void* r,
                const void* x0, void* x, void* u, void* lam, int32_t* status, void* workspace,
@@ -338,6 +434,7 @@ int solve_impl(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int m,
             return fail(LQR_EINVAL, "misaligned warm start");
     }
     Plan p = make_plan(batch, N, n, m, es, o, tun);
+    if (!sched_fits(p)) return fail(LQR_EINVAL, "chunked schedule does not fit the tree records of N=%d", N);
     const Layout lay = layout(p, es);
     if (workspace_bytes < lay.total)
         return fail(LQR_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", workspace_bytes, lay.total);
@@ -345,23 +442,28 @@ int solve_impl(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int m,
     HIPCHK(hipSetDevice(h->device));
     hipStream_t s = (hipStream_t)stream;
     char* wsb = (char*)workspace;
-    int32_t* iws = (int32_t*)(wsb + lay.int_off);
-    double* dws = (double*)(wsb + lay.dbl_off);
     const int ts = pick_ts(n, m, tun);
+    const Ctx cx = make_ctx(p, lay, wsb, ts == kBigTS);
     const int refine = o.method == LQR_METHOD_SCAN ? o.refine_sweeps : 0;
-    TimerScope ts_scope(h->timing ? &h->timer : nullptr);
-    if (o.dtype == LQR_F32) {
-        In<float> in{(const float*)A, (const float*)B, (const float*)c, (const float*)Q, (const float*)R,
-                     (const float*)M, (const float*)q, (const float*)r, (const float*)x0};
-        Out<float> out{(float*)x, (float*)u, (float*)lam, status};
-        const Warm<float> warm{(const float*)o.warm_x, (const float*)o.warm_u, (const float*)o.warm_lam};
-        return dispatch<float>(ts, o.method, p, s, in, out, (float*)wsb, iws, dws, refine, o.resid_out, warm);
+    int rc;
+    {
+        TimerScope ts_scope(h->timing ? &h->timer : nullptr);
+        if (o.dtype == LQR_F32) {
+            In<float> in{(const float*)A, (const float*)B, (const float*)c, (const float*)Q, (const float*)R,
+                         (const float*)M, (const float*)q, (const float*)r, (const float*)x0};
+            Out<float> out{(float*)x, (float*)u, (float*)lam, status};
+            const Warm<float> warm{(const float*)o.warm_x, (const float*)o.warm_u, (const float*)o.warm_lam};
+            rc = dispatch<float>(ts, o.method, p, s, in, out, (float*)wsb, cx, refine, o.resid_out, warm);
+        } else {
+            In<double> in{(const double*)A, (const double*)B, (const double*)c, (const double*)Q, (const double*)R,
+                          (const double*)M, (const double*)q, (const double*)r, (const double*)x0};
+            Out<double> out{(double*)x, (double*)u, (double*)lam, status};
+            const Warm<double> warm{(const double*)o.warm_x, (const double*)o.warm_u, (const double*)o.warm_lam};
+            rc = dispatch<double>(ts, o.method, p, s, in, out, (double*)wsb, cx, refine, o.resid_out, warm);
+        }
     }
-    In<double> in{(const double*)A, (const double*)B, (const double*)c, (const double*)Q, (const double*)R,
-                  (const double*)M, (const double*)q, (const double*)r, (const double*)x0};
-    Out<double> out{(double*)x, (double*)u, (double*)lam, status};
-    const Warm<double> warm{(const double*)o.warm_x, (const double*)o.warm_u, (const double*)o.warm_lam};
-    return dispatch<double>(ts, o.method, p, s, in, out, (double*)wsb, iws, dws, refine, o.resid_out, warm);
+    if (rc != LQR_OK || !o.sync_status) return rc;
+    return sync_status_check(s, status, batch);
 }
 }  // namespace
 
@@ -463,7 +565,7 @@ int pack_launch(hipStream_t s, bool gather, const std::vector<void*>& ptrs, cons
         const int64_t gx = std::min<int64_t>((words + 255) / 256, 64);
         uint32_t* pk = reinterpret_cast<uint32_t*>(packed + c0 * elems * es);
         Timer* tm = current_timer();
-        if (tm) tm->before(s, F_PACK, 0, 2.0 * words * 4 * t.count);
+        if (tm) tm->before(s, F_PACK, 0, 2.0 * words * 4 * t.count, 0);
         if (gather)
             hipLaunchKernelGGL(k_pack<true>, dim3((unsigned)gx, (unsigned)t.count), dim3(256), 0, s, t, pk, words);
         else
@@ -546,6 +648,7 @@ int lqr_kkt_solve_ragged(lqr_handle_t h, void* stream, int64_t count, const lqr_
         }
         lqr_opts og = o;
         og.resid_out = rel_out ? prel : nullptr;
+        og.sync_status = 0;
         LCHK(solve_impl(h, stream, k, g.N, g.n, g.m, fin[0], fin[1], fin[2], fin[3], fin[4], fin[5], fin[6],
                         fin[7], fin[8], fout[0], fout[1], fout[2], pst, pws, gb.solve, og,
                         h->find(k, g.N, g.n, g.m, o.dtype)));
@@ -568,8 +671,76 @@ int lqr_kkt_solve_ragged(lqr_handle_t h, void* stream, int64_t count, const lqr_
             HIPCHK(hipGetLastError());
         }
     }
+    if (o.sync_status) return sync_status_check(s, status, count);
     return LQR_OK;
 }
+
+}  // extern "C"
+
+namespace {
+Tuning from_abi(const lqr_tuning& t) {
+    Tuning tu;
+    tu.engine = t.engine;
+    tu.fused = t.fused;
+    tu.big_grid = t.big_grid;
+    tu.split = t.split;
+    tu.chunk = t.chunk;
+    tu.sweep = t.sweep;
+    tu.fwd_seq = t.fwd_seq;
+    return tu;
+}
+void to_abi(const Tuning& t, float ms, lqr_tuning* o) {
+    o->engine = t.engine;
+    o->fused = t.fused;
+    o->big_grid = t.big_grid;
+    o->ms = ms;
+    o->split = t.split;
+    o->chunk = t.chunk;
+    o->sweep = t.sweep;
+    o->fwd_seq = t.fwd_seq;
+}
+
+int check_tuning(int N, int n, int m, const Tuning& t) {
+    if (t.engine < 0 || t.engine > 2 || t.fused < -1 || t.fused > 2 || t.big_grid < 0 || t.split < 0 || t.split > 2 ||
+        t.chunk < 0 || t.sweep < 0 || t.fwd_seq < 0 || t.fwd_seq > 1)
+        return fail(LQR_EINVAL, "bad tuning (engine %d, fused %d, big_grid %d, split %d, chunk %d, sweep %d, fwd_seq %d)",
+                    t.engine, t.fused, t.big_grid, t.split, t.chunk, t.sweep, t.fwd_seq);
+    const bool big = t.engine == 2 || pick_ts(n, m) == kBigTS;
+    if (t.split && (big || t.fused == 2))
+        return fail(LQR_EINVAL, "the split and chunked schedules run on the wavefront engine with level-by-level launches");
+    if (t.split == 2 && (t.chunk < 1 || t.sweep < 1 || t.sweep > N + 1))
+        return fail(LQR_EINVAL, "chunked schedule needs chunk >= 1 and 1 <= sweep <= N+1 (chunk %d, sweep %d)", t.chunk,
+                    t.sweep);
+    if (t.engine == 1 && pick_ts(n, m) == kBigTS)
+        return fail(LQR_EINVAL, "the wavefront engine takes orders up to 64 (n=%d m=%d)", n, m);
+    if (t.fused == 2 && big)
+        return fail(LQR_EINVAL, "the one-launch solve runs on the wavefront engine (orders up to 64)");
+    if (t.fwd_seq && t.fused == 2)
+        return fail(LQR_EINVAL, "the one-launch solve has its own vector passes (fwd_seq needs fused 0 or 1)");
+    lqr_opts o;
+    lqr_opts_default(&o, LQR_F32);
+    if (!sched_fits(make_plan(1, N, n, m, 4, o, &t)))
+        return fail(LQR_EINVAL, "chunked schedule does not fit the tree records of N=%d", N);
+    return LQR_OK;
+}
+
+// bucket of a size for the tuning cache: the next power of two
+int64_t bucket(int64_t v) {
+    int64_t b = 1;
+    while (b < v) b <<= 1;
+    return b;
+}
+}  // namespace
+
+const Tuning* lqr_handle_s::find(int64_t batch, int N, int n, int m, int dtype) const {
+    auto it = tuned.find(std::make_tuple(batch, N, n, m, dtype));
+    if (it != tuned.end()) return &it->second;
+    auto jt = cached.find(std::make_tuple(bucket(batch), (int)bucket(N), n, m, dtype));
+    if (jt != cached.end()) return &jt->second;
+    return nullptr;
+}
+
+extern "C" {
 
 int lqr_set_tuning(lqr_handle_t h, int64_t batch, int N, int n, int m, int32_t dtype, const lqr_tuning* t) {
     if (!h) return fail(LQR_EINVAL, "null handle");
@@ -577,23 +748,11 @@ int lqr_set_tuning(lqr_handle_t h, int64_t batch, int N, int n, int m, int32_t d
     const auto key = std::make_tuple(batch, N, n, m, (int)dtype);
     if (!t) {
         h->tuned.erase(key);
+        h->cached.erase(std::make_tuple(bucket(batch), (int)bucket(N), n, m, (int)dtype));
         return LQR_OK;
     }
-    if (t->engine < 0 || t->engine > 2 || t->fused < -1 || t->fused > 2 || t->big_grid < 0 || t->split < 0 ||
-        t->split > 1)
-        return fail(LQR_EINVAL, "bad tuning (engine %d, fused %d, big_grid %d, split %d)", t->engine, t->fused,
-                    t->big_grid, t->split);
-    if (t->split && (t->engine == 2 || pick_ts(n, m) == kBigTS || t->fused == 2))
-        return fail(LQR_EINVAL, "the split schedule runs on the wavefront engine with level-by-level launches");
-    if (t->engine == 1 && pick_ts(n, m) == kBigTS)
-        return fail(LQR_EINVAL, "the wavefront engine takes orders up to 64 (n=%d m=%d)", n, m);
-    if (t->fused == 2 && (t->engine == 2 || pick_ts(n, m) == kBigTS))
-        return fail(LQR_EINVAL, "the one-launch solve runs on the wavefront engine (orders up to 64)");
-    Tuning tu;
-    tu.engine = t->engine;
-    tu.fused = t->fused;
-    tu.big_grid = t->big_grid;
-    tu.split = t->split;
+    const Tuning tu = from_abi(*t);
+    LCHK(check_tuning(N, n, m, tu));
     h->tuned[key] = tu;
     return LQR_OK;
 }
@@ -606,28 +765,36 @@ int lqr_autotune(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int 
     if (reps < 1 || reps > 100) return fail(LQR_EINVAL, "reps must be in 1..100");
     lqr_opts o;
     if (opts) o = *opts; else lqr_opts_default(&o, LQR_F32);
+    o.sync_status = 0;
     LCHK(check_dims(batch, N, n, m));
     if (o.dtype != LQR_F32 && o.dtype != LQR_F64) return fail(LQR_EINVAL, "bad dtype %d", o.dtype);
     const size_t es = o.dtype == LQR_F32 ? 4 : 8;
-    // candidate mappings: engine x vector-pass form x matrix-core grid
+    // candidate mappings: engine x schedule of the reverse scan x form of the
+    // vector passes (x matrix-core grid)
     std::vector<Tuning> cands;
     const bool small_ok = pick_ts(n, m) != kBigTS;
-    for (int eng : {1, 2}) {
-        if (eng == 1 && !small_ok) continue;
-        for (int fu : {0, 1, 2}) {
-            if (eng == 2 && fu == 2) continue;
-            if (eng == 1) {
-                Tuning t; t.engine = 1; t.fused = fu; cands.push_back(t);
-                if (fu != 2) {
-                    Tuning ts = t; ts.split = 1; cands.push_back(ts);
-                }
-            } else {
-                for (int g : {256, 512, 1024}) {
-                    Tuning t; t.engine = 2; t.fused = fu; t.big_grid = g; cands.push_back(t);
-                }
+    if (small_ok) {
+        for (int fs : {0, 1}) {
+            for (int fu : {0, 1}) {
+                if (fs && fu) continue;   // the sequential passes are already per instance
+                Tuning t; t.engine = 1; t.fused = fu; t.fwd_seq = fs; cands.push_back(t);
+            }
+            Tuning sp; sp.engine = 1; sp.fused = 0; sp.fwd_seq = fs; sp.split = 1; cands.push_back(sp);
+            for (int ch : {1, 4, 8, 16, 32}) {
+                if (ch > 1 && ch >= N) continue;
+                Tuning t; t.engine = 1; t.fused = 0; t.fwd_seq = fs; t.split = 2; t.chunk = ch; t.sweep = 1;
+                cands.push_back(t);
             }
         }
+        Tuning one; one.engine = 1; one.fused = 2; cands.push_back(one);
     }
+    for (int fs : {0, 1})
+        for (int fu : {0, 1}) {
+            if (fs && fu) continue;
+            for (int g : {256, 512, 1024}) {
+                Tuning t; t.engine = 2; t.fused = fu; t.fwd_seq = fs; t.big_grid = g; cands.push_back(t);
+            }
+        }
     HIPCHK(hipSetDevice(h->device));
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -638,7 +805,8 @@ int lqr_autotune(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int 
     Tuning best_t;
     int rc = LQR_OK;
     for (const Tuning& t : cands) {
-        if (layout(make_plan(batch, N, n, m, es, o, &t), es).total > workspace_bytes) continue;
+        const Plan pl = make_plan(batch, N, n, m, es, o, &t);
+        if (!sched_fits(pl) || layout(pl, es).total > workspace_bytes) continue;
         auto run = [&]() {
             return solve_impl(h, stream, batch, N, n, m, A, B, c, Q, R, M, q, r, x0, x, u, lam, status, workspace,
                               workspace_bytes, o, &t);
@@ -673,12 +841,70 @@ int lqr_autotune(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int 
     if (rc != LQR_OK) return rc;
     if (best_ms < 0.f) return fail(LQR_ENOMEM, "no candidate mapping fits the workspace with a clean status");
     h->tuned[std::make_tuple(batch, N, n, m, (int)o.dtype)] = best_t;
-    best->engine = best_t.engine;
-    best->fused = best_t.fused;
-    best->big_grid = best_t.big_grid;
-    best->split = best_t.split;
-    best->ms = best_ms;
+    h->cached[std::make_tuple(bucket(batch), (int)bucket(N), n, m, (int)o.dtype)] = best_t;
+    to_abi(best_t, best_ms, best);
     return LQR_OK;
+}
+
+// Tuning cache file: one line per shape bucket,
+//   "lqr-tune-1 <arch> <dtype> <n> <m> <N bucket> <batch bucket> <engine> <fused> <big_grid> <split> <chunk>
+//    <sweep> <fwd_seq>"
+// (sizes rounded up to powers of two).  Lines of another device architecture
+// are kept in the file but not loaded.
+int lqr_tuning_save(lqr_handle_t h, const char* path) {
+    if (!h || !path) return fail(LQR_EINVAL, "null handle or path");
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, h->device));
+    const std::string arch = std::string(prop.gcnArchName).substr(0, std::string(prop.gcnArchName).find(':'));
+    std::vector<std::string> keep;
+    if (FILE* f = std::fopen(path, "r")) {
+        char line[512];
+        while (std::fgets(line, sizeof line, f)) {
+            char a[64] = {0};
+            if (std::sscanf(line, "lqr-tune-1 %63s", a) == 1 && arch != a) keep.push_back(line);
+        }
+        std::fclose(f);
+    }
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return fail(LQR_EINVAL, "cannot write %s", tmp.c_str());
+    for (const auto& l : keep) std::fputs(l.c_str(), f);
+    for (const auto& kv : h->cached) {
+        const auto& k = kv.first;
+        const Tuning& t = kv.second;
+        std::fprintf(f, "lqr-tune-1 %s %d %d %d %lld %lld %d %d %d %d %d %d %d\n", arch.c_str(), std::get<4>(k),
+                     std::get<2>(k), std::get<3>(k), (long long)std::get<1>(k), (long long)std::get<0>(k), t.engine,
+                     t.fused, t.big_grid, t.split, t.chunk, t.sweep, t.fwd_seq);
+    }
+    std::fclose(f);
+    if (std::rename(tmp.c_str(), path) != 0) return fail(LQR_EINVAL, "cannot replace %s", path);
+    return LQR_OK;
+}
+
+int lqr_tuning_load(lqr_handle_t h, const char* path) {
+    if (!h || !path) return fail(LQR_EINVAL, "null handle or path");
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, h->device));
+    const std::string arch = std::string(prop.gcnArchName).substr(0, std::string(prop.gcnArchName).find(':'));
+    FILE* f = std::fopen(path, "r");
+    if (!f) return fail(LQR_EINVAL, "cannot read %s", path);
+    char line[512];
+    int loaded = 0;
+    while (std::fgets(line, sizeof line, f)) {
+        char a[64] = {0};
+        int dt, n, m;
+        long long Nb, Bb;
+        Tuning t;
+        if (std::sscanf(line, "lqr-tune-1 %63s %d %d %d %lld %lld %d %d %d %d %d %d %d", a, &dt, &n, &m, &Nb, &Bb,
+                        &t.engine, &t.fused, &t.big_grid, &t.split, &t.chunk, &t.sweep, &t.fwd_seq) != 13)
+            continue;
+        if (arch != a || n < 1 || m < 1 || Nb < 1 || Bb < 1) continue;
+        if (check_tuning((int)Nb, n, m, t) != LQR_OK) continue;
+        h->cached[std::make_tuple((int64_t)Bb, (int)Nb, n, m, dt)] = t;
+        ++loaded;
+    }
+    std::fclose(f);
+    return loaded;
 }
 
 int lqr_autotune_workspace_size(int64_t batch, int N, int n, int m, const lqr_opts* opts, size_t* bytes) {
@@ -739,6 +965,35 @@ int lqr_kkt_residual(lqr_handle_t h, void* stream, int64_t batch, int N, int n, 
                                   (double*)wsb, dws, rel);
 }
 
+int lqr_kkt_factors(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int m, int32_t dtype,
+                    const void* workspace, size_t workspace_bytes, void* P, void* p, void* K, void* kff) {
+    if (!h) return fail(LQR_EINVAL, "null handle");
+    LCHK(check_dims(batch, N, n, m));
+    if (dtype != LQR_F32 && dtype != LQR_F64) return fail(LQR_EINVAL, "bad dtype %d", dtype);
+    if (!workspace || !P || !p || !K || !kff) return fail(LQR_EINVAL, "null pointer argument");
+    lqr_opts o;
+    lqr_opts_default(&o, dtype);
+    const size_t es = dtype == LQR_F32 ? 4 : 8;
+    const void* outs[] = {P, p, K, kff};
+    for (const void* ptr : outs)
+        if (!aligned(ptr, es)) return fail(LQR_EINVAL, "misaligned output");
+    const Plan pl = make_plan(batch, N, n, m, es, o, h->find(batch, N, n, m, dtype));
+    if (workspace_bytes < layout(pl, es).total)
+        return fail(LQR_ENOMEM, "workspace of %zu bytes is smaller than the %zu of this shape", workspace_bytes,
+                    layout(pl, es).total);
+    HIPCHK(hipSetDevice(h->device));
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t grid = batch * (N + 1);
+    if (dtype == LQR_F32)
+        hipLaunchKernelGGL(k_factors<float>, dim3((unsigned)grid), dim3(256), 0, s, pl, (const float*)workspace,
+                           (float*)P, (float*)p, (float*)K, (float*)kff);
+    else
+        hipLaunchKernelGGL(k_factors<double>, dim3((unsigned)grid), dim3(256), 0, s, pl, (const double*)workspace,
+                           (double*)P, (double*)p, (double*)K, (double*)kff);
+    HIPCHK(hipGetLastError());
+    return LQR_OK;
+}
+
 int lqr_timing_enable(lqr_handle_t h, int enable) {
     if (!h) return fail(LQR_EINVAL, "null handle");
     h->timing = enable != 0;
@@ -748,7 +1003,7 @@ int lqr_timing_enable(lqr_handle_t h, int enable) {
 int lqr_timing_report(lqr_handle_t h, char* buf, size_t len) {
     if (!h || !buf || len == 0) return fail(LQR_EINVAL, "null handle or buffer");
     HIPCHK(hipSetDevice(h->device));
-    struct Acc { int64_t launches = 0; double ms = 0, flops = 0, bytes = 0; } acc[F_COUNT];
+    struct Acc { int64_t launches = 0; double ms = 0, flops = 0, bytes = 0, flops_min = 0; } acc[F_COUNT];
     for (auto& r : h->timer.recs) {
         HIPCHK(hipEventSynchronize(r.b));
         float ms = 0.f;
@@ -758,6 +1013,7 @@ int lqr_timing_report(lqr_handle_t h, char* buf, size_t len) {
         a.ms += ms;
         a.flops += r.flops;
         a.bytes += r.bytes;
+        a.flops_min += r.flops_min;
         h->timer.pool.push_back(r.a);
         h->timer.pool.push_back(r.b);
     }
@@ -766,8 +1022,8 @@ int lqr_timing_report(lqr_handle_t h, char* buf, size_t len) {
     char line[256];
     for (int f = 0; f < F_COUNT; ++f) {
         if (!acc[f].launches) continue;
-        snprintf(line, sizeof line, "%s %lld %.6f %.6e %.6e\n", kFamNames[f], (long long)acc[f].launches, acc[f].ms,
-                 acc[f].flops, acc[f].bytes);
+        snprintf(line, sizeof line, "%s %lld %.6f %.6e %.6e %.6e\n", kFamNames[f], (long long)acc[f].launches,
+                 acc[f].ms, acc[f].flops, acc[f].bytes, acc[f].flops_min);
         out += line;
     }
     if (out.size() + 1 > len) return fail(LQR_ENOMEM, "report needs %zu bytes", out.size() + 1);

@@ -120,15 +120,21 @@ class Server:
             q = self.pending[shape]
             # at most one request per client per batch, and none for a client
             # with a request in flight: the next request of a client runs
-            # after its predecessor and starts from that solution
-            batch, keep, seen = [], [], set()
+            # after its predecessor and starts from that solution.  A batch
+            # holds only warm-started or only cold requests: the solve of a
+            # batch with warm starts refines every member from its warm state,
+            # so a cold member would otherwise start from zeros and get one
+            # refinement sweep fewer than alone.
+            batch, keep, seen, kind = [], [], set(), None
             while q and len(batch) < self.max_batch:
                 r = q.popleft()
-                if r.client in seen or r.client in self.busy_clients:
+                st = self._warm_of(r, shape)
+                if r.client in seen or r.client in self.busy_clients or (kind is not None and (st is not None) != kind):
                     keep.append(r)
                 else:
                     batch.append(r)
                     seen.add(r.client)
+                    kind = st is not None
             for r in reversed(keep):
                 q.appendleft(r)
             if not batch:
@@ -136,16 +142,22 @@ class Server:
                 continue
             warm = []
             for r in batch:
-                st = self.warm_state.get(r.client) if self.use_warm else None
-                if st is not None and st[0] != shape:
-                    st = None
+                st = self._warm_of(r, shape)
                 r.warm = st is not None
-                warm.append(None if st is None else st[1])
+                warm.append(st)
                 r.launched = now
             h = self.be.launch(shape, batch, warm)
             self.busy_clients |= seen
             self.inflight.append((h, shape, batch, sum(self.cost(shape) for _ in batch)))
             self.launch_log.append((shape, len(batch)))
+
+    def _warm_of(self, r: Request, shape):
+        """Device state of the client's last solution if it can warm-start
+        this request (same shape), else None."""
+        st = self.warm_state.get(r.client) if self.use_warm else None
+        if st is None or st[0] != shape:
+            return None
+        return st[1]
 
     def _retire(self):
         still = []
@@ -239,12 +251,9 @@ class GpuBackend:
                     dev[f][i].copy_(src, non_blocking=True)
             warm = None
             if any(w is not None for w in warm_list):
-                N, n, m = shape
-                z = {"x": torch.zeros((N + 1, n), dtype=self.dtype, device=dn),
-                     "u": torch.zeros((N, m), dtype=self.dtype, device=dn),
-                     "lam": torch.zeros((N + 1, n), dtype=self.dtype, device=dn)}
-                warm = tuple(torch.stack([(w[f] if w is not None else z[f]) for w in warm_list])
-                             for f in ("x", "u", "lam"))
+                if not all(w is not None for w in warm_list):
+                    raise ValueError("a batch holds only warm-started or only cold requests")
+                warm = tuple(torch.stack([w[f] for w in warm_list]) for f in ("x", "u", "lam"))
             out = self.L.solve(*[dev[f] for f in FIELDS], refine=self.refine, want_resid=True, warm=warm,
                                workspace=self.ws[sid], stream=s)
             host_out = {f: torch.empty(tuple(out[f].shape), dtype=out[f].dtype, pin_memory=True)

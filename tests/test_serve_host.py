@@ -118,3 +118,30 @@ def test_fifo_across_shapes():
     _drive(srv, reqs)
     assert srv.launch_log[0] == ((10, 12, 12), 2)
     assert srv.launch_log[1] == ((20, 36, 12), 1)
+
+
+def test_batches_never_mix_warm_and_cold_requests():
+    """A client's first request (cold) and another client's later request
+    (warm-started) of the same shape are admitted together but launched in
+    separate batches, so every member of a batch starts the way it would
+    alone."""
+    be = FakeBackend(nstreams=1, delay=1)
+    srv = Server(be, budget_bytes=10 ** 12, max_batch=64, warm=True, itemsize=4)
+    first = [_req(0, 0, 10, 4, 2), _req(1, 1, 10, 4, 2)]
+    _drive(srv, first)
+    assert len(srv.done) == 2
+    # client 0 now has a warm state; client 2 is new (cold)
+    later = [_req(2, 0, 10, 4, 2), _req(3, 2, 10, 4, 2), _req(4, 1, 10, 4, 2)]
+    launches = []
+    orig = be.launch
+
+    def spy(shape, reqs, warm):
+        launches.append([w is not None for w in warm])
+        return orig(shape, reqs, warm)
+
+    be.launch = spy
+    _drive(srv, later)
+    assert len(srv.done) == 5
+    for kinds in launches:
+        assert all(kinds) or not any(kinds), launches
+    assert any(all(k) for k in launches) and any(not any(k) for k in launches)
