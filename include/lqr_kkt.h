@@ -153,6 +153,31 @@ int lqr_kkt_solve(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int
                   const void* x0, void* x, void* u, void* lam, int32_t* status,
                   void* workspace, size_t workspace_bytes, const lqr_opts* opts);
 
+/* lqr_kkt_solve without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation).  The workspace is a fixed array
+ * of lqr_noalloc_workspace_bytes() bytes (64 MiB) in the library's device
+ * code, one per GPU, held until the process ends; its device address is
+ * looked up once per device by lqr_create.  Nothing is allocated on this
+ * path.  Arguments, layout, asynchrony and per-instance status are those of
+ * lqr_kkt_solve.  Errors: LQR_ENOMEM (nothing launched) when the problem's
+ * workspace (lqr_workspace_size) exceeds that size -- e.g. a single
+ * whole-body instance (n=36, m=12, N=100) needs about 7 MB, so about eight
+ * fit; LQR_EINVAL for opts->sync_status (it would allocate a host buffer)
+ * and the argument errors of lqr_kkt_solve.  Every call on a GPU shares that
+ * GPU's array and leaves its contents behind: calls that overlap on one GPU
+ * (concurrent streams, several host threads) race and must be serialized by
+ * the caller; successive calls on one stream are safe (no kernel reads
+ * workspace contents it did not write in the same call). */
+int lqr_kkt_solve_noalloc(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int m,
+                          const void* A, const void* B, const void* c, const void* Q,
+                          const void* R, const void* M, const void* q, const void* r,
+                          const void* x0, void* x, void* u, void* lam, int32_t* status,
+                          const lqr_opts* opts);
+
+/* Size of the workspace lqr_kkt_solve_noalloc uses (bytes, per GPU). */
+size_t lqr_noalloc_workspace_bytes(void);
+
 /* FP64 KKT residual of a given solution (x, u, lam) of the problem above:
  * writes rel[b] = ||r||_2 / ||(x0, c, q, r)||_2 per instance (device FP64
  * array).  The residual blocks are the stationarity conditions of the

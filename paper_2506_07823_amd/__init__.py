@@ -81,6 +81,11 @@ _lib.lqr_workspace_size.restype = ctypes.c_int
 _lib.lqr_kkt_solve.argtypes = [_vp, _vp, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int] + [_vp] * 9 + \
     [_vp, _vp, _vp, _vp, _vp, _sz, ctypes.POINTER(lqr_opts)]
 _lib.lqr_kkt_solve.restype = ctypes.c_int
+_lib.lqr_kkt_solve_noalloc.argtypes = [_vp, _vp, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int] + [_vp] * 9 + \
+    [_vp, _vp, _vp, _vp, ctypes.POINTER(lqr_opts)]
+_lib.lqr_kkt_solve_noalloc.restype = ctypes.c_int
+_lib.lqr_noalloc_workspace_bytes.argtypes = []
+_lib.lqr_noalloc_workspace_bytes.restype = _sz
 _lib.lqr_kkt_residual.argtypes = [_vp, _vp, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, _i32] + \
     [_vp] * 9 + [_vp] * 3 + [_vp, _vp, _sz]
 _lib.lqr_kkt_residual.restype = ctypes.c_int
@@ -121,6 +126,8 @@ lqr_create = _lib.lqr_create
 lqr_destroy = _lib.lqr_destroy
 lqr_workspace_size = _lib.lqr_workspace_size
 lqr_kkt_solve = _lib.lqr_kkt_solve
+lqr_kkt_solve_noalloc = _lib.lqr_kkt_solve_noalloc
+lqr_noalloc_workspace_bytes = _lib.lqr_noalloc_workspace_bytes
 lqr_kkt_residual = _lib.lqr_kkt_residual
 lqr_max_dim = _lib.lqr_max_dim
 lqr_last_error = _lib.lqr_last_error

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <string>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <vector>
 
@@ -18,6 +19,18 @@
 #include "runs.hpp"
 
 using namespace lqr;
+
+// Workspace of lqr_kkt_solve_noalloc: one array of kNoAllocBytes in each
+// GPU's copy of the library's device code, held until the process ends.  In
+// host code its name is only a stand-in: the device address of each GPU's
+// copy is looked up once per device (lqr_create) and kept in g_scratch.
+constexpr size_t kNoAllocBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+}  // namespace
 
 thread_local std::string g_err;
 thread_local lqr::Timer* g_timer = nullptr;
@@ -337,6 +350,22 @@ int lqr_create(lqr_handle_t* h, int device) {
     int count = 0;
     HIPCHK(hipGetDeviceCount(&count));
     if (device < 0 || device >= count) return fail(LQR_EINVAL, "device %d out of range (%d devices)", device, count);
+    if (device >= kMaxDevices) return fail(LQR_EINVAL, "device %d beyond the %d this library tracks", device, kMaxDevices);
+    {
+        // device address of this GPU's no-allocation workspace (once per device)
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch[device]) {
+            int prev = 0;
+            HIPCHK(hipGetDevice(&prev));
+            HIPCHK(hipSetDevice(device));
+            void* ptr = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            HIPCHK(hipSetDevice(prev));
+            if (e != hipSuccess)
+                return fail(LQR_EDEVICE, "hipGetSymbolAddress of the no-allocation workspace: %s", hipGetErrorString(e));
+            g_scratch[device] = ptr;
+        }
+    }
     lqr_handle_s* hh = new lqr_handle_s;
     hh->device = device;
     *h = hh;
@@ -479,6 +508,30 @@ int lqr_kkt_solve(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int
     return solve_impl(h, stream, batch, N, n, m, A, B, c, Q, R, M, q, r, x0, x, u, lam, status, workspace,
                       workspace_bytes, o, h->find(batch, N, n, m, o.dtype));
 }
+
+int lqr_kkt_solve_noalloc(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int m, const void* A,
+                          const void* B, const void* c, const void* Q, const void* R, const void* M, const void* q,
+                          const void* r, const void* x0, void* x, void* u, void* lam, int32_t* status,
+                          const lqr_opts* opts) {
+    if (!h) return fail(LQR_EINVAL, "null handle");
+    lqr_opts o;
+    if (opts) o = *opts; else lqr_opts_default(&o, LQR_F32);
+    if (o.sync_status) return fail(LQR_EINVAL, "sync_status is not available without allocation");
+    void* ws = g_scratch[h->device];
+    if (!ws) return fail(LQR_EDEVICE, "no-allocation workspace of device %d not set up", h->device);
+    LCHK(check_dims(batch, N, n, m));
+    if (o.dtype != LQR_F32 && o.dtype != LQR_F64) return fail(LQR_EINVAL, "bad dtype %d", o.dtype);
+    const Tuning* tun = h->find(batch, N, n, m, o.dtype);
+    const size_t es = o.dtype == LQR_F32 ? 4 : 8;
+    const size_t need = layout(make_plan(batch, N, n, m, es, o, tun), es).total;
+    if (need > kNoAllocBytes)
+        return fail(LQR_ENOMEM, "this solve needs %zu bytes of workspace, more than the %zu of the no-allocation "
+                    "workspace; use lqr_kkt_solve with a caller workspace", need, kNoAllocBytes);
+    return solve_impl(h, stream, batch, N, n, m, A, B, c, Q, R, M, q, r, x0, x, u, lam, status, ws, kNoAllocBytes,
+                      o, tun);
+}
+
+size_t lqr_noalloc_workspace_bytes(void) { return kNoAllocBytes; }
 
 }  // extern "C"
 
