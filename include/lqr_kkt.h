@@ -322,6 +322,42 @@ int lqr_ragged_workspace_size(lqr_handle_t h, int64_t count, const lqr_problem* 
 int lqr_kkt_solve_ragged(lqr_handle_t h, void* stream, int64_t count, const lqr_problem* probs,
                          int32_t* status, void* workspace, size_t workspace_bytes, const lqr_opts* opts);
 
+/* Ragged batch from a device descriptor table (persistent form).  Problem
+ * i is described by descs[i] (device memory, read by the kernels): its sizes,
+ * the element offsets of its nine input arrays (A, B, c, Q, R, M, q, r, x0, in
+ * the per-instance layout above) in the packed input buffer `in`, the
+ * offsets of its outputs (x, u, lam) in the packed output buffer `out`, and
+ * status_idx, the index of its status word (and residual, opts->resid_out)
+ * in [0, count).  Every problem is solved whole -- scan elements, reverse
+ * scan, policy, forward scan, recovery, FP64 residual and refinement sweeps
+ * (Sec. II-C / II-D) -- by one workgroup of a persistent kernel per padded
+ * order class (orders up to 64): `slots` workgroups, each with one workspace
+ * slot sized for N <= maxN and n, m <= maxd, take the problems from an
+ * atomic counter, so problems of any mix of shapes share launches and the
+ * host never reads the table.  Problems marked for the FP64 fallback are
+ * then solved again whole in FP64.  The call is asynchronous on `stream`
+ * and can be captured into a graph and replayed with new table and buffer
+ * contents (a descriptor with N = 0 marks an unused entry of a fixed-size
+ * table).  A descriptor with malformed sizes (N = 0 included), n or m above
+ * 64 or shapes beyond (maxN, maxd) is not solved: its status word gets
+ * LQR_ST_BAD_DESC and its residual -1; a descriptor whose status_idx is out
+ * of range is ignored.  opts->warm_x/u/lam, when given, are packed buffers laid
+ * out like `out` (every problem warm-started).  The workspace must hold
+ * lqr_ragged_dev_workspace_size bytes (proportional to slots, not count),
+ * 256-byte aligned. */
+typedef struct {
+    int32_t N, n, m, status_idx;
+    int64_t in_off[9];    /* A, B, c, Q, R, M, q, r, x0 (elements into `in`) */
+    int64_t out_off[3];   /* x, u, lam (elements into `out`) */
+} lqr_problem_desc;
+#define LQR_ST_BAD_DESC 16   /* ragged descriptor malformed or beyond the slots (not solved) */
+
+int lqr_ragged_dev_workspace_size(int64_t count, int32_t slots, int32_t maxN, int32_t maxd, const lqr_opts* opts,
+                                  size_t* bytes);
+int lqr_kkt_solve_ragged_dev(lqr_handle_t h, void* stream, int64_t count, const lqr_problem_desc* descs,
+                             const void* in, void* out, int32_t* status, int32_t slots, int32_t maxN, int32_t maxd,
+                             void* workspace, size_t workspace_bytes, const lqr_opts* opts);
+
 /* Largest n, m supported by the built shape classes (n, m <= this). */
 int lqr_max_dim(void);
 

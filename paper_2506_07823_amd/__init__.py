@@ -19,6 +19,7 @@ import ctypes
 import os
 import threading
 
+import numpy as np
 import torch  # loads the HIP runtime the library links against (must come first)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -28,7 +29,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "lqr_kkt.h")
 LQR_OK, LQR_EINVAL, LQR_ENOMEM, LQR_ENUMERIC, LQR_EDEVICE, LQR_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 LQR_F32, LQR_F64 = 0, 1
 LQR_METHOD_SCAN, LQR_METHOD_SEQ_RICCATI = 0, 1
-ST_NONFINITE, ST_NOT_SPD, ST_P_NOT_SPD, ST_FP64_FALLBACK = 1, 2, 4, 8
+ST_NONFINITE, ST_NOT_SPD, ST_P_NOT_SPD, ST_FP64_FALLBACK, ST_BAD_DESC = 1, 2, 4, 8, 16
 
 
 class lqr_opts(ctypes.Structure):
@@ -104,6 +105,11 @@ _lib.lqr_ragged_workspace_size.restype = ctypes.c_int
 _lib.lqr_kkt_solve_ragged.argtypes = [_vp, _vp, _i64, ctypes.POINTER(lqr_problem), _vp, _vp, _sz,
                                       ctypes.POINTER(lqr_opts)]
 _lib.lqr_kkt_solve_ragged.restype = ctypes.c_int
+_lib.lqr_ragged_dev_workspace_size.argtypes = [_i64, _i32, _i32, _i32, ctypes.POINTER(lqr_opts), ctypes.POINTER(_sz)]
+_lib.lqr_ragged_dev_workspace_size.restype = ctypes.c_int
+_lib.lqr_kkt_solve_ragged_dev.argtypes = [_vp, _vp, _i64, _vp, _vp, _vp, _vp, _i32, _i32, _i32, _vp, _sz,
+                                          ctypes.POINTER(lqr_opts)]
+_lib.lqr_kkt_solve_ragged_dev.restype = ctypes.c_int
 _lib.lqr_max_dim.argtypes = []
 _lib.lqr_max_dim.restype = ctypes.c_int
 _lib.lqr_last_error.argtypes = []
@@ -138,6 +144,8 @@ lqr_autotune = _lib.lqr_autotune
 lqr_autotune_workspace_size = _lib.lqr_autotune_workspace_size
 lqr_ragged_workspace_size = _lib.lqr_ragged_workspace_size
 lqr_kkt_solve_ragged = _lib.lqr_kkt_solve_ragged
+lqr_ragged_dev_workspace_size = _lib.lqr_ragged_dev_workspace_size
+lqr_kkt_solve_ragged_dev = _lib.lqr_kkt_solve_ragged_dev
 lqr_tuning_save = _lib.lqr_tuning_save
 lqr_kkt_factors = _lib.lqr_kkt_factors
 lqr_tuning_load = _lib.lqr_tuning_load
@@ -321,6 +329,106 @@ def solve_ragged(problems, *, refine: int | None = None, want_resid: bool = Fals
     s = (stream or torch.cuda.current_stream(device)).cuda_stream
     _check(_lib.lqr_kkt_solve_ragged(h, s, count, table, status.data_ptr(), wbuf.data_ptr(), wbuf.numel(),
                                      ctypes.byref(op)))
+    return outs, status, resid
+
+
+# lqr_problem_desc of the C ABI (112 bytes)
+DESC_DTYPE = np.dtype([("N", "<i4"), ("n", "<i4"), ("m", "<i4"), ("status_idx", "<i4"), ("in_off", "<i8", (9,)),
+                       ("out_off", "<i8", (3,))])
+
+
+def field_sizes(N, n, m):
+    """Elements of one instance's input arrays (A, B, c, Q, R, M, q, r, x0) and
+    output arrays (x, u, lam)."""
+    ins = (N * n * n, N * n * m, N * n, (N + 1) * n * n, N * m * m, N * n * m, (N + 1) * n, N * m, n)
+    outs = ((N + 1) * n, N * m, (N + 1) * n)
+    return ins, outs
+
+
+def ragged_layout(shapes):
+    """Descriptor table (numpy, DESC_DTYPE) and packed buffer sizes for
+    problems of the given (N, n, m) shapes, in order: problem i's arrays
+    follow problem i-1's, status_idx = i."""
+    descs = np.zeros(len(shapes), dtype=DESC_DTYPE)
+    ioff = ooff = 0
+    for i, (N, n, m) in enumerate(shapes):
+        ins, outs = field_sizes(N, n, m)
+        d = descs[i]
+        d["N"], d["n"], d["m"], d["status_idx"] = N, n, m, i
+        for f, k in enumerate(ins):
+            d["in_off"][f] = ioff
+            ioff += k
+        for f, k in enumerate(outs):
+            d["out_off"][f] = ooff
+            ooff += k
+    return descs, ioff, ooff
+
+
+def solve_ragged_packed(descs, inbuf, outbuf, status, *, count=None, slots=256, maxN, maxd, refine=None,
+                        resid=None, warm=None, workspace: Workspace | None = None, stream=None):
+    """lqr_kkt_solve_ragged_dev on device buffers: `descs` a uint8 device
+    tensor holding `count` descriptors, `inbuf`/`outbuf` packed device
+    buffers of the call's dtype, `status` int32 [count], `resid` optional
+    float64 [count], `warm` optional packed buffer triple laid out like
+    `outbuf` (x, u, lam: here one buffer given three times is accepted)."""
+    dtype = inbuf.dtype
+    device = inbuf.device.index
+    count = descs.numel() // DESC_DTYPE.itemsize if count is None else count
+    o = default_opts(dtype)
+    if refine is not None:
+        o.refine_sweeps = int(refine)
+    if resid is not None:
+        o.resid_out = resid.data_ptr()
+    if warm is not None:
+        o.warm_x, o.warm_u, o.warm_lam = (w.data_ptr() for w in warm)
+    nbytes = _sz()
+    _check(_lib.lqr_ragged_dev_workspace_size(count, int(slots), int(maxN), int(maxd), ctypes.byref(o),
+                                              ctypes.byref(nbytes)))
+    if workspace is None:
+        workspace = _default_ws.setdefault(device, Workspace(device))
+    wbuf = workspace.get(nbytes.value)
+    s = (stream or torch.cuda.current_stream(device)).cuda_stream
+    _check(_lib.lqr_kkt_solve_ragged_dev(handle(device), s, count, descs.data_ptr(), inbuf.data_ptr(),
+                                         outbuf.data_ptr(), status.data_ptr(), int(slots), int(maxN), int(maxd),
+                                         wbuf.data_ptr(), wbuf.numel(), ctypes.byref(o)))
+
+
+def solve_ragged_dev(problems, *, slots=256, refine: int | None = None, want_resid: bool = False,
+                     workspace: Workspace | None = None, stream=None):
+    """Ragged batch through the persistent device-descriptor form: `problems`
+    as for solve_ragged (single-instance device tensors of mixed shapes,
+    orders up to 64).  Packs them, builds the descriptor table, solves, and
+    returns (list of dicts x, u, lam; status [count]; residual [count] or
+    None) in the order of `problems`."""
+    count = len(problems)
+    first = problems[0]["A"]
+    dtype, dev = first.dtype, first.device
+    shapes = []
+    for pr in problems:
+        _validate(pr, dtype, dev.index)
+        N, n, _ = pr["A"].shape
+        shapes.append((int(N), int(n), int(pr["B"].shape[-1])))
+        _expect_shapes({k: v.unsqueeze(0) for k, v in pr.items()}, 1, *shapes[-1])
+    descs, nin, nout = ragged_layout(shapes)
+    inbuf = torch.empty(max(nin, 1), dtype=dtype, device=dev)
+    for pr, d in zip(problems, descs):
+        for f, name in enumerate(FIELDS):
+            t = pr[name].reshape(-1)
+            inbuf[int(d["in_off"][f]):int(d["in_off"][f]) + t.numel()].copy_(t)
+    outbuf = torch.empty(max(nout, 1), dtype=dtype, device=dev)
+    dtab = torch.from_numpy(descs.view(np.uint8).copy()).to(dev)
+    status = torch.empty((count,), dtype=torch.int32, device=dev)
+    resid = torch.empty((count,), dtype=torch.float64, device=dev) if want_resid else None
+    solve_ragged_packed(dtab, inbuf, outbuf, status, count=count, slots=min(int(slots), count),
+                        maxN=max(s[0] for s in shapes), maxd=max(max(s[1], s[2]) for s in shapes), refine=refine,
+                        resid=resid, workspace=workspace, stream=stream)
+    outs = []
+    for (N, n, m), d in zip(shapes, descs):
+        o = {}
+        for f, (name, shp) in enumerate((("x", (N + 1, n)), ("u", (N, m)), ("lam", (N + 1, n)))):
+            off = int(d["out_off"][f])
+            o[name] = outbuf[off:off + shp[0] * shp[1]].view(shp)
+        outs.append(o)
     return outs, status, resid
 
 

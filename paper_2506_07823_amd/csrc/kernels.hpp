@@ -63,6 +63,70 @@ struct Plan {
     int big_grid;            //   workgroups of a task launch (scratch slots)
 };
 
+// Balanced tree over `leaves` nodes, level by level (a level of c nodes has
+// ceil(c / 2) parents; an odd last node is carried up)
+__host__ __device__ inline Tree make_tree(int leaves) {
+    Tree t{};
+    t.nlev = 1;
+    t.cnt[0] = leaves;
+    t.off[0] = 0;
+    t.total = leaves;
+    while (t.cnt[t.nlev - 1] > 1) {
+        t.cnt[t.nlev] = (t.cnt[t.nlev - 1] + 1) / 2;
+        t.off[t.nlev] = t.total;
+        t.total += t.cnt[t.nlev];
+        ++t.nlev;
+    }
+    return t;
+}
+
+__host__ __device__ inline int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+// Per-instance record layout of a scan solve of shape (N, n, m), in elements
+// of the storage type (every section 64-element aligned):
+//   tree  reverse-scan nodes (A, C, P, b, p)       suf   complete suffixes (P, p)
+//   K, kff, LG  policy and its Cholesky factor      ftree forward-scan nodes (M, v)
+//   xs, w, pend  node vectors of the vector scans   cp .. kffp  refinement data
+__host__ __device__ inline void plan_records(Plan& p, int N, int n, int m) {
+    p.N = N; p.n = n; p.m = m;
+    const int64_t nn = (int64_t)n * n;
+    p.rec = (int)(3 * nn + 2 * n);
+    p.srec = (int)(nn + n);
+    p.frec = (int)(nn + n);
+    p.rt = make_tree(N + 1);
+    p.ft = make_tree(N);
+    int64_t off = 0;
+    auto sec = [&](int64_t count) { const int64_t o = off; off = align_up(off + count, 64); return o; };
+    p.o_tree = sec((int64_t)p.rt.total * p.rec);
+    p.o_suf = sec((int64_t)p.rt.total * p.srec);
+    p.o_K = sec((int64_t)N * m * n);
+    p.o_kff = sec((int64_t)N * m);
+    p.o_LG = sec((int64_t)N * m * m);
+    p.o_ftree = sec((int64_t)p.ft.total * p.frec);
+    p.o_xs = sec((int64_t)p.ft.total * n);
+    p.o_w = sec((int64_t)p.ft.total * n);
+    p.o_pend = sec((int64_t)p.ft.total * n);
+    p.o_cp = sec((int64_t)N * n);
+    p.o_qp = sec((int64_t)(N + 1) * n);
+    p.o_rp = sec((int64_t)N * m);
+    p.o_x0p = sec(n);
+    p.o_pp = sec((int64_t)(N + 1) * n);
+    p.o_kffp = sec((int64_t)N * m);
+    p.stride = off;
+    p.dstride = 2 * (N + 1);
+}
+
+// Layout of one FP64 redo slot (the sequential recursion's P_k, p_k by stage,
+// K_k, k_k), in doubles: sets o_suf, o_K, o_kff, stride of r
+__host__ __device__ inline void redo_records(Plan& r) {
+    int64_t off = 0;
+    auto sec = [&](int64_t count) { const int64_t o = off; off = align_up(off + count, 64); return o; };
+    r.o_suf = sec((int64_t)(r.N + 1) * r.srec);
+    r.o_K = sec((int64_t)r.N * r.m * r.n);
+    r.o_kff = sec((int64_t)r.N * r.m);
+    r.stride = off;
+}
+
 #define LQR_GATE(p, b) \
     do {               \
         if ((p).active && !(p).active[(b)]) return; \
@@ -1699,16 +1763,15 @@ constexpr int fused_waves() {
     return w < 1 ? 1 : (w > lim ? lim : w);
 }
 
+// The whole solve of instance b by the W wavefronts of the calling
+// workgroup (F: their LDS, sh_rel: one shared double).
 template <typename S, class E, class E64, int MB>
-__global__ __launch_bounds__(64 * fused_waves<E>()) void k_solve_fused(Plan p, In<S> in, Out<S> out, S* ws,
-                                                                      double* dws, double* rel_out, Warm<S> warm,
-                                                                      int refine) {
+__device__ __forceinline__ void fused_body(FusedLds<E, E64>* F, double& sh_rel, const Plan& p, const In<S>& in,
+                                           const Out<S>& out, S* ws, double* dws, double* rel_out,
+                                           const Warm<S>& warm, int refine, int64_t b) {
     static_assert(!E::BIG && E::NT == 64, "wavefront engine only");
     constexpr int W = fused_waves<E>();
-    __shared__ FusedLds<E, E64> F[W];
-    __shared__ double sh_rel;
     const int wv = (int)(threadIdx.x >> 6);
-    const int64_t b = blockIdx.x;
     const int N = p.N, n = p.n;
     auto& Lm = F[wv].m;
     auto& Lv = F[wv].v;
@@ -1806,6 +1869,150 @@ __global__ __launch_bounds__(64 * fused_waves<E>()) void k_solve_fused(Plan p, I
         changed = true;
     }
     if (rel_out && changed) residual(std::false_type{});
+}
+
+template <typename S, class E, class E64, int MB>
+__global__ __launch_bounds__(64 * fused_waves<E>()) void k_solve_fused(Plan p, In<S> in, Out<S> out, S* ws,
+                                                                      double* dws, double* rel_out, Warm<S> warm,
+                                                                      int refine) {
+    __shared__ FusedLds<E, E64> F[fused_waves<E>()];
+    __shared__ double sh_rel;
+    fused_body<S, E, E64, MB>(F, sh_rel, p, in, out, ws, dws, rel_out, warm, refine, (int64_t)blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Ragged batches from a device descriptor table: persistent workgroups (one
+// workspace slot each) take problems from an atomic counter and solve each
+// whole (fused_body) with a plan built on the device from its sizes.  One
+// launch per padded-order class; a launch skips the problems of the other
+// classes.  Problems are addressed as instance 0 of a batch of one: their
+// arrays are offsets into packed buffers, their status and residual words
+// are at status_idx.
+// ---------------------------------------------------------------------------
+struct RaggedDesc {
+    int32_t N, n, m, status_idx;
+    int64_t in_off[9], out_off[3];
+};
+
+// padded-order class of a problem on the wavefront engine (0: none)
+__host__ __device__ inline int wave_class(int n, int m) {
+    const int d = n > m ? n : m;
+    const int ts = (d + 7) / 8;
+    return d < 1 ? 0 : ts <= 6 ? ts : ts <= 8 ? 8 : 0;
+}
+
+template <typename S>
+struct RaggedArgs {
+    const RaggedDesc* desc;
+    int64_t count;
+    const S* in;           // packed inputs
+    S* out;                // packed outputs
+    int32_t* status;       // [count], by status_idx
+    double* rel;           // [count] by status_idx, or nullptr
+    S* ws;                 // slots of slot_elems
+    int64_t slot_elems;
+    double* dws;           // FP64 partial sums, dslot per slot
+    int64_t dslot;
+    double* ws64;          // FP64 redo slots of slot64 doubles
+    int64_t slot64;
+    const S *warm_x, *warm_u, *warm_lam;   // packed like the outputs, or nullptr (cold)
+    int32_t* counter;      // work counter of this launch (zero before it)
+    int maxN, maxd;        // bounds the slots were sized for
+    int refine, fallback;
+    double cond_thr, refine_tol;
+};
+
+// plan of problem d (instance 0 of a batch of one); false if the problem
+// is malformed or larger than the slots
+template <typename S>
+__device__ __forceinline__ bool ragged_plan(const RaggedArgs<S>& a, const RaggedDesc& d, Plan& p) {
+    if (d.N < 1 || d.n < 1 || d.m < 1 || d.N > a.maxN || d.n > a.maxd || d.m > a.maxd) return false;
+    p = Plan{};
+    p.batch = 1;
+    plan_records(p, d.N, d.n, d.m);
+    p.cond_thr = a.cond_thr;
+    p.refine_tol = a.refine_tol;
+    p.fallback = a.fallback;
+    return p.stride <= a.slot_elems && p.dstride + 1 <= a.dslot;
+}
+
+template <typename S>
+__device__ __forceinline__ In<S> ragged_in(const RaggedArgs<S>& a, const RaggedDesc& d) {
+    return In<S>{a.in + d.in_off[0], a.in + d.in_off[1], a.in + d.in_off[2], a.in + d.in_off[3], a.in + d.in_off[4],
+                 a.in + d.in_off[5], a.in + d.in_off[6], a.in + d.in_off[7], a.in + d.in_off[8]};
+}
+
+// the next problem index of this workgroup's loop (same value in every thread)
+__device__ __forceinline__ int64_t ragged_next(int32_t* counter, int64_t* sh) {
+    __syncthreads();
+    if (threadIdx.x == 0) *sh = atomicAdd(counter, 1);
+    __syncthreads();
+    return *sh;
+}
+
+template <typename S, class E, class E64>
+__global__ __launch_bounds__(64 * fused_waves<E>()) void k_ragged_fused(RaggedArgs<S> a) {
+    __shared__ FusedLds<E, E64> F[fused_waves<E>()];
+    __shared__ double sh_rel;
+    __shared__ int64_t sh_i;
+    S* slot = a.ws + (int64_t)blockIdx.x * a.slot_elems;
+    double* dslot = a.dws + (int64_t)blockIdx.x * a.dslot;
+    for (int64_t i = ragged_next(a.counter, &sh_i); i < a.count; i = ragged_next(a.counter, &sh_i)) {
+        const RaggedDesc d = a.desc[i];
+        if (d.status_idx < 0 || d.status_idx >= a.count || wave_class(d.n, d.m) != E::TS) continue;
+        Plan p;
+        if (!ragged_plan(a, d, p)) continue;
+        const Out<S> out{a.out + d.out_off[0], a.out + d.out_off[1], a.out + d.out_off[2], a.status + d.status_idx};
+        const Warm<S> warm = a.warm_x ? Warm<S>{a.warm_x + d.out_off[0], a.warm_u + d.out_off[1],
+                                                a.warm_lam + d.out_off[2]}
+                                      : Warm<S>{nullptr, nullptr, nullptr};
+        fused_body<S, E, E64, E::TS>(F, sh_rel, p, ragged_in(a, d), out, slot, dslot,
+                                     a.rel ? a.rel + d.status_idx : nullptr, warm, a.refine, 0);
+    }
+}
+
+// FP64 redo of the marked problems of one class (as k_redo), then the FP64
+// residual of the new solution
+template <typename S, class E64>
+__global__ __launch_bounds__(64) void k_ragged_redo(RaggedArgs<S> a) {
+    __shared__ Lds3<E64> L;
+    __shared__ ResidLds<E64> RL;
+    __shared__ int64_t sh_i;
+    double* slot64 = a.ws64 + (int64_t)blockIdx.x * a.slot64;
+    double* dslot = a.dws + (int64_t)blockIdx.x * a.dslot;
+    for (int64_t i = ragged_next(a.counter, &sh_i); i < a.count; i = ragged_next(a.counter, &sh_i)) {
+        const RaggedDesc d = a.desc[i];
+        if (d.status_idx < 0 || d.status_idx >= a.count || wave_class(d.n, d.m) != E64::TS) continue;
+        if (!(a.status[d.status_idx] & 8)) continue;
+        Plan p;
+        if (!ragged_plan(a, d, p)) continue;
+        Plan r = p;
+        redo_records(r);
+        if (r.stride > a.slot64) continue;
+        const In<S> in = ragged_in(a, d);
+        const Out<S> out{a.out + d.out_off[0], a.out + d.out_off[1], a.out + d.out_off[2], a.status + d.status_idx};
+        wg_sync();
+        if (threadIdx.x == 0) *out.status = 8;
+        plain_body<S, double, E64, E64::TS>(L, r, in, out, slot64, 0);
+        wg_sync();
+        if (a.rel)
+            resid_inst_body<S, E64, false>(RL, p, in, out.x, out.u, out.lam, (S*)nullptr, dslot, a.rel + d.status_idx,
+                                           (int32_t*)nullptr, p.refine_tol, (const int32_t*)nullptr, 0);
+    }
+}
+
+// status words of the problems no class launch takes (malformed sizes,
+// orders above the wavefront classes, larger than the slots): bit 16
+template <typename S>
+__global__ void k_ragged_check(RaggedArgs<S> a) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.count) return;
+    const RaggedDesc d = a.desc[i];
+    if (d.status_idx < 0 || d.status_idx >= a.count) return;
+    Plan p;
+    const bool ok = wave_class(d.n, d.m) != 0 && ragged_plan(a, d, p);
+    a.status[d.status_idx] = ok ? 0 : 16;
+    if (!ok && a.rel) a.rel[d.status_idx] = -1.0;
 }
 
 }  // namespace lqr

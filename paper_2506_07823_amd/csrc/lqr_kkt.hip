@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <algorithm>
+#include <cstddef>
 #include <cstring>
 #include <string>
 #include <map>
@@ -60,22 +61,6 @@ LQR_DECLARE_RUNS(32)
 
 namespace {
 
-Tree make_tree(int leaves) {
-    Tree t;
-    std::memset(&t, 0, sizeof t);
-    t.nlev = 1;
-    t.cnt[0] = leaves;
-    t.off[0] = 0;
-    t.total = leaves;
-    while (t.cnt[t.nlev - 1] > 1) {
-        t.cnt[t.nlev] = (t.cnt[t.nlev - 1] + 1) / 2;
-        t.off[t.nlev] = t.total;
-        t.total += t.cnt[t.nlev];
-        ++t.nlev;
-    }
-    return t;
-}
-
 // padded-order class: TS = ceil(max(n, m) / 8) for the wavefront engine
 // (orders up to 64), the large-block engine (kBigTS) up to kMaxDim
 constexpr int kTS[] = {1, 2, 3, 4, 5, 6, 8};
@@ -108,38 +93,11 @@ constexpr int kBigGrid = 512;
 // slots of the FP64 redo of marked instances
 constexpr int kRedoSlots = 128;
 
-int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
-
 Plan make_plan(int64_t batch, int N, int n, int m, size_t esize, const lqr_opts& o, const Tuning* tun = nullptr) {
     Plan p;
     std::memset(&p, 0, sizeof p);
     p.batch = batch;
-    p.N = N; p.n = n; p.m = m;
-    const int64_t nn = (int64_t)n * n;
-    p.rec = (int)(3 * nn + 2 * n);
-    p.srec = (int)(nn + n);
-    p.frec = (int)(nn + n);
-    p.rt = make_tree(N + 1);
-    p.ft = make_tree(N);
-    int64_t off = 0;
-    auto sec = [&](int64_t count) { int64_t o = off; off = align_up(off + count, 64); return o; };
-    p.o_tree = sec((int64_t)p.rt.total * p.rec);
-    p.o_suf = sec((int64_t)p.rt.total * p.srec);
-    p.o_K = sec((int64_t)N * m * n);
-    p.o_kff = sec((int64_t)N * m);
-    p.o_LG = sec((int64_t)N * m * m);
-    p.o_ftree = sec((int64_t)p.ft.total * p.frec);
-    p.o_xs = sec((int64_t)p.ft.total * n);
-    p.o_w = sec((int64_t)p.ft.total * n);
-    p.o_pend = sec((int64_t)p.ft.total * n);
-    p.o_cp = sec((int64_t)N * n);
-    p.o_qp = sec((int64_t)(N + 1) * n);
-    p.o_rp = sec((int64_t)N * m);
-    p.o_x0p = sec(n);
-    p.o_pp = sec((int64_t)(N + 1) * n);
-    p.o_kffp = sec((int64_t)N * m);
-    p.stride = off;
-    p.dstride = 2 * (N + 1);
+    plan_records(p, N, n, m);
     p.cond_thr = o.cond_threshold;
     p.refine_tol = o.refine_tol;
     p.active = nullptr;
@@ -186,12 +144,7 @@ Plan make_plan(int64_t batch, int N, int n, int m, size_t esize, const lqr_opts&
 Plan make_redo_plan(const Plan& p, bool big, int64_t& slots, size_t& bytes) {
     Plan r = p;
     r.active = nullptr;
-    int64_t off = 0;
-    auto sec = [&](int64_t count) { int64_t o = off; off = align_up(off + count, 64); return o; };
-    r.o_suf = sec((int64_t)(p.N + 1) * p.srec);
-    r.o_K = sec((int64_t)p.N * p.m * p.n);
-    r.o_kff = sec((int64_t)p.N * p.m);
-    r.stride = off;
+    redo_records(r);
     slots = std::min<int64_t>(p.batch, kRedoSlots);
     r.big_grid = (int)slots;
     bytes = (size_t)(slots * r.stride * 8);
@@ -284,7 +237,7 @@ const char* const kFamNames[F_COUNT] = {
     "clear", "element", "up", "root", "down", "policy", "fwd_up", "fwd_root", "fwd_down", "recover", "residual",
     "ref_d", "bwd_up", "bwd_root", "bwd_down", "ref_kff", "fwd_up_vec", "recover_add", "reduce", "plain_riccati",
     "fwd_inst", "refine_inst", "warm_copy", "ragged_pack", "fused_solve", "tail_sweep", "tail_root",
-    "tail_sweep_up0", "chunk_up", "chunk_mid", "chunk_down", "fwd_seq", "refine_seq", "fp64_redo", "mark_redo"};
+    "tail_sweep_up0", "chunk_up", "chunk_mid", "chunk_down", "fwd_seq", "refine_seq", "fp64_redo", "mark_redo", "ragged_solve"};
 
 // Per-handle launch timer: two HIP events around every launch, read back by
 // lqr_timing_report.
@@ -794,6 +747,141 @@ const Tuning* lqr_handle_s::find(int64_t batch, int N, int n, int m, int dtype) 
 }
 
 extern "C" {
+
+static_assert(sizeof(lqr_problem_desc) == sizeof(RaggedDesc), "descriptor layout");
+static_assert(offsetof(lqr_problem_desc, in_off) == offsetof(RaggedDesc, in_off), "descriptor layout");
+static_assert(offsetof(lqr_problem_desc, out_off) == offsetof(RaggedDesc, out_off), "descriptor layout");
+
+}  // extern "C"
+
+namespace {
+// workspace of a device-descriptor ragged call: work counters | slots of
+// records | FP64 partial sums per slot | FP64 redo slots
+struct DevRaggedLayout {
+    int64_t slot_elems, dslot, slot64, redo_slots;
+    size_t cnt_off, rec_off, dbl_off, redo_off, total;
+};
+
+int dev_ragged_layout(int64_t count, int slots, int maxN, int maxd, const lqr_opts& o, DevRaggedLayout& l) {
+    if (count < 1 || count > 0x7fffffff) return fail(LQR_EINVAL, "count must be in 1..2^31-1");
+    if (slots < 1 || slots > 65536) return fail(LQR_EINVAL, "slots must be in 1..65536 (got %d)", slots);
+    if (maxN < 1 || maxN + 1 > (1 << (LQR_MAXLEV - 2))) return fail(LQR_EINVAL, "bad maxN %d", maxN);
+    if (maxd < 1 || maxd > 64) return fail(LQR_EINVAL, "maxd must be in 1..64 (the wavefront classes; got %d)", maxd);
+    if (o.dtype != LQR_F32 && o.dtype != LQR_F64) return fail(LQR_EINVAL, "bad dtype %d", o.dtype);
+    const size_t es = o.dtype == LQR_F32 ? 4 : 8;
+    Plan p;
+    std::memset(&p, 0, sizeof p);
+    plan_records(p, maxN, maxd, maxd);
+    l.slot_elems = p.stride;
+    l.dslot = align_up(p.dstride + 1, 8);
+    Plan r = p;
+    redo_records(r);
+    l.slot64 = r.stride;
+    l.redo_slots = (o.dtype == LQR_F32 && o.fallback) ? std::min<int64_t>(slots, kRedoSlots) : 0;
+    l.cnt_off = 0;
+    l.rec_off = 256;
+    l.dbl_off = l.rec_off + (size_t)align_up((int64_t)slots * l.slot_elems * (int64_t)es, 256);
+    l.redo_off = l.dbl_off + (size_t)align_up((int64_t)slots * l.dslot * 8, 256);
+    l.total = l.redo_off + (size_t)align_up(l.redo_slots * l.slot64 * 8, 256);
+    return LQR_OK;
+}
+
+template <typename S>
+int solve_ragged_dev(hipStream_t s, int64_t count, const lqr_problem_desc* descs, const void* in, void* out,
+                     int32_t* status, int slots, int maxN, int maxd, char* ws, const DevRaggedLayout& l,
+                     const lqr_opts& o) {
+    RaggedArgs<S> a;
+    std::memset(&a, 0, sizeof a);
+    a.desc = reinterpret_cast<const RaggedDesc*>(descs);
+    a.count = count;
+    a.in = (const S*)in;
+    a.out = (S*)out;
+    a.status = status;
+    a.rel = o.resid_out;
+    a.ws = (S*)(ws + l.rec_off);
+    a.slot_elems = l.slot_elems;
+    a.dws = (double*)(ws + l.dbl_off);
+    a.dslot = l.dslot;
+    a.ws64 = (double*)(ws + l.redo_off);
+    a.slot64 = l.slot64;
+    a.warm_x = (const S*)o.warm_x;
+    a.warm_u = (const S*)o.warm_u;
+    a.warm_lam = (const S*)o.warm_lam;
+    a.maxN = maxN;
+    a.maxd = maxd;
+    a.refine = o.refine_sweeps;
+    a.fallback = sizeof(S) == 4 ? o.fallback : 0;
+    a.cond_thr = o.cond_threshold;
+    a.refine_tol = o.refine_tol;
+    int32_t* counters = (int32_t*)(ws + l.cnt_off);
+    LCHK(launch_nt(256, F_CLEAR, 0, 0, k_clear<int32_t>, 1, s, counters, (int64_t)64));
+    LCHK(launch_nt(256, F_CLEAR, 0, 0, k_ragged_check<S>, (count + 255) / 256, s, a));
+    const int rs = (int)l.redo_slots;
+    const int classes[] = {1, 2, 3, 4, 5, 6, 8};
+    for (int ci = 0; ci < 7; ++ci) {
+        int32_t* c = counters + 2 * ci;
+        int rc;
+        switch (classes[ci]) {
+            case 1: rc = run_ragged<S, 1>(s, a, slots, rs, c); break;
+            case 2: rc = run_ragged<S, 2>(s, a, slots, rs, c); break;
+            case 3: rc = run_ragged<S, 3>(s, a, slots, rs, c); break;
+            case 4: rc = run_ragged<S, 4>(s, a, slots, rs, c); break;
+            case 5: rc = run_ragged<S, 5>(s, a, slots, rs, c); break;
+            case 6: rc = run_ragged<S, 6>(s, a, slots, rs, c); break;
+            default: rc = run_ragged<S, 8>(s, a, slots, rs, c); break;
+        }
+        LCHK(rc);
+    }
+    return LQR_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int lqr_ragged_dev_workspace_size(int64_t count, int32_t slots, int32_t maxN, int32_t maxd, const lqr_opts* opts,
+                                  size_t* bytes) {
+    if (!bytes) return fail(LQR_EINVAL, "null output pointer");
+    lqr_opts o;
+    if (opts) o = *opts; else lqr_opts_default(&o, LQR_F32);
+    DevRaggedLayout l;
+    LCHK(dev_ragged_layout(count, slots, maxN, maxd, o, l));
+    *bytes = l.total;
+    return LQR_OK;
+}
+
+int lqr_kkt_solve_ragged_dev(lqr_handle_t h, void* stream, int64_t count, const lqr_problem_desc* descs,
+                             const void* in, void* out, int32_t* status, int32_t slots, int32_t maxN, int32_t maxd,
+                             void* workspace, size_t workspace_bytes, const lqr_opts* opts) {
+    if (!h) return fail(LQR_EINVAL, "null handle");
+    lqr_opts o;
+    if (opts) o = *opts; else lqr_opts_default(&o, LQR_F32);
+    if (o.method != LQR_METHOD_SCAN) return fail(LQR_EINVAL, "the ragged persistent solve is the scan method");
+    if (o.refine_sweeps < 0 || o.refine_sweeps > 4) return fail(LQR_EINVAL, "refine_sweeps must be in 0..4");
+    if (!(o.refine_tol > 0.0) || !(o.cond_threshold > 1.0)) return fail(LQR_EINVAL, "bad refine_tol / cond_threshold");
+    DevRaggedLayout l;
+    LCHK(dev_ragged_layout(count, slots, maxN, maxd, o, l));
+    const size_t es = o.dtype == LQR_F32 ? 4 : 8;
+    if (!descs || !in || !out || !status || !workspace) return fail(LQR_EINVAL, "null pointer argument");
+    if (!aligned(descs, 8) || !aligned(in, es) || !aligned(out, es) || !aligned(status, 4) || !aligned(workspace, 256))
+        return fail(LQR_EINVAL, "misaligned argument");
+    if (o.resid_out && !aligned(o.resid_out, 8)) return fail(LQR_EINVAL, "misaligned resid_out");
+    const bool has_warm = o.warm_x || o.warm_u || o.warm_lam;
+    if (has_warm && (!o.warm_x || !o.warm_u || !o.warm_lam)) return fail(LQR_EINVAL, "warm start needs x, u and lam");
+    if (workspace_bytes < l.total)
+        return fail(LQR_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", workspace_bytes, l.total);
+    HIPCHK(hipSetDevice(h->device));
+    hipStream_t s = (hipStream_t)stream;
+    int rc;
+    {
+        TimerScope ts_scope(h->timing ? &h->timer : nullptr);
+        rc = o.dtype == LQR_F32 ? solve_ragged_dev<float>(s, count, descs, in, out, status, slots, maxN, maxd,
+                                                          (char*)workspace, l, o)
+                                : solve_ragged_dev<double>(s, count, descs, in, out, status, slots, maxN, maxd,
+                                                           (char*)workspace, l, o);
+    }
+    if (rc != LQR_OK || !o.sync_status) return rc;
+    return sync_status_check(s, status, count);
+}
 
 int lqr_set_tuning(lqr_handle_t h, int64_t batch, int N, int n, int m, int32_t dtype, const lqr_tuning* t) {
     if (!h) return fail(LQR_EINVAL, "null handle");

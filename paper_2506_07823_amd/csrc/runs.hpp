@@ -51,7 +51,7 @@ enum Fam {
     F_CLEAR, F_ELEM, F_UP, F_ROOT, F_DOWN, F_POLICY, F_FUP, F_FROOT, F_FDOWN, F_RECOVER, F_RESID, F_REF_D, F_BUP,
     F_BROOT, F_BDOWN, F_REF_KFF, F_FUPV, F_RECOVER_ADD, F_REDUCE, F_PLAIN, F_FWD_INST, F_REFINE_INST, F_WARM, F_PACK,
     F_FUSED, F_TAIL, F_TROOT, F_TAIL_UP0, F_CHUNK_UP, F_CHUNK_MID, F_CHUNK_DOWN, F_FWD_SEQ, F_REFINE_SEQ, F_REDO,
-    F_MARK, F_COUNT
+    F_MARK, F_RAGGED, F_COUNT
 };
 
 // Optional per-launch timer (HIP events around each launch on its stream),
@@ -443,6 +443,28 @@ int run_resid(const Plan& p, hipStream_t s, const In<S>& in, const S* x, const S
     return LQR_OK;
 }
 
+// Ragged batch from a device descriptor table, the problems of one padded
+// order class: the persistent one-launch solve over `slots` workgroups,
+// then the FP64 redo of the problems it marked (ragged_redo_slots workgroups).
+template <typename S, int TS>
+int run_ragged(hipStream_t s, const RaggedArgs<S>& a, int slots, int redo_slots, int32_t* counters) {
+    if constexpr (TS == kBigTS) {
+        return fail(LQR_EUNSUPPORTED, "the ragged persistent solve runs on the wavefront engine");
+    } else {
+        using E = EngOf<S, TS>;
+        using E64 = EngOf<double, TS>;
+        RaggedArgs<S> af = a;
+        af.counter = counters;
+        LCHK(launch_nt(64 * fused_waves<E>(), F_RAGGED, 0, 0, k_ragged_fused<S, E, E64>, slots, s, af));
+        if (a.fallback && redo_slots > 0) {
+            RaggedArgs<S> ar = a;
+            ar.counter = counters + 1;
+            LCHK(launch_nt(64, F_REDO, 0, 0, k_ragged_redo<S, E64>, redo_slots, s, ar));
+        }
+        return LQR_OK;
+    }
+}
+
 // explicit instantiation per (padded-order class, storage type): each pair
 // is its own translation unit (inst.hip), so the classes compile in parallel
 #define LQR_RUNS(PREFIX, TSV, SV)                                                                              \
@@ -451,7 +473,8 @@ int run_resid(const Plan& p, hipStream_t s, const In<S>& in, const S* x, const S
     PREFIX template int run_plain<SV, TSV>(const Plan&, hipStream_t, const In<SV>&, const Out<SV>&, SV*,        \
                                            const Ctx&, double*);                                               \
     PREFIX template int run_resid<SV, TSV>(const Plan&, hipStream_t, const In<SV>&, const SV*, const SV*,       \
-                                           const SV*, SV*, double*, double*);
+                                           const SV*, SV*, double*, double*);                                  \
+    PREFIX template int run_ragged<SV, TSV>(hipStream_t, const RaggedArgs<SV>&, int, int, int32_t*);
 
 #define LQR_DECLARE_RUNS(TSV) LQR_RUNS(extern, TSV, float) LQR_RUNS(extern, TSV, double)
 #define LQR_DEFINE_RUNS(TSV, SV) LQR_RUNS(, TSV, SV)

@@ -13,11 +13,12 @@ OUTS = ("x", "u", "lam")
 # Element-wise gates (see elem_err): FP64 paths against the FP64 oracle, and
 # the FP32 path (FP32 storage of inputs and results, one FP64-residual
 # refinement sweep) against the oracle solved on the same FP32-rounded
-# inputs.  The FP32 bound follows from the FP32 storage of the result
-# (relative rounding 6e-8 per entry) times the conditioning of the KKT
-# system of these instances (up to ~1e3), with a margin of ~10.
+# inputs.  After the sweep the solve error is below the FP32 rounding of the
+# stored result (6e-8 relative per entry) times the conditioning of these
+# KKT systems (up to ~10 at the scale of elem_err): measured at most 6.3e-7
+# over every FP32 test instance; the gate is that times ~8.
 FP64_ELEM_TOL = 1e-9
-FP32_ELEM_TOL = 5e-4
+FP32_ELEM_TOL = 5e-6
 RESID_TOL = 1e-5
 
 
