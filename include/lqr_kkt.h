@@ -153,6 +153,25 @@ int lqr_kkt_solve(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int
                   const void* x0, void* x, void* u, void* lam, int32_t* status,
                   void* workspace, size_t workspace_bytes, const lqr_opts* opts);
 
+/* Re-solve with cached factors (the real-time-iteration pattern of Sec. II-F,
+ * where successive subproblems of a stream often differ only in their
+ * linear terms): same arguments as lqr_kkt_solve, where A, B, Q, R, M must be
+ * the matrices of the last LQR_METHOD_SCAN lqr_kkt_solve of this shape on
+ * this handle and this `workspace` (nothing else may have used it since),
+ * and only x0, c, q, r may have changed.  The value function, policy and
+ * closed-loop matrices that solve left in the workspace are reused: one
+ * backward sweep of the gradient recursion of eq. (lqr) with the policy
+ * fixed and one forward sweep per instance, O(N n^2) instead of O(N n^3),
+ * then the FP64-residual refinement sweeps of opts (the matrices are read for
+ * the residual).  On entry `status` must hold that solve's status words: an
+ * instance with bit 8 (solved by the FP64 fallback) is solved again whole
+ * in FP64, the others keep their bits.  Warm starts are not accepted. */
+int lqr_kkt_resolve(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int m,
+                    const void* A, const void* B, const void* c, const void* Q,
+                    const void* R, const void* M, const void* q, const void* r,
+                    const void* x0, void* x, void* u, void* lam, int32_t* status,
+                    void* workspace, size_t workspace_bytes, const lqr_opts* opts);
+
 /* lqr_kkt_solve without a workspace argument, for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving
  * loops, harnesses that forbid allocation).  The workspace is a fixed array

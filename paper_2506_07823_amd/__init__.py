@@ -82,6 +82,8 @@ _lib.lqr_workspace_size.restype = ctypes.c_int
 _lib.lqr_kkt_solve.argtypes = [_vp, _vp, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int] + [_vp] * 9 + \
     [_vp, _vp, _vp, _vp, _vp, _sz, ctypes.POINTER(lqr_opts)]
 _lib.lqr_kkt_solve.restype = ctypes.c_int
+_lib.lqr_kkt_resolve.argtypes = _lib.lqr_kkt_solve.argtypes
+_lib.lqr_kkt_resolve.restype = ctypes.c_int
 _lib.lqr_kkt_solve_noalloc.argtypes = [_vp, _vp, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int] + [_vp] * 9 + \
     [_vp, _vp, _vp, _vp, ctypes.POINTER(lqr_opts)]
 _lib.lqr_kkt_solve_noalloc.restype = ctypes.c_int
@@ -133,6 +135,7 @@ lqr_destroy = _lib.lqr_destroy
 lqr_workspace_size = _lib.lqr_workspace_size
 lqr_kkt_solve = _lib.lqr_kkt_solve
 lqr_kkt_solve_noalloc = _lib.lqr_kkt_solve_noalloc
+lqr_kkt_resolve = _lib.lqr_kkt_resolve
 lqr_noalloc_workspace_bytes = _lib.lqr_noalloc_workspace_bytes
 lqr_kkt_residual = _lib.lqr_kkt_residual
 lqr_max_dim = _lib.lqr_max_dim
@@ -284,6 +287,34 @@ def solve(A, B, c, Q, R, M, q, r, x0, *, method: str = "scan", refine: int | Non
                             out["x"].data_ptr(), out["u"].data_ptr(), out["lam"].data_ptr(),
                             out["status"].data_ptr(), wbuf.data_ptr(), wbuf.numel(), ctypes.byref(o))
     _check(rc)
+    return out
+
+
+def resolve(A, B, c, Q, R, M, q, r, x0, *, out, workspace: Workspace, refine: int | None = None,
+            want_resid: bool = False, stream=None):
+    """lqr_kkt_resolve: re-solve with the factors the last scan solve of
+    these matrices left in `workspace` (only x0, c, q, r changed).  `out` is
+    that solve's output dict: its status words enter the call (instances
+    the FP64 fallback solved are solved again in FP64), and x, u, lam (and
+    resid) are overwritten."""
+    d = dict(A=A, B=B, c=c, Q=Q, R=R, M=M, q=q, r=r, x0=x0)
+    dtype = A.dtype
+    device = A.device.index
+    batch, N, n, m = dims_of(A, B)
+    _validate(d, dtype, device)
+    _expect_shapes(d, batch, N, n, m)
+    o = default_opts(dtype)
+    if refine is not None:
+        o.refine_sweeps = int(refine)
+    if want_resid:
+        if "resid" not in out:
+            out["resid"] = torch.empty((batch,), dtype=torch.float64, device=A.device)
+        o.resid_out = out["resid"].data_ptr()
+    s = (stream or torch.cuda.current_stream(device)).cuda_stream
+    _check(_lib.lqr_kkt_resolve(handle(device), s, batch, N, n, m, *[d[k].data_ptr() for k in FIELDS],
+                                out["x"].data_ptr(), out["u"].data_ptr(), out["lam"].data_ptr(),
+                                out["status"].data_ptr(), workspace.buf.data_ptr(), workspace.buf.numel(),
+                                ctypes.byref(o)))
     return out
 
 

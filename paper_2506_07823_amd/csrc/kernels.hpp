@@ -1384,7 +1384,7 @@ __device__ __forceinline__ typename E::T g_solve(const E& e, const S* LG, int m,
 // x_0 = x0, x_{k+1} = Abar_k x_k + bbar_k (eq. (controlled_dynamics)),
 // u_k = K_k x_k + k_k, lambda_k = P_k x_k + p_k.  ADD: the refinement's
 // correction (p' and k' from the backward sweep) is added to the outputs.
-template <typename S, class E, bool ADD, class LT>
+template <typename S, class E, bool ADD, class LT, bool ALT = ADD>
 __device__ __forceinline__ void fwd_seq_body(LT& L, const Plan& p, S* ws, const S* x0, const Out<S>& out, int64_t b) {
     using T = typename E::T;
     const E e(unit_tid<E::NT>());
@@ -1394,7 +1394,7 @@ __device__ __forceinline__ void fwd_seq_body(LT& L, const Plan& p, S* ws, const 
     bool fin = true;
     for (int k = 0; k <= N; ++k) {
         const S* Pk = inst + p.o_suf + (int64_t)suffix_id(p.rt, 0, k) * p.srec;
-        const S* pv = ADD ? inst + p.o_pp + (int64_t)k * n : Pk + nn;
+        const S* pv = ALT ? inst + p.o_pp + (int64_t)k * n : Pk + nn;
         const T lam = e.template gmv<false>(Pk, n, n, n, x, L.vb[0]) + e.vload(pv, n);
         S* xo = out.x + (b * (N + 1) + k) * n;
         S* lo = out.lam + (b * (N + 1) + k) * n;
@@ -1406,7 +1406,7 @@ __device__ __forceinline__ void fwd_seq_body(LT& L, const Plan& p, S* ws, const 
             fin = fin && finite_(xv) && finite_(lv);
         }
         if (k == N) break;
-        const S* kf = inst + (ADD ? p.o_kffp : p.o_kff) + (int64_t)k * m;
+        const S* kf = inst + (ALT ? p.o_kffp : p.o_kff) + (int64_t)k * m;
         const T u = e.template gmv<false>(inst + p.o_K + (int64_t)k * m * n, m, n, n, x, L.vb[1]) + e.vload(kf, m);
         S* uo = out.u + (b * N + k) * m;
         if (e.lg < m) {
@@ -1427,33 +1427,32 @@ __global__ __launch_bounds__(E::NT) void k_fwd_seq(Plan p, S* ws, const S* x0, O
     fwd_seq_body<S, E, false>(L, p, ws, x0 + b * p.n, out, b);
 }
 
-// One refinement sweep of instance b with the factors of the first solve
-// (after the FP64 residual pass wrote c', q', r', x0'): the gradient
-// recursion of eq. (lqr) with the policy fixed, backward,
+// Backward sweep of the gradient recursion of eq. (lqr) with the policy of
+// the first solve fixed, for right-hand sides (c', q', r') read from the
+// workspace's refinement area (RHS_IN false) or from the inputs (true):
 //   v = p'_{k+1} + P_{k+1} c'_k,  k'_k = -G_k^{-1}(B_k' v + r'_k),
 //   p'_k = Abar_k' v + K_k' r'_k + q'_k,
-// the correction's closed-loop offsets B_k k'_k + c'_k written over the leaf
-// vectors, then the forward sweep of the correction, added to the outputs.
-template <typename S, class E, class LT>
-__device__ __forceinline__ void refine_seq_body(LT& L, const Plan& p, const In<S>& in, S* ws, const Out<S>& out,
-                                                int64_t b) {
+// storing p'_k, k'_k and the closed-loop offsets B_k k'_k + c'_k over the
+// leaf vectors.
+template <typename S, class E, bool RHS_IN, class LT>
+__device__ __forceinline__ void bwd_seq_body(LT& L, const Plan& p, const In<S>& in, S* ws, int64_t b) {
     using T = typename E::T;
     const E e(unit_tid<E::NT>());
     const int N = p.N, n = p.n, m = p.m, nn = n * n;
     const Ptr<S> P(p, in);
     S* inst = ws + b * p.stride;
-    T pn = e.vload(inst + p.o_qp + (int64_t)N * n, n);
+    auto qv = [&](int k) { return RHS_IN ? P.q(b, k) : (const S*)(inst + p.o_qp + (int64_t)k * n); };
+    T pn = e.vload(qv(N), n);
     e.vstore(inst + p.o_pp + (int64_t)N * n, n, pn);
     for (int k = N - 1; k >= 0; --k) {
         const S* Pn = inst + p.o_suf + (int64_t)suffix_id(p.rt, 0, k + 1) * p.srec;
         S* leaf = inst + p.o_ftree + (int64_t)k * p.frec;
-        const T cpv = e.vload(inst + p.o_cp + (int64_t)k * n, n);
-        const T rpv = e.vload(inst + p.o_rp + (int64_t)k * m, m);
+        const T cpv = e.vload(RHS_IN ? P.c(b, k) : (const S*)(inst + p.o_cp + (int64_t)k * n), n);
+        const T rpv = e.vload(RHS_IN ? P.r(b, k) : (const S*)(inst + p.o_rp + (int64_t)k * m), m);
         const T v = pn + e.template gmv<false>(Pn, n, n, n, cpv, L.vb[0]);
         const T h = e.template gmv<true>(P.B(b, k), n, m, m, v, L.vb[1]) + rpv;
         pn = e.template gmv<true>(leaf, n, n, n, v, L.vb[0]) +
-             e.template gmv<true>(inst + p.o_K + (int64_t)k * m * n, m, n, n, rpv, L.vb[1]) +
-             e.vload(inst + p.o_qp + (int64_t)k * n, n);
+             e.template gmv<true>(inst + p.o_K + (int64_t)k * m * n, m, n, n, rpv, L.vb[1]) + e.vload(qv(k), n);
         e.vstore(inst + p.o_pp + (int64_t)k * n, n, pn);
         const T kf = -g_solve(e, inst + p.o_LG + (int64_t)k * m * m, m, h, L.vb[0], L.vb[1]);
         e.vstore(inst + p.o_kffp + (int64_t)k * m, m, kf);
@@ -1461,7 +1460,17 @@ __device__ __forceinline__ void refine_seq_body(LT& L, const Plan& p, const In<S
         e.vstore(leaf + nn, n, bb);
         E::sync();
     }
-    fwd_seq_body<S, E, true>(L, p, ws, (const S*)(inst + p.o_x0p), out, b);
+}
+
+// One refinement sweep of instance b with the factors of the first solve
+// (after the FP64 residual pass wrote c', q', r', x0'): the backward sweep
+// above on the correction data, then the forward sweep of the correction,
+// added to the outputs.
+template <typename S, class E, class LT>
+__device__ __forceinline__ void refine_seq_body(LT& L, const Plan& p, const In<S>& in, S* ws, const Out<S>& out,
+                                                int64_t b) {
+    bwd_seq_body<S, E, false>(L, p, in, ws, b);
+    fwd_seq_body<S, E, true>(L, p, ws, (const S*)(ws + b * p.stride + p.o_x0p), out, b);
 }
 
 template <typename S, class E>
@@ -1470,6 +1479,21 @@ __global__ __launch_bounds__(E::NT) void k_refine_seq(Plan p, In<S> in, S* ws, O
     const int64_t b = blockIdx.x;
     LQR_GATE(p, b);
     refine_seq_body<S, E>(L, p, in, ws, out, b);
+}
+
+// Re-solve with the cached factors: the value function, policy and
+// closed-loop matrices of the last solve of these matrices stay in the
+// workspace, new (x0, c, q, r) come from the inputs: the backward sweep on
+// them, then the forward sweep.  O(N n^2) per instance.  Instances the last
+// solve sent to the FP64 redo (status bit 8) are skipped here (their FP32
+// factors are not usable; the redo launch solves them again).
+template <typename S, class E>
+__global__ __launch_bounds__(E::NT) void k_resolve_seq(Plan p, In<S> in, S* ws, Out<S> out) {
+    __shared__ VecLds<E> L;
+    const int64_t b = blockIdx.x;
+    if (out.status[b] & 8) return;
+    bwd_seq_body<S, E, true>(L, p, in, ws, b);
+    fwd_seq_body<S, E, false, VecLds<E>, true>(L, p, ws, in.x0 + b * p.n, out, b);
 }
 
 // relative KKT residual of instance b from its per-stage partial sums

@@ -203,6 +203,9 @@ bool sched_fits(const Plan& p) {
     return true;
 }
 
+// internal method code of lqr_kkt_resolve
+constexpr int kResolve = -1;
+
 template <typename S>
 int dispatch(int ts, int method, const Plan& p, hipStream_t s, const In<S>& in, const Out<S>& out, S* ws,
              const Ctx& cx, int refine, double* resid_out, const Warm<S>& warm) {
@@ -210,7 +213,8 @@ int dispatch(int ts, int method, const Plan& p, hipStream_t s, const In<S>& in, 
     case TSV:                                                                            \
         return method == LQR_METHOD_SCAN                                                 \
                    ? run_scan<S, TSV>(p, s, in, out, ws, cx, refine, resid_out, warm)    \
-                   : run_plain<S, TSV>(p, s, in, out, ws, cx, resid_out);
+                   : method == kResolve ? run_resolve<S, TSV>(p, s, in, out, ws, cx, refine, resid_out) \
+                                        : run_plain<S, TSV>(p, s, in, out, ws, cx, resid_out);
     switch (ts) {
         LQR_CASE(1) LQR_CASE(2) LQR_CASE(3) LQR_CASE(4) LQR_CASE(5) LQR_CASE(6) LQR_CASE(8) LQR_CASE(32)
         default: return fail(LQR_EUNSUPPORTED, "no shape class for TS=%d", ts);
@@ -237,7 +241,7 @@ const char* const kFamNames[F_COUNT] = {
     "clear", "element", "up", "root", "down", "policy", "fwd_up", "fwd_root", "fwd_down", "recover", "residual",
     "ref_d", "bwd_up", "bwd_root", "bwd_down", "ref_kff", "fwd_up_vec", "recover_add", "reduce", "plain_riccati",
     "fwd_inst", "refine_inst", "warm_copy", "ragged_pack", "fused_solve", "tail_sweep", "tail_root",
-    "tail_sweep_up0", "chunk_up", "chunk_mid", "chunk_down", "fwd_seq", "refine_seq", "fp64_redo", "mark_redo", "ragged_solve"};
+    "tail_sweep_up0", "chunk_up", "chunk_mid", "chunk_down", "fwd_seq", "refine_seq", "fp64_redo", "mark_redo", "ragged_solve", "resolve"};
 
 // Per-handle launch timer: two HIP events around every launch, read back by
 // lqr_timing_report.
@@ -392,7 +396,7 @@ int solve_impl(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int m,
                size_t workspace_bytes, const lqr_opts& o, const Tuning* tun) {
     LCHK(check_dims(batch, N, n, m));
     if (o.dtype != LQR_F32 && o.dtype != LQR_F64) return fail(LQR_EINVAL, "bad dtype %d", o.dtype);
-    if (o.method != LQR_METHOD_SCAN && o.method != LQR_METHOD_SEQ_RICCATI)
+    if (o.method != LQR_METHOD_SCAN && o.method != LQR_METHOD_SEQ_RICCATI && o.method != kResolve)
         return fail(LQR_EINVAL, "bad method %d", o.method);
     if (o.refine_sweeps < 0 || o.refine_sweeps > 4) return fail(LQR_EINVAL, "refine_sweeps must be in 0..4");
     if (!(o.refine_tol > 0.0)) return fail(LQR_EINVAL, "refine_tol must be > 0");
@@ -426,7 +430,7 @@ int solve_impl(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int m,
     char* wsb = (char*)workspace;
     const int ts = pick_ts(n, m, tun);
     const Ctx cx = make_ctx(p, lay, wsb, ts == kBigTS);
-    const int refine = o.method == LQR_METHOD_SCAN ? o.refine_sweeps : 0;
+    const int refine = o.method != LQR_METHOD_SEQ_RICCATI ? o.refine_sweeps : 0;
     int rc;
     {
         TimerScope ts_scope(h->timing ? &h->timer : nullptr);
@@ -458,6 +462,7 @@ int lqr_kkt_solve(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int
     if (!h) return fail(LQR_EINVAL, "null handle");
     lqr_opts o;
     if (opts) o = *opts; else lqr_opts_default(&o, LQR_F32);
+    if (o.method == kResolve) return fail(LQR_EINVAL, "bad method %d", o.method);
     return solve_impl(h, stream, batch, N, n, m, A, B, c, Q, R, M, q, r, x0, x, u, lam, status, workspace,
                       workspace_bytes, o, h->find(batch, N, n, m, o.dtype));
 }
@@ -470,6 +475,7 @@ int lqr_kkt_solve_noalloc(lqr_handle_t h, void* stream, int64_t batch, int N, in
     lqr_opts o;
     if (opts) o = *opts; else lqr_opts_default(&o, LQR_F32);
     if (o.sync_status) return fail(LQR_EINVAL, "sync_status is not available without allocation");
+    if (o.method == kResolve) return fail(LQR_EINVAL, "bad method %d", o.method);
     void* ws = g_scratch[h->device];
     if (!ws) return fail(LQR_EDEVICE, "no-allocation workspace of device %d not set up", h->device);
     LCHK(check_dims(batch, N, n, m));
@@ -482,6 +488,20 @@ int lqr_kkt_solve_noalloc(lqr_handle_t h, void* stream, int64_t batch, int N, in
                     "workspace; use lqr_kkt_solve with a caller workspace", need, kNoAllocBytes);
     return solve_impl(h, stream, batch, N, n, m, A, B, c, Q, R, M, q, r, x0, x, u, lam, status, ws, kNoAllocBytes,
                       o, tun);
+}
+
+int lqr_kkt_resolve(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int m, const void* A, const void* B,
+                    const void* c, const void* Q, const void* R, const void* M, const void* q, const void* r,
+                    const void* x0, void* x, void* u, void* lam, int32_t* status, void* workspace,
+                    size_t workspace_bytes, const lqr_opts* opts) {
+    if (!h) return fail(LQR_EINVAL, "null handle");
+    lqr_opts o;
+    if (opts) o = *opts; else lqr_opts_default(&o, LQR_F32);
+    if (o.method != LQR_METHOD_SCAN) return fail(LQR_EINVAL, "lqr_kkt_resolve reuses the factors of the scan method");
+    if (o.warm_x || o.warm_u || o.warm_lam) return fail(LQR_EINVAL, "lqr_kkt_resolve takes no warm start");
+    o.method = kResolve;
+    return solve_impl(h, stream, batch, N, n, m, A, B, c, Q, R, M, q, r, x0, x, u, lam, status, workspace,
+                      workspace_bytes, o, h->find(batch, N, n, m, o.dtype));
 }
 
 size_t lqr_noalloc_workspace_bytes(void) { return kNoAllocBytes; }

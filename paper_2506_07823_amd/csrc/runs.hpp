@@ -51,7 +51,7 @@ enum Fam {
     F_CLEAR, F_ELEM, F_UP, F_ROOT, F_DOWN, F_POLICY, F_FUP, F_FROOT, F_FDOWN, F_RECOVER, F_RESID, F_REF_D, F_BUP,
     F_BROOT, F_BDOWN, F_REF_KFF, F_FUPV, F_RECOVER_ADD, F_REDUCE, F_PLAIN, F_FWD_INST, F_REFINE_INST, F_WARM, F_PACK,
     F_FUSED, F_TAIL, F_TROOT, F_TAIL_UP0, F_CHUNK_UP, F_CHUNK_MID, F_CHUNK_DOWN, F_FWD_SEQ, F_REFINE_SEQ, F_REDO,
-    F_MARK, F_RAGGED, F_COUNT
+    F_MARK, F_RAGGED, F_RESOLVE, F_COUNT
 };
 
 // Optional per-launch timer (HIP events around each launch on its stream),
@@ -402,6 +402,47 @@ int run_scan(const Plan& p, hipStream_t s, const In<S>& in, const Out<S>& out, S
     return run_redo<S, TS>(p, s, in, out, ws, cx, resid_out);
 }
 
+// Re-solve with the factors the last scan solve of these matrices left in
+// the workspace (new x0, c, q, r): one backward + forward vector sweep per
+// instance, the FP64 residual and refinement sweeps as in run_scan, then
+// the FP64 redo of the instances the last solve marked (bit 8 of the
+// incoming status words).
+template <typename S, int TS>
+int run_resolve(const Plan& p, hipStream_t s, const In<S>& in, const Out<S>& out, S* ws, const Ctx& cx, int refine,
+                double* resid_out) {
+    using E = EngOf<S, TS>;
+    using E64 = EngOf<double, TS>;
+    constexpr int NT = E::NT;
+    const Work w(p, sizeof(S));
+    const double B = (double)p.batch;
+    const int64_t Bi = p.batch;
+    const int N = p.N;
+    int32_t* st = out.status;
+    LCHK(launch_nt(NT, F_RESOLVE, B * N * w.rseq_f(), B * N * w.rseq_b(), k_resolve_seq<S, E>, Bi, s, p, in, ws,
+                   out));
+    int32_t* active = cx.active;
+    double* rel = resid_out ? resid_out : cx.dws + Bi * p.dstride;
+    Plan pg = p;
+    const double rf = B * (N + 1) * w.resid_f(), rb = B * (N + 1) * w.resid_b();
+    for (int sw = 0; sw < refine; ++sw) {
+        const Plan& pr = sw >= 1 ? pg : p;
+        LCHK(launch_nt(NT, F_RESID, rf, rb, k_resid<S, E64, true>, Bi * (N + 1), s, pr, in, (const S*)out.x,
+                       (const S*)out.u, (const S*)out.lam, ws, cx.dws));
+        LCHK(launch_nt(WG, F_REDUCE, 0, B * 16.0 * (N + 1), k_resid_reduce<double>, (Bi + 63) / 64, s, pr,
+                       (const double*)cx.dws, rel, active, p.refine_tol, (const int32_t*)st));
+        pg.active = active;
+        LCHK(launch_nt(NT, F_REFINE_SEQ, B * N * w.rseq_f(), B * N * w.rseq_b(), k_refine_seq<S, E>, Bi, s, pg, in,
+                       ws, out));
+    }
+    if (resid_out) {
+        LCHK(launch_nt(NT, F_RESID, rf, rb, k_resid<S, E64, false>, Bi * (N + 1), s, pg, in, (const S*)out.x,
+                       (const S*)out.u, (const S*)out.lam, ws, cx.dws));
+        LCHK(launch_nt(WG, F_REDUCE, 0, B * 16.0 * (N + 1), k_resid_reduce<double>, (Bi + 63) / 64, s, pg,
+                       (const double*)cx.dws, resid_out, (int32_t*)nullptr, p.refine_tol, (const int32_t*)st));
+    }
+    return run_redo<S, TS>(p, s, in, out, ws, cx, resid_out);
+}
+
 template <typename S, int TS>
 int run_plain(const Plan& p, hipStream_t s, const In<S>& in, const Out<S>& out, S* ws, const Ctx& cx,
               double* resid_out) {
@@ -474,7 +515,9 @@ int run_ragged(hipStream_t s, const RaggedArgs<S>& a, int slots, int redo_slots,
                                            const Ctx&, double*);                                               \
     PREFIX template int run_resid<SV, TSV>(const Plan&, hipStream_t, const In<SV>&, const SV*, const SV*,       \
                                            const SV*, SV*, double*, double*);                                  \
-    PREFIX template int run_ragged<SV, TSV>(hipStream_t, const RaggedArgs<SV>&, int, int, int32_t*);
+    PREFIX template int run_ragged<SV, TSV>(hipStream_t, const RaggedArgs<SV>&, int, int, int32_t*);         \
+    PREFIX template int run_resolve<SV, TSV>(const Plan&, hipStream_t, const In<SV>&, const Out<SV>&, SV*,      \
+                                             const Ctx&, int, double*);
 
 #define LQR_DECLARE_RUNS(TSV) LQR_RUNS(extern, TSV, float) LQR_RUNS(extern, TSV, double)
 #define LQR_DEFINE_RUNS(TSV, SV) LQR_RUNS(, TSV, SV)
