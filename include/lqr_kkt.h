@@ -209,6 +209,71 @@ int lqr_kkt_residual(lqr_handle_t h, void* stream, int64_t batch, int N, int n, 
                      const void* lam, double* rel, void* workspace,
                      size_t workspace_bytes);
 
+/* QP-data builder (the step before the solve, Sec. II-F): the blocks Q, M,
+ * R, q, r of the subproblem from a nonlinear least-squares cost
+ * 1/2 eps' W eps and relaxed barriers of constraints xi(x, u) >= 0, with the
+ * Gauss-Newton approximation:
+ *   Q = Ex' W Ex + Gx' D2 Gx,  M = Ex' W Eu + Gx' D2 Gu,  R = Eu' W Eu + Gu' D2 Gu,
+ *   q = Ex' W eps + Gx' D1,    r = Eu' W eps + Gu' D1,
+ * D1 = B'(xi), D2 = diag(B''(xi)) of the relaxed barrier
+ *   B(xi) = -mu ln(xi) (xi >= delta), mu/2 (((xi - 2 delta)/delta)^2 - 1) - mu ln(delta) (xi < delta).
+ * Inputs (device, dtype, row-major, batch-major): Ex [batch][N+1][p][n],
+ * Eu [batch][N][p][m], e [batch][N+1][p] (eps at the linearization point),
+ * W [batch][N+1][p][p], Gx [batch][N+1][nc][n], Gu [batch][N][nc][m],
+ * g [batch][N+1][nc] (xi there), mu [nc], delta [nc] (per constraint, shared
+ * by every instance and stage).  Outputs in the layout of lqr_kkt_solve's
+ * Q, M, R, q, r.  nc may be 0 (the constraint arrays may then be NULL);
+ * p (n + m) must fit one workgroup's LDS (64 KiB).  Asynchronous on
+ * `stream`; needs no workspace. */
+int lqr_qp_build(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int m, int p, int nc, int32_t dtype,
+                 const void* Ex, const void* Eu, const void* e, const void* W, const void* Gx, const void* Gu,
+                 const void* g, const void* mu, const void* delta, void* Q, void* M, void* R, void* q, void* r);
+
+/* SQP iteration around the solve (Sec. II-B, II-E, II-F) on a synthetic
+ * nonlinear model with a bilinear dynamics term, standing in for the robot
+ * models:
+ *   h(x, u) = A x + B u + c + gamma (P x) .* (V u),
+ *   stage cost 1/2 sum wx_k (x_k - xr_k)^2 + 1/2 sum wu_k (u_k - ur_k)^2
+ *              + sum_j B(xi_j),  xi = Gx x + Gu u + g0 >= 0 (relaxed barrier
+ *              of lqr_qp_build, parameters mu_j, delta_j),
+ *   terminal cost without the control terms, initial state xhat0.
+ * Arrays (device, call dtype, batch-major): A [batch][n][n], B [batch][n][m],
+ * c [batch][n], P [batch][n][n], V [batch][n][m] (time-invariant per
+ * instance), xr [batch][N+1][n], ur [batch][N][m], wx [batch][N+1][n],
+ * wu [batch][N][m], Gx [batch][nc][n], Gu [batch][nc][m], g0 [batch][nc],
+ * mu [nc], delta [nc], xhat0 [batch][n]. */
+typedef struct {
+    int64_t batch;
+    int32_t N, n, m, nc;
+    double gamma;
+    const void *A, *B, *c, *P, *V, *xr, *ur, *wx, *wu, *Gx, *Gu, *g0, *mu, *delta, *xhat0;
+} lqr_bilinear_model;
+
+/* `iters` SQP iterations from the iterate (x [batch][N+1][n], u [batch][N][m],
+ * lam [batch][N+1][n]; updated in place), each: linearize the dynamics and
+ * the cost at the iterate (dynamics Jacobians, defects c_k = h(x_k, u_k) -
+ * x_{k+1}, Gauss-Newton blocks by the QP-data builder), solve the
+ * subproblem with lqr_kkt_solve's scan (opts: dtype, refinement, fallback,
+ * mapping of the handle), then the parallel filter line search of Sec. II-E:
+ * the ten trial steps alpha = 2^0 .. 2^-9 are evaluated at once (dynamics
+ * violation theta = sum_k ||x_{k+1} - h(x_k, u_k)||_2 and cost, FP64
+ * sums), and the largest accepted one is taken: with theta0 > theta_max
+ * only a decrease of theta is accepted, else on a descent direction the
+ * Armijo condition (eta 1e-4) on the cost, else a decrease of cost or
+ * theta.  Update x += alpha dx, u += alpha du, lam += alpha (lam_QP - lam).
+ * alpha_out (optional, [iters][batch]) receives the steps; a line search
+ * that accepts none leaves the iterate and sets status bit 32.  status
+ * ([batch]) holds the last iteration's solve status plus that bit.  n, m,
+ * nc <= 64.  Workspace: lqr_sqp_workspace_size bytes, 256-byte aligned.
+ * Asynchronous on `stream` (with opts->sync_status: LQR_ENUMERIC check at
+ * the end). */
+int lqr_sqp_workspace_size(lqr_handle_t h, int64_t batch, int N, int n, int m, int nc, const lqr_opts* opts,
+                           size_t* bytes);
+int lqr_sqp_solve(lqr_handle_t h, void* stream, const lqr_bilinear_model* mdl, int iters, double theta_max, void* x,
+                  void* u, void* lam, void* alpha_out, int32_t* status, void* workspace, size_t workspace_bytes,
+                  const lqr_opts* opts);
+#define LQR_ST_LS_REJECTED 32   /* (lqr_sqp_solve) the line search accepted no step */
+
 /* Diagnostics: the value function and policy of Sec. II-C that the last
  * LQR_METHOD_SCAN solve of this shape (same handle mapping, same workspace)
  * left in `workspace`: P [batch][N+1][n][n] and p [batch][N+1][n] (the

@@ -29,7 +29,8 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "lqr_kkt.h")
 LQR_OK, LQR_EINVAL, LQR_ENOMEM, LQR_ENUMERIC, LQR_EDEVICE, LQR_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 LQR_F32, LQR_F64 = 0, 1
 LQR_METHOD_SCAN, LQR_METHOD_SEQ_RICCATI = 0, 1
-ST_NONFINITE, ST_NOT_SPD, ST_P_NOT_SPD, ST_FP64_FALLBACK, ST_BAD_DESC = 1, 2, 4, 8, 16
+ST_NONFINITE, ST_NOT_SPD, ST_P_NOT_SPD, ST_FP64_FALLBACK, ST_BAD_DESC, ST_LS_REJECTED = 1, 2, 4, 8, 16, 32
+MODEL_FIELDS = ("A", "B", "c", "P", "V", "xr", "ur", "wx", "wu", "Gx", "Gu", "g0", "mu", "delta", "xhat0")
 
 
 class lqr_opts(ctypes.Structure):
@@ -57,6 +58,13 @@ class lqr_tuning(ctypes.Structure):
 class lqr_problem(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int32), ("n", ctypes.c_int32), ("m", ctypes.c_int32), ("reserved", ctypes.c_int32)] + \
         [(f, ctypes.c_void_p) for f in ("A", "B", "c", "Q", "R", "M", "q", "r", "x0", "x", "u", "lam")]
+
+
+class lqr_bilinear_model(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_int64), ("N", ctypes.c_int32), ("n", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("nc", ctypes.c_int32), ("gamma", ctypes.c_double)] + \
+        [(f, ctypes.c_void_p) for f in ("A", "B", "c", "P", "V", "xr", "ur", "wx", "wu", "Gx", "Gu", "g0", "mu",
+                                        "delta", "xhat0")]
 
 
 class LqrError(RuntimeError):
@@ -123,6 +131,15 @@ _lib.lqr_timing_report.restype = ctypes.c_int
 _lib.lqr_kkt_factors.argtypes = [_vp, _vp, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, _i32, _vp, _sz,
                                  _vp, _vp, _vp, _vp]
 _lib.lqr_kkt_factors.restype = ctypes.c_int
+_lib.lqr_qp_build.argtypes = [_vp, _vp, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                              _i32] + [_vp] * 14
+_lib.lqr_qp_build.restype = ctypes.c_int
+_lib.lqr_sqp_workspace_size.argtypes = [_vp, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        ctypes.POINTER(lqr_opts), ctypes.POINTER(_sz)]
+_lib.lqr_sqp_workspace_size.restype = ctypes.c_int
+_lib.lqr_sqp_solve.argtypes = [_vp, _vp, ctypes.POINTER(lqr_bilinear_model), ctypes.c_int, ctypes.c_double, _vp, _vp,
+                               _vp, _vp, _vp, _vp, _sz, ctypes.POINTER(lqr_opts)]
+_lib.lqr_sqp_solve.restype = ctypes.c_int
 _lib.lqr_tuning_save.argtypes = [_vp, ctypes.c_char_p]
 _lib.lqr_tuning_save.restype = ctypes.c_int
 _lib.lqr_tuning_load.argtypes = [_vp, ctypes.c_char_p]
@@ -136,6 +153,9 @@ lqr_workspace_size = _lib.lqr_workspace_size
 lqr_kkt_solve = _lib.lqr_kkt_solve
 lqr_kkt_solve_noalloc = _lib.lqr_kkt_solve_noalloc
 lqr_kkt_resolve = _lib.lqr_kkt_resolve
+lqr_qp_build = _lib.lqr_qp_build
+lqr_sqp_workspace_size = _lib.lqr_sqp_workspace_size
+lqr_sqp_solve = _lib.lqr_sqp_solve
 lqr_noalloc_workspace_bytes = _lib.lqr_noalloc_workspace_bytes
 lqr_kkt_residual = _lib.lqr_kkt_residual
 lqr_max_dim = _lib.lqr_max_dim
@@ -461,6 +481,73 @@ def solve_ragged_dev(problems, *, slots=256, refine: int | None = None, want_res
             o[name] = outbuf[off:off + shp[0] * shp[1]].view(shp)
         outs.append(o)
     return outs, status, resid
+
+
+def qp_build(Ex, Eu, e, W, Gx=None, Gu=None, g=None, mu=None, delta=None, *, out=None, stream=None) -> dict:
+    """lqr_qp_build: Gauss-Newton + relaxed-barrier QP blocks (Q, M, R, q, r
+    in the solve's layout) from the residual and constraint Jacobians."""
+    dtype, dev = Ex.dtype, Ex.device
+    batch, N1, p, n = Ex.shape
+    N, m = N1 - 1, Eu.shape[-1]
+    nc = 0 if Gx is None else Gx.shape[-2]
+    d = dict(Ex=Ex, Eu=Eu, e=e, W=W)
+    if nc:
+        d.update(Gx=Gx, Gu=Gu, g=g, mu=mu, delta=delta)
+    _validate(d, dtype, dev.index)
+    want = {"Ex": (batch, N + 1, p, n), "Eu": (batch, N, p, m), "e": (batch, N + 1, p), "W": (batch, N + 1, p, p)}
+    if nc:
+        want.update(Gx=(batch, N + 1, nc, n), Gu=(batch, N, nc, m), g=(batch, N + 1, nc), mu=(nc,), delta=(nc,))
+    for k, shp in want.items():
+        if tuple(d[k].shape) != shp:
+            raise ValueError(f"{k} has shape {tuple(d[k].shape)}, expected {shp}")
+    if out is None:
+        out = {"Q": torch.empty((batch, N + 1, n, n), dtype=dtype, device=dev),
+               "M": torch.empty((batch, N, n, m), dtype=dtype, device=dev),
+               "R": torch.empty((batch, N, m, m), dtype=dtype, device=dev),
+               "q": torch.empty((batch, N + 1, n), dtype=dtype, device=dev),
+               "r": torch.empty((batch, N, m), dtype=dtype, device=dev)}
+    ptr = lambda k: d[k].data_ptr() if k in d else None  # noqa: E731
+    s = (stream or torch.cuda.current_stream(dev.index)).cuda_stream
+    _check(_lib.lqr_qp_build(handle(dev.index), s, batch, N, n, m, p, nc, LQR_F32 if dtype == torch.float32 else LQR_F64,
+                             ptr("Ex"), ptr("Eu"), ptr("e"), ptr("W"), ptr("Gx"), ptr("Gu"), ptr("g"), ptr("mu"),
+                             ptr("delta"), *[out[k].data_ptr() for k in ("Q", "M", "R", "q", "r")]))
+    return out
+
+
+def sqp_solve(model: dict, x, u, lam, *, iters: int = 1, theta_max: float = 1e-2, refine: int | None = None,
+              want_alpha: bool = True, workspace: Workspace | None = None, stream=None):
+    """lqr_sqp_solve: `iters` SQP iterations (linearize, QP blocks, scan solve,
+    parallel filter line search, update) of the bilinear model `model` (device
+    tensors named as in MODEL_FIELDS plus the float `gamma`) from the iterate
+    (x, u, lam), updated in place.  Returns (status [batch], alphas
+    [iters][batch] or None)."""
+    A = model["A"]
+    dtype, dev = A.dtype, A.device
+    batch, n, _ = A.shape
+    N, m = u.shape[1], u.shape[2]
+    nc = model["Gx"].shape[1] if "Gx" in model and model["Gx"] is not None else 0
+    _validate({k: model[k] for k in MODEL_FIELDS if k in model and model[k] is not None}, dtype, dev.index)
+    _validate(dict(x=x, u=u, lam=lam), dtype, dev.index)
+    md = lqr_bilinear_model()
+    md.batch, md.N, md.n, md.m, md.nc, md.gamma = batch, N, n, m, nc, float(model["gamma"])
+    for f in MODEL_FIELDS:
+        t = model.get(f)
+        setattr(md, f, t.data_ptr() if t is not None else None)
+    o = default_opts(dtype)
+    if refine is not None:
+        o.refine_sweeps = int(refine)
+    nbytes = _sz()
+    _check(_lib.lqr_sqp_workspace_size(handle(dev.index), batch, N, n, m, nc, ctypes.byref(o), ctypes.byref(nbytes)))
+    if workspace is None:
+        workspace = _default_ws.setdefault(dev.index, Workspace(dev.index))
+    wbuf = workspace.get(nbytes.value)
+    status = torch.empty((batch,), dtype=torch.int32, device=dev)
+    alphas = torch.empty((max(iters, 1), batch), dtype=dtype, device=dev) if want_alpha else None
+    s = (stream or torch.cuda.current_stream(dev.index)).cuda_stream
+    _check(_lib.lqr_sqp_solve(handle(dev.index), s, ctypes.byref(md), int(iters), float(theta_max), x.data_ptr(),
+                              u.data_ptr(), lam.data_ptr(), alphas.data_ptr() if alphas is not None else None,
+                              status.data_ptr(), wbuf.data_ptr(), wbuf.numel(), ctypes.byref(o)))
+    return status, alphas
 
 
 def kkt_residual(A, B, c, Q, R, M, q, r, x0, x, u, lam, *, workspace=None, stream=None):

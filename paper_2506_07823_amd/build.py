@@ -41,7 +41,8 @@ def torch_lib_dir() -> str:
 
 
 def _sources():
-    deps = [os.path.join(CSRC, f) for f in ("engine.hpp", "bigeng.hpp", "kernels.hpp", "kernels_big.hpp", "runs.hpp", "pack.hpp")]
+    deps = [os.path.join(CSRC, f) for f in ("engine.hpp", "bigeng.hpp", "kernels.hpp", "kernels_big.hpp", "runs.hpp", "pack.hpp",
+                                            "qpdata.hpp", "sqp.hpp")]
     deps.append(os.path.join(HERE, "..", "include", "lqr_kkt.h"))
     units = [("lqr_kkt", os.path.join(CSRC, "lqr_kkt.hip"), [])]
     # the slowest units first, so the parallel build ends sooner

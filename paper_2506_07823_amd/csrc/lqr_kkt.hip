@@ -17,7 +17,9 @@
 
 #include "../../include/lqr_kkt.h"
 #include "pack.hpp"
+#include "qpdata.hpp"
 #include "runs.hpp"
+#include "sqp.hpp"
 
 using namespace lqr;
 
@@ -241,7 +243,7 @@ const char* const kFamNames[F_COUNT] = {
     "clear", "element", "up", "root", "down", "policy", "fwd_up", "fwd_root", "fwd_down", "recover", "residual",
     "ref_d", "bwd_up", "bwd_root", "bwd_down", "ref_kff", "fwd_up_vec", "recover_add", "reduce", "plain_riccati",
     "fwd_inst", "refine_inst", "warm_copy", "ragged_pack", "fused_solve", "tail_sweep", "tail_root",
-    "tail_sweep_up0", "chunk_up", "chunk_mid", "chunk_down", "fwd_seq", "refine_seq", "fp64_redo", "mark_redo", "ragged_solve", "resolve"};
+    "tail_sweep_up0", "chunk_up", "chunk_mid", "chunk_down", "fwd_seq", "refine_seq", "fp64_redo", "mark_redo", "ragged_solve", "resolve", "sqp"};
 
 // Per-handle launch timer: two HIP events around every launch, read back by
 // lqr_timing_report.
@@ -1153,6 +1155,174 @@ int lqr_kkt_factors(lqr_handle_t h, void* stream, int64_t batch, int N, int n, i
                            (double*)P, (double*)p, (double*)K, (double*)kff);
     HIPCHK(hipGetLastError());
     return LQR_OK;
+}
+
+int lqr_qp_build(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int m, int p, int nc, int32_t dtype,
+                 const void* Ex, const void* Eu, const void* e, const void* W, const void* Gx, const void* Gu,
+                 const void* g, const void* mu, const void* delta, void* Q, void* M, void* R, void* q, void* r) {
+    if (!h) return fail(LQR_EINVAL, "null handle");
+    if (batch < 1 || N < 1 || n < 1 || m < 1 || p < 1 || nc < 0)
+        return fail(LQR_EINVAL, "bad sizes (batch %lld, N %d, n %d, m %d, p %d, nc %d)", (long long)batch, N, n, m, p,
+                    nc);
+    if (dtype != LQR_F32 && dtype != LQR_F64) return fail(LQR_EINVAL, "bad dtype %d", dtype);
+    const size_t es = dtype == LQR_F32 ? 4 : 8;
+    const size_t lds = es * ((size_t)p * (n + m) + p + 2 * (size_t)nc);
+    if (lds > 65536) return fail(LQR_EINVAL, "p (n + m) too large for one workgroup's LDS (%zu bytes)", lds);
+    if (batch * (int64_t)(N + 1) > 0x7fffffff) return fail(LQR_EINVAL, "batch*(N+1) exceeds the grid limit");
+    const void* need[] = {Ex, Eu, e, W, Q, M, R, q, r};
+    for (const void* ptr : need)
+        if (!ptr || !aligned(ptr, es)) return fail(LQR_EINVAL, "null or misaligned array");
+    if (nc > 0) {
+        const void* cons[] = {Gx, Gu, g, mu, delta};
+        for (const void* ptr : cons)
+            if (!ptr || !aligned(ptr, es)) return fail(LQR_EINVAL, "null or misaligned constraint array");
+    }
+    HIPCHK(hipSetDevice(h->device));
+    hipStream_t s = (hipStream_t)stream;
+    const dim3 grid((unsigned)(batch * (N + 1)));
+    if (dtype == LQR_F32) {
+        QpArgs<float> a{batch, N, n, m, p, nc, (const float*)Ex, (const float*)Eu, (const float*)e, (const float*)W,
+                        (const float*)Gx, (const float*)Gu, (const float*)g, (const float*)mu,
+                        (const float*)delta, (float*)Q, (float*)M, (float*)R, (float*)q, (float*)r};
+        hipLaunchKernelGGL(k_qp_build<float>, grid, dim3(256), lds, s, a);
+    } else {
+        QpArgs<double> a{batch, N, n, m, p, nc, (const double*)Ex, (const double*)Eu, (const double*)e,
+                         (const double*)W, (const double*)Gx, (const double*)Gu, (const double*)g,
+                         (const double*)mu, (const double*)delta, (double*)Q, (double*)M, (double*)R, (double*)q,
+                         (double*)r};
+        hipLaunchKernelGGL(k_qp_build<double>, grid, dim3(256), lds, s, a);
+    }
+    HIPCHK(hipGetLastError());
+    return LQR_OK;
+}
+
+}  // extern "C"
+
+namespace {
+// workspace of lqr_sqp_solve: the subproblem's arrays, its solution, the
+// line search's sums, then the KKT solve's own workspace
+struct SqpLayout {
+    size_t off[22];
+    size_t solve_off, total;
+};
+
+SqpLayout sqp_layout(lqr_handle_t h, int64_t B, int N, int n, int m, int nc, const lqr_opts& o) {
+    const size_t es = o.dtype == LQR_F32 ? 4 : 8;
+    const int64_t p = n + m, N1 = N + 1;
+    const int64_t elems[22] = {B * N * n * n, B * N * n * m, B * N * n, B * n,            // A B c x0
+                               B * N1 * p * n, B * N * p * m, B * N1 * p, B * N1 * p * p,  // Ex Eu e W
+                               B * N1 * nc * n, B * N * nc * m, B * N1 * nc,               // Gx Gu g
+                               B * N1 * n * n, B * N * n * m, B * N * m * m, B * N1 * n, B * N * m,   // Q M R q r
+                               B * N1 * n, B * N * m, B * N1 * n,                           // dx du lqp
+                               B * (kAlphas + 1), B * (kAlphas + 1), B};                     // th J dJ (double)
+    SqpLayout l;
+    size_t cur = 0;
+    for (int i = 0; i < 22; ++i) {
+        l.off[i] = cur;
+        cur += (size_t)align_up(elems[i] * (int64_t)(i >= 19 ? 8 : es), 256);
+    }
+    l.solve_off = cur;
+    const Tuning* tun = h ? h->find(B, N, n, m, o.dtype) : nullptr;
+    l.total = cur + layout(make_plan(B, N, n, m, es, o, tun), es).total;
+    return l;
+}
+
+int sqp_check(int64_t batch, int N, int n, int m, int nc, const lqr_opts& o) {
+    LCHK(check_dims(batch, N, n, m));
+    if (n > 64 || m > 64 || nc < 0 || nc > 64)
+        return fail(LQR_EINVAL, "the SQP kernels take n, m, nc <= 64 (n %d m %d nc %d)", n, m, nc);
+    if (o.dtype != LQR_F32 && o.dtype != LQR_F64) return fail(LQR_EINVAL, "bad dtype %d", o.dtype);
+    if (o.method != LQR_METHOD_SCAN) return fail(LQR_EINVAL, "the SQP iteration uses the scan method");
+    if (o.warm_x || o.warm_u || o.warm_lam) return fail(LQR_EINVAL, "the SQP iteration takes no warm start");
+    return LQR_OK;
+}
+
+template <typename S>
+int sqp_run(lqr_handle_t h, hipStream_t s, const lqr_bilinear_model& mdl, int iters, double theta_max, S* X, S* U,
+            S* L, S* alpha_out, int32_t* status, char* ws, size_t ws_bytes, const SqpLayout& l, const lqr_opts& o) {
+    SqpModel<S> md;
+    md.batch = mdl.batch; md.N = mdl.N; md.n = mdl.n; md.m = mdl.m; md.nc = mdl.nc;
+    md.A = (const S*)mdl.A; md.B = (const S*)mdl.B; md.c = (const S*)mdl.c; md.P = (const S*)mdl.P;
+    md.V = (const S*)mdl.V; md.xr = (const S*)mdl.xr; md.ur = (const S*)mdl.ur; md.wx = (const S*)mdl.wx;
+    md.wu = (const S*)mdl.wu; md.Gx = (const S*)mdl.Gx; md.Gu = (const S*)mdl.Gu; md.g0 = (const S*)mdl.g0;
+    md.mu = (const S*)mdl.mu; md.delta = (const S*)mdl.delta; md.xhat0 = (const S*)mdl.xhat0;
+    md.gamma = mdl.gamma;
+    SqpWork<S> w;
+    S** slots[19] = {&w.A, &w.B, &w.c, &w.x0, &w.Ex, &w.Eu, &w.e, &w.W, &w.Gx, &w.Gu, &w.g,
+                     &w.Q, &w.M, &w.R, &w.q, &w.r, &w.dx, &w.du, &w.lqp};
+    for (int i = 0; i < 19; ++i) *slots[i] = (S*)(ws + l.off[i]);
+    w.th = (double*)(ws + l.off[19]);
+    w.J = (double*)(ws + l.off[20]);
+    w.dJ = (double*)(ws + l.off[21]);
+    const int64_t B = mdl.batch;
+    const int N = mdl.N, n = mdl.n, m = mdl.m, nc = mdl.nc, p = n + m;
+    const size_t es = sizeof(S);
+    const Tuning* tun = h->find(B, N, n, m, o.dtype);
+    LCHK(launch_nt(64, F_SQP, 0, 0, k_sqp_setup<S>, B * (N + 1), s, md, w));
+    QpArgs<S> qa{B, N, n, m, p, nc, w.Ex, w.Eu, w.e, w.W, w.Gx, w.Gu, w.g, md.mu, md.delta,
+                 w.Q, w.M, w.R, w.q, w.r};
+    const size_t qlds = es * ((size_t)p * (n + m) + p + 2 * (size_t)nc);
+    for (int it = 0; it < iters; ++it) {
+        LCHK(launch_nt(64, F_SQP, 0, 0, k_sqp_linearize<S>, B * (N + 1), s, md, w, (const S*)X, (const S*)U));
+        hipLaunchKernelGGL(k_qp_build<S>, dim3((unsigned)(B * (N + 1))), dim3(256), qlds, s, qa);
+        HIPCHK(hipGetLastError());
+        LCHK(solve_impl(h, s, B, N, n, m, w.A, w.B, w.c, w.Q, w.R, w.M, w.q, w.r, w.x0, w.dx, w.du, w.lqp, status,
+                        ws + l.solve_off, ws_bytes - l.solve_off, o, tun));
+        LCHK(launch_nt(64, F_SQP, 0, 0, k_sqp_trials<S>, B * (kAlphas + 1), s, md, w, (const S*)X, (const S*)U));
+        LCHK(launch_nt(64, F_SQP, 0, 0, k_sqp_update<S>, B, s, md, w, X, U, L,
+                       alpha_out ? alpha_out + (int64_t)it * B : (S*)nullptr, status, theta_max, 1e-4));
+    }
+    return LQR_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int lqr_sqp_workspace_size(lqr_handle_t h, int64_t batch, int N, int n, int m, int nc, const lqr_opts* opts,
+                           size_t* bytes) {
+    if (!bytes) return fail(LQR_EINVAL, "null output pointer");
+    lqr_opts o;
+    if (opts) o = *opts; else lqr_opts_default(&o, LQR_F32);
+    LCHK(sqp_check(batch, N, n, m, nc, o));
+    *bytes = sqp_layout(h, batch, N, n, m, nc, o).total;
+    return LQR_OK;
+}
+
+int lqr_sqp_solve(lqr_handle_t h, void* stream, const lqr_bilinear_model* mdl, int iters, double theta_max, void* x,
+                  void* u, void* lam, void* alpha_out, int32_t* status, void* workspace, size_t workspace_bytes,
+                  const lqr_opts* opts) {
+    if (!h || !mdl) return fail(LQR_EINVAL, "null handle or model");
+    lqr_opts o;
+    if (opts) o = *opts; else lqr_opts_default(&o, LQR_F32);
+    LCHK(sqp_check(mdl->batch, mdl->N, mdl->n, mdl->m, mdl->nc, o));
+    if (iters < 0 || iters > 1000) return fail(LQR_EINVAL, "iters must be in 0..1000");
+    if (!(theta_max >= 0.0)) return fail(LQR_EINVAL, "theta_max must be >= 0");
+    const size_t es = o.dtype == LQR_F32 ? 4 : 8;
+    const void* need[] = {mdl->A, mdl->B, mdl->c, mdl->P, mdl->V, mdl->xr, mdl->ur, mdl->wx, mdl->wu, mdl->xhat0,
+                          x, u, lam, status, workspace};
+    for (const void* ptr : need)
+        if (!ptr) return fail(LQR_EINVAL, "null pointer argument");
+    if (mdl->nc > 0 && (!mdl->Gx || !mdl->Gu || !mdl->g0 || !mdl->mu || !mdl->delta))
+        return fail(LQR_EINVAL, "null constraint array");
+    if (!aligned(workspace, 256) || !aligned(x, es) || !aligned(u, es) || !aligned(lam, es))
+        return fail(LQR_EINVAL, "misaligned argument");
+    const SqpLayout l = sqp_layout(h, mdl->batch, mdl->N, mdl->n, mdl->m, mdl->nc, o);
+    if (workspace_bytes < l.total)
+        return fail(LQR_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", workspace_bytes, l.total);
+    HIPCHK(hipSetDevice(h->device));
+    hipStream_t s = (hipStream_t)stream;
+    o.sync_status = 0;
+    int rc;
+    {
+        TimerScope ts_scope(h->timing ? &h->timer : nullptr);
+        rc = o.dtype == LQR_F32
+                 ? sqp_run<float>(h, s, *mdl, iters, theta_max, (float*)x, (float*)u, (float*)lam, (float*)alpha_out,
+                                  status, (char*)workspace, workspace_bytes, l, o)
+                 : sqp_run<double>(h, s, *mdl, iters, theta_max, (double*)x, (double*)u, (double*)lam,
+                                   (double*)alpha_out, status, (char*)workspace, workspace_bytes, l, o);
+    }
+    if (rc != LQR_OK || !(opts && opts->sync_status)) return rc;
+    return sync_status_check(s, status, mdl->batch);
 }
 
 int lqr_timing_enable(lqr_handle_t h, int enable) {

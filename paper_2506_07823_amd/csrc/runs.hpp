@@ -51,7 +51,7 @@ enum Fam {
     F_CLEAR, F_ELEM, F_UP, F_ROOT, F_DOWN, F_POLICY, F_FUP, F_FROOT, F_FDOWN, F_RECOVER, F_RESID, F_REF_D, F_BUP,
     F_BROOT, F_BDOWN, F_REF_KFF, F_FUPV, F_RECOVER_ADD, F_REDUCE, F_PLAIN, F_FWD_INST, F_REFINE_INST, F_WARM, F_PACK,
     F_FUSED, F_TAIL, F_TROOT, F_TAIL_UP0, F_CHUNK_UP, F_CHUNK_MID, F_CHUNK_DOWN, F_FWD_SEQ, F_REFINE_SEQ, F_REDO,
-    F_MARK, F_RAGGED, F_RESOLVE, F_COUNT
+    F_MARK, F_RAGGED, F_RESOLVE, F_SQP, F_COUNT
 };
 
 // Optional per-launch timer (HIP events around each launch on its stream),

@@ -240,3 +240,104 @@ def gen_batch(gen, count: int, dtype=np.float32, workers: int | None = None,
         with _cf.ThreadPoolExecutor(workers) as ex:
             list(ex.map(fill, range(count)))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Inputs of the QP-data builder (Gauss-Newton least-squares cost plus relaxed
+# barriers): a tracking-like residual eps = [x - x_ref; u - u_ref] whose
+# Jacobians are the selection matrices plus N(0, 0.1) perturbations
+# (p = n + m rows, so the Gauss-Newton Hessian is positive definite),
+# diagonal weights W with the c2 Q/R ranges, and nc linear-in-(x, u)
+# constraints with values xi ~ U[-0.05, 1] (about one in seven inside the
+# relaxation zone xi < delta = U[0.05, 0.2]) and mu ~ U[0.01, 0.1].  The
+# dynamics A, B, c and x0 are drawn as in c1 (dt = 0.02).
+QP_FIELDS = ("Ex", "Eu", "e", "W", "Gx", "Gu", "g")
+
+
+def gen_qpdata(N: int, n: int, m: int, nc: int, seed) -> dict:
+    rng = np.random.default_rng(seed)
+    p = n + m
+    sel_x = np.zeros((p, n))
+    sel_x[:n, :n] = np.eye(n)
+    sel_u = np.zeros((p, m))
+    sel_u[n:, :m] = np.eye(m)
+    Ex = sel_x[None] + rng.normal(0.0, 0.1, (N + 1, p, n))
+    Eu = sel_u[None] + rng.normal(0.0, 0.1, (N, p, m))
+    e = rng.normal(0.0, 0.1, (N + 1, p))
+    wd = np.concatenate([rng.uniform(1.0, 100.0, (N + 1, n)), rng.uniform(1e-3, 1e-1, (N + 1, m))], axis=1)
+    W = _diag_stack(wd)
+    Gx = rng.normal(0.0, 0.1, (N + 1, nc, n))
+    Gu = rng.normal(0.0, 1.0, (N, nc, m))
+    g = rng.uniform(-0.05, 1.0, (N + 1, nc))
+    mu = rng.uniform(0.01, 0.1, nc)
+    delta = rng.uniform(0.05, 0.2, nc)
+    A = np.eye(n)[None] + 0.02 * rng.normal(0.0, 1.0, (N, n, n))
+    B = rng.normal(0.0, 0.1, (N, n, m))
+    c = rng.normal(0.0, 1e-3, (N, n))
+    x0 = rng.normal(0.0, 0.1, n)
+    return {"Ex": Ex, "Eu": Eu, "e": e, "W": W, "Gx": Gx, "Gu": Gu, "g": g, "mu": mu, "delta": delta,
+            "A": A, "B": B, "c": c, "x0": x0}
+
+
+def gen_qp_batch(count: int, N: int, n: int, m: int, nc: int, seed0, dtype=np.float64) -> dict:
+    """``count`` instances of gen_qpdata (seeds [seed0..., i]) stacked on a
+    batch axis; mu and delta (per constraint, shared by every instance and
+    stage) are those of instance 0."""
+    insts = [gen_qpdata(N, n, m, nc, list(np.atleast_1d(seed0)) + [i]) for i in range(count)]
+    out = {k: np.ascontiguousarray(np.stack([d[k] for d in insts]), dtype=dtype)
+           for k in QP_FIELDS + ("A", "B", "c", "x0")}
+    out["mu"] = np.ascontiguousarray(insts[0]["mu"], dtype=dtype)
+    out["delta"] = np.ascontiguousarray(insts[0]["delta"], dtype=dtype)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Synthetic nonlinear model for the line search and the SQP iteration: the
+# c2-like linear part (A = I + dt F, F 30 % nonzero ~ N(0, 1); B ~ N(0, dt);
+# c ~ N(0, 1e-3)) plus a bilinear term gamma (P x) * (V u) with P, V ~
+# N(0, 1/sqrt(n)), gamma = `gamma`; tracking references xr ~ N(0, 0.1),
+# ur = 0, weights wx ~ U[1, 10], wu ~ U[0.01, 0.1]; nc linear constraints
+# Gx ~ N(0, 0.1), Gu ~ N(0, 1), g0 ~ U[0.2, 1] (feasible at x = u = 0) with
+# barrier parameters mu ~ U[0.01, 0.1], delta ~ U[0.05, 0.2]; the measured
+# initial state xhat0 ~ N(0, 0.5).
+MODEL_FIELDS = ("A", "B", "c", "P", "V", "xr", "ur", "wx", "wu", "Gx", "Gu", "g0")
+
+
+def gen_bilinear(N: int, n: int, m: int, nc: int, seed, gamma: float = 0.05, dt: float = 0.02) -> dict:
+    rng = np.random.default_rng(seed)
+    A = np.eye(n) + dt * _sparse(rng, (n, n), 0.3, 1.0)
+    B = rng.normal(0.0, dt, (n, m))
+    c = rng.normal(0.0, 1e-3, n)
+    P = rng.normal(0.0, 1.0 / np.sqrt(n), (n, n))
+    V = rng.normal(0.0, 1.0 / np.sqrt(n), (n, m))
+    xr = rng.normal(0.0, 0.1, (N + 1, n))
+    ur = np.zeros((N, m))
+    wx = rng.uniform(1.0, 10.0, (N + 1, n))
+    wu = rng.uniform(0.01, 0.1, (N, m))
+    Gx = rng.normal(0.0, 0.1, (nc, n))
+    Gu = rng.normal(0.0, 1.0, (nc, m))
+    g0 = rng.uniform(0.2, 1.0, nc)
+    mu = rng.uniform(0.01, 0.1, nc)
+    delta = rng.uniform(0.05, 0.2, nc)
+    xhat0 = rng.normal(0.0, 0.5, n)
+    return {"A": A, "B": B, "c": c, "P": P, "V": V, "gamma": float(gamma), "xr": xr, "ur": ur, "wx": wx, "wu": wu,
+            "Gx": Gx, "Gu": Gu, "g0": g0, "mu": mu, "delta": delta, "xhat0": xhat0}
+
+
+def gen_bilinear_batch(count: int, N: int, n: int, m: int, nc: int, seed0, gamma: float = 0.05,
+                       dtype=np.float64) -> dict:
+    """``count`` models of gen_bilinear (seeds [seed0..., i]) with a batch
+    axis on every array; gamma, mu and delta are shared (instance 0's)."""
+    ms = [gen_bilinear(N, n, m, nc, list(np.atleast_1d(seed0)) + [i], gamma) for i in range(count)]
+    out = {k: np.ascontiguousarray(np.stack([d[k] for d in ms]), dtype=dtype) for k in MODEL_FIELDS + ("xhat0",)}
+    out["mu"] = np.ascontiguousarray(ms[0]["mu"], dtype=dtype)
+    out["delta"] = np.ascontiguousarray(ms[0]["delta"], dtype=dtype)
+    out["gamma"] = float(gamma)
+    return out
+
+
+def model_instance(batch: dict, b: int) -> dict:
+    """One model of a gen_bilinear_batch dict."""
+    d = {k: batch[k][b] for k in MODEL_FIELDS + ("xhat0",)}
+    d.update(gamma=batch["gamma"], mu=batch["mu"], delta=batch["delta"])
+    return d
