@@ -362,10 +362,12 @@ def batch_sweep_leg(L, batches=(16, 64, 256, 1024), steps: int = 10):
     return rows
 
 
-def serving_leg(L, n_clients: int, warm_requests: int, sat_requests: int, requests: int, load: float):
+def serving_leg(L, n_clients: int, warm_requests: int, sat_requests: int, requests: int, loads=(0.5, 0.7, 0.9),
+                graphs: bool = True):
     """Serving mix through the continuous-batching loop: a saturated run
     (every request present at t = 0) gives the capacity; then Poisson
-    arrivals at `load` x capacity give the latency distribution."""
+    arrivals at each fraction of it in `loads` give the latency
+    distribution (overall and per request shape)."""
     import torch
     import synth
     from paper_2506_07823_amd.serve import GpuBackend, Request, Server, latency_report
@@ -375,8 +377,8 @@ def serving_leg(L, n_clients: int, warm_requests: int, sat_requests: int, reques
     # request ships them (and its own x0) to the device
     pinned = [{k: torch.from_numpy(np.ascontiguousarray(v, np.float32)).pin_memory()
                for k, v in model.items() if k != "x0"} for model, _ in clients]
-    walks = [synth.x0_walk(model, seed, warm_requests + sat_requests + requests + 1)
-             for model, seed in clients]
+    total = warm_requests + sat_requests + requests * len(loads) + 1
+    walks = [synth.x0_walk(model, seed, total) for model, seed in clients]
     used = [0] * len(clients)
     rng = np.random.default_rng([5, 4])
 
@@ -394,35 +396,36 @@ def serving_leg(L, n_clients: int, warm_requests: int, sat_requests: int, reques
 
     free, _ = torch.cuda.mem_get_info()
     budget = int(0.5 * free)
+    be = GpuBackend(nstreams=4, refine=1, graphs=graphs)
 
     def phase(count, rate, rid0):
-        be = GpuBackend(nstreams=4, refine=2)
         srv = Server(be, budget, max_batch=64, warm=True)
         done = srv.run(make(count, rate, rid0))
         torch.cuda.synchronize()
         return done, srv
 
-    log("[bench] serving: warmup")
+    log(f"[bench] serving: warmup ({warm_requests} requests)")
     phase(warm_requests, None, 0)
-    log("[bench] serving: saturated run")
+    log(f"[bench] serving: saturated run ({sat_requests} requests)")
     done, _ = phase(sat_requests, None, warm_requests)
     cap = latency_report(done)["solves_per_s"]
-    rate = load * cap
-    log(f"[bench] serving: capacity {cap:.0f} solves/s; Poisson arrivals at {rate:.0f}/s")
-    done, srv = phase(requests, rate, warm_requests + sat_requests)
-    rep = latency_report(done)
-    resid = max(float(r.result["resid"]) for r in done)
-    bad = sum(int(r.result["status"] != 0) for r in done)
-    shapes = {}
-    for r in done:
-        key = "N%d_n%d_m%d" % r.shape
-        shapes[key] = shapes.get(key, 0) + 1
-    return {"offered_per_s": rate, "capacity_solves_per_s": cap, "load": load, **rep,
-            "max_rel_kkt_residual": resid, "instances_with_status": bad,
+    out = {"capacity_solves_per_s": cap, "clients": n_clients, "budget_bytes": budget, "graph_replay": graphs,
+           "latency": "arrival to device completion, host->device copies included", "loads": {}}
+    rid = warm_requests + sat_requests
+    for load in loads:
+        rate = load * cap
+        log(f"[bench] serving: capacity {cap:.0f} solves/s; {requests} Poisson arrivals at {rate:.0f}/s ({load:.0%})")
+        done, srv = phase(requests, rate, rid)
+        rid += requests
+        rep = latency_report(done)
+        out["loads"][f"{int(round(100 * load))}pct"] = {
+            "offered_per_s": rate, **rep,
+            "max_rel_kkt_residual": max(float(r.result["resid"]) for r in done),
+            "instances_with_status": sum(int(r.result["status"] != 0) for r in done),
             "warm_started": sum(r.warm for r in done), "batches": len(srv.launch_log),
-            "mean_batch": float(np.mean([k for _, k in srv.launch_log])), "budget_bytes": budget,
-            "peak_admitted_bytes": srv.peak_used, "clients": n_clients, "mix": shapes,
-            "latency": "arrival to device completion, host->device copies included"}
+            "mean_batch": float(np.mean([k for _, k in srv.launch_log])), "peak_admitted_bytes": srv.peak_used}
+    out["graph_replays"] = be.graph_replays
+    return out
 
 
 def main():
@@ -437,7 +440,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-mix workload")
     ap.add_argument("--no-latency", action="store_true", help="skip the single-solve latency workload")
     ap.add_argument("--no-sweep", action="store_true", help="skip the whole-body batch-size sweep")
-    ap.add_argument("--serving-requests", type=int, default=1600)
+    ap.add_argument("--serving-requests", type=int, default=10000, help="requests per offered load")
     ap.add_argument("--replays", type=int, default=LAT_REPLAYS, help="graph replays of the p50/p99 loop")
     ap.add_argument("--no-tune", action="store_true", help="use the default mapping instead of autotuning it")
     ap.add_argument("--split", action="store_true",
@@ -505,7 +508,8 @@ def main():
     if not a.no_sweep:
         result["batch_sweep"] = batch_sweep_leg(L)
     if not a.no_serving:
-        result["serving"] = serving_leg(L, 40, 100, max(200, a.serving_requests // 2), a.serving_requests, 0.7)
+        result["serving"] = serving_leg(L, 40, max(100, a.serving_requests // 10), max(200, a.serving_requests // 5),
+                                        a.serving_requests)
     if not a.no_cpu:
         log("[bench] whole-body: CPU oracle baseline")
         result["cpu_baseline"] = cpu_baseline(synth.gen_c3, a.cpu_sample, BATCH, "whole-body")

@@ -203,9 +203,17 @@ class Server:
 class GpuBackend:
     """Batched solves on a pool of HIP streams (default priority) through
     the library's C ABI; inputs go host -> device on the launch stream and
-    results come back to pinned host buffers on the same stream."""
+    results come back to pinned host buffers on the same stream.
 
-    def __init__(self, device: int = 0, nstreams: int = 4, refine: int = 2, dtype=np.float32):
+    graphs=True: the solve of a batch is captured into a HIP graph once per
+    (shape, batch size, warm or cold, stream) with buffers of its own, and
+    replayed for every later batch of that key: a batch then costs its
+    copies and one graph launch instead of the whole launch sequence.
+    Shapes with an order above `graph_max_order` run eagerly (their
+    per-key buffers would be large)."""
+
+    def __init__(self, device: int = 0, nstreams: int = 4, refine: int = 1, dtype=np.float32, graphs: bool = False,
+                 graph_max_order: int = 64):
         import torch
         import paper_2506_07823_amd as L
         self.torch, self.L = torch, L
@@ -217,6 +225,10 @@ class GpuBackend:
         self.streams = [torch.cuda.Stream(device=device) for _ in range(nstreams)]
         self.free = list(range(nstreams))
         self.ws = [L.Workspace(device) for _ in range(nstreams)]
+        self.graphs = graphs
+        self.graph_max_order = graph_max_order
+        self._graphs = {}
+        self.graph_replays = 0
         self.t0 = None
 
     def workspace_bytes(self, shape) -> int:
@@ -231,56 +243,121 @@ class GpuBackend:
         self.t0.record(torch.cuda.current_stream(self.device))
         torch.cuda.synchronize(self.device)
 
+    def _stage_inputs(self, reqs, dev):
+        """host -> device on the current stream, straight from each
+        request's buffers (asynchronous when they are pinned)"""
+        torch = self.torch
+        for f in FIELDS:
+            for i, r in enumerate(reqs):
+                src = r.data[f]
+                if not isinstance(src, torch.Tensor):
+                    src = torch.from_numpy(np.ascontiguousarray(src, dtype=self.np_dtype))
+                dev[f][i].copy_(src, non_blocking=True)
+
+    def _graph(self, shape, k, warm, sid):
+        """Buffers and captured solve of one key (built on first use)."""
+        key = (shape, k, warm, sid)
+        ent = self._graphs.get(key)
+        if ent is not None:
+            return ent
+        torch, L = self.torch, self.L
+        N, n, m = shape
+        dn = f"cuda:{self.device}"
+        shapes = {"A": (N, n, n), "B": (N, n, m), "c": (N, n), "Q": (N + 1, n, n), "R": (N, m, m),
+                  "M": (N, n, m), "q": (N + 1, n), "r": (N, m), "x0": (n,)}
+        dev = {f: torch.zeros((k,) + s, dtype=self.dtype, device=dn) for f, s in shapes.items()}
+        # a valid problem in every slot for the capture's warm-up solve
+        eye_n = torch.eye(n, dtype=self.dtype, device=dn)
+        eye_m = torch.eye(m, dtype=self.dtype, device=dn)
+        dev["A"][:] = eye_n
+        dev["Q"][:] = eye_n
+        dev["R"][:] = eye_m
+        out = {"x": torch.zeros((k, N + 1, n), dtype=self.dtype, device=dn),
+               "u": torch.zeros((k, N, m), dtype=self.dtype, device=dn),
+               "lam": torch.zeros((k, N + 1, n), dtype=self.dtype, device=dn),
+               "status": torch.zeros((k,), dtype=torch.int32, device=dn),
+               "resid": torch.zeros((k,), dtype=torch.float64, device=dn)}
+        wbuf = tuple(torch.zeros_like(out[f]) for f in ("x", "u", "lam")) if warm else None
+        ws = L.Workspace(self.device)
+        s = self.streams[sid]
+        s.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.stream(s):
+            L.solve(*[dev[f] for f in FIELDS], refine=self.refine, want_resid=True, warm=wbuf, workspace=ws,
+                    out=out, stream=s)
+        s.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            L.solve(*[dev[f] for f in FIELDS], refine=self.refine, want_resid=True, warm=wbuf, workspace=ws,
+                    out=out, stream=s)
+        s.synchronize()
+        ent = self._graphs[key] = {"dev": dev, "out": out, "warm": wbuf, "ws": ws, "graph": g}
+        return ent
+
     def launch(self, shape, reqs, warm_list):
         torch = self.torch
         sid = self.free.pop()
         s = self.streams[sid]
         k = len(reqs)
-        dev = {}
         dn = f"cuda:{self.device}"
+        has_warm = any(w is not None for w in warm_list)
+        if has_warm and not all(w is not None for w in warm_list):
+            raise ValueError("a batch holds only warm-started or only cold requests")
+        use_graph = self.graphs and max(shape[1], shape[2]) <= self.graph_max_order
+        ent = self._graph(shape, k, has_warm, sid) if use_graph else None
         with torch.cuda.stream(s):
-            # host -> device on the launch stream, straight from each
-            # request's buffers (asynchronous when they are pinned)
-            for f in FIELDS:
-                first = reqs[0].data[f]
-                dev[f] = torch.empty((k,) + tuple(first.shape), dtype=self.dtype, device=dn)
-                for i, r in enumerate(reqs):
-                    src = r.data[f]
-                    if not isinstance(src, torch.Tensor):
-                        src = torch.from_numpy(np.ascontiguousarray(src, dtype=self.np_dtype))
-                    dev[f][i].copy_(src, non_blocking=True)
-            warm = None
-            if any(w is not None for w in warm_list):
-                if not all(w is not None for w in warm_list):
-                    raise ValueError("a batch holds only warm-started or only cold requests")
-                warm = tuple(torch.stack([w[f] for w in warm_list]) for f in ("x", "u", "lam"))
-            out = self.L.solve(*[dev[f] for f in FIELDS], refine=self.refine, want_resid=True, warm=warm,
-                               workspace=self.ws[sid], stream=s)
+            if ent is not None:
+                dev, out = ent["dev"], ent["out"]
+                self._stage_inputs(reqs, dev)
+                if has_warm:
+                    for j, f in enumerate(("x", "u", "lam")):
+                        for i, w in enumerate(warm_list):
+                            ent["warm"][j][i].copy_(w[f], non_blocking=True)
+                ent["graph"].replay()
+                self.graph_replays += 1
+            else:
+                dev = {}
+                for f in FIELDS:
+                    first = reqs[0].data[f]
+                    dev[f] = torch.empty((k,) + tuple(first.shape), dtype=self.dtype, device=dn)
+                self._stage_inputs(reqs, dev)
+                warm = None
+                if has_warm:
+                    warm = tuple(torch.stack([w[f] for w in warm_list]) for f in ("x", "u", "lam"))
+                out = self.L.solve(*[dev[f] for f in FIELDS], refine=self.refine, want_resid=True, warm=warm,
+                                   workspace=self.ws[sid], stream=s)
             host_out = {f: torch.empty(tuple(out[f].shape), dtype=out[f].dtype, pin_memory=True)
                         for f in ("x", "u", "lam", "status", "resid")}
             for f, h in host_out.items():
                 h.copy_(out[f], non_blocking=True)
+            # the device state of each solution (the warm start of the
+            # client's next request) outlives the graph's output buffers
+            states = [{f: out[f][i].clone() for f in ("x", "u", "lam")} for i in range(k)]
             ev = torch.cuda.Event(enable_timing=True)
             ev.record(s)
-        return (sid, ev, out, host_out, dev)
+        return (sid, ev, states, host_out, dev)
 
     def poll(self, h) -> bool:
         return h[1].query()
 
     def collect(self, h):
-        sid, ev, out, host_out, _ = h
+        sid, ev, states, host_out, _ = h
         done_ms = self.t0.elapsed_time(ev)
         k = host_out["x"].shape[0]
         results = [{f: host_out[f][i].numpy() for f in host_out} for i in range(k)]
-        states = [{f: out[f][i] for f in ("x", "u", "lam")} for i in range(k)]
         self.free.append(sid)
         return results, done_ms, states
 
 
 def latency_report(done, t_first: float = 0.0) -> dict:
-    """p50/p99 latency (ms, arrival -> device completion) and throughput."""
+    """p50/p99 latency (ms, arrival -> device completion) and throughput,
+    overall and per request shape."""
     lat = np.array([r.done_ms - 1e3 * r.arrival for r in done])
     span = (max(r.done_ms for r in done) - 1e3 * min(r.arrival for r in done)) * 1e-3
+    per = {}
+    for shape in sorted({r.shape for r in done}):
+        ls = np.array([r.done_ms - 1e3 * r.arrival for r in done if r.shape == shape])
+        per["N%d_n%d_m%d" % shape] = {"requests": int(ls.size), "p50_ms": float(np.percentile(ls, 50)),
+                                      "p99_ms": float(np.percentile(ls, 99))}
     return {"requests": len(done), "p50_ms": float(np.percentile(lat, 50)),
             "p99_ms": float(np.percentile(lat, 99)), "max_ms": float(lat.max()),
-            "solves_per_s": len(done) / span if span > 0 else float("inf")}
+            "solves_per_s": len(done) / span if span > 0 else float("inf"), "per_shape": per}

@@ -61,13 +61,17 @@ def test_warm_start_same_solution(N, n, m):
 
 
 def _clients():
-    """(shape generator, seed) per client: SRBD-like, whole-body-like and a
-    large-block shape (short horizon to keep the test quick)."""
+    """(shape generator, seed) per client: SRBD-shaped at N = 25 and 100,
+    whole-body-shaped at N = 50 and 100, the multi-robot shape (n = m = 192,
+    N = 50) and another large-block shape."""
     gens = []
     for c in range(3):
         gens.append(lambda k, c=c: synth.gen_c2(25, c))
+    gens.append(lambda k: synth.gen_c2(100, 5))
     for c in range(2):
         gens.append(lambda k, c=c: synth.gen_c1_like(50, 36, 12, [710, c]))
+    gens.append(lambda k: synth.gen_c3(3))
+    gens.append(lambda k: synth.gen_c4(0))
     gens.append(lambda k: synth.gen_rand(8, 70, 70, seed=[720]))
     return gens
 
@@ -96,13 +100,13 @@ def _alone(req):
     return run(batch, np.float32, want_resid=True)
 
 
-@pytest.mark.parametrize("warm", [False, True])
-def test_serving_mix_equals_alone(warm):
+@pytest.mark.parametrize("warm,graphs", [(False, False), (True, False), (False, True), (True, True)])
+def test_serving_mix_equals_alone(warm, graphs):
     from paper_2506_07823_amd.serve import GpuBackend, Server, latency_report
     reqs = _stream()
-    say(f"[serving] {len(reqs)} mixed requests, warm={warm}")
-    be = GpuBackend(nstreams=3, refine=1)
-    srv = Server(be, budget_bytes=1 << 30, max_batch=16, warm=warm)
+    say(f"[serving] {len(reqs)} mixed requests, warm={warm}, graph replay={graphs}")
+    be = GpuBackend(nstreams=3, refine=1, graphs=graphs)
+    srv = Server(be, budget_bytes=16 << 30, max_batch=16, warm=warm)
     done = srv.run(reqs)
     assert len(done) == len(reqs)
     rep = latency_report(done)
@@ -119,3 +123,5 @@ def test_serving_mix_equals_alone(warm):
                 assert np.array_equal(r.result[f], a[f][0]), (r.rid, f)
     if warm:
         assert sum(r.warm for r in done) >= len(done) - len(_clients())
+    if graphs:
+        assert be.graph_replays > 0
