@@ -362,6 +362,87 @@ def batch_sweep_leg(L, batches=(16, 64, 256, 1024), steps: int = 10):
     return rows
 
 
+def resolve_leg(L, batch=BATCH, replays=20):
+    """Whole-body batch: a full solve, then lqr_kkt_resolve with new
+    (x0, c, q, r) (the factors cached in the workspace reused), both as graph
+    replays: the real-time-iteration re-solve against the full solve."""
+    import torch
+    import synth
+    host = synth.gen_batch(synth.gen_c3, batch, np.float32)
+    dev = {k: torch.from_numpy(v).to("cuda:0") for k, v in host.items()}
+    del host
+    ws = L.Workspace()
+    out = L.solve(*[dev[k] for k in L.FIELDS], workspace=ws, want_resid=True, refine=1)
+    torch.cuda.synchronize()
+    dev2 = dict(dev)
+    g = torch.Generator(device="cpu").manual_seed(11)
+    for f, sd in (("x0", 1e-2), ("q", 1e-1)):
+        dev2[f] = dev[f] + (sd * torch.randn(dev[f].shape, generator=g)).to("cuda:0")
+    L.resolve(*[dev2[k] for k in L.FIELDS], out=out, workspace=ws, want_resid=True, refine=1)
+    torch.cuda.synchronize()
+    gr = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gr):
+        L.resolve(*[dev2[k] for k in L.FIELDS], out=out, workspace=ws, want_resid=True, refine=1)
+    gs = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gs):
+        L.solve(*[dev[k] for k in L.FIELDS], workspace=ws, want_resid=True, refine=1, out=out)
+    times = {}
+    for name, gg in (("solve", gs), ("resolve", gr)):
+        gg.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(replays):
+            gg.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        times[name] = e0.elapsed_time(e1) / replays
+    gr.replay()
+    torch.cuda.synchronize()
+    res = {"workload": f"whole-body-shaped, batch {batch}: full solve, then new x0 and q with the same matrices",
+           "solve_ms": times["solve"], "resolve_ms": times["resolve"], "speedup": times["solve"] / times["resolve"],
+           "resolve_solves_per_s": batch / times["resolve"] * 1e3,
+           "resolve_max_rel_kkt_residual": out["resid"].max().item(),
+           "instances_with_status": int(out["status"].ne(0).sum().item())}
+    log(f"[bench] resolve: solve {times['solve']:.2f} ms, resolve {times['resolve']:.2f} ms")
+    return res
+
+
+def sqp_leg(L, batch=1024, iters=10):
+    """Batched SQP iterations (linearize, QP blocks, scan solve, parallel
+    filter line search, update) on the synthetic bilinear model at the
+    whole-body shape with 24 constraints; ms per iteration and the step
+    lengths taken."""
+    import torch
+    import synth
+    N, n, m, nc = 100, 36, 12, 24
+    mb = synth.gen_bilinear_batch(batch, N, n, m, nc, [7], 0.05, dtype=np.float32)
+    md = {k: torch.from_numpy(np.ascontiguousarray(mb[k])).to("cuda:0") for k in L.MODEL_FIELDS}
+    md["gamma"] = mb["gamma"]
+
+    def start():
+        X = torch.from_numpy(np.ascontiguousarray(np.repeat(mb["xhat0"][:, None, :], N + 1, axis=1))).to("cuda:0")
+        return X, torch.zeros((batch, N, m), device="cuda:0"), torch.zeros((batch, N + 1, n), device="cuda:0")
+
+    X, U, Lm = start()
+    L.sqp_solve(md, X, U, Lm, iters=1)
+    torch.cuda.synchronize()
+    X, U, Lm = start()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    st, al = L.sqp_solve(md, X, U, Lm, iters=iters)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / iters
+    alphas = al.cpu().numpy()
+    res = {"workload": f"bilinear model, n=36 m=12 N=100, 24 constraints, batch {batch}, FP32",
+           "iterations": iters, "ms_per_iteration": ms, "instance_iterations_per_s": batch / ms * 1e3,
+           "mean_step": float(alphas.mean()), "full_steps_last_iteration": int((alphas[-1] == 1.0).sum()),
+           "line_search_rejections": int((st.cpu().numpy() & 32 != 0).sum())}
+    log(f"[bench] sqp: {ms:.2f} ms per iteration of {batch} instances")
+    return res
+
+
 def serving_leg(L, n_clients: int, warm_requests: int, sat_requests: int, requests: int, loads=(0.5, 0.7, 0.9),
                 graphs: bool = True):
     """Serving mix through the continuous-batching loop: a saturated run
@@ -440,11 +521,16 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-mix workload")
     ap.add_argument("--no-latency", action="store_true", help="skip the single-solve latency workload")
     ap.add_argument("--no-sweep", action="store_true", help="skip the whole-body batch-size sweep")
+    ap.add_argument("--no-resolve", action="store_true", help="skip the cached-factor re-solve leg")
+    ap.add_argument("--no-sqp", action="store_true", help="skip the SQP-iteration leg")
     ap.add_argument("--serving-requests", type=int, default=10000, help="requests per offered load")
     ap.add_argument("--replays", type=int, default=LAT_REPLAYS, help="graph replays of the p50/p99 loop")
     ap.add_argument("--no-tune", action="store_true", help="use the default mapping instead of autotuning it")
     ap.add_argument("--split", action="store_true",
                     help="pin the split schedule (wavefront engine) for the whole-body workload instead of autotuning")
+    ap.add_argument("--sequential", action="store_true",
+                    help="pin the chunked schedule with chunk 1 and sequential vector passes (the mapping the "
+                         "autotuner picks for the whole-body batch) instead of autotuning")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of graph replays")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (calibrates the HBM byte "
@@ -469,8 +555,9 @@ def main():
     import synth
 
     wb, fams = measure(L, synth.gen_c3, BATCH, a.steps, a.warmup, a.eager, 1, not a.no_plain, "whole-body",
-                       tune=not a.no_tune, pin=({"engine": "wavefront", "fused": 0, "split": True}
-                                                if a.split else None), replays=a.replays)
+                       tune=not a.no_tune, pin=({"engine": "wavefront", "fused": 0, "split": True} if a.split else
+                                                {"engine": "wavefront", "fused": 0, "split": 2, "chunk": 1, "sweep": 1,
+                                                 "fwd_seq": True} if a.sequential else None), replays=a.replays)
     result = {
         "metric": METRIC, "value": wb.pop("value"), "unit": "solves/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": wb.pop("ms_per_step"), "higher_is_better": True,
@@ -507,6 +594,10 @@ def main():
         result["latency"] = latency_leg(L)
     if not a.no_sweep:
         result["batch_sweep"] = batch_sweep_leg(L)
+    if not a.no_resolve:
+        result["resolve"] = resolve_leg(L)
+    if not a.no_sqp:
+        result["sqp"] = sqp_leg(L)
     if not a.no_serving:
         result["serving"] = serving_leg(L, 40, max(100, a.serving_requests // 10), max(200, a.serving_requests // 5),
                                         a.serving_requests)
