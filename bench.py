@@ -55,7 +55,9 @@ LAT_REPLAYS = 200   # graph replays of the dedicated p50/p99 loops
 # FETCH_SIZE / WRITE_SIZE runs, calibrated against a copy of known size;
 # valid only for the kernel and launch sources they were taken on (hash of
 # every source file of the library)
-TRAFFIC = {"kernel": None, "src_hash": None, "bytes_per_launch": None, "note": None}
+TRAFFIC = {"kernel": "chunk_mid", "src_hash": "d95383a8ecc1dcc0", "bytes_per_launch": 10.572e9,
+           "note": "rocprofv3 FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (factors from a 1 GiB device copy), "
+                   "16 eager dispatches of k_chunk_mid at batch 4096, chunk 1: 8.383 + 2.189 GB per launch"}
 
 
 def kernel_src_hash() -> str:
@@ -343,22 +345,29 @@ def batch_sweep_leg(L, batches=(16, 64, 256, 1024), steps: int = 10):
         wall, lat, _, resid, bad = timed_steps(L, dev, "scan", steps, 2, False, graph=True, refine=1)
         fwall, flat, _, fresid, fbad = fused_steps(L, dev, 100, 36, 12, B, steps)
         swall, slat, _, sresid, sbad = fused_steps(L, dev, 100, 36, 12, B, steps, fused=0, split=True)
+        qwall, qlat, _, qresid, qbad = fused_steps(L, dev, 100, 36, 12, B, steps, fused=0, split=2, chunk=1,
+                                                   sweep=1, fwd_seq=True)
         dev64 = {k: v.double() for k, v in dev.items()}
         pwall, plat, _, presid, pbad = timed_steps(L, dev64, "plain", steps, 2, False, graph=True)
         rows[f"B{B}"] = {"scan_solves_per_s": B * steps / wall, "one_launch_solves_per_s": B * steps / fwall,
-                         "split_solves_per_s": B * steps / swall, "plain_solves_per_s": B * steps / pwall,
+                         "split_solves_per_s": B * steps / swall, "sequential_solves_per_s": B * steps / qwall,
+                         "plain_solves_per_s": B * steps / pwall,
                          "scan_p50_ms": float(np.percentile(lat, 50)), "one_launch_p50_ms": float(np.percentile(flat, 50)),
-                         "split_p50_ms": float(np.percentile(slat, 50)), "plain_p50_ms": float(np.percentile(plat, 50)),
-                         "scan_rel_kkt_residual": max(resid, fresid, sresid),
-                         "instances_with_status": bad + fbad + sbad + pbad}
+                         "split_p50_ms": float(np.percentile(slat, 50)),
+                         "sequential_p50_ms": float(np.percentile(qlat, 50)),
+                         "plain_p50_ms": float(np.percentile(plat, 50)),
+                         "scan_rel_kkt_residual": max(resid, fresid, sresid, qresid),
+                         "instances_with_status": bad + fbad + sbad + qbad + pbad}
         log(f"[bench] batch {B}: scan {rows[f'B{B}']['scan_solves_per_s']:.0f}/s, "
             f"one launch {rows[f'B{B}']['one_launch_solves_per_s']:.0f}/s, "
             f"split {rows[f'B{B}']['split_solves_per_s']:.0f}/s, "
+            f"chunk 1 {rows[f'B{B}']['sequential_solves_per_s']:.0f}/s, "
             f"plain {rows[f'B{B}']['plain_solves_per_s']:.0f}/s")
         del dev, dev64
     rows["workload"] = ("whole-body-shaped (n=36, m=12, N=100), hipGraph replays: default mapping (level-by-level "
                         "launches, balanced tree), the one-launch form, the split schedule (tree over 64 elements, "
-                        "sequential sweep over 37), and the FP64 plain sweep")
+                        "sequential sweep over 37), the chunked schedule with chunk 1 and sequential vector passes, and the "
+                        "FP64 plain sweep")
     return rows
 
 
@@ -459,7 +468,10 @@ def serving_leg(L, n_clients: int, warm_requests: int, sat_requests: int, reques
     pinned = [{k: torch.from_numpy(np.ascontiguousarray(v, np.float32)).pin_memory()
                for k, v in model.items() if k != "x0"} for model, _ in clients]
     total = warm_requests + sat_requests + requests * len(loads) + 1
-    walks = [synth.x0_walk(model, seed, total) for model, seed in clients]
+    # one page-locked block per client holds all its initial states (a
+    # request takes a row view): no page-locked allocation per request
+    walks = [torch.from_numpy(synth.x0_walk(model, seed, total).astype(np.float32)).pin_memory()
+             for model, seed in clients]
     used = [0] * len(clients)
     rng = np.random.default_rng([5, 4])
 
@@ -470,7 +482,7 @@ def serving_leg(L, n_clients: int, warm_requests: int, sat_requests: int, reques
             if rate:
                 t += rng.exponential(1.0 / rate)
             data = dict(pinned[c])
-            data["x0"] = torch.from_numpy(walks[c][used[c]].astype(np.float32)).pin_memory()
+            data["x0"] = walks[c][used[c]]
             used[c] += 1
             reqs.append(Request(rid=rid0 + j, client=c, data=data, arrival=t))
         return reqs

@@ -343,7 +343,9 @@ class GpuBackend:
         sid, ev, states, host_out, _ = h
         done_ms = self.t0.elapsed_time(ev)
         k = host_out["x"].shape[0]
-        results = [{f: host_out[f][i].numpy() for f in host_out} for i in range(k)]
+        # copies, not views: a view would pin the whole batch's page-locked
+        # block for as long as the request's result lives
+        results = [{f: host_out[f][i].numpy().copy() for f in host_out} for i in range(k)]
         self.free.append(sid)
         return results, done_ms, states
 
