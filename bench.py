@@ -253,6 +253,19 @@ def measure(L, gen, batch, steps, warmup, eager, refine, plain, label, tune=True
     lat = replay_latency(L, dev, "scan", refine, replays)
     log(f"[bench] {label}: FP32 scan, kernel timing pass (eager, HIP events around every launch)")
     _, _, fams, _, _ = timed_steps(L, dev, "scan", max(3, steps // 5), 1, True, refine=refine)
+    fams_split = None
+    if isinstance(mapping, dict) and mapping.get("streams", 0) > 1:
+        # The batch split over streams overlaps the parts' launches, so a
+        # launch's event-to-event time also holds other parts' GPU time.
+        # The kernels' own rates come from a second pass of the same mapping
+        # on one stream (each launch then has the GPU to itself).
+        fams_split = fams
+        one = mapping_kwargs(mapping)
+        one["streams"] = 0
+        log(f"[bench] {label}: FP32 scan, kernel timing pass of the same mapping on one stream")
+        L.set_tuning(batch, N_, n_, m_, torch.float32, **one)
+        _, _, fams, _, _ = timed_steps(L, dev, "scan", max(3, steps // 5), 1, True, refine=refine)
+        L.set_tuning(batch, N_, n_, m_, torch.float32, **mapping_kwargs(mapping))
     tol = L.default_opts().refine_tol
     r = {"value": batch * steps / wall, "unit": "solves/s", "steps": steps, "ms_per_step": 1e3 * wall / steps,
          "p50_ms": lat["p50_ms"], "p99_ms": lat["p99_ms"], "latency_replays": replays,
@@ -260,6 +273,13 @@ def measure(L, gen, batch, steps, warmup, eager, refine, plain, label, tune=True
          "refinement": {"sweeps": refine, **residual_profile(L, dev, tol)}}
     steps_t = fams["clear"]["launches"] if "clear" in fams else 1
     r["kernel_ms_per_step"] = {f: v["ms"] / steps_t for f, v in fams.items()}
+    if fams_split is not None:
+        st = mapping["streams"]
+        r["kernel_timing"] = "eager pass of the same mapping on one stream (kernel_ms_per_step, roofline)"
+        r["kernel_ms_per_step_overlapped"] = {
+            "note": f"eager pass with the batch in {st} parts on {st} streams: event-to-event time of each part's "
+                    f"launches, summed over the parts, which overlap one another",
+            **{f: v["ms"] / steps_t for f, v in fams_split.items()}}
     r["mapping"] = mapping
     # useful work: the plain sequential Riccati's count of the same solves
     plain_f = N_ * (4 * n_ ** 3 + 6 * n_ ** 2 * m_ + 4 * n_ * m_ ** 2 + m_ ** 3 / 3)
@@ -287,6 +307,14 @@ def measure(L, gen, batch, steps, warmup, eager, refine, plain, label, tune=True
         del dev
     torch.cuda.empty_cache()
     return r, fams
+
+
+def mapping_kwargs(mapping):
+    """set_tuning keyword arguments of an autotuned (or pinned) mapping."""
+    kw = {k: v for k, v in mapping.items() if k != "ms"}
+    if "fwd_seq" in kw:
+        kw["fwd_seq"] = bool(kw["fwd_seq"])
+    return kw
 
 
 def fused_steps(L, dev, N, n, m, batch, steps, **mapping):
@@ -543,6 +571,8 @@ def main():
     ap.add_argument("--sequential", action="store_true",
                     help="pin the chunked schedule with chunk 1 and sequential vector passes (the mapping the "
                          "autotuner picks for the whole-body batch) instead of autotuning")
+    ap.add_argument("--streams", type=int, default=0,
+                    help="with --sequential: also pin the batch split over this many streams")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of graph replays")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (calibrates the HBM byte "
@@ -569,7 +599,8 @@ def main():
     wb, fams = measure(L, synth.gen_c3, BATCH, a.steps, a.warmup, a.eager, 1, not a.no_plain, "whole-body",
                        tune=not a.no_tune, pin=({"engine": "wavefront", "fused": 0, "split": True} if a.split else
                                                 {"engine": "wavefront", "fused": 0, "split": 2, "chunk": 1, "sweep": 1,
-                                                 "fwd_seq": True} if a.sequential else None), replays=a.replays)
+                                                 "fwd_seq": True, "streams": a.streams} if a.sequential else None),
+                       replays=a.replays)
     result = {
         "metric": METRIC, "value": wb.pop("value"), "unit": "solves/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": wb.pop("ms_per_step"), "higher_is_better": True,

@@ -330,7 +330,19 @@ int lqr_timing_report(lqr_handle_t h, char* buf, size_t len);
  *            terminal element is always in it)
  *   fwd_seq  1 = forward scan, control/costate recovery and refinement
  *            vector passes as sequential sweeps over the stages (one task
- *            unit per instance, no forward-tree map products); fused 0 or 1 */
+ *            unit per instance, no forward-tree map products); fused 0 or 1
+ *   streams  0 or 1 = the whole batch on the caller's stream; 2..4 = the
+ *            batch in that many contiguous parts of ceil(batch / streams)
+ *            instances, part 0 on the caller's stream and the others on
+ *            side streams of the handle that wait for the work queued on
+ *            the caller's stream before the call and that the caller's
+ *            stream waits for after it (so the call stays asynchronous and
+ *            stream-ordered, and can be captured into a graph).  The parts'
+ *            launch sequences overlap on the GPU.  Each part has its own
+ *            slice of the workspace; lqr_kkt_resolve and lqr_kkt_factors
+ *            of the shape find the records in the same slices as long as
+ *            the mapping is unchanged.  A handle's calls must not overlap
+ *            (they share the side streams).  Ignored by the plain method. */
 typedef struct {
     int32_t engine;
     int32_t fused;
@@ -340,6 +352,7 @@ typedef struct {
     int32_t chunk;
     int32_t sweep;
     int32_t fwd_seq;
+    int32_t streams;
 } lqr_tuning;
 
 /* Pin (t != NULL) or clear (t == NULL) the mapping of the shape
@@ -356,7 +369,9 @@ int lqr_set_tuning(lqr_handle_t h, int64_t batch, int N, int n, int m, int32_t d
  * the wavefront engine), the reverse-scan schedules of the wavefront engine
  * (balanced tree, split, chunked with chunk 1 / 4 / 8 / 16 / 32 and a
  * one-element sweep), matrix-core grids of 256 / 512 / 1024
- * workgroups -- then `reps` more times on the stream, timed with HIP events;
+ * workgroups, and the three fastest of these again with the batch split
+ * over 2 and 4 streams -- then `reps` more times on the stream, timed with
+ * HIP events;
  * candidates whose status words are not clean (other than the FP64-fallback
  * bit) or whose workspace does not fit are skipped.  The fastest mapping is
  * stored on the handle for this shape (as lqr_set_tuning) and written to

@@ -52,7 +52,7 @@ class lqr_opts(ctypes.Structure):
 class lqr_tuning(ctypes.Structure):
     _fields_ = [("engine", ctypes.c_int32), ("fused", ctypes.c_int32), ("big_grid", ctypes.c_int32),
                 ("ms", ctypes.c_float), ("split", ctypes.c_int32), ("chunk", ctypes.c_int32),
-                ("sweep", ctypes.c_int32), ("fwd_seq", ctypes.c_int32)]
+                ("sweep", ctypes.c_int32), ("fwd_seq", ctypes.c_int32), ("streams", ctypes.c_int32)]
 
 
 class lqr_problem(ctypes.Structure):
@@ -601,12 +601,13 @@ def autotune(A, B, c, Q, R, M, q, r, x0, *, method: str = "scan", refine: int | 
                              ctypes.byref(best)))
     return {"engine": {1: "wavefront", 2: "matrix-core"}[best.engine], "fused": int(best.fused),
             "big_grid": int(best.big_grid), "split": int(best.split), "chunk": int(best.chunk),
-            "sweep": int(best.sweep), "fwd_seq": int(best.fwd_seq), "ms": float(best.ms)}
+            "sweep": int(best.sweep), "fwd_seq": int(best.fwd_seq), "streams": int(best.streams),
+            "ms": float(best.ms)}
 
 
 def set_tuning(batch: int, N: int, n: int, m: int, dtype=torch.float32, *, engine: str | None = None,
                fused: bool | int | None = None, big_grid: int = 0, split: bool | int = False, chunk: int = 0,
-               sweep: int = 0, fwd_seq: bool = False, device: int = 0, clear: bool = False):
+               sweep: int = 0, fwd_seq: bool = False, streams: int = 0, device: int = 0, clear: bool = False):
     """Pin (or clear) the mapping of a problem shape on the device's handle.
 
     fused: None = default; 0 / False = vector-only passes level by level;
@@ -616,7 +617,9 @@ def set_tuning(batch: int, N: int, n: int, m: int, dtype=torch.float32, *, engin
     elements, a sequential sweep over the rest), 2 = chunked (`sweep`
     elements swept sequentially, chunks of `chunk` elements over the rest);
     wavefront engine, fused 0 or 1.  fwd_seq: sequential forward and
-    refinement vector passes (no forward-tree products)."""
+    refinement vector passes (no forward-tree products).  streams: 2..4
+    splits the batch into that many contiguous parts whose launch sequences
+    run on forked streams (0 or 1: one stream)."""
     dt = LQR_F32 if dtype == torch.float32 else LQR_F64
     if clear:
         _check(_lib.lqr_set_tuning(handle(device), batch, N, n, m, dt, None))
@@ -629,6 +632,7 @@ def set_tuning(batch: int, N: int, n: int, m: int, dtype=torch.float32, *, engin
     t.chunk = int(chunk)
     t.sweep = int(sweep)
     t.fwd_seq = 1 if fwd_seq else 0
+    t.streams = int(streams)
     _check(_lib.lqr_set_tuning(handle(device), batch, N, n, m, dt, ctypes.byref(t)))
 
 

@@ -83,7 +83,12 @@ struct Tuning {
     int chunk = 0;      // chunked schedule: chunk length (>= 1)
     int sweep = 0;      // chunked schedule: leaves of the sequential sweep (>= 1, the terminal included)
     int fwd_seq = 0;    // 1: sequential forward and refinement vector passes
+    int streams = 0;    // 2..kMaxParts: the batch in that many contiguous parts, one stream each
 };
+
+// Most parts of a batch split over streams (part 0 on the caller's stream,
+// the others on the handle's side streams)
+constexpr int kMaxParts = 4;
 
 int pick_ts(int n, int m, const Tuning* t) {
     const int ts = pick_ts(n, m);
@@ -182,6 +187,36 @@ Layout layout(const Plan& p, size_t esize) {
 }
 
 bool aligned(const void* ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
+
+// A batch split over streams: `count` contiguous parts of `size` instances
+// (the last may be smaller), each with a workspace slice of `bytes`.
+struct Parts {
+    int count;
+    int64_t size;
+    size_t bytes;
+};
+
+Parts parts_of(int64_t batch, int N, int n, int m, size_t es, const lqr_opts& o, const Tuning* tun) {
+    Parts r;
+    int k = tun && tun->streams > 1 ? std::min(tun->streams, kMaxParts) : 1;
+    if (o.method == LQR_METHOD_SEQ_RICCATI || k > batch) k = 1;
+    r.size = (batch + k - 1) / k;
+    r.count = (int)((batch + r.size - 1) / r.size);
+    // slices always hold the FP64 redo area, so that their offsets do not
+    // depend on the call's options (a re-solve or a factor read-back of
+    // this shape finds the records where the solve left them)
+    lqr_opts of = o;
+    of.fallback = 1;
+    r.bytes = (size_t)align_up((int64_t)layout(make_plan(r.size, N, n, m, es, of, tun), es).total, 256);
+    return r;
+}
+
+// workspace bytes of a solve (every part's slice)
+size_t solve_bytes(int64_t batch, int N, int n, int m, size_t es, const lqr_opts& o, const Tuning* tun) {
+    const Parts pt = parts_of(batch, N, n, m, es, o, tun);
+    if (pt.count == 1) return layout(make_plan(batch, N, n, m, es, o, tun), es).total;
+    return pt.bytes * (size_t)pt.count;
+}
 
 int check_dims(int64_t batch, int N, int n, int m) {
     if (batch < 1) return fail(LQR_EINVAL, "batch must be >= 1 (got %lld)", (long long)batch);
@@ -287,6 +322,19 @@ struct lqr_handle_s {
     // what the tuning cache file holds)
     std::map<std::tuple<int64_t, int, int, int, int>, Tuning> tuned, cached;
     const Tuning* find(int64_t batch, int N, int n, int m, int dtype) const;
+    // side streams of a batch split over streams (non-blocking, default
+    // priority) and the events that fork them from the caller's stream and
+    // join them back; made with the handle, so that a solve under stream
+    // capture creates nothing
+    hipStream_t side[kMaxParts - 1] = {};
+    hipEvent_t fork = nullptr, join[kMaxParts - 1] = {};
+    ~lqr_handle_s() {
+        for (hipStream_t st : side)
+            if (st) (void)hipStreamDestroy(st);
+        for (hipEvent_t ev : join)
+            if (ev) (void)hipEventDestroy(ev);
+        if (fork) (void)hipEventDestroy(fork);
+    }
 };
 
 extern "C" {
@@ -327,6 +375,19 @@ int lqr_create(lqr_handle_t* h, int device) {
     }
     lqr_handle_s* hh = new lqr_handle_s;
     hh->device = device;
+    int prev = 0;
+    hipError_t e = hipGetDevice(&prev);
+    if (e == hipSuccess) e = hipSetDevice(device);
+    for (int i = 0; i < kMaxParts - 1 && e == hipSuccess; ++i) {
+        e = hipStreamCreateWithFlags(&hh->side[i], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&hh->join[i], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&hh->fork, hipEventDisableTiming);
+    (void)hipSetDevice(prev);
+    if (e != hipSuccess) {
+        delete hh;
+        return fail(LQR_EDEVICE, "creating the handle's side streams: %s", hipGetErrorString(e));
+    }
     *h = hh;
     return LQR_OK;
 }
@@ -349,7 +410,7 @@ int lqr_workspace_size(lqr_handle_t h, int64_t batch, int N, int n, int m, const
     if (o.dtype != LQR_F32 && o.dtype != LQR_F64) return fail(LQR_EINVAL, "bad dtype %d", o.dtype);
     const size_t es = o.dtype == LQR_F32 ? 4 : 8;
     const Tuning* tun = h ? h->find(batch, N, n, m, o.dtype) : nullptr;
-    *bytes = layout(make_plan(batch, N, n, m, es, o, tun), es).total;
+    *bytes = solve_bytes(batch, N, n, m, es, o, tun);
     return LQR_OK;
 }
 
@@ -421,33 +482,76 @@ int solve_impl(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int m,
         if (!aligned(o.warm_x, es) || !aligned(o.warm_u, es) || !aligned(o.warm_lam, es))
             return fail(LQR_EINVAL, "misaligned warm start");
     }
-    Plan p = make_plan(batch, N, n, m, es, o, tun);
-    if (!sched_fits(p)) return fail(LQR_EINVAL, "chunked schedule does not fit the tree records of N=%d", N);
-    const Layout lay = layout(p, es);
-    if (workspace_bytes < lay.total)
-        return fail(LQR_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", workspace_bytes, lay.total);
-    p.o_scr = (int64_t)lay.scr_off;
+    if (!sched_fits(make_plan(1, N, n, m, es, o, tun)))
+        return fail(LQR_EINVAL, "chunked schedule does not fit the tree records of N=%d", N);
+    const Parts pt = parts_of(batch, N, n, m, es, o, tun);
+    const size_t need = solve_bytes(batch, N, n, m, es, o, tun);
+    if (workspace_bytes < need)
+        return fail(LQR_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", workspace_bytes, need);
     HIPCHK(hipSetDevice(h->device));
     hipStream_t s = (hipStream_t)stream;
-    char* wsb = (char*)workspace;
     const int ts = pick_ts(n, m, tun);
-    const Ctx cx = make_ctx(p, lay, wsb, ts == kBigTS);
     const int refine = o.method != LQR_METHOD_SEQ_RICCATI ? o.refine_sweeps : 0;
-    int rc;
+    // instances [b0, b0 + cnt) on stream sj with the workspace at wsb
+    auto run_part = [&](int64_t b0, int64_t cnt, hipStream_t sj, char* wsb) -> int {
+        Plan p = make_plan(cnt, N, n, m, es, o, tun);
+        const Layout lay = layout(p, es);
+        p.o_scr = (int64_t)lay.scr_off;
+        const Ctx cx = make_ctx(p, lay, wsb, ts == kBigTS);
+        const int64_t sN = b0 * N, sN1 = b0 * (N + 1);
+        double* rout = o.resid_out ? o.resid_out + b0 : nullptr;
+        if (o.dtype == LQR_F32) {
+            using F = float;
+            In<F> in{(const F*)A + sN * n * n, (const F*)B + sN * n * m, (const F*)c + sN * n,
+                     (const F*)Q + sN1 * n * n, (const F*)R + sN * m * m, (const F*)M + sN * n * m,
+                     (const F*)q + sN1 * n, (const F*)r + sN * m, (const F*)x0 + b0 * n};
+            Out<F> out{(F*)x + sN1 * n, (F*)u + sN * m, (F*)lam + sN1 * n, status + b0};
+            const Warm<F> warm{o.warm_x ? (const F*)o.warm_x + sN1 * n : nullptr,
+                               o.warm_u ? (const F*)o.warm_u + sN * m : nullptr,
+                               o.warm_lam ? (const F*)o.warm_lam + sN1 * n : nullptr};
+            return dispatch<F>(ts, o.method, p, sj, in, out, (F*)wsb, cx, refine, rout, warm);
+        } else {
+            using F = double;
+            In<F> in{(const F*)A + sN * n * n, (const F*)B + sN * n * m, (const F*)c + sN * n,
+                     (const F*)Q + sN1 * n * n, (const F*)R + sN * m * m, (const F*)M + sN * n * m,
+                     (const F*)q + sN1 * n, (const F*)r + sN * m, (const F*)x0 + b0 * n};
+            Out<F> out{(F*)x + sN1 * n, (F*)u + sN * m, (F*)lam + sN1 * n, status + b0};
+            const Warm<F> warm{o.warm_x ? (const F*)o.warm_x + sN1 * n : nullptr,
+                               o.warm_u ? (const F*)o.warm_u + sN * m : nullptr,
+                               o.warm_lam ? (const F*)o.warm_lam + sN1 * n : nullptr};
+            return dispatch<F>(ts, o.method, p, sj, in, out, (F*)wsb, cx, refine, rout, warm);
+        }
+    };
+    int rc = LQR_OK;
     {
         TimerScope ts_scope(h->timing ? &h->timer : nullptr);
-        if (o.dtype == LQR_F32) {
-            In<float> in{(const float*)A, (const float*)B, (const float*)c, (const float*)Q, (const float*)R,
-                         (const float*)M, (const float*)q, (const float*)r, (const float*)x0};
-            Out<float> out{(float*)x, (float*)u, (float*)lam, status};
-            const Warm<float> warm{(const float*)o.warm_x, (const float*)o.warm_u, (const float*)o.warm_lam};
-            rc = dispatch<float>(ts, o.method, p, s, in, out, (float*)wsb, cx, refine, o.resid_out, warm);
+        if (pt.count == 1) {
+            rc = run_part(0, batch, s, (char*)workspace);
         } else {
-            In<double> in{(const double*)A, (const double*)B, (const double*)c, (const double*)Q, (const double*)R,
-                          (const double*)M, (const double*)q, (const double*)r, (const double*)x0};
-            Out<double> out{(double*)x, (double*)u, (double*)lam, status};
-            const Warm<double> warm{(const double*)o.warm_x, (const double*)o.warm_u, (const double*)o.warm_lam};
-            rc = dispatch<double>(ts, o.method, p, s, in, out, (double*)wsb, cx, refine, o.resid_out, warm);
+            // fork: every side stream waits for the work queued so far on
+            // the caller's stream; join: the caller's stream waits for every
+            // side stream that was forked (also after an error, so that no
+            // side stream is left outside a stream capture)
+            HIPCHK(hipEventRecord(h->fork, s));
+            int forked = 0;
+            for (int j = 0; j < pt.count && rc == LQR_OK; ++j) {
+                hipStream_t sj = s;
+                if (j > 0) {
+                    if (hipStreamWaitEvent(h->side[j - 1], h->fork, 0) != hipSuccess) {
+                        rc = fail(LQR_EDEVICE, "forking side stream %d failed", j);
+                        break;
+                    }
+                    forked = j;
+                    sj = h->side[j - 1];
+                }
+                const int64_t b0 = j * pt.size;
+                rc = run_part(b0, std::min(pt.size, batch - b0), sj, (char*)workspace + (size_t)j * pt.bytes);
+            }
+            for (int j = 1; j <= forked; ++j) {
+                const hipError_t e1 = hipEventRecord(h->join[j - 1], h->side[j - 1]);
+                const hipError_t e2 = e1 == hipSuccess ? hipStreamWaitEvent(s, h->join[j - 1], 0) : e1;
+                if (e2 != hipSuccess && rc == LQR_OK) rc = fail(LQR_EDEVICE, "joining side stream %d failed", j);
+            }
         }
     }
     if (rc != LQR_OK || !o.sync_status) return rc;
@@ -484,7 +588,7 @@ int lqr_kkt_solve_noalloc(lqr_handle_t h, void* stream, int64_t batch, int N, in
     if (o.dtype != LQR_F32 && o.dtype != LQR_F64) return fail(LQR_EINVAL, "bad dtype %d", o.dtype);
     const Tuning* tun = h->find(batch, N, n, m, o.dtype);
     const size_t es = o.dtype == LQR_F32 ? 4 : 8;
-    const size_t need = layout(make_plan(batch, N, n, m, es, o, tun), es).total;
+    const size_t need = solve_bytes(batch, N, n, m, es, o, tun);
     if (need > kNoAllocBytes)
         return fail(LQR_ENOMEM, "this solve needs %zu bytes of workspace, more than the %zu of the no-allocation "
                     "workspace; use lqr_kkt_solve with a caller workspace", need, kNoAllocBytes);
@@ -574,7 +678,7 @@ GroupBytes group_bytes(const lqr_handle_s* h, const RaggedGroup& g, size_t es, c
     b.st = (size_t)align_up(k * 4, 256);
     b.rel = (size_t)align_up(k * 8, 256);
     const Tuning* tun = h ? h->find(k, g.N, g.n, g.m, o.dtype) : nullptr;
-    b.solve = layout(make_plan(k, g.N, g.n, g.m, es, o, tun), es).total;
+    b.solve = solve_bytes(k, g.N, g.n, g.m, es, o, tun);
     b.total = b.in + b.out + b.st + b.rel + b.solve;
     return b;
 }
@@ -715,6 +819,7 @@ Tuning from_abi(const lqr_tuning& t) {
     tu.chunk = t.chunk;
     tu.sweep = t.sweep;
     tu.fwd_seq = t.fwd_seq;
+    tu.streams = t.streams;
     return tu;
 }
 void to_abi(const Tuning& t, float ms, lqr_tuning* o) {
@@ -726,13 +831,15 @@ void to_abi(const Tuning& t, float ms, lqr_tuning* o) {
     o->chunk = t.chunk;
     o->sweep = t.sweep;
     o->fwd_seq = t.fwd_seq;
+    o->streams = t.streams;
 }
 
 int check_tuning(int N, int n, int m, const Tuning& t) {
     if (t.engine < 0 || t.engine > 2 || t.fused < -1 || t.fused > 2 || t.big_grid < 0 || t.split < 0 || t.split > 2 ||
-        t.chunk < 0 || t.sweep < 0 || t.fwd_seq < 0 || t.fwd_seq > 1)
-        return fail(LQR_EINVAL, "bad tuning (engine %d, fused %d, big_grid %d, split %d, chunk %d, sweep %d, fwd_seq %d)",
-                    t.engine, t.fused, t.big_grid, t.split, t.chunk, t.sweep, t.fwd_seq);
+        t.chunk < 0 || t.sweep < 0 || t.fwd_seq < 0 || t.fwd_seq > 1 || t.streams < 0 || t.streams > kMaxParts)
+        return fail(LQR_EINVAL,
+                    "bad tuning (engine %d, fused %d, big_grid %d, split %d, chunk %d, sweep %d, fwd_seq %d, streams %d)",
+                    t.engine, t.fused, t.big_grid, t.split, t.chunk, t.sweep, t.fwd_seq, t.streams);
     const bool big = t.engine == 2 || pick_ts(n, m) == kBigTS;
     if (t.split && (big || t.fused == 2))
         return fail(LQR_EINVAL, "the split and chunked schedules run on the wavefront engine with level-by-level launches");
@@ -966,39 +1073,56 @@ int lqr_autotune(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int 
     std::vector<int32_t> st((size_t)batch);
     float best_ms = -1.0f;
     Tuning best_t;
-    int rc = LQR_OK;
-    for (const Tuning& t : cands) {
+    // time one candidate: *ms < 0 if it does not fit or its status is not clean
+    auto time_one = [&](const Tuning& t, float* ms) -> int {
+        *ms = -1.f;
         const Plan pl = make_plan(batch, N, n, m, es, o, &t);
-        if (!sched_fits(pl) || layout(pl, es).total > workspace_bytes) continue;
+        if (!sched_fits(pl) || solve_bytes(batch, N, n, m, es, o, &t) > workspace_bytes) return LQR_OK;
         auto run = [&]() {
             return solve_impl(h, stream, batch, N, n, m, A, B, c, Q, R, M, q, r, x0, x, u, lam, status, workspace,
                               workspace_bytes, o, &t);
         };
-        if ((rc = run()) != LQR_OK) break;   // warm-up (and the status check below)
+        LCHK(run());   // warm-up (and the status check below)
         if (hipMemcpyAsync(st.data(), status, sizeof(int32_t) * (size_t)batch, hipMemcpyDeviceToHost, s) !=
-                hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
-            rc = fail(LQR_EDEVICE, "reading the status words failed");
-            break;
-        }
+                hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+            return fail(LQR_EDEVICE, "reading the status words failed");
         bool clean = true;
         for (int32_t v : st) clean = clean && (v & ~LQR_ST_FP64_FALLBACK) == 0;
-        if (!clean) continue;
+        if (!clean) return LQR_OK;
         (void)hipEventRecord(e0, s);
-        for (int i = 0; i < reps && rc == LQR_OK; ++i) rc = run();
-        if (rc != LQR_OK) break;
+        for (int i = 0; i < reps; ++i) LCHK(run());
         (void)hipEventRecord(e1, s);
-        if (hipEventSynchronize(e1) != hipSuccess) {
-            rc = fail(LQR_EDEVICE, "timing event failed");
-            break;
-        }
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        ms /= (float)reps;
-        if (best_ms < 0.f || ms < best_ms) {
-            best_ms = ms;
+        if (hipEventSynchronize(e1) != hipSuccess) return fail(LQR_EDEVICE, "timing event failed");
+        float t_ms = 0.f;
+        (void)hipEventElapsedTime(&t_ms, e0, e1);
+        *ms = t_ms / (float)reps;
+        if (best_ms < 0.f || *ms < best_ms) {
+            best_ms = *ms;
             best_t = t;
         }
+        return LQR_OK;
+    };
+    int rc = LQR_OK;
+    std::vector<std::pair<float, Tuning>> timed;
+    for (const Tuning& t : cands) {
+        float ms;
+        if ((rc = time_one(t, &ms)) != LQR_OK) break;
+        if (ms >= 0.f) timed.emplace_back(ms, t);
     }
+    // the three fastest mappings again with the batch split over 2 and 4
+    // streams (parts of at least 2 instances)
+    std::stable_sort(timed.begin(), timed.end(),
+                     [](const std::pair<float, Tuning>& x1, const std::pair<float, Tuning>& x2) {
+                         return x1.first < x2.first;
+                     });
+    for (size_t i = 0; i < timed.size() && i < 3 && rc == LQR_OK; ++i)
+        for (int k : {2, 4}) {
+            if (batch < 2 * k) continue;
+            Tuning t = timed[i].second;
+            t.streams = k;
+            float ms;
+            if ((rc = time_one(t, &ms)) != LQR_OK) break;
+        }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != LQR_OK) return rc;
@@ -1011,9 +1135,10 @@ int lqr_autotune(lqr_handle_t h, void* stream, int64_t batch, int N, int n, int 
 
 // Tuning cache file: one line per shape bucket,
 //   "lqr-tune-1 <arch> <dtype> <n> <m> <N bucket> <batch bucket> <engine> <fused> <big_grid> <split> <chunk>
-//    <sweep> <fwd_seq>"
-// (sizes rounded up to powers of two).  Lines of another device architecture
-// are kept in the file but not loaded.
+//    <sweep> <fwd_seq> [<streams>]"
+// (sizes rounded up to powers of two; a line without the last field maps
+// to one stream).  Lines of another device architecture are kept in the
+// file but not loaded.
 int lqr_tuning_save(lqr_handle_t h, const char* path) {
     if (!h || !path) return fail(LQR_EINVAL, "null handle or path");
     hipDeviceProp_t prop;
@@ -1035,9 +1160,9 @@ int lqr_tuning_save(lqr_handle_t h, const char* path) {
     for (const auto& kv : h->cached) {
         const auto& k = kv.first;
         const Tuning& t = kv.second;
-        std::fprintf(f, "lqr-tune-1 %s %d %d %d %lld %lld %d %d %d %d %d %d %d\n", arch.c_str(), std::get<4>(k),
+        std::fprintf(f, "lqr-tune-1 %s %d %d %d %lld %lld %d %d %d %d %d %d %d %d\n", arch.c_str(), std::get<4>(k),
                      std::get<2>(k), std::get<3>(k), (long long)std::get<1>(k), (long long)std::get<0>(k), t.engine,
-                     t.fused, t.big_grid, t.split, t.chunk, t.sweep, t.fwd_seq);
+                     t.fused, t.big_grid, t.split, t.chunk, t.sweep, t.fwd_seq, t.streams);
     }
     std::fclose(f);
     if (std::rename(tmp.c_str(), path) != 0) return fail(LQR_EINVAL, "cannot replace %s", path);
@@ -1058,9 +1183,10 @@ int lqr_tuning_load(lqr_handle_t h, const char* path) {
         int dt, n, m;
         long long Nb, Bb;
         Tuning t;
-        if (std::sscanf(line, "lqr-tune-1 %63s %d %d %d %lld %lld %d %d %d %d %d %d %d", a, &dt, &n, &m, &Nb, &Bb,
-                        &t.engine, &t.fused, &t.big_grid, &t.split, &t.chunk, &t.sweep, &t.fwd_seq) != 13)
-            continue;
+        const int got = std::sscanf(line, "lqr-tune-1 %63s %d %d %d %lld %lld %d %d %d %d %d %d %d %d", a, &dt, &n, &m,
+                                    &Nb, &Bb, &t.engine, &t.fused, &t.big_grid, &t.split, &t.chunk, &t.sweep,
+                                    &t.fwd_seq, &t.streams);
+        if (got != 13 && got != 14) continue;
         if (arch != a || n < 1 || m < 1 || Nb < 1 || Bb < 1) continue;
         if (check_tuning((int)Nb, n, m, t) != LQR_OK) continue;
         h->cached[std::make_tuple((int64_t)Bb, (int)Nb, n, m, dt)] = t;
@@ -1077,15 +1203,20 @@ int lqr_autotune_workspace_size(int64_t batch, int N, int n, int m, const lqr_op
     LCHK(check_dims(batch, N, n, m));
     if (o.dtype != LQR_F32 && o.dtype != LQR_F64) return fail(LQR_EINVAL, "bad dtype %d", o.dtype);
     const size_t es = o.dtype == LQR_F32 ? 4 : 8;
-    Tuning t;
-    t.engine = 2;
-    t.big_grid = 1024;
-    size_t need = layout(make_plan(batch, N, n, m, es, o, &t), es).total;
-    if (pick_ts(n, m) != kBigTS) {
-        Tuning w;
-        w.engine = 1;
-        const size_t nw = layout(make_plan(batch, N, n, m, es, o, &w), es).total;
-        need = nw > need ? nw : need;
+    // the largest of: each engine, on one stream and split over 2 and 4
+    size_t need = 0;
+    for (int k : {0, 2, 4}) {
+        Tuning t;
+        t.engine = 2;
+        t.big_grid = 1024;
+        t.streams = k;
+        need = std::max(need, solve_bytes(batch, N, n, m, es, o, &t));
+        if (pick_ts(n, m) != kBigTS) {
+            Tuning w;
+            w.engine = 1;
+            w.streams = k;
+            need = std::max(need, solve_bytes(batch, N, n, m, es, o, &w));
+        }
     }
     *bytes = need;
     return LQR_OK;
@@ -1140,20 +1271,29 @@ int lqr_kkt_factors(lqr_handle_t h, void* stream, int64_t batch, int N, int n, i
     const void* outs[] = {P, p, K, kff};
     for (const void* ptr : outs)
         if (!aligned(ptr, es)) return fail(LQR_EINVAL, "misaligned output");
-    const Plan pl = make_plan(batch, N, n, m, es, o, h->find(batch, N, n, m, dtype));
-    if (workspace_bytes < layout(pl, es).total)
-        return fail(LQR_ENOMEM, "workspace of %zu bytes is smaller than the %zu of this shape", workspace_bytes,
-                    layout(pl, es).total);
+    const Tuning* tun = h->find(batch, N, n, m, dtype);
+    const size_t need = solve_bytes(batch, N, n, m, es, o, tun);
+    if (workspace_bytes < need)
+        return fail(LQR_ENOMEM, "workspace of %zu bytes is smaller than the %zu of this shape", workspace_bytes, need);
     HIPCHK(hipSetDevice(h->device));
     hipStream_t s = (hipStream_t)stream;
-    const int64_t grid = batch * (N + 1);
-    if (dtype == LQR_F32)
-        hipLaunchKernelGGL(k_factors<float>, dim3((unsigned)grid), dim3(256), 0, s, pl, (const float*)workspace,
-                           (float*)P, (float*)p, (float*)K, (float*)kff);
-    else
-        hipLaunchKernelGGL(k_factors<double>, dim3((unsigned)grid), dim3(256), 0, s, pl, (const double*)workspace,
-                           (double*)P, (double*)p, (double*)K, (double*)kff);
-    HIPCHK(hipGetLastError());
+    // the records of each part of a batch split over streams sit in its slice
+    const Parts pt = parts_of(batch, N, n, m, es, o, tun);
+    for (int j = 0; j < pt.count; ++j) {
+        const int64_t b0 = j * pt.size, cnt = std::min(pt.size, batch - b0);
+        const Plan pl = make_plan(cnt, N, n, m, es, o, tun);
+        const char* wsb = (const char*)workspace + (pt.count > 1 ? (size_t)j * pt.bytes : 0);
+        const int64_t grid = cnt * (N + 1), sN1 = b0 * (N + 1), sN = b0 * N;
+        if (dtype == LQR_F32)
+            hipLaunchKernelGGL(k_factors<float>, dim3((unsigned)grid), dim3(256), 0, s, pl, (const float*)wsb,
+                               (float*)P + sN1 * n * n, (float*)p + sN1 * n, (float*)K + sN * m * n,
+                               (float*)kff + sN * m);
+        else
+            hipLaunchKernelGGL(k_factors<double>, dim3((unsigned)grid), dim3(256), 0, s, pl, (const double*)wsb,
+                               (double*)P + sN1 * n * n, (double*)p + sN1 * n, (double*)K + sN * m * n,
+                               (double*)kff + sN * m);
+        HIPCHK(hipGetLastError());
+    }
     return LQR_OK;
 }
 
@@ -1223,7 +1363,7 @@ SqpLayout sqp_layout(lqr_handle_t h, int64_t B, int N, int n, int m, int nc, con
     }
     l.solve_off = cur;
     const Tuning* tun = h ? h->find(B, N, n, m, o.dtype) : nullptr;
-    l.total = cur + layout(make_plan(B, N, n, m, es, o, tun), es).total;
+    l.total = cur + solve_bytes(B, N, n, m, es, o, tun);
     return l;
 }
 
