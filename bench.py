@@ -55,9 +55,9 @@ LAT_REPLAYS = 200   # graph replays of the dedicated p50/p99 loops
 # FETCH_SIZE / WRITE_SIZE runs, calibrated against a copy of known size;
 # valid only for the kernel and launch sources they were taken on (hash of
 # every source file of the library)
-TRAFFIC = {"kernel": "chunk_mid", "src_hash": "d95383a8ecc1dcc0", "bytes_per_launch": 10.572e9,
+TRAFFIC = {"kernel": "chunk_mid", "src_hash": "21f63e2d56c6dd43", "bytes_per_launch": 10.564e9,
            "note": "rocprofv3 FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (factors from a 1 GiB device copy), "
-                   "16 eager dispatches of k_chunk_mid at batch 4096, chunk 1: 8.383 + 2.189 GB per launch"}
+                   "4 eager one-stream dispatches of k_chunk_mid at batch 4096, chunk 1: 8.375 + 2.189 GB per launch"}
 
 
 def kernel_src_hash() -> str:
@@ -375,27 +375,33 @@ def batch_sweep_leg(L, batches=(16, 64, 256, 1024), steps: int = 10):
         swall, slat, _, sresid, sbad = fused_steps(L, dev, 100, 36, 12, B, steps, fused=0, split=True)
         qwall, qlat, _, qresid, qbad = fused_steps(L, dev, 100, 36, 12, B, steps, fused=0, split=2, chunk=1,
                                                    sweep=1, fwd_seq=True)
+        mapping = L.autotune(*[dev[k] for k in L.FIELDS], refine=1, reps=2)
+        twall, tlat, _, tresid, tbad = timed_steps(L, dev, "scan", steps, 2, False, graph=True, refine=1)
+        L.set_tuning(B, 100, 36, 12, torch.float32, clear=True)
         dev64 = {k: v.double() for k, v in dev.items()}
         pwall, plat, _, presid, pbad = timed_steps(L, dev64, "plain", steps, 2, False, graph=True)
         rows[f"B{B}"] = {"scan_solves_per_s": B * steps / wall, "one_launch_solves_per_s": B * steps / fwall,
                          "split_solves_per_s": B * steps / swall, "sequential_solves_per_s": B * steps / qwall,
+                         "tuned_solves_per_s": B * steps / twall, "tuned_mapping": mapping,
                          "plain_solves_per_s": B * steps / pwall,
                          "scan_p50_ms": float(np.percentile(lat, 50)), "one_launch_p50_ms": float(np.percentile(flat, 50)),
                          "split_p50_ms": float(np.percentile(slat, 50)),
                          "sequential_p50_ms": float(np.percentile(qlat, 50)),
+                         "tuned_p50_ms": float(np.percentile(tlat, 50)),
                          "plain_p50_ms": float(np.percentile(plat, 50)),
-                         "scan_rel_kkt_residual": max(resid, fresid, sresid, qresid),
-                         "instances_with_status": bad + fbad + sbad + qbad + pbad}
+                         "scan_rel_kkt_residual": max(resid, fresid, sresid, qresid, tresid),
+                         "instances_with_status": bad + fbad + sbad + qbad + tbad + pbad}
         log(f"[bench] batch {B}: scan {rows[f'B{B}']['scan_solves_per_s']:.0f}/s, "
             f"one launch {rows[f'B{B}']['one_launch_solves_per_s']:.0f}/s, "
             f"split {rows[f'B{B}']['split_solves_per_s']:.0f}/s, "
             f"chunk 1 {rows[f'B{B}']['sequential_solves_per_s']:.0f}/s, "
+            f"autotuned {rows[f'B{B}']['tuned_solves_per_s']:.0f}/s, "
             f"plain {rows[f'B{B}']['plain_solves_per_s']:.0f}/s")
         del dev, dev64
     rows["workload"] = ("whole-body-shaped (n=36, m=12, N=100), hipGraph replays: default mapping (level-by-level "
                         "launches, balanced tree), the one-launch form, the split schedule (tree over 64 elements, "
-                        "sequential sweep over 37), the chunked schedule with chunk 1 and sequential vector passes, and the "
-                        "FP64 plain sweep")
+                        "sequential sweep over 37), the chunked schedule with chunk 1 and sequential vector passes, the "
+                        "mapping the autotuner picks for the batch (tuned_mapping), and the FP64 plain sweep")
     return rows
 
 
@@ -461,6 +467,13 @@ def sqp_leg(L, batch=1024, iters=10):
         X = torch.from_numpy(np.ascontiguousarray(np.repeat(mb["xhat0"][:, None, :], N + 1, axis=1))).to("cuda:0")
         return X, torch.zeros((batch, N, m), device="cuda:0"), torch.zeros((batch, N + 1, n), device="cuda:0")
 
+    # the mapping of the iteration's KKT solves: autotuned for their shape
+    # on whole-body-shaped data of that shape
+    host = synth.gen_batch(synth.gen_c3, batch, np.float32)
+    dev = {k: torch.from_numpy(v).to("cuda:0") for k, v in host.items()}
+    mapping = L.autotune(*[dev[k] for k in L.FIELDS], refine=1, reps=2)
+    del dev, host
+    log(f"[bench] sqp: solve mapping {mapping}")
     X, U, Lm = start()
     L.sqp_solve(md, X, U, Lm, iters=1)
     torch.cuda.synchronize()
@@ -474,6 +487,7 @@ def sqp_leg(L, batch=1024, iters=10):
     alphas = al.cpu().numpy()
     res = {"workload": f"bilinear model, n=36 m=12 N=100, 24 constraints, batch {batch}, FP32",
            "iterations": iters, "ms_per_iteration": ms, "instance_iterations_per_s": batch / ms * 1e3,
+           "solve_mapping": mapping,
            "mean_step": float(alphas.mean()), "full_steps_last_iteration": int((alphas[-1] == 1.0).sum()),
            "line_search_rejections": int((st.cpu().numpy() & 32 != 0).sum())}
     log(f"[bench] sqp: {ms:.2f} ms per iteration of {batch} instances")
