@@ -126,9 +126,23 @@ struct BigEng {
     // staging of x (256 elements).
     template <bool TR, typename S>
     __device__ __forceinline__ T gmv(const S* M, int rows, int cols, int ld, T x, T* vb) const {
-        __shared__ T yb[256];
+        stage_vec(vb, x);
+        return gmv_v<TR>(M, rows, cols, ld, vb);
+    }
+
+    // stage a workgroup vector in vb (the interface of the wavefront
+    // engine's staged products)
+    __device__ __forceinline__ void stage_vec(T* vb, T x) const {
         __syncthreads();
         vb[lg] = x;
+        __syncthreads();
+    }
+
+    // gmv of a vector already staged in vb; the leading barrier keeps the
+    // shared row results of the previous call until every thread read them
+    template <bool TR, typename S>
+    __device__ __forceinline__ T gmv_v(const S* M, int rows, int cols, int ld, const T* vb) const {
+        __shared__ T yb[256];
         __syncthreads();
         if (TR) {
             T s = T(0);

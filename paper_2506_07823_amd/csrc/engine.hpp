@@ -30,6 +30,25 @@ template <typename T> __device__ __forceinline__ T dsqrt(T x);
 template <> __device__ __forceinline__ float dsqrt<float>(float x) { return __builtin_sqrtf(x); }
 template <> __device__ __forceinline__ double dsqrt<double>(double x) { return __builtin_sqrt(x); }
 
+// Pivot of a Cholesky step (d > 0): s = sqrt(d) and inv = 1 / s.  FP32: the
+// hardware reciprocal square root (about 1 ulp) and one product, two
+// instructions on the factorization's dependent chain where the correctly
+// rounded square root and division take about 25 (the FP32 solution is
+// refined against an FP64 residual).  The hardware operation reads a
+// subnormal input as zero, so a pivot below the smallest normal number is
+// scaled by 2^32 first (exact) and the result by 2^16, since
+// rsq(2^32 d) = 2^-16 rsq(d): selects, no branch.  FP64: correctly rounded.
+__device__ __forceinline__ void pivot_root(float d, float& s, float& inv) {
+    const bool tiny = d < 1.17549435e-38f;
+    const float r = __builtin_amdgcn_rsqf(tiny ? d * 4294967296.0f : d);
+    inv = tiny ? r * 65536.0f : r;
+    s = d * inv;
+}
+__device__ __forceinline__ void pivot_root(double d, double& s, double& inv) {
+    s = __builtin_sqrt(d);
+    inv = 1.0 / s;
+}
+
 // Every kernel of this library runs workgroups of exactly one wavefront, so
 // lanes hand data to each other through LDS with a wavefront-scope fence:
 // LDS instructions of one wavefront execute in issue order, and the fence
@@ -279,8 +298,22 @@ struct Eng {
     // i reads its own row.
     template <bool TR, typename S>
     __device__ __forceinline__ T gmv(const S* M, int rows, int cols, int ld, T x, T* vb) const {
+        stage_vec(vb, x);
+        return gmv_v<TR>(M, rows, cols, ld, vb);
+    }
+
+    // Stage a lane vector in vb (one wave barrier).  Products of vectors
+    // staged together then run as gmv_v calls with no barrier between them,
+    // so their global loads are issued back to back instead of one product
+    // at a time.
+    __device__ __forceinline__ void stage_vec(T* vb, T x) const {
         if (lg < NP) vb[lg] = x;
         wg_sync();
+    }
+
+    // gmv of a vector already staged in vb (stage_vec)
+    template <bool TR, typename S>
+    __device__ __forceinline__ T gmv_v(const S* M, int rows, int cols, int ld, const T* vb) const {
         T s = T(0);
         if (TR) {
             if (lg < cols) {
@@ -360,8 +393,8 @@ struct Eng {
                 const bool good = d > T(0);
                 ok = ok && good;
                 if (!good) d = T(1);
-                const T s = dsqrt(d);
-                const T inv = T(1) / s;
+                T s, inv;
+                pivot_root(d, s, inv);
                 if (first) { dmin = s; dmax = s; first = false; }
                 dmin = s < dmin ? s : dmin;
                 dmax = s > dmax ? s : dmax;

@@ -203,7 +203,7 @@ struct VecLds {
 
 template <class E>
 struct ResidLds {
-    double vb[2][E::NP];
+    double vb[3][E::NP];
 };
 
 template <class E>
@@ -1124,22 +1124,27 @@ __device__ __forceinline__ void resid_body(ResidLds<E>& RL, Plan p, In<S> in, co
     const double x = e.vload(xk, n), lam = e.vload(lk, n);
     double rr = 0.0, bb = 0.0;
     S* inst = ws + b * p.stride;
-    // Q x + q - lam (+ M u + A' lam1 for k < N); products read straight from global memory
+    // Q x + q - lam (+ M u + A' lam1 for k < N); products read straight from
+    // global memory, with x, u, lam1 staged together so that the loads of
+    // all the stage's matrices are in flight at once
     double qv = e.vload(P.q(b, k), n);
-    double rx = e.template gmv<false>(P.Q(b, k), n, n, n, x, RL.vb[0]) + qv - lam;
+    e.stage_vec(RL.vb[0], x);
+    if (k < N) {
+        e.stage_vec(RL.vb[1], e.vload(us_ + (b * N + k) * m, m));
+        e.stage_vec(RL.vb[2], e.vload(lk + n, n));
+    }
+    double rx = e.template gmv_v<false>(P.Q(b, k), n, n, n, RL.vb[0]) + qv - lam;
     bb += qv * qv;
     if (k < N) {
-        const double u = e.vload(us_ + (b * N + k) * m, m);
-        const double lam1 = e.vload(lk + n, n);
         const double x1 = e.vload(xk + n, n);
-        double rd = e.template gmv<false>(P.A(b, k), n, n, n, x, RL.vb[1]);
-        rx += e.template gmv<true>(P.A(b, k), n, n, n, lam1, RL.vb[0]);
-        rd += e.template gmv<false>(P.B(b, k), n, m, m, u, RL.vb[1]);
-        double ru = e.template gmv<true>(P.B(b, k), n, m, m, lam1, RL.vb[0]);
-        rx += e.template gmv<false>(P.M(b, k), n, m, m, u, RL.vb[1]);
-        ru += e.template gmv<true>(P.M(b, k), n, m, m, x, RL.vb[0]);
+        double rd = e.template gmv_v<false>(P.A(b, k), n, n, n, RL.vb[0]);
+        rx += e.template gmv_v<true>(P.A(b, k), n, n, n, RL.vb[2]);
+        rd += e.template gmv_v<false>(P.B(b, k), n, m, m, RL.vb[1]);
+        double ru = e.template gmv_v<true>(P.B(b, k), n, m, m, RL.vb[2]);
+        rx += e.template gmv_v<false>(P.M(b, k), n, m, m, RL.vb[1]);
+        ru += e.template gmv_v<true>(P.M(b, k), n, m, m, RL.vb[0]);
         const double cv = e.vload(P.c(b, k), n), rv = e.vload(P.r(b, k), m);
-        ru += e.template gmv<false>(P.R(b, k), m, m, m, u, RL.vb[1]) + rv;
+        ru += e.template gmv_v<false>(P.R(b, k), m, m, m, RL.vb[1]) + rv;
         rd += cv - x1;
         bb += cv * cv + rv * rv;
         rr += (e.lg < n ? rd * rd : 0.0) + (e.lg < m ? ru * ru : 0.0);
@@ -1395,7 +1400,10 @@ __device__ __forceinline__ void fwd_seq_body(LT& L, const Plan& p, S* ws, const 
     for (int k = 0; k <= N; ++k) {
         const S* Pk = inst + p.o_suf + (int64_t)suffix_id(p.rt, 0, k) * p.srec;
         const S* pv = ALT ? inst + p.o_pp + (int64_t)k * n : Pk + nn;
-        const T lam = e.template gmv<false>(Pk, n, n, n, x, L.vb[0]) + e.vload(pv, n);
+        // x_k staged once for its three products (P_k, K_k, Abar_k), whose
+        // loads then go out together
+        e.stage_vec(L.vb[0], x);
+        const T lam = e.template gmv_v<false>(Pk, n, n, n, L.vb[0]) + e.vload(pv, n);
         S* xo = out.x + (b * (N + 1) + k) * n;
         S* lo = out.lam + (b * (N + 1) + k) * n;
         if (e.lg < n) {
@@ -1407,7 +1415,7 @@ __device__ __forceinline__ void fwd_seq_body(LT& L, const Plan& p, S* ws, const 
         }
         if (k == N) break;
         const S* kf = inst + (ALT ? p.o_kffp : p.o_kff) + (int64_t)k * m;
-        const T u = e.template gmv<false>(inst + p.o_K + (int64_t)k * m * n, m, n, n, x, L.vb[1]) + e.vload(kf, m);
+        const T u = e.template gmv_v<false>(inst + p.o_K + (int64_t)k * m * n, m, n, n, L.vb[0]) + e.vload(kf, m);
         S* uo = out.u + (b * N + k) * m;
         if (e.lg < m) {
             const T uv = ADD ? T(uo[e.lg]) + u : u;
@@ -1415,7 +1423,7 @@ __device__ __forceinline__ void fwd_seq_body(LT& L, const Plan& p, S* ws, const 
             fin = fin && finite_(uv);
         }
         const S* leaf = inst + p.o_ftree + (int64_t)k * p.frec;
-        x = e.template gmv<false>(leaf, n, n, n, x, L.vb[0]) + e.vload(leaf + nn, n);
+        x = e.template gmv_v<false>(leaf, n, n, n, L.vb[0]) + e.vload(leaf + nn, n);
     }
     if (!E::all(fin)) set_status<E::NT>(out.status, b, 1);
 }
@@ -1449,10 +1457,15 @@ __device__ __forceinline__ void bwd_seq_body(LT& L, const Plan& p, const In<S>& 
         S* leaf = inst + p.o_ftree + (int64_t)k * p.frec;
         const T cpv = e.vload(RHS_IN ? P.c(b, k) : (const S*)(inst + p.o_cp + (int64_t)k * n), n);
         const T rpv = e.vload(RHS_IN ? P.r(b, k) : (const S*)(inst + p.o_rp + (int64_t)k * m), m);
-        const T v = pn + e.template gmv<false>(Pn, n, n, n, cpv, L.vb[0]);
-        const T h = e.template gmv<true>(P.B(b, k), n, m, m, v, L.vb[1]) + rpv;
-        pn = e.template gmv<true>(leaf, n, n, n, v, L.vb[0]) +
-             e.template gmv<true>(inst + p.o_K + (int64_t)k * m * n, m, n, n, rpv, L.vb[1]) + e.vload(qv(k), n);
+        // products grouped by the vector they need: (P_{k+1} c', K' r')
+        // first, then (B' v, Abar' v), so each group's loads go out together
+        e.stage_vec(L.vb[0], cpv);
+        e.stage_vec(L.vb[1], rpv);
+        const T v = pn + e.template gmv_v<false>(Pn, n, n, n, L.vb[0]);
+        const T kr = e.template gmv_v<true>(inst + p.o_K + (int64_t)k * m * n, m, n, n, L.vb[1]);
+        e.stage_vec(L.vb[0], v);
+        const T h = e.template gmv_v<true>(P.B(b, k), n, m, m, L.vb[0]) + rpv;
+        pn = e.template gmv_v<true>(leaf, n, n, n, L.vb[0]) + kr + e.vload(qv(k), n);
         e.vstore(inst + p.o_pp + (int64_t)k * n, n, pn);
         const T kf = -g_solve(e, inst + p.o_LG + (int64_t)k * m * m, m, h, L.vb[0], L.vb[1]);
         e.vstore(inst + p.o_kffp + (int64_t)k * m, m, kf);
