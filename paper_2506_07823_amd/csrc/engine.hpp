@@ -371,9 +371,10 @@ struct Eng {
         (void)cb;
         dl = T(1);
         bool ok = true;
-        dmin = T(0);
+        // every pivot root is positive (a failed pivot is replaced by 1), so
+        // the running extremes start from the largest finite value and zero
+        dmin = sizeof(T) == 4 ? T(3.0e38f) : T(1.0e300);
         dmax = T(0);
-        bool first = true;
 #pragma unroll
         for (int a0 = 0; a0 < NB; ++a0) {
             for (int t = 0; t < G; ++t) {
@@ -395,7 +396,6 @@ struct Eng {
                 if (!good) d = T(1);
                 T s, inv;
                 pivot_root(d, s, inv);
-                if (first) { dmin = s; dmax = s; first = false; }
                 dmin = s < dmin ? s : dmin;
                 dmax = s > dmax ? s : dmax;
                 T li[NB], lj[NB];
@@ -413,15 +413,15 @@ struct Eng {
                         if (a > a0 && b > a0) S[a][b] = fma_(-li[a], lj[b], S[a][b]);
                         else if (row(a) > k && col(b) > k) S[a][b] = fma_(-li[a], lj[b], S[a][b]);
                     }
+                // column k of L; its zeros above the diagonal are the only
+                // upper-triangle writes needed: row k right of the diagonal
+                // is zeroed by the column writes of the later steps, and the
+                // padding past n is zero on entry and stays zero (its
+                // multipliers are zero)
                 if (tx == t) {
 #pragma unroll
                     for (int a = 0; a < NB; ++a)
                         S[a][a0] = row(a) > k ? li[a] : (row(a) == k ? s : T(0));
-                }
-                if (ty == t) {
-#pragma unroll
-                    for (int b = 0; b < NB; ++b)
-                        if (col(b) > k) S[a0][b] = T(0);
                 }
                 if (lg == k) dl = inv;
                 if (NV > 0) {
