@@ -400,28 +400,33 @@ struct Eng {
                 dmax = s > dmax ? s : dmax;
                 T li[NB], lj[NB];
 #pragma unroll
-                for (int a = 0; a < NB; ++a) li[a] = cr[a] * inv;
+                for (int a = a0; a < NB; ++a) li[a] = cr[a] * inv;
 #pragma unroll
                 for (int b = a0; b < NB; ++b) lj[b] = cc[b] * inv;
+                // In the pivot block only the rows and columns past k take
+                // part: their multipliers are zeroed instead of masking the
+                // updates (subtracting 0 x leaves an entry as it is).  Blocks
+                // past the pivot block lie entirely below and right of k.
+                li[a0] = row(a0) > k ? li[a0] : T(0);
+                lj[a0] = col(a0) > k ? lj[a0] : T(0);
                 // trailing update of the lower triangle: blocks a >= b >= a0
-                // (blocks past the pivot block lie entirely below and right
-                // of k: only the pivot block row and column need the test)
 #pragma unroll
                 for (int a = a0; a < NB; ++a)
 #pragma unroll
-                    for (int b = a0; b <= a; ++b) {
-                        if (a > a0 && b > a0) S[a][b] = fma_(-li[a], lj[b], S[a][b]);
-                        else if (row(a) > k && col(b) > k) S[a][b] = fma_(-li[a], lj[b], S[a][b]);
-                    }
+                    for (int b = a0; b <= a; ++b) S[a][b] = fma_(-li[a], lj[b], S[a][b]);
                 // column k of L; its zeros above the diagonal are the only
                 // upper-triangle writes needed: row k right of the diagonal
                 // is zeroed by the column writes of the later steps, and the
                 // padding past n is zero on entry and stays zero (its
-                // multipliers are zero)
+                // multipliers are zero).  Blocks above the pivot block hold
+                // rows before k, blocks below it rows after k.
                 if (tx == t) {
 #pragma unroll
-                    for (int a = 0; a < NB; ++a)
-                        S[a][a0] = row(a) > k ? li[a] : (row(a) == k ? s : T(0));
+                    for (int a = 0; a < NB; ++a) {
+                        if (a < a0) S[a][a0] = T(0);
+                        else if (a == a0) S[a][a0] = row(a) == k ? s : li[a];
+                        else S[a][a0] = li[a];
+                    }
                 }
                 if (lg == k) dl = inv;
                 if (NV > 0) {
