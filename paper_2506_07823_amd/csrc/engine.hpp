@@ -239,6 +239,36 @@ struct Eng {
             slot[i * LD + j] = (i < rows && j < cols) ? T(g[(int64_t)i * ldg + j]) : T(0);
         }
     }
+
+    // g2s for the dependent chains of the combine: each lane copies
+    // NP^2 / GL elements (NP is a multiple of 8, so that is exact) in groups
+    // of G2S_U whose loads are all issued before the group's stores, one
+    // wait per group instead of one per element (more registers in flight)
+    static constexpr int G2S_IT = NP * NP / GL;
+    static constexpr int G2S_U = G2S_IT % 8 == 0 ? 8 : G2S_IT % 5 == 0 ? 5 : G2S_IT % 4 == 0 ? 4
+                               : G2S_IT % 3 == 0 ? 3 : G2S_IT % 2 == 0 ? 2 : 1;
+    template <typename S>
+    __device__ __forceinline__ void g2s_batched(T* slot, const S* g, int rows, int cols, int ldg) const {
+        static_assert(G2S_IT * GL == NP * NP, "whole slot in equal lane shares");
+#pragma unroll 1
+        for (int it0 = 0; it0 < G2S_IT; it0 += G2S_U) {
+            T v[G2S_U];
+#pragma unroll
+            for (int u = 0; u < G2S_U; ++u) {
+                const int idx = lg + (it0 + u) * GL;
+                const int i = idx / NP, j = idx - (idx / NP) * NP;
+                // 32-bit offset from the uniform base (a slot's matrix is at
+                // most 256 x 256)
+                v[u] = (i < rows && j < cols) ? T(g[i * ldg + j]) : T(0);
+            }
+#pragma unroll
+            for (int u = 0; u < G2S_U; ++u) {
+                const int idx = lg + (it0 + u) * GL;
+                const int i = idx / NP, j = idx - (idx / NP) * NP;
+                slot[i * LD + j] = v[u];
+            }
+        }
+    }
     // rows x cols of an LDS slot to global memory (coalesced)
     template <typename S>
     __device__ __forceinline__ void s2g(const T* slot, S* g, int rows, int cols, int ldg) const {
@@ -285,6 +315,9 @@ struct Eng {
         wg_sync();
         T s = T(0);
         if (lg < rows) {
+            // unrolled so that several LDS reads are in flight per wait (the
+            // accumulation order is unchanged)
+#pragma unroll 4
             for (int k = 0; k < K; ++k)
                 s = fma_(TX ? X[k * LD + lg] : X[lg * LD + k], vb[k], s);
         }

@@ -194,6 +194,26 @@ struct Lds {
 template <typename T>
 struct Lds<BigEng<T>> : BigLds<T> {};
 
+// Wavefronts per SIMD that the two-slot LDS of a one-wavefront workgroup
+// allows (160 KiB per CU, 4 SIMDs): the register budget a kernel gets
+// without costing occupancy, passed as its launch bound's minimum
+template <class E>
+constexpr int lds_waves_per_simd() {
+    constexpr int w = ((int)(163840 / sizeof(Lds<E>)) + 3) / 4;   // the fullest SIMD
+    return w < 1 ? 1 : (w > 8 ? 8 : w);
+}
+
+// Launch bound of the FP32 sweeps of cheap combines (k_chunk_mid,
+// k_chunk_down, k_tail): where their two LDS matrix slots hold occupancy to
+// 3 wavefronts per SIMD or fewer, the register budget of that occupancy, so
+// that the batched slot copies of the cheap combine do not cost a wavefront;
+// otherwise no bound
+template <class E>
+constexpr int combine_min_waves() {
+    constexpr int w = lds_waves_per_simd<E>();
+    return (sizeof(typename E::T) == 4 && w <= 3) ? w : 1;
+}
+
 // LDS of the vector-only passes: two staging vectors (nothing else, so these
 // kernels keep many wavefronts resident to hide their memory latency)
 template <class E>
@@ -428,7 +448,7 @@ __global__ __launch_bounds__(E::NT) void k_element(Plan p, In<S> in, S* ws, int3
 // (I + C1 P2)^{-1} = L^{-T} S^{-1} L').  CHEAP: e2 is a complete suffix
 // (A2 = C2 = b2 = 0), only P and p are formed and written to a suffix record.
 // ---------------------------------------------------------------------------
-template <class E, bool CHEAP, typename S>
+template <class E, bool CHEAP, bool BATCH = false, typename S>
 __device__ __forceinline__ void combine(const E& e, Lds<E>& L, int n, const S* e1, const S* P2, const S* p2v,
                                         const S* e2, S* outA, S* outC, S* outP, S* outb, S* outp, bool& okp,
                                         typename E::T& kappa) {
@@ -443,15 +463,23 @@ __device__ __forceinline__ void combine(const E& e, Lds<E>& L, int n, const S* e
     // wavefront per SIMD.
     typename E::Tile tA1, tP1;
     T b1pre = T(0), p1pre = T(0);
+    // L = chol(P2), g = L^{-1} p2
+    // BATCH (the FP32 sequential sweeps of cheap combines): the slot copies
+    // issue their loads in groups, one wait per group (more registers, which
+    // those kernels' launch bound budgets)
+    if constexpr (BATCH) {
+        e.g2s_batched(L.sA, P2, n, n, n);
+        e.g2s_batched(L.sX, e1 + nn, n, n, n);                 // sX = C1
+    } else {
+        e.g2s(L.sA, P2, n, n, n);
+        e.g2s(L.sX, e1 + nn, n, n, n);
+    }
     if constexpr (CHEAP) {
         e.load(tA1, e1, n, n, n);
         e.load(tP1, e1 + 2 * nn, n, n, n);
         b1pre = e.vload(e1 + 3 * nn, n);
         p1pre = e.vload(e1 + 3 * nn + n, n);
     }
-    // L = chol(P2), g = L^{-1} p2
-    e.g2s(L.sA, P2, n, n, n);
-    e.g2s(L.sX, e1 + nn, n, n, n);                         // sX = C1
     T g[1] = {e.vload(p2v, n)};
     const T p2l = g[0];
     wg_sync();
@@ -670,7 +698,7 @@ __global__ __launch_bounds__(E::NT) void k_down(Plan p, S* ws, int lvl, int32_t*
 // next step's loads (all lanes of the wave share one CU's caches).  A
 // flagged step marks the instance for the FP64 redo.
 // ---------------------------------------------------------------------------
-template <typename S, class E>
+template <typename S, class E, bool BATCH = false>
 __device__ __forceinline__ void tail_task(Lds<E>& L, const Plan& p, S* ws, int32_t* status, int64_t b) {
     static_assert(!E::BIG, "wavefront engine only");
     const E e(unit_tid<E::NT>());
@@ -692,7 +720,7 @@ __device__ __forceinline__ void tail_task(Lds<E>& L, const Plan& p, S* ws, int32
         S* out = suf + (int64_t)suffix_id(p.rt, 0, k) * p.srec;
         bool ok;
         typename E::T kappa;
-        combine<E, true>(e, L, n, node, s2, s2 + nn, (const S*)nullptr, (S*)nullptr, (S*)nullptr, out,
+        combine<E, true, BATCH>(e, L, n, node, s2, s2 + nn, (const S*)nullptr, (S*)nullptr, (S*)nullptr, out,
                          (S*)nullptr, out + nn, ok, kappa);
         ok_all = ok_all && ok;
         if (!(kappa <= kmax)) kmax = kappa;   // NaN propagates
@@ -702,9 +730,9 @@ __device__ __forceinline__ void tail_task(Lds<E>& L, const Plan& p, S* ws, int32
 }
 
 template <typename S, class E>
-__global__ __launch_bounds__(E::NT) void k_tail(Plan p, S* ws, int32_t* status) {
+__global__ __launch_bounds__(E::NT, combine_min_waves<E>()) void k_tail(Plan p, S* ws, int32_t* status) {
     __shared__ Lds<E> L;
-    auto body = [&](int64_t t) { tail_task<S, E>(L, p, ws, status, t); };
+    auto body = [&](int64_t t) { tail_task<S, E, sizeof(typename E::T) == 4>(L, p, ws, status, t); };
     LQR_TASKS(E, p.batch, body);
 }
 
@@ -821,7 +849,7 @@ __global__ __launch_bounds__(E::NT) void k_chunk_up(Plan p, S* ws, int32_t* stat
 
 // phase 2: complete suffixes at the chunk starts, one task unit per instance
 template <typename S, class E>
-__global__ __launch_bounds__(E::NT) void k_chunk_mid(Plan p, S* ws, int32_t* status) {
+__global__ __launch_bounds__(E::NT, combine_min_waves<E>()) void k_chunk_mid(Plan p, S* ws, int32_t* status) {
     static_assert(!E::BIG, "wavefront engine only");
     __shared__ Lds<E> L;
     const int64_t b = blockIdx.x;
@@ -837,7 +865,7 @@ __global__ __launch_bounds__(E::NT) void k_chunk_mid(Plan p, S* ws, int32_t* sta
         S* out = suf + (int64_t)suffix_id(p.rt, 0, c * p.chunk) * p.srec;
         bool ok;
         typename E::T kappa;
-        combine<E, true>(e, L, n, node, s2, s2 + nn, (const S*)nullptr, (S*)nullptr, (S*)nullptr, out,
+        combine<E, true, sizeof(typename E::T) == 4>(e, L, n, node, s2, s2 + nn, (const S*)nullptr, (S*)nullptr, (S*)nullptr, out,
                          (S*)nullptr, out + nn, ok, kappa);
         ok_all = ok_all && ok;
         if (!(kappa <= kmax)) kmax = kappa;
@@ -848,7 +876,7 @@ __global__ __launch_bounds__(E::NT) void k_chunk_mid(Plan p, S* ws, int32_t* sta
 
 // phase 3: the other leaves of every chunk, one task unit per chunk
 template <typename S, class E>
-__global__ __launch_bounds__(E::NT) void k_chunk_down(Plan p, S* ws, int32_t* status) {
+__global__ __launch_bounds__(E::NT, combine_min_waves<E>()) void k_chunk_down(Plan p, S* ws, int32_t* status) {
     static_assert(!E::BIG, "wavefront engine only");
     __shared__ Lds<E> L;
     const int64_t b = blockIdx.x / p.nchunk;
@@ -866,7 +894,7 @@ __global__ __launch_bounds__(E::NT) void k_chunk_down(Plan p, S* ws, int32_t* st
         S* out = suf + (int64_t)suffix_id(p.rt, 0, k) * p.srec;
         bool ok;
         typename E::T kappa;
-        combine<E, true>(e, L, n, node, s2, s2 + nn, (const S*)nullptr, (S*)nullptr, (S*)nullptr, out,
+        combine<E, true, sizeof(typename E::T) == 4>(e, L, n, node, s2, s2 + nn, (const S*)nullptr, (S*)nullptr, (S*)nullptr, out,
                          (S*)nullptr, out + nn, ok, kappa);
         ok_all = ok_all && ok;
         if (!(kappa <= kmax)) kmax = kappa;
