@@ -138,6 +138,12 @@ struct BigEng {
         __syncthreads();
     }
 
+    // (the wavefront engine's prefetching form; here the same product)
+    template <bool TR, typename S>
+    __device__ __forceinline__ T gmv_pf(const S* M, int rows, int cols, int ld, const T* vb) const {
+        return gmv_v<TR>(M, rows, cols, ld, vb);
+    }
+
     // gmv of a vector already staged in vb; the leading barrier keeps the
     // shared row results of the previous call until every thread read them
     template <bool TR, typename S>

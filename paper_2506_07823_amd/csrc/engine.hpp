@@ -383,6 +383,61 @@ struct Eng {
         return s;
     }
 
+    // gmv_v for the sequential sweeps (one wavefront per instance walking
+    // its stages: nothing else on the SIMD hides their load latency): the
+    // loads go out in groups (8 column entries, or 5 16-byte row pieces) and
+    // the FMAs follow in gmv_v's order, so the result is the same to the bit
+    template <bool TR, typename S>
+    __device__ __forceinline__ T gmv_pf(const S* M, int rows, int cols, int ld, const T* vb) const {
+        T s = T(0);
+        if (TR) {
+            constexpr int U = 8;
+            // the group loop stays a loop: unrolled, the compiler would
+            // hoist every group's loads together (registers past the
+            // sweep's budget)
+#pragma unroll 1
+            for (int i0 = 0; i0 < NP; i0 += U) {
+                T c[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    c[u] = (lg < cols && i0 + u < rows) ? T(M[(i0 + u) * ld + lg]) : T(0);
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (i0 + u < rows) s = fma_(c[u], vb[i0 + u], s);
+            }
+            return lg < cols ? s : T(0);
+        }
+        constexpr int V = 16 / (int)sizeof(S);
+        if ((cols % V) == 0 && (ld % V) == 0 && ((uintptr_t)M & 15) == 0) {
+            using S4 = typename std::conditional<sizeof(S) == 4, float4, double2>::type;
+            constexpr int NV4 = (NP + V - 1) / V, U = 5;
+            const S4* r4 = reinterpret_cast<const S4*>(M + (int64_t)lg * ld);
+            const int nv = cols / V;
+#pragma unroll 1
+            for (int j0 = 0; j0 < NV4; j0 += U) {
+                S4 w[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (lg < rows && j0 + u < nv) w[u] = r4[j0 + u];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (j0 + u >= nv) break;
+                    if constexpr (sizeof(S) == 4) {
+                        s = fma_(T(w[u].x), vb[4 * (j0 + u)], s);
+                        s = fma_(T(w[u].y), vb[4 * (j0 + u) + 1], s);
+                        s = fma_(T(w[u].z), vb[4 * (j0 + u) + 2], s);
+                        s = fma_(T(w[u].w), vb[4 * (j0 + u) + 3], s);
+                    } else {
+                        s = fma_(T(w[u].x), vb[2 * (j0 + u)], s);
+                        s = fma_(T(w[u].y), vb[2 * (j0 + u) + 1], s);
+                    }
+                }
+            }
+            return lg < rows ? s : T(0);
+        }
+        return gmv_v<false>(M, rows, cols, ld, vb);
+    }
+
     // --------------------------------------------------------- Cholesky
     // In-register right-looking Cholesky of the n x n SPD matrix held in S
     // (lower triangle used).  On return S holds L (lower, zero above) and

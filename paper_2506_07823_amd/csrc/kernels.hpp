@@ -1414,6 +1414,12 @@ __device__ __forceinline__ typename E::T g_solve(const E& e, const S* LG, int m,
     }
 }
 
+// Launch bound of the sequential sweeps (one wavefront per instance): 4
+// wavefronts per SIMD keep a whole 4096-instance batch resident at once
+// with the prefetched products in registers
+template <class E>
+constexpr int seq_min_waves() { return E::BIG ? 1 : 4; }
+
 // x_0 = x0, x_{k+1} = Abar_k x_k + bbar_k (eq. (controlled_dynamics)),
 // u_k = K_k x_k + k_k, lambda_k = P_k x_k + p_k.  ADD: the refinement's
 // correction (p' and k' from the backward sweep) is added to the outputs.
@@ -1431,7 +1437,7 @@ __device__ __forceinline__ void fwd_seq_body(LT& L, const Plan& p, S* ws, const 
         // x_k staged once for its three products (P_k, K_k, Abar_k), whose
         // loads then go out together
         e.stage_vec(L.vb[0], x);
-        const T lam = e.template gmv_v<false>(Pk, n, n, n, L.vb[0]) + e.vload(pv, n);
+        const T lam = e.template gmv_pf<false>(Pk, n, n, n, L.vb[0]) + e.vload(pv, n);
         S* xo = out.x + (b * (N + 1) + k) * n;
         S* lo = out.lam + (b * (N + 1) + k) * n;
         if (e.lg < n) {
@@ -1443,7 +1449,7 @@ __device__ __forceinline__ void fwd_seq_body(LT& L, const Plan& p, S* ws, const 
         }
         if (k == N) break;
         const S* kf = inst + (ALT ? p.o_kffp : p.o_kff) + (int64_t)k * m;
-        const T u = e.template gmv_v<false>(inst + p.o_K + (int64_t)k * m * n, m, n, n, L.vb[0]) + e.vload(kf, m);
+        const T u = e.template gmv_pf<false>(inst + p.o_K + (int64_t)k * m * n, m, n, n, L.vb[0]) + e.vload(kf, m);
         S* uo = out.u + (b * N + k) * m;
         if (e.lg < m) {
             const T uv = ADD ? T(uo[e.lg]) + u : u;
@@ -1451,13 +1457,13 @@ __device__ __forceinline__ void fwd_seq_body(LT& L, const Plan& p, S* ws, const 
             fin = fin && finite_(uv);
         }
         const S* leaf = inst + p.o_ftree + (int64_t)k * p.frec;
-        x = e.template gmv_v<false>(leaf, n, n, n, L.vb[0]) + e.vload(leaf + nn, n);
+        x = e.template gmv_pf<false>(leaf, n, n, n, L.vb[0]) + e.vload(leaf + nn, n);
     }
     if (!E::all(fin)) set_status<E::NT>(out.status, b, 1);
 }
 
 template <typename S, class E>
-__global__ __launch_bounds__(E::NT) void k_fwd_seq(Plan p, S* ws, const S* x0, Out<S> out) {
+__global__ __launch_bounds__(E::NT, seq_min_waves<E>()) void k_fwd_seq(Plan p, S* ws, const S* x0, Out<S> out) {
     __shared__ VecLds<E> L;
     const int64_t b = blockIdx.x;
     fwd_seq_body<S, E, false>(L, p, ws, x0 + b * p.n, out, b);
@@ -1489,15 +1495,16 @@ __device__ __forceinline__ void bwd_seq_body(LT& L, const Plan& p, const In<S>& 
         // first, then (B' v, Abar' v), so each group's loads go out together
         e.stage_vec(L.vb[0], cpv);
         e.stage_vec(L.vb[1], rpv);
-        const T v = pn + e.template gmv_v<false>(Pn, n, n, n, L.vb[0]);
-        const T kr = e.template gmv_v<true>(inst + p.o_K + (int64_t)k * m * n, m, n, n, L.vb[1]);
+        const T v = pn + e.template gmv_pf<false>(Pn, n, n, n, L.vb[0]);
+        const T kr = e.template gmv_pf<true>(inst + p.o_K + (int64_t)k * m * n, m, n, n, L.vb[1]);
         e.stage_vec(L.vb[0], v);
-        const T h = e.template gmv_v<true>(P.B(b, k), n, m, m, L.vb[0]) + rpv;
-        pn = e.template gmv_v<true>(leaf, n, n, n, L.vb[0]) + kr + e.vload(qv(k), n);
+        const T h = e.template gmv_pf<true>(P.B(b, k), n, m, m, L.vb[0]) + rpv;
+        pn = e.template gmv_pf<true>(leaf, n, n, n, L.vb[0]) + kr + e.vload(qv(k), n);
         e.vstore(inst + p.o_pp + (int64_t)k * n, n, pn);
         const T kf = -g_solve(e, inst + p.o_LG + (int64_t)k * m * m, m, h, L.vb[0], L.vb[1]);
         e.vstore(inst + p.o_kffp + (int64_t)k * m, m, kf);
-        const T bb = e.template gmv<false>(P.B(b, k), n, m, m, kf, L.vb[1]) + cpv;
+        e.stage_vec(L.vb[1], kf);
+        const T bb = e.template gmv_pf<false>(P.B(b, k), n, m, m, L.vb[1]) + cpv;
         e.vstore(leaf + nn, n, bb);
         E::sync();
     }
@@ -1515,7 +1522,7 @@ __device__ __forceinline__ void refine_seq_body(LT& L, const Plan& p, const In<S
 }
 
 template <typename S, class E>
-__global__ __launch_bounds__(E::NT) void k_refine_seq(Plan p, In<S> in, S* ws, Out<S> out) {
+__global__ __launch_bounds__(E::NT, seq_min_waves<E>()) void k_refine_seq(Plan p, In<S> in, S* ws, Out<S> out) {
     __shared__ VecLds<E> L;
     const int64_t b = blockIdx.x;
     LQR_GATE(p, b);
@@ -1529,7 +1536,7 @@ __global__ __launch_bounds__(E::NT) void k_refine_seq(Plan p, In<S> in, S* ws, O
 // solve sent to the FP64 redo (status bit 8) are skipped here (their FP32
 // factors are not usable; the redo launch solves them again).
 template <typename S, class E>
-__global__ __launch_bounds__(E::NT) void k_resolve_seq(Plan p, In<S> in, S* ws, Out<S> out) {
+__global__ __launch_bounds__(E::NT, seq_min_waves<E>()) void k_resolve_seq(Plan p, In<S> in, S* ws, Out<S> out) {
     __shared__ VecLds<E> L;
     const int64_t b = blockIdx.x;
     if (out.status[b] & 8) return;
