@@ -256,7 +256,7 @@ __device__ __forceinline__ void coop_zero(D* dst, int count) {
 template <class E, bool TR = false, typename S>
 __device__ __forceinline__ void stage(const E& e, typename E::T* slot, const S* g, int rows, int cols, int ldg) {
     if (!TR) {
-        e.g2s(slot, g, rows, cols, ldg);
+        e.g2s_batched(slot, g, rows, cols, ldg);
     } else {
         typename E::Tile t;
         e.template load<TR>(t, g, rows, cols, ldg);
@@ -396,11 +396,17 @@ __device__ __forceinline__ void element_task(Lds<E>& L, const Plan& p, const In<
     typename E::Tile tR;
     e.load(tR, P.R(b, k), m, m, m);
     // loaded before the factorization (its wave barrier keeps later loads
-    // from moving up), so their latency overlaps it
+    // from moving up), so their latency overlaps it; A, Q, c, q too (the
+    // LDS already holds the kernel to 3 wavefronts per SIMD, whose register
+    // budget has room for them)
     typename E::Tile W[2];
     e.template load<true>(W[0], P.B(b, k), m, n, m);   // B' (m x n)
     e.template load<true>(W[1], P.M(b, k), m, n, m);   // M' (m x n)
     T vv[1] = {e.vload(P.r(b, k), m)};
+    typename E::Tile tA, tQ;
+    e.load(tA, P.A(b, k), n, n, n);
+    e.load(tQ, P.Q(b, k), n, n, n);
+    const T cpre = e.vload(P.c(b, k), n), qpre = e.vload(P.q(b, k), n);
     T dmin, dmax, nov[1];
     T dlA;
     const bool ok = e.template chol<0, MB>(tR, m, L.cb, dlA, nov, dmin, dmax);
@@ -411,24 +417,22 @@ __device__ __forceinline__ void element_task(Lds<E>& L, const Plan& p, const In<
     e.to_lds(W[0], L.sA);
     e.to_lds(W[1], L.sX);
     wg_sync();
+    e.template gemm_sub<true, false>(tA, L.sA, L.sX, m);
+    e.store(tA, rec, n, n, n);                         // At
     typename E::Tile t;
-    e.load(t, P.A(b, k), n, n, n);
-    e.template gemm_sub<true, false>(t, L.sA, L.sX, m);
-    e.store(t, rec, n, n, n);                          // At
     e.zero(t);
     e.template gemm<true, false, true>(t, L.sA, L.sA, m);
     e.store_sym(t, rec + nn, n);                       // Ct
-    e.load(t, P.Q(b, k), n, n, n);
-    e.template gemm_sub<true, false, true>(t, L.sX, L.sX, m);
-    e.store_sym(t, rec + 2 * nn, n);                   // Pt
+    e.template gemm_sub<true, false, true>(tQ, L.sX, L.sX, m);
+    e.store_sym(tQ, rec + 2 * nn, n);                  // Pt
     const T bw = e.template matvec<true>(L.sA, L.vb, vv[0], m, n);
-    e.vstore(rec + 3 * nn, n, e.vload(P.c(b, k), n) - bw);
+    e.vstore(rec + 3 * nn, n, cpre - bw);
     const T pw = e.template matvec<true>(L.sX, L.vb, vv[0], m, n);
-    e.vstore(rec + 3 * nn + n, n, e.vload(P.q(b, k), n) - pw);
+    e.vstore(rec + 3 * nn + n, n, qpre - pw);
 }
 
 template <typename S, class E, int MB>
-__global__ __launch_bounds__(E::NT) void k_element(Plan p, In<S> in, S* ws, int32_t* status) {
+__global__ __launch_bounds__(E::NT, combine_min_waves<E>()) void k_element(Plan p, In<S> in, S* ws, int32_t* status) {
     __shared__ Lds<E> L;
     auto body = [&](int64_t t) {
         if constexpr (E::BIG) big_element_task<S, E>(L, p, in, ws, status, t);
@@ -973,7 +977,7 @@ __device__ __forceinline__ void policy_task(Lds<E>& L, const Plan& p, const In<S
 }
 
 template <typename S, class E, int MB>
-__global__ __launch_bounds__(E::NT) void k_policy(Plan p, In<S> in, S* ws, int32_t* status) {
+__global__ __launch_bounds__(E::NT, combine_min_waves<E>()) void k_policy(Plan p, In<S> in, S* ws, int32_t* status) {
     __shared__ Lds<E> L;
     auto body = [&](int64_t t) {
         if constexpr (E::BIG) big_policy_task<S, E>(L, p, in, ws, status, t);
@@ -1338,16 +1342,34 @@ __global__ __launch_bounds__(E::NT) void k_bvec_down(Plan p, S* ws, int lvl) {
 
 // v <- L^{-1} v (FWD) or L^{-T} v, L (m x m, lower, row-major) in global
 // memory, v a lane vector: the pivot comes from its lane by a cross-lane
-// read, every other lane updates its element (no LDS)
+// read, every other lane updates its element (no LDS).  The steps go in
+// groups of 8 whose entries of L (the lane's row or column and the
+// diagonal) are loaded before the group's first step, so the dependent
+// chain waits on one load per group instead of one per step.
 template <bool FWD, class E, typename S>
 __device__ __forceinline__ typename E::T lane_trsv(const E& e, const S* Lm, int m, typename E::T v) {
     using T = typename E::T;
-    for (int s = 0; s < m; ++s) {
-        const int k = FWD ? s : m - 1 - s;
-        const T yk = __shfl(v, k, 64) / T(Lm[k * m + k]);
-        if (e.lg == k) v = yk;
-        else if (FWD ? (e.lg > k && e.lg < m) : (e.lg < k))
-            v = fma_(-T(FWD ? Lm[e.lg * m + k] : Lm[k * m + e.lg]), yk, v);
+    constexpr int U = 8;
+    const int ng = (m + U - 1) / U;
+#pragma unroll 1
+    for (int gi = 0; gi < ng; ++gi) {
+        const int k0 = FWD ? gi * U : (ng - 1 - gi) * U;
+        T lr[U], dg[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = k0 + u;
+            dg[u] = k < m ? T(Lm[k * m + k]) : T(1);
+            lr[u] = (k < m && e.lg < m) ? T(FWD ? Lm[e.lg * m + k] : Lm[k * m + e.lg]) : T(0);
+        }
+#pragma unroll
+        for (int us = 0; us < U; ++us) {
+            const int u = FWD ? us : U - 1 - us;
+            const int k = k0 + u;
+            if (k >= m) continue;
+            const T yk = __shfl(v, k, 64) / dg[u];
+            if (e.lg == k) v = yk;
+            else if (FWD ? (e.lg > k && e.lg < m) : (e.lg < k)) v = fma_(-lr[u], yk, v);
+        }
     }
     return v;
 }
@@ -1414,12 +1436,6 @@ __device__ __forceinline__ typename E::T g_solve(const E& e, const S* LG, int m,
     }
 }
 
-// Launch bound of the sequential sweeps (one wavefront per instance): 4
-// wavefronts per SIMD keep a whole 4096-instance batch resident at once
-// with the prefetched products in registers
-template <class E>
-constexpr int seq_min_waves() { return E::BIG ? 1 : 4; }
-
 // x_0 = x0, x_{k+1} = Abar_k x_k + bbar_k (eq. (controlled_dynamics)),
 // u_k = K_k x_k + k_k, lambda_k = P_k x_k + p_k.  ADD: the refinement's
 // correction (p' and k' from the backward sweep) is added to the outputs.
@@ -1463,7 +1479,7 @@ __device__ __forceinline__ void fwd_seq_body(LT& L, const Plan& p, S* ws, const 
 }
 
 template <typename S, class E>
-__global__ __launch_bounds__(E::NT, seq_min_waves<E>()) void k_fwd_seq(Plan p, S* ws, const S* x0, Out<S> out) {
+__global__ __launch_bounds__(E::NT) void k_fwd_seq(Plan p, S* ws, const S* x0, Out<S> out) {
     __shared__ VecLds<E> L;
     const int64_t b = blockIdx.x;
     fwd_seq_body<S, E, false>(L, p, ws, x0 + b * p.n, out, b);
@@ -1522,7 +1538,7 @@ __device__ __forceinline__ void refine_seq_body(LT& L, const Plan& p, const In<S
 }
 
 template <typename S, class E>
-__global__ __launch_bounds__(E::NT, seq_min_waves<E>()) void k_refine_seq(Plan p, In<S> in, S* ws, Out<S> out) {
+__global__ __launch_bounds__(E::NT) void k_refine_seq(Plan p, In<S> in, S* ws, Out<S> out) {
     __shared__ VecLds<E> L;
     const int64_t b = blockIdx.x;
     LQR_GATE(p, b);
@@ -1536,7 +1552,7 @@ __global__ __launch_bounds__(E::NT, seq_min_waves<E>()) void k_refine_seq(Plan p
 // solve sent to the FP64 redo (status bit 8) are skipped here (their FP32
 // factors are not usable; the redo launch solves them again).
 template <typename S, class E>
-__global__ __launch_bounds__(E::NT, seq_min_waves<E>()) void k_resolve_seq(Plan p, In<S> in, S* ws, Out<S> out) {
+__global__ __launch_bounds__(E::NT) void k_resolve_seq(Plan p, In<S> in, S* ws, Out<S> out) {
     __shared__ VecLds<E> L;
     const int64_t b = blockIdx.x;
     if (out.status[b] & 8) return;
