@@ -496,12 +496,12 @@ __device__ __forceinline__ void combine(const E& e, Lds<E>& L, int n, const S* e
     T cp = T(0);
     if (!CHEAP) cp = e.template matvec<false>(L.sX, L.vb, p2l, n, n);   // C1 p2
     e.zero(tS);
-    e.template gemm<false, false>(tS, L.sX, L.sA, n);      // W = C1 L
+    e.template gemm_tri<false, false, false, 1>(tS, L.sX, L.sA, n);   // W = C1 L (L lower)
     wg_sync();
     e.to_lds(tS, L.sX);                                   // sX = W
     wg_sync();
     e.zero(tS);
-    e.template gemm<true, false, true>(tS, L.sA, L.sX, n); // L' W (lower)
+    e.template gemm_tri<true, false, true, 2>(tS, L.sA, L.sX, n);     // L' W (lower part; L' upper)
     e.add_identity(tS, n);
     T nov[1];
     ok = e.template chol<0>(tS, n, L.cb, dlB, nov, dmin, dmax) && ok;   // tS = L_S
@@ -526,7 +526,7 @@ __device__ __forceinline__ void combine(const E& e, Lds<E>& L, int n, const S* e
     else e.g2s(L.sX, e1, n, n, n);
     wg_sync();
     e.zero(YZ[0]);
-    e.template gemm<true, false>(YZ[0], L.sA, L.sX, n);    // L' A1
+    e.template gemm_tri<true, false, false, 2>(YZ[0], L.sA, L.sX, n); // L' A1 (L' upper)
     const T b1 = CHEAP ? b1pre : e.vload(e1 + 3 * nn, n);
     T vv[2];
     vv[0] = g[0] + e.template matvec<true>(L.sA, L.vb, b1, n, n);
@@ -745,7 +745,7 @@ __global__ __launch_bounds__(E::NT, combine_min_waves<E>()) void k_tail(Plan p, 
 // they are the long ones), the others combine leaf pairs of the heads, so
 // the combines fill the CUs while the sweeps run their dependent steps.
 template <typename S, class E>
-__global__ __launch_bounds__(E::NT) void k_tail_up0(Plan p, S* ws, int32_t* status) {
+__global__ __launch_bounds__(E::NT, combine_min_waves<E>()) void k_tail_up0(Plan p, S* ws, int32_t* status) {
     static_assert(!E::BIG, "wavefront engine only");
     __shared__ Lds<E> L;
     const int64_t t = blockIdx.x;
@@ -839,7 +839,7 @@ __device__ __forceinline__ void chunk_agg_task(Lds<E>& L, const Plan& p, S* ws, 
 
 // phase 1: workgroups 0 .. batch-1 sweep the tails, the others aggregate chunks
 template <typename S, class E>
-__global__ __launch_bounds__(E::NT) void k_chunk_up(Plan p, S* ws, int32_t* status) {
+__global__ __launch_bounds__(E::NT, combine_min_waves<E>()) void k_chunk_up(Plan p, S* ws, int32_t* status) {
     static_assert(!E::BIG, "wavefront engine only");
     __shared__ Lds<E> L;
     const int64_t t = blockIdx.x;
