@@ -914,7 +914,7 @@ __global__ __launch_bounds__(E::NT, combine_min_waves<E>()) void k_chunk_down(Pl
 // then eq. (controlled_dynamics): Abar = A + B K, bbar = B k + c, written as
 // the leaf of the forward tree.  Stores K, k and L_G (reused by refinement).
 // ---------------------------------------------------------------------------
-template <typename S, class E, int MB>
+template <typename S, class E, int MB, bool KEEP_B = false>
 __device__ __forceinline__ void policy_task(Lds<E>& L, const Plan& p, const In<S>& in, S* ws, int32_t* status,
                             int64_t task) {
     using T = typename E::T;
@@ -931,8 +931,31 @@ __device__ __forceinline__ void policy_task(Lds<E>& L, const Plan& p, const In<S
     e.load(tA, P.A(b, k), n, n, n);
     e.load(tG, P.R(b, k), m, m, m);
     e.template load<true>(tH, P.M(b, k), m, n, m);        // M'
+    // KEEP_B (the policy kernel, m <= 16): B (n x m) is read only in the
+    // first MB column blocks, and the lane's part of them stays in registers
+    // for both of its stagings below (no second global read); otherwise the
+    // slot copy reads it each time
+    T tb[E::TS][KEEP_B ? MB : 1];
+    if constexpr (KEEP_B) {
+        const S* Bg = P.B(b, k);
+#pragma unroll
+        for (int a = 0; a < E::TS; ++a)
+#pragma unroll
+            for (int c = 0; c < MB; ++c)
+                tb[a][c] = (e.row(a) < n && e.col(c) < m) ? T(Bg[e.row(a) * m + e.col(c)]) : T(0);
+    }
+    auto stage_b = [&]() {
+        if constexpr (KEEP_B) {
+#pragma unroll
+            for (int a = 0; a < E::TS; ++a)
+#pragma unroll
+                for (int c = 0; c < MB; ++c) L.sX[e.row(a) * E::LD + e.col(c)] = tb[a][c];
+        } else {
+            stage(e, L.sX, P.B(b, k), n, m, m);
+        }
+    };
     stage(e, L.sA, Pn, n, n, n);                          // sA = P'
-    stage(e, L.sX, P.B(b, k), n, m, m);                   // sX = B
+    stage_b();                                            // sX = B (first MB column blocks)
     wg_sync();
     const T v = e.template matvec<false>(L.sA, L.vb, e.vload(P.c(b, k), n), n, n) + e.vload(Pn + nn, n);
     e.zero(t);
@@ -967,7 +990,7 @@ __device__ __forceinline__ void policy_task(Lds<E>& L, const Plan& p, const In<S
     e.store(tG, inst + p.o_LG + (int64_t)k * m * m, m, m, m);
     // closed loop: Abar = A + B K, bbar = B k + c
     e.to_lds(KK[0], L.sA);                                // sA = K (m x n)
-    stage(e, L.sX, P.B(b, k), n, m, m);                   // sX = B
+    stage_b();                                            // sX = B
     wg_sync();
     e.template gemm<false, false>(tA, L.sX, L.sA, m);     // A + B K
     S* leaf = inst + p.o_ftree + (int64_t)k * p.frec;
@@ -981,7 +1004,7 @@ __global__ __launch_bounds__(E::NT, combine_min_waves<E>()) void k_policy(Plan p
     __shared__ Lds<E> L;
     auto body = [&](int64_t t) {
         if constexpr (E::BIG) big_policy_task<S, E>(L, p, in, ws, status, t);
-        else policy_task<S, E, MB>(L, p, in, ws, status, t);
+        else policy_task<S, E, MB, (MB <= 2)>(L, p, in, ws, status, t);
     };
     LQR_TASKS(E, p.batch * p.N, body);
 }
