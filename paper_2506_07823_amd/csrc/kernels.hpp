@@ -452,10 +452,15 @@ __global__ __launch_bounds__(E::NT, combine_min_waves<E>()) void k_element(Plan 
 // (I + C1 P2)^{-1} = L^{-T} S^{-1} L').  CHEAP: e2 is a complete suffix
 // (A2 = C2 = b2 = 0), only P and p are formed and written to a suffix record.
 // ---------------------------------------------------------------------------
+// Sequential sweeps carry the suffix from one cheap combine to the next
+// (carry != nullptr): the combine leaves P in slot sA (staged there for its
+// store) and p in *carry, and a following call with P2 == nullptr takes
+// them from there instead of reading back what was just stored (the same
+// values: an FP32 store and load are exact, padding included).
 template <class E, bool CHEAP, bool BATCH = false, typename S>
 __device__ __forceinline__ void combine(const E& e, Lds<E>& L, int n, const S* e1, const S* P2, const S* p2v,
                                         const S* e2, S* outA, S* outC, S* outP, S* outb, S* outp, bool& okp,
-                                        typename E::T& kappa) {
+                                        typename E::T& kappa, typename E::T* carry = nullptr) {
     using T = typename E::T;
     const int nn = n * n;
     typename E::Tile tS;
@@ -472,10 +477,10 @@ __device__ __forceinline__ void combine(const E& e, Lds<E>& L, int n, const S* e
     // issue their loads in groups, one wait per group (more registers, which
     // those kernels' launch bound budgets)
     if constexpr (BATCH) {
-        e.g2s_batched(L.sA, P2, n, n, n);
+        if (P2) e.g2s_batched(L.sA, P2, n, n, n);
         e.g2s_batched(L.sX, e1 + nn, n, n, n);                 // sX = C1
     } else {
-        e.g2s(L.sA, P2, n, n, n);
+        if (P2) e.g2s(L.sA, P2, n, n, n);
         e.g2s(L.sX, e1 + nn, n, n, n);
     }
     if constexpr (CHEAP) {
@@ -484,7 +489,7 @@ __device__ __forceinline__ void combine(const E& e, Lds<E>& L, int n, const S* e
         b1pre = e.vload(e1 + 3 * nn, n);
         p1pre = e.vload(e1 + 3 * nn + n, n);
     }
-    T g[1] = {e.vload(p2v, n)};
+    T g[1] = {P2 ? e.vload(p2v, n) : *carry};
     const T p2l = g[0];
     wg_sync();
     e.from_lds(tS, L.sA);
@@ -575,6 +580,7 @@ __device__ __forceinline__ void combine(const E& e, Lds<E>& L, int n, const S* e
     e.template gemm<true, false, true>(tS, L.sX, L.sX, n); // P1 + Y'Y (lower)
     const T pv = e.template matvec<true>(L.sX, L.vb, vv[0], n, n) + (CHEAP ? p1pre : e.vload(e1 + 3 * nn + n, n));
     e.vstore(outp, n, pv);
+    if (carry) *carry = pv;
     wg_sync();
     e.to_lds_sym(tS, L.sA);                                // sA = P
     wg_sync();
@@ -718,14 +724,15 @@ __device__ __forceinline__ void tail_task(Lds<E>& L, const Plan& p, S* ws, int32
     E::sync();
     bool ok_all = true;
     typename E::T kmax = 0;
+    typename E::T pcar = 0;
     for (int k = N - 1; k >= p.tail; --k) {
         const S* node = tree + (int64_t)(p.rt.off[0] + k) * p.rec;
         const S* s2 = suf + (int64_t)suffix_id(p.rt, 0, k + 1) * p.srec;
         S* out = suf + (int64_t)suffix_id(p.rt, 0, k) * p.srec;
         bool ok;
         typename E::T kappa;
-        combine<E, true, BATCH>(e, L, n, node, s2, s2 + nn, (const S*)nullptr, (S*)nullptr, (S*)nullptr, out,
-                         (S*)nullptr, out + nn, ok, kappa);
+        combine<E, true, BATCH>(e, L, n, node, k == N - 1 ? s2 : (const S*)nullptr, s2 + nn, (const S*)nullptr,
+                                (S*)nullptr, (S*)nullptr, out, (S*)nullptr, out + nn, ok, kappa, &pcar);
         ok_all = ok_all && ok;
         if (!(kappa <= kmax)) kmax = kappa;   // NaN propagates
         E::sync();
@@ -863,14 +870,16 @@ __global__ __launch_bounds__(E::NT, combine_min_waves<E>()) void k_chunk_mid(Pla
     S* suf = ws + b * p.stride + p.o_suf;
     bool ok_all = true;
     typename E::T kmax = 0;
+    typename E::T pcar = 0;
     for (int c = p.nchunk - 1; c >= 0; --c) {
         const S* node = chunk_agg(p, tree, c);
         const S* s2 = suf + (int64_t)suffix_id(p.rt, 0, chunk_end(p, c)) * p.srec;
         S* out = suf + (int64_t)suffix_id(p.rt, 0, c * p.chunk) * p.srec;
         bool ok;
         typename E::T kappa;
-        combine<E, true, sizeof(typename E::T) == 4>(e, L, n, node, s2, s2 + nn, (const S*)nullptr, (S*)nullptr, (S*)nullptr, out,
-                         (S*)nullptr, out + nn, ok, kappa);
+        combine<E, true, sizeof(typename E::T) == 4>(e, L, n, node, c == p.nchunk - 1 ? s2 : (const S*)nullptr, s2 + nn,
+                                                     (const S*)nullptr, (S*)nullptr, (S*)nullptr, out, (S*)nullptr,
+                                                     out + nn, ok, kappa, &pcar);
         ok_all = ok_all && ok;
         if (!(kappa <= kmax)) kmax = kappa;
         E::sync();
@@ -892,14 +901,16 @@ __global__ __launch_bounds__(E::NT, combine_min_waves<E>()) void k_chunk_down(Pl
     const int c0 = c * p.chunk, c1 = chunk_end(p, c);
     bool ok_all = true;
     typename E::T kmax = 0;
+    typename E::T pcar = 0;
     for (int k = c1 - 1; k > c0; --k) {
         const S* node = tree + (int64_t)(p.rt.off[0] + k) * p.rec;
         const S* s2 = suf + (int64_t)suffix_id(p.rt, 0, k + 1) * p.srec;
         S* out = suf + (int64_t)suffix_id(p.rt, 0, k) * p.srec;
         bool ok;
         typename E::T kappa;
-        combine<E, true, sizeof(typename E::T) == 4>(e, L, n, node, s2, s2 + nn, (const S*)nullptr, (S*)nullptr, (S*)nullptr, out,
-                         (S*)nullptr, out + nn, ok, kappa);
+        combine<E, true, sizeof(typename E::T) == 4>(e, L, n, node, k == c1 - 1 ? s2 : (const S*)nullptr, s2 + nn,
+                                                     (const S*)nullptr, (S*)nullptr, (S*)nullptr, out, (S*)nullptr,
+                                                     out + nn, ok, kappa, &pcar);
         ok_all = ok_all && ok;
         if (!(kappa <= kmax)) kmax = kappa;
         E::sync();
