@@ -476,14 +476,18 @@ __device__ __forceinline__ void combine(const E& e, Lds<E>& L, int n, const S* e
     // BATCH (the FP32 sequential sweeps of cheap combines): the slot copies
     // issue their loads in groups, one wait per group (more registers, which
     // those kernels' launch bound budgets)
+    // In the sweeps (BATCH), C1 is loaded to registers before the first
+    // factorization and staged after it, A1 / P1 loaded after it: both
+    // factorizations then overlap outstanding loads.
+    typename E::Tile tC1;
     if constexpr (BATCH) {
         if (P2) e.g2s_batched(L.sA, P2, n, n, n);
-        e.g2s_batched(L.sX, e1 + nn, n, n, n);                 // sX = C1
+        e.load(tC1, e1 + nn, n, n, n);
     } else {
         if (P2) e.g2s(L.sA, P2, n, n, n);
         e.g2s(L.sX, e1 + nn, n, n, n);
     }
-    if constexpr (CHEAP) {
+    if constexpr (CHEAP && !BATCH) {
         e.load(tA1, e1, n, n, n);
         e.load(tP1, e1 + 2 * nn, n, n, n);
         b1pre = e.vload(e1 + 3 * nn, n);
@@ -497,6 +501,13 @@ __device__ __forceinline__ void combine(const E& e, Lds<E>& L, int n, const S* e
     bool ok = e.template chol<1>(tS, n, L.cb, dlA, g, dmin, dmax);
     T kap = cond_est(dmin, dmax);
     e.to_lds(tS, L.sA);                                   // sA = L
+    if constexpr (BATCH) {
+        e.to_lds(tC1, L.sX);                              // sX = C1
+        e.load(tA1, e1, n, n, n);
+        e.load(tP1, e1 + 2 * nn, n, n, n);
+        b1pre = e.vload(e1 + 3 * nn, n);
+        p1pre = e.vload(e1 + 3 * nn + n, n);
+    }
     wg_sync();
     T cp = T(0);
     if (!CHEAP) cp = e.template matvec<false>(L.sX, L.vb, p2l, n, n);   // C1 p2
