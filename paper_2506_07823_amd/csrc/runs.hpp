@@ -110,6 +110,12 @@ struct Work {
     double cheap_f() const { return 6.7 * n * n * n; }
     double cheap_min() const { return 31.0 / 6.0 * n * n * n; }
     double cheap_b() const { return es * (rec + 2 * srec); }
+    // a cheap combine inside a sequential sweep: the suffix matrix it
+    // extends was made by the step before and stays on chip, so only the
+    // leaf, the suffix vector and the new suffix move (the first step of a
+    // sweep also reads its n x n matrix: sweep_b)
+    double seq_b() const { return es * (rec + srec + n); }
+    double sweep_b() const { return es * n * n; }
     double pol_f() const { return 6 * n * n * m + 4 * n * m * m + m * m * m / 3; }
     double pol_b() const { return es * (n * n + 2 * n * m + m * m + 2 * n + m + srec + n * m + m + m * m + frec); }
     double fup_f() const { return 2 * n * n * n; }
@@ -273,10 +279,12 @@ int run_scan(const Plan& p, hipStream_t s, const In<S>& in, const Out<S>& out, S
                           st));
             if (p.nchunk > 0) {
                 const double um = B * p.nchunk, ud = B * (p.tail - p.nchunk);
-                LCHK(launch_w(NT, F_CHUNK_MID, um * w.cheap_f(), um * w.cheap_b(), um * w.cheap_min(),
-                              k_chunk_mid<S, E>, Bi, s, p, ws, st));
-                LCHK(launch_w(NT, F_CHUNK_DOWN, ud * w.cheap_f(), ud * w.cheap_b(), ud * w.cheap_min(),
-                              k_chunk_down<S, E>, Bi * p.nchunk, s, p, ws, st));
+                int down_sweeps = 0;   // chunks with at least one leaf after their start
+                for (int c = 0; c < p.nchunk; ++c) down_sweeps += chunk_end(p, c) - c * p.chunk >= 2;
+                LCHK(launch_w(NT, F_CHUNK_MID, um * w.cheap_f(), um * w.seq_b() + B * w.sweep_b(),
+                              um * w.cheap_min(), k_chunk_mid<S, E>, Bi, s, p, ws, st));
+                LCHK(launch_w(NT, F_CHUNK_DOWN, ud * w.cheap_f(), ud * w.seq_b() + B * down_sweeps * w.sweep_b(),
+                              ud * w.cheap_min(), k_chunk_down<S, E>, Bi * p.nchunk, s, p, ws, st));
             }
         }
     }
