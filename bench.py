@@ -187,7 +187,7 @@ def roofline_of(fams, bound, peak, unit):
             "launches": d["launches"], "flops_per_launch": d["flops"] / d["launches"],
             "algorithmic_bytes_per_launch": d["bytes"] / d["launches"],
             "algorithmic_GBps": d["bytes"] / (d["ms"] * 1e-3) / 1e9,
-            "achieved_cholesky_form_count": d["flops_min"] / (d["ms"] * 1e-3) / 1e12}
+            "achieved_executed_form_count": d["flops_min"] / (d["ms"] * 1e-3) / 1e12}
 
 
 def replay_latency(L, dev, method, refine, replays):

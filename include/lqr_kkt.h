@@ -61,7 +61,10 @@
  *
  * FP64 fallback (FP32 calls, opts.fallback = 1): a Cholesky factorization of
  * the scan (R_k in the element, G_k in the policy, the value matrix and the
- * inner matrix of a combine) with a non-positive pivot or a condition
+ * inner matrix of a combine; in the chunked schedule's sweeps at orders
+ * 17..64 with m <= 16, where a leaf is combined through its rank-m factor
+ * V = B R^{-1/2} by the Woodbury identity, the m x m matrix I + V' P V) with
+ * a non-positive pivot or a condition
  * estimate (max L_ii / min L_ii)^2 above opts.cond_threshold marks its
  * instance; after the FP32 solve every marked instance is solved again whole
  * with FP64 arithmetic and FP64 intermediates (the sequential recursion of

@@ -674,7 +674,7 @@ def kernel_timing(enable: bool, device: int = 0):
 def kernel_report(device: int = 0) -> dict:
     """Per kernel family: launches, total ms, algorithmic flops (the method's
     per-unit cost model) and bytes, and the flops with the combines counted
-    at the minimal cost of their Cholesky form, of the launches timed since
+    at the minimal cost of the form the kernels execute, of the launches timed since
     the last report (waits for them)."""
     buf = ctypes.create_string_buffer(1 << 16)
     _check(_lib.lqr_timing_report(handle(device), buf, len(buf)))

@@ -58,6 +58,10 @@ struct Plan {
     int nchunk;              // chunks over [0, tail) (schedule 2)
     int fwdseq;              // 1: forward scan and refinement vector passes as sequential sweeps
                              // over the stages, one task unit per instance
+    int64_t o_V;             // V_k' = L_R^{-1} B_k' (m x n) of the leaves k < N, for the low-rank
+                             // leaf combine of the sequential sweeps (-1: no such section)
+    int leafv;               // 1: the elements store V_k' and the chunked schedule's sweeps
+                             // combine leaves through it (leaf_combine)
     int64_t o_scr;           // large-block engine: byte offset of the per-workgroup scratch area
     int64_t scr_elems;       //   its elements per workgroup
     int big_grid;            //   workgroups of a task launch (scratch slots)
@@ -82,12 +86,18 @@ __host__ __device__ inline Tree make_tree(int leaves) {
 
 __host__ __device__ inline int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
+// Shapes whose sequential sweeps combine each leaf through its rank-m factor
+// (wavefront-engine orders 17..64 with m <= 16: an m x m factorization in
+// place of two n x n ones)
+__host__ __device__ inline bool leaf_lowrank(int n, int m) { return m <= 16 && n > 16 && n <= 64; }
+
 // Per-instance record layout of a scan solve of shape (N, n, m), in elements
 // of the storage type (every section 64-element aligned):
 //   tree  reverse-scan nodes (A, C, P, b, p)       suf   complete suffixes (P, p)
 //   K, kff, LG  policy and its Cholesky factor      ftree forward-scan nodes (M, v)
 //   xs, w, pend  node vectors of the vector scans   cp .. kffp  refinement data
-__host__ __device__ inline void plan_records(Plan& p, int N, int n, int m) {
+//   V     the leaves' rank-m factors (leaf_lowrank shapes only)
+__host__ __device__ inline void plan_records(Plan& p, int N, int n, int m, bool with_v = true) {
     p.N = N; p.n = n; p.m = m;
     const int64_t nn = (int64_t)n * n;
     p.rec = (int)(3 * nn + 2 * n);
@@ -112,6 +122,8 @@ __host__ __device__ inline void plan_records(Plan& p, int N, int n, int m) {
     p.o_x0p = sec(n);
     p.o_pp = sec((int64_t)(N + 1) * n);
     p.o_kffp = sec((int64_t)N * m);
+    p.o_V = with_v && leaf_lowrank(n, m) ? sec((int64_t)N * m * n) : -1;
+    p.leafv = 0;
     p.stride = off;
     p.dstride = 2 * (N + 1);
 }
@@ -417,6 +429,8 @@ __device__ __forceinline__ void element_task(Lds<E>& L, const Plan& p, const In<
     e.to_lds(W[0], L.sA);
     e.to_lds(W[1], L.sX);
     wg_sync();
+    // C_t = V V' with V = W_B' (n x m): the leaf combine of the sweeps uses V
+    if (p.leafv) e.s2g(L.sA, ws + b * p.stride + p.o_V + (int64_t)k * m * n, m, n, n);
     e.template gemm_sub<true, false>(tA, L.sA, L.sX, m);
     e.store(tA, rec, n, n, n);                         // At
     typename E::Tile t;
@@ -620,6 +634,83 @@ __device__ __forceinline__ void combine(const E& e, Lds<E>& L, int n, const S* e
     wg_sync();
     okp = ok;
     kappa = kap;
+}
+
+// ---------------------------------------------------------------------------
+// Cheap combine of a leaf e1 = (A1, b1, C1, P1, p1) with a complete suffix
+// (P2, p2), Sec. II-D eq. (combination_rule), where C1 = V V' has rank m
+// (V = B R^{-1/2}, eq. (initialization)).  By the Woodbury identity
+//   (I + P2 C1)^{-1} P2 = P2 - P2 V S^{-1} V' P2,   S = I_m + V' P2 V,
+// so with S = L_S L_S', U = L_S^{-1} V' P2 (m x n) and z = p2 + P2 b1:
+//   P = P1 + A1' (P2 - U'U) A1,   p = p1 + A1' (z - U' L_S^{-1} V' z),
+// the same (P, p) as the form above, with one m x m factorization in place
+// of the two n x n ones (S >= I: its pivots are at least 1).  The products
+// with an m-row operand form only the first MB row blocks.  Vt: the leaf's
+// V' (m x n, row-major).  P2 == nullptr: the suffix is the one the previous
+// call left in slot sA and *carry (the carry convention of combine).
+// ---------------------------------------------------------------------------
+template <class E, int MB, typename S>
+__device__ __forceinline__ void leaf_combine(const E& e, Lds<E>& L, int n, int m, const S* e1, const S* Vt,
+                                             const S* P2, const S* p2v, S* outP, S* outp, bool& okp,
+                                             typename E::T& kappa, typename E::T* carry) {
+    using T = typename E::T;
+    static_assert(MB >= 1 && MB < E::TS, "m spans fewer row blocks than the order");
+    const int nn = n * n;
+    typename E::Tile tA1, tP1, tM, tS;
+    typename E::Tile TU[1];
+    e.load(tA1, e1, n, n, n);                       // its latency overlaps the products below
+    const T b1 = e.vload(e1 + 3 * nn, n);
+    const T p1 = e.vload(e1 + 3 * nn + n, n);
+    if (P2) e.g2s_batched(L.sA, P2, n, n, n);       // sA = P2
+    // sX = V' in its first MB row blocks (zero past m and n)
+    for (int idx = e.lg; idx < MB * E::G * E::NP; idx += E::GL) {
+        const int i = idx / E::NP, j = idx - (idx / E::NP) * E::NP;
+        L.sX[i * E::LD + j] = (i < m && j < n) ? T(Vt[i * n + j]) : T(0);
+    }
+    const T p2 = P2 ? e.vload(p2v, n) : *carry;
+    wg_sync();
+    e.from_lds(tM, L.sA);                           // P2
+    e.zero(TU[0]);
+    e.template gemm<false, false, false, false, MB, E::TS>(TU[0], L.sX, L.sA, n);   // V' P2
+    const T z = p2 + e.template matvec<false>(L.sA, L.vb, b1, n, n);                // p2 + P2 b1
+    T w[1] = {e.template matvec<false>(L.sX, L.vb, z, n, m)};                       // V' z
+    wg_sync();
+    e.to_lds(TU[0], L.sA);                          // sA = V' P2
+    wg_sync();
+    e.zero(tS);
+    e.template gemm<false, true, false, false, MB, MB>(tS, L.sA, L.sX, n);         // V' P2 V
+    e.add_identity(tS, m);
+    T dl, dmin, dmax;
+    const bool ok = e.template chol<1, MB>(tS, m, L.cb, dl, w, dmin, dmax);        // L_S; w = L_S^{-1} V' z
+    e.to_lds(tS, L.sX);                             // sX = L_S
+    wg_sync();
+    T nov[1];
+    e.template trsm<true, 1, 0, MB>(L.sX, dl, m, TU, nov, L.rb);                    // U = L_S^{-1} V' P2
+    e.load(tP1, e1 + 2 * nn, n, n, n);
+    e.to_lds(TU[0], L.sA);                          // sA = U
+    wg_sync();
+    e.template gemm_sub<true, false, true>(tM, L.sA, L.sA, m);                      // P2 - U'U (lower)
+    const T y = z - e.template matvec<true>(L.sA, L.vb, w[0], m, n);                // z - U' w
+    wg_sync();
+    e.to_lds_sym(tM, L.sX);                         // sX = M = P2 - U'U
+    e.to_lds(tA1, L.sA);                            // sA = A1
+    wg_sync();
+    e.zero(tS);
+    e.template gemm<false, false>(tS, L.sX, L.sA, n);                               // M A1
+    wg_sync();
+    e.to_lds(tS, L.sX);                             // sX = M A1
+    wg_sync();
+    e.template gemm<true, false, true>(tP1, L.sA, L.sX, n);                         // P1 + A1' M A1 (lower)
+    const T pv = e.template matvec<true>(L.sA, L.vb, y, n, n) + p1;                // p1 + A1' y
+    e.vstore(outp, n, pv);
+    if (carry) *carry = pv;
+    wg_sync();
+    e.to_lds_sym(tP1, L.sA);                        // sA = P (kept for a carried call)
+    wg_sync();
+    e.s2g(L.sA, outP, n, n, n);
+    wg_sync();
+    okp = ok;
+    kappa = cond_est(dmin, dmax);
 }
 
 template <typename S, class E>
@@ -869,8 +960,10 @@ __global__ __launch_bounds__(E::NT, combine_min_waves<E>()) void k_chunk_up(Plan
     }
 }
 
-// phase 2: complete suffixes at the chunk starts, one task unit per instance
-template <typename S, class E>
+// phase 2: complete suffixes at the chunk starts, one task unit per instance.
+// LW > 0 (p.leafv, chunk length 1: every chunk is a leaf): through the
+// leaves' rank-m factors (leaf_combine, V' in LW row blocks)
+template <typename S, class E, int LW>
 __global__ __launch_bounds__(E::NT, combine_min_waves<E>()) void k_chunk_mid(Plan p, S* ws, int32_t* status) {
     static_assert(!E::BIG, "wavefront engine only");
     __shared__ Lds<E> L;
@@ -888,9 +981,13 @@ __global__ __launch_bounds__(E::NT, combine_min_waves<E>()) void k_chunk_mid(Pla
         S* out = suf + (int64_t)suffix_id(p.rt, 0, c * p.chunk) * p.srec;
         bool ok;
         typename E::T kappa;
-        combine<E, true, sizeof(typename E::T) == 4>(e, L, n, node, c == p.nchunk - 1 ? s2 : (const S*)nullptr, s2 + nn,
-                                                     (const S*)nullptr, (S*)nullptr, (S*)nullptr, out, (S*)nullptr,
-                                                     out + nn, ok, kappa, &pcar);
+        const S* first = c == p.nchunk - 1 ? s2 : (const S*)nullptr;
+        if constexpr (LW > 0)
+            leaf_combine<E, LW>(e, L, n, p.m, node, ws + b * p.stride + p.o_V + (int64_t)c * p.m * n, first, s2 + nn,
+                                out, out + nn, ok, kappa, &pcar);
+        else
+            combine<E, true, sizeof(typename E::T) == 4>(e, L, n, node, first, s2 + nn, (const S*)nullptr, (S*)nullptr,
+                                                         (S*)nullptr, out, (S*)nullptr, out + nn, ok, kappa, &pcar);
         ok_all = ok_all && ok;
         if (!(kappa <= kmax)) kmax = kappa;
         E::sync();
@@ -898,8 +995,9 @@ __global__ __launch_bounds__(E::NT, combine_min_waves<E>()) void k_chunk_mid(Pla
     fb_flag<E::NT>(p, ok_all, kmax, b, status, 4);
 }
 
-// phase 3: the other leaves of every chunk, one task unit per chunk
-template <typename S, class E>
+// phase 3: the other leaves of every chunk, one task unit per chunk (LW > 0:
+// through their rank-m factors, as in phase 2)
+template <typename S, class E, int LW>
 __global__ __launch_bounds__(E::NT, combine_min_waves<E>()) void k_chunk_down(Plan p, S* ws, int32_t* status) {
     static_assert(!E::BIG, "wavefront engine only");
     __shared__ Lds<E> L;
@@ -919,9 +1017,13 @@ __global__ __launch_bounds__(E::NT, combine_min_waves<E>()) void k_chunk_down(Pl
         S* out = suf + (int64_t)suffix_id(p.rt, 0, k) * p.srec;
         bool ok;
         typename E::T kappa;
-        combine<E, true, sizeof(typename E::T) == 4>(e, L, n, node, k == c1 - 1 ? s2 : (const S*)nullptr, s2 + nn,
-                                                     (const S*)nullptr, (S*)nullptr, (S*)nullptr, out, (S*)nullptr,
-                                                     out + nn, ok, kappa, &pcar);
+        const S* first = k == c1 - 1 ? s2 : (const S*)nullptr;
+        if constexpr (LW > 0)
+            leaf_combine<E, LW>(e, L, n, p.m, node, ws + b * p.stride + p.o_V + (int64_t)k * p.m * n, first, s2 + nn,
+                                out, out + nn, ok, kappa, &pcar);
+        else
+            combine<E, true, sizeof(typename E::T) == 4>(e, L, n, node, first, s2 + nn, (const S*)nullptr, (S*)nullptr,
+                                                         (S*)nullptr, out, (S*)nullptr, out + nn, ok, kappa, &pcar);
         ok_all = ok_all && ok;
         if (!(kappa <= kmax)) kmax = kappa;
         E::sync();
@@ -2062,7 +2164,7 @@ __device__ __forceinline__ bool ragged_plan(const RaggedArgs<S>& a, const Ragged
     if (d.N < 1 || d.n < 1 || d.m < 1 || d.N > a.maxN || d.n > a.maxd || d.m > a.maxd) return false;
     p = Plan{};
     p.batch = 1;
-    plan_records(p, d.N, d.n, d.m);
+    plan_records(p, d.N, d.n, d.m, false);   // the one-launch solve combines leaves in the general form
     p.cond_thr = a.cond_thr;
     p.refine_tol = a.refine_tol;
     p.fallback = a.fallback;

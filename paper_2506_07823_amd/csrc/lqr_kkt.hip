@@ -134,6 +134,8 @@ Plan make_plan(int64_t batch, int N, int n, int m, size_t esize, const lqr_opts&
         }
     }
     p.fwdseq = tun && tun->fwd_seq && p.fused != 2 ? 1 : 0;
+    // the chunked schedule's sweeps combine each leaf through its rank-m factor
+    p.leafv = p.sched == 2 && p.o_V >= 0 ? 1 : 0;
     if (big) {
         if (p.fused == 2) p.fused = 1;   // the one-launch solve is a wavefront-engine form
         const int64_t d = n > m ? n : m;
@@ -900,7 +902,7 @@ int dev_ragged_layout(int64_t count, int slots, int maxN, int maxd, const lqr_op
     const size_t es = o.dtype == LQR_F32 ? 4 : 8;
     Plan p;
     std::memset(&p, 0, sizeof p);
-    plan_records(p, maxN, maxd, maxd);
+    plan_records(p, maxN, maxd, maxd, false);
     l.slot_elems = p.stride;
     l.dslot = align_up(p.dstride + 1, 8);
     Plan r = p;

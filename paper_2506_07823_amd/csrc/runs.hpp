@@ -27,6 +27,18 @@ constexpr int kBigTS = 32;
 template <typename S, int TS>
 using EngOf = typename std::conditional<TS == kBigTS, BigEng<S>, Eng<S, 8, TS>>::type;
 
+// Row blocks of the leaves' rank-m factors for the sweeps of the chunked
+// schedule (p.leafv: m <= 16 at orders 17..64, i.e. one or two blocks of a
+// tile of at least three), 0: the general cheap combine
+template <int TS, typename Fn>
+int with_lw(const Plan& p, Fn&& fn) {
+    if constexpr (TS != kBigTS && TS > 2) {
+        if (p.leafv && p.m <= 8) return fn(std::integral_constant<int, 1>{});
+        if (p.leafv && p.m <= 16) return fn(std::integral_constant<int, 2>{});
+    }
+    return fn(std::integral_constant<int, 0>{});
+}
+
 // host-side choice of the control-block count MB (see kernels.hpp): calls
 // fn(std::integral_constant<int, MB>) with MB = 1, 2 or TS (0 for the
 // large-block engine, which does not use it)
@@ -57,8 +69,8 @@ enum Fam {
 // Optional per-launch timer (HIP events around each launch on its stream),
 // installed by the ABI layer for the duration of a call.  `flops` is the
 // algorithmic count of the launch (per-unit figures of Work below), `flops_min`
-// the same with the combines counted at the minimal cost of their Cholesky
-// form.
+// the same with the combines counted at the minimal cost of the form the
+// kernels execute (the Cholesky form, or the leaf form of the chunked sweeps).
 struct Timer {
     virtual ~Timer() {}
     virtual void before(hipStream_t s, int fam, double flops, double bytes, double flops_min) = 0;
@@ -97,7 +109,8 @@ inline int64_t task_grid(const Plan& p, int64_t tasks) {
 // combine with a complete suffix ~6.7 n^3, a forward map composition 2 n^3);
 // comb_min / cheap_min are the minimal counts of the Cholesky form the
 // kernels execute (67/6 n^3 and 31/6 n^3: two factorizations, the
-// triangular solves and products at their triangular/symmetric cost).
+// triangular solves and products at their triangular/symmetric cost),
+// leaf_min that of the leaf form of a cheap combine (leaf_combine).
 struct Work {
     double n, m, es, rec, srec, frec;
     explicit Work(const Plan& p, size_t esize)
@@ -116,6 +129,12 @@ struct Work {
     // sweep also reads its n x n matrix: sweep_b)
     double seq_b() const { return es * (rec + srec + n); }
     double sweep_b() const { return es * n * n; }
+    // the same step in the leaf form: the leaf without C, its n x m factor
+    // V, the suffix vector, the new suffix; minimal flops of that form
+    // (V'P2, V'P2V, the m x m factorization and solve, P2 - U'U, M A1,
+    // A1'(M A1) at their symmetric/triangular cost)
+    double leaf_b() const { return es * (2 * n * n + 2 * n + n * m + srec + n); }
+    double leaf_min() const { return 3 * n * n * n + 3 * n * n * m + 2 * n * m * m + m * m * m / 3; }
     double pol_f() const { return 6 * n * n * m + 4 * n * m * m + m * m * m / 3; }
     double pol_b() const { return es * (n * n + 2 * n * m + m * m + 2 * n + m + srec + n * m + m + m * m + frec); }
     double fup_f() const { return 2 * n * n * n; }
@@ -281,10 +300,21 @@ int run_scan(const Plan& p, hipStream_t s, const In<S>& in, const Out<S>& out, S
                 const double um = B * p.nchunk, ud = B * (p.tail - p.nchunk);
                 int down_sweeps = 0;   // chunks with at least one leaf after their start
                 for (int c = 0; c < p.nchunk; ++c) down_sweeps += chunk_end(p, c) - c * p.chunk >= 2;
-                LCHK(launch_w(NT, F_CHUNK_MID, um * w.cheap_f(), um * w.seq_b() + B * w.sweep_b(),
-                              um * w.cheap_min(), k_chunk_mid<S, E>, Bi, s, p, ws, st));
-                LCHK(launch_w(NT, F_CHUNK_DOWN, ud * w.cheap_f(), ud * w.seq_b() + B * down_sweeps * w.sweep_b(),
-                              ud * w.cheap_min(), k_chunk_down<S, E>, Bi * p.nchunk, s, p, ws, st));
+                LCHK(with_lw<TS>(p, [&](auto lw) {
+                    constexpr int LW = decltype(lw)::value;
+                    // phase 2 in the leaf form only when every chunk is one leaf
+                    if (LW > 0 && p.chunk == 1) {
+                        LCHK(launch_w(NT, F_CHUNK_MID, um * w.cheap_f(), um * w.leaf_b() + B * w.sweep_b(),
+                                      um * w.leaf_min(), k_chunk_mid<S, E, LW>, Bi, s, p, ws, st));
+                    } else {
+                        LCHK(launch_w(NT, F_CHUNK_MID, um * w.cheap_f(), um * w.seq_b() + B * w.sweep_b(),
+                                      um * w.cheap_min(), k_chunk_mid<S, E, 0>, Bi, s, p, ws, st));
+                    }
+                    return launch_w(NT, F_CHUNK_DOWN, ud * w.cheap_f(),
+                                    ud * (LW > 0 ? w.leaf_b() : w.seq_b()) + B * down_sweeps * w.sweep_b(),
+                                    ud * (LW > 0 ? w.leaf_min() : w.cheap_min()), k_chunk_down<S, E, LW>,
+                                    Bi * p.nchunk, s, p, ws, st);
+                }));
             }
         }
     }

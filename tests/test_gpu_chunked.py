@@ -61,6 +61,42 @@ def test_chunked_fp64_meets_oracle(N, n, m, chunk, sweep, fwd_seq):
     assert res.max() <= 1e-11
 
 
+# Shapes whose chunked sweeps combine each leaf through its rank-m factor
+# V = B R^{-1/2} (orders 17..64 with m <= 16): factors of one and two row
+# blocks, tile orders 3, 5, 6 and 8, m = 1 and m = 16 at the class edges.
+# Schedules: chunk 1 (every chunk-start suffix in the leaf form), chunks of
+# 4 behind a 3-leaf sweep (the chunk interiors in the leaf form), chunk 1
+# behind a 5-leaf sweep (the leaf form takes over a suffix the general form
+# stored), chunks of 5 with a short last chunk.
+LEAF_SHAPES = [(9, 17, 16), (20, 24, 1), (12, 40, 8), (7, 64, 16), (30, 50, 5)]
+LEAF_SCHEDS = [(1, 1), (4, 3), (1, 5), (5, 1)]
+
+
+@pytest.mark.parametrize("N,n,m", LEAF_SHAPES)
+@pytest.mark.parametrize("chunk,sweep", LEAF_SCHEDS)
+def test_chunked_leaf_form_fp64(N, n, m, chunk, sweep):
+    batch = synth.gen_batch(lambda i: synth.gen_rand(N, n, m, seed=[966, N, n, m, i]), 3, np.float64)
+    say(f"[chunked leaf form fp64] N={N} n={n} m={m} chunk={chunk} sweep={sweep}")
+    out = _pinned(batch, np.float64, _chunked(chunk, sweep, True))
+    assert not out["status"].any(), out["status"]
+    errs, res, _ = oracle_check_all(batch, out)
+    assert errs.max() <= FP64_ELEM_TOL, errs
+    assert res.max() <= 1e-11
+
+
+@pytest.mark.parametrize("N,n,m", [(60, 24, 8), (50, 48, 16), (40, 64, 3)])
+@pytest.mark.parametrize("chunk,sweep", [(1, 1), (4, 3)])
+def test_chunked_leaf_form_fp32_refined(N, n, m, chunk, sweep):
+    batch = synth.gen_batch(lambda i: synth.gen_c1_like(N, n, m, [967, N, n, m, i], dt=0.01), 5, np.float32)
+    say(f"[chunked leaf form fp32] N={N} n={n} m={m} chunk={chunk} sweep={sweep}")
+    out = _pinned(batch, np.float32, _chunked(chunk, sweep, True), want_resid=True, refine=1)
+    assert not out["status"].any(), out["status"]
+    errs, res, _ = oracle_check_all(batch, out, as_f32=True)
+    describe(f"n={n} m={m}", errs, res)
+    assert out["resid"].max() <= RESID_TOL and res.max() <= RESID_TOL
+    assert errs.max() <= FP32_ELEM_TOL
+
+
 @pytest.mark.parametrize("mapping", [{"engine": "wavefront", "fused": 0, "fwd_seq": True},
                                      {"engine": "wavefront", "fused": 0, "split": 1, "fwd_seq": True},
                                      {"engine": "matrix-core", "fused": 0, "fwd_seq": True}])
