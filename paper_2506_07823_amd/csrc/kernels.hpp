@@ -62,6 +62,8 @@ struct Plan {
                              // leaf combine of the sequential sweeps (-1: no such section)
     int leafv;               // 1: the elements store V_k' and the chunked schedule's sweeps
                              // combine leaves through it (leaf_combine)
+    int noC;                 // 1: no combine reads a leaf's C (every leaf goes through V), so the
+                             // elements leave that part of their records unwritten
     int64_t o_scr;           // large-block engine: byte offset of the per-workgroup scratch area
     int64_t scr_elems;       //   its elements per workgroup
     int big_grid;            //   workgroups of a task launch (scratch slots)
@@ -124,6 +126,7 @@ __host__ __device__ inline void plan_records(Plan& p, int N, int n, int m, bool 
     p.o_kffp = sec((int64_t)N * m);
     p.o_V = with_v && leaf_lowrank(n, m) ? sec((int64_t)N * m * n) : -1;
     p.leafv = 0;
+    p.noC = 0;
     p.stride = off;
     p.dstride = 2 * (N + 1);
 }
@@ -386,7 +389,7 @@ namespace lqr {
 // The terminal element (k = N) is (0, 0, 0, Q_N, q_N).  A factorization of
 // R_k with a non-positive pivot or a condition estimate above the threshold
 // marks the instance for the FP64 redo.
-// Record layout: A | C | P | b | p.
+// Record layout: A | C | P | b | p (C left unwritten under p.noC).
 // ---------------------------------------------------------------------------
 template <typename S, class E, int MB>
 __device__ __forceinline__ void element_task(Lds<E>& L, const Plan& p, const In<S>& in, S* ws, int32_t* status,
@@ -433,10 +436,12 @@ __device__ __forceinline__ void element_task(Lds<E>& L, const Plan& p, const In<
     if (p.leafv) e.s2g(L.sA, ws + b * p.stride + p.o_V + (int64_t)k * m * n, m, n, n);
     e.template gemm_sub<true, false>(tA, L.sA, L.sX, m);
     e.store(tA, rec, n, n, n);                         // At
-    typename E::Tile t;
-    e.zero(t);
-    e.template gemm<true, false, true>(t, L.sA, L.sA, m);
-    e.store_sym(t, rec + nn, n);                       // Ct
+    if (!p.noC) {
+        typename E::Tile t;
+        e.zero(t);
+        e.template gemm<true, false, true>(t, L.sA, L.sA, m);
+        e.store_sym(t, rec + nn, n);                   // Ct
+    }
     e.template gemm_sub<true, false, true>(tQ, L.sX, L.sX, m);
     e.store_sym(tQ, rec + 2 * nn, n);                  // Pt
     const T bw = e.template matvec<true>(L.sA, L.vb, vv[0], m, n);

@@ -136,6 +136,9 @@ Plan make_plan(int64_t batch, int N, int n, int m, size_t esize, const lqr_opts&
     p.fwdseq = tun && tun->fwd_seq && p.fused != 2 ? 1 : 0;
     // the chunked schedule's sweeps combine each leaf through its rank-m factor
     p.leafv = p.sched == 2 && p.o_V >= 0 ? 1 : 0;
+    // chunk length 1 and a sweep of the terminal element only: every leaf
+    // is combined in the leaf form, none reads its C
+    p.noC = p.leafv && p.chunk == 1 && p.tail == N ? 1 : 0;
     if (big) {
         if (p.fused == 2) p.fused = 1;   // the one-launch solve is a wavefront-engine form
         const int64_t d = n > m ? n : m;

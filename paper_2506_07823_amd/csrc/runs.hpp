@@ -112,11 +112,13 @@ inline int64_t task_grid(const Plan& p, int64_t tasks) {
 // triangular solves and products at their triangular/symmetric cost),
 // leaf_min that of the leaf form of a cheap combine (leaf_combine).
 struct Work {
-    double n, m, es, rec, srec, frec;
+    double n, m, es, rec, srec, frec, vb, cb;
     explicit Work(const Plan& p, size_t esize)
-        : n(p.n), m(p.m), es((double)esize), rec(p.rec), srec(p.srec), frec(p.frec) {}
-    double elem_f() const { return m * m * m / 3 + 2 * n * m * m + 4 * n * n * m; }
-    double elem_b() const { return es * (2 * n * n + 2 * n * m + m * m + 2 * n + m + rec); }
+        : n(p.n), m(p.m), es((double)esize), rec(p.rec), srec(p.srec), frec(p.frec),
+          vb(p.leafv ? (double)p.n * p.m : 0.0), cb(p.noC ? (double)p.n * p.n : 0.0) {}
+    double elem_f() const { return m * m * m / 3 + 2 * n * m * m + 4 * n * n * m - (cb > 0 ? n * n * m : 0.0); }
+    // inputs read, the record written (with V, without C where the plan says so)
+    double elem_b() const { return es * (2 * n * n + 2 * n * m + m * m + 2 * n + m + rec + vb - cb); }
     double comb_f() const { return 17.0 * n * n * n; }
     double comb_min() const { return 67.0 / 6.0 * n * n * n; }
     double comb_b() const { return es * 3 * rec; }

@@ -199,6 +199,45 @@ def test_chunked_in_a_graph_replays_identically():
         L.set_tuning(count, N, n, m, torch.float32, clear=True)
 
 
+def test_chunked_leaf_form_in_a_graph_replays_identically():
+    """Chunk length 1 at a leaf-form shape (every leaf combined through its
+    rank-m factor, the elements' C parts left unwritten): replays with the
+    whole workspace overwritten between them give the eager bits, so no
+    kernel reads a record part the solve did not write."""
+    import torch
+    import paper_2506_07823_amd as L
+    N, n, m, count = 40, 24, 8, 6
+    b = synth.gen_batch(lambda i: synth.gen_c1_like(N, n, m, [968, i], dt=0.01), count, np.float32)
+    dev = to_dev(b, np.float32)
+    args = [dev[k] for k in L.FIELDS]
+    L.set_tuning(count, N, n, m, torch.float32, **_chunked(1, 1, True))
+    try:
+        eager = L.solve(*args, want_resid=True, refine=1)
+        torch.cuda.synchronize()
+        ref = {k: v.clone() for k, v in eager.items()}
+        ws = L.Workspace()
+        out = L.solve(*args, want_resid=True, refine=1, workspace=ws)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            L.solve(*args, want_resid=True, refine=1, workspace=ws, out=out)
+        torch.cuda.synchronize()
+        for rep in range(3):
+            for v in out.values():
+                v.fill_(-1)
+            ws.buf.fill_(0x7f)
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            for k in ("x", "u", "lam", "status", "resid"):
+                assert torch.equal(out[k], ref[k]), (rep, k)
+        assert not ref["status"].any() and ref["resid"].max().item() <= RESID_TOL
+        errs, res, _ = oracle_check_all(b, {k: v.cpu().numpy() for k, v in ref.items()}, as_f32=True)
+        assert res.max() <= RESID_TOL and errs.max() <= FP32_ELEM_TOL
+    finally:
+        L.set_tuning(count, N, n, m, torch.float32, clear=True)
+
+
 def test_chunked_mappings_rejected():
     import torch
     import paper_2506_07823_amd as L
