@@ -192,10 +192,12 @@ int run_redo(const Plan& p, hipStream_t s, const In<S>& in, const Out<S>& out, S
         LCHK(launch_nt(256, F_MARK, 0, 0, k_mark_status<8>, (Bi + 255) / 256, s, (const int32_t*)out.status, cx.active, Bi));
         Plan pm = p;
         pm.active = cx.active;
-        LCHK(launch_nt(E64::NT, F_RESID, 0, 0, k_resid<S, E64, false>, Bi * (p.N + 1), s, pm, in, (const S*)out.x,
-                       (const S*)out.u, (const S*)out.lam, ws, cx.dws));
-        LCHK(launch_nt(WG, F_REDUCE, 0, 0, k_resid_reduce<double>, (Bi + 63) / 64, s, pm, (const double*)cx.dws,
-                       resid_out, (int32_t*)nullptr, p.refine_tol, (const int32_t*)out.status));
+        // one task unit per instance (the same sums in the same order as the
+        // per-stage launch and its reduction): an instance that was not
+        // redone leaves at its gate, so the launch costs a few microseconds
+        LCHK(launch_nt(E64::NT, F_RESID, 0, 0, k_resid_inst<S, E64, false>, Bi, s, pm, in, (const S*)out.x,
+                       (const S*)out.u, (const S*)out.lam, ws, cx.dws, resid_out, (int32_t*)nullptr, p.refine_tol,
+                       (const int32_t*)out.status));
     }
     return LQR_OK;
 }
@@ -295,9 +297,11 @@ int run_scan(const Plan& p, hipStream_t s, const In<S>& in, const Out<S>& out, S
             // chunked: chunk aggregates beside the sweep, suffixes at the
             // chunk starts, then the other leaves of every chunk
             const double ug = B * (p.tail - p.nchunk);   // general combines of the aggregates
+            // chunks of one leaf have no aggregate to form: at chunk length 1
+            // the launch holds the sweep tasks only
+            const int64_t agg_tasks = p.chunk == 1 ? 0 : Bi * p.nchunk;
             LCHK(launch_w(NT, F_CHUNK_UP, ut * w.cheap_f() + ug * w.comb_f(), ut * w.cheap_b() + ug * w.comb_b(),
-                          ut * w.cheap_min() + ug * w.comb_min(), k_chunk_up<S, E>, Bi + Bi * p.nchunk, s, p, ws,
-                          st));
+                          ut * w.cheap_min() + ug * w.comb_min(), k_chunk_up<S, E>, Bi + agg_tasks, s, p, ws, st));
             if (p.nchunk > 0) {
                 const double um = B * p.nchunk, ud = B * (p.tail - p.nchunk);
                 int down_sweeps = 0;   // chunks with at least one leaf after their start
@@ -312,6 +316,8 @@ int run_scan(const Plan& p, hipStream_t s, const In<S>& in, const Out<S>& out, S
                         LCHK(launch_w(NT, F_CHUNK_MID, um * w.cheap_f(), um * w.seq_b() + B * w.sweep_b(),
                                       um * w.cheap_min(), k_chunk_mid<S, E, 0>, Bi, s, p, ws, st));
                     }
+                    // no chunk with a leaf after its start: nothing for phase 3
+                    if (down_sweeps == 0) return (int)LQR_OK;
                     return launch_w(NT, F_CHUNK_DOWN, ud * w.cheap_f(),
                                     ud * (LW > 0 ? w.leaf_b() : w.seq_b()) + B * down_sweeps * w.sweep_b(),
                                     ud * (LW > 0 ? w.leaf_min() : w.cheap_min()), k_chunk_down<S, E, LW>,
