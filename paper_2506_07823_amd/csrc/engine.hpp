@@ -185,6 +185,16 @@ struct Eng {
             for (int b = 0; b < TS; ++b) s[row(a) * LD + col(b)] = t[a][b];
     }
 
+    // the first RB row blocks of t (rows < G * RB) to an LDS region
+    template <int RB>
+    __device__ __forceinline__ void to_lds_rows(const Tile& t, T* s) const {
+        static_assert(RB <= TS, "block limit");
+#pragma unroll
+        for (int a = 0; a < RB; ++a)
+#pragma unroll
+            for (int b = 0; b < TS; ++b) s[row(a) * LD + col(b)] = t[a][b];
+    }
+
     __device__ __forceinline__ void from_lds(Tile& t, const T* s) const {
 #pragma unroll
         for (int a = 0; a < TS; ++a)

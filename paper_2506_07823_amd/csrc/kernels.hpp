@@ -64,6 +64,8 @@ struct Plan {
                              // combine leaves through it (leaf_combine)
     int noC;                 // 1: no combine reads a leaf's C (every leaf goes through V), so the
                              // elements leave that part of their records unwritten
+    int fuse_elem;           // 1: the chunk-1 sweep builds each leaf itself (k_chunk_mid_elem):
+                             // no element launch, no leaf records
     int64_t o_scr;           // large-block engine: byte offset of the per-workgroup scratch area
     int64_t scr_elems;       //   its elements per workgroup
     int big_grid;            //   workgroups of a task launch (scratch slots)
@@ -127,6 +129,7 @@ __host__ __device__ inline void plan_records(Plan& p, int N, int n, int m, bool 
     p.o_V = with_v && leaf_lowrank(n, m) ? sec((int64_t)N * m * n) : -1;
     p.leafv = 0;
     p.noC = 0;
+    p.fuse_elem = 0;
     p.stride = off;
     p.dstride = 2 * (N + 1);
 }
@@ -654,26 +657,19 @@ __device__ __forceinline__ void combine(const E& e, Lds<E>& L, int n, const S* e
 // V' (m x n, row-major).  P2 == nullptr: the suffix is the one the previous
 // call left in slot sA and *carry (the carry convention of combine).
 // ---------------------------------------------------------------------------
-template <class E, int MB, typename S>
-__device__ __forceinline__ void leaf_combine(const E& e, Lds<E>& L, int n, int m, const S* e1, const S* Vt,
-                                             const S* P2, const S* p2v, S* outP, S* outp, bool& okp,
-                                             typename E::T& kappa, typename E::T* carry) {
+// The combine proper: V' staged in the first MB row blocks of sX, P2 in sA,
+// the leaf's A1 (tile), b1, p1 (lane vectors) and P1 given (LATE_P1: loaded
+// from P1g after the factorization, whose latency it then overlaps; else
+// already in tP1, lower triangle).
+template <class E, int MB, bool LATE_P1, typename S>
+__device__ __forceinline__ void leaf_core(const E& e, Lds<E>& L, int n, int m, typename E::Tile& tA1,
+                                          typename E::Tile& tP1, const S* P1g, typename E::T b1, typename E::T p1,
+                                          typename E::T p2, S* outP, S* outp, bool& okp, typename E::T& kappa,
+                                          typename E::T* carry) {
     using T = typename E::T;
     static_assert(MB >= 1 && MB < E::TS, "m spans fewer row blocks than the order");
-    const int nn = n * n;
-    typename E::Tile tA1, tP1, tM, tS;
+    typename E::Tile tM, tS;
     typename E::Tile TU[1];
-    e.load(tA1, e1, n, n, n);                       // its latency overlaps the products below
-    const T b1 = e.vload(e1 + 3 * nn, n);
-    const T p1 = e.vload(e1 + 3 * nn + n, n);
-    if (P2) e.g2s_batched(L.sA, P2, n, n, n);       // sA = P2
-    // sX = V' in its first MB row blocks (zero past m and n)
-    for (int idx = e.lg; idx < MB * E::G * E::NP; idx += E::GL) {
-        const int i = idx / E::NP, j = idx - (idx / E::NP) * E::NP;
-        L.sX[i * E::LD + j] = (i < m && j < n) ? T(Vt[i * n + j]) : T(0);
-    }
-    const T p2 = P2 ? e.vload(p2v, n) : *carry;
-    wg_sync();
     e.from_lds(tM, L.sA);                           // P2
     e.zero(TU[0]);
     e.template gemm<false, false, false, false, MB, E::TS>(TU[0], L.sX, L.sA, n);   // V' P2
@@ -691,7 +687,7 @@ __device__ __forceinline__ void leaf_combine(const E& e, Lds<E>& L, int n, int m
     wg_sync();
     T nov[1];
     e.template trsm<true, 1, 0, MB>(L.sX, dl, m, TU, nov, L.rb);                    // U = L_S^{-1} V' P2
-    e.load(tP1, e1 + 2 * nn, n, n, n);
+    if constexpr (LATE_P1) e.load(tP1, P1g, n, n, n);
     e.to_lds(TU[0], L.sA);                          // sA = U
     wg_sync();
     e.template gemm_sub<true, false, true>(tM, L.sA, L.sA, m);                      // P2 - U'U (lower)
@@ -716,6 +712,79 @@ __device__ __forceinline__ void leaf_combine(const E& e, Lds<E>& L, int n, int m
     wg_sync();
     okp = ok;
     kappa = cond_est(dmin, dmax);
+}
+
+template <class E, int MB, typename S>
+__device__ __forceinline__ void leaf_combine(const E& e, Lds<E>& L, int n, int m, const S* e1, const S* Vt,
+                                             const S* P2, const S* p2v, S* outP, S* outp, bool& okp,
+                                             typename E::T& kappa, typename E::T* carry) {
+    using T = typename E::T;
+    const int nn = n * n;
+    typename E::Tile tA1, tP1;
+    e.load(tA1, e1, n, n, n);                       // its latency overlaps the products
+    const T b1 = e.vload(e1 + 3 * nn, n);
+    const T p1 = e.vload(e1 + 3 * nn + n, n);
+    if (P2) e.g2s_batched(L.sA, P2, n, n, n);       // sA = P2
+    // sX = V' in its first MB row blocks (zero past m and n)
+    for (int idx = e.lg; idx < MB * E::G * E::NP; idx += E::GL) {
+        const int i = idx / E::NP, j = idx - (idx / E::NP) * E::NP;
+        L.sX[i * E::LD + j] = (i < m && j < n) ? T(Vt[i * n + j]) : T(0);
+    }
+    const T p2 = P2 ? e.vload(p2v, n) : *carry;
+    wg_sync();
+    leaf_core<E, MB, true>(e, L, n, m, tA1, tP1, e1 + 2 * nn, b1, p1, p2, outP, outp, okp, kappa, carry);
+}
+
+// The same step with the leaf built in place from the stage inputs
+// (eq. (initialization), as element_task: R = L_R L_R', [W_B; W_M] =
+// L_R^{-1} [B'; M'], w_r = L_R^{-1} r, At = A - W_B'W_M, Pt = Q - W_M'W_M,
+// bt = c - W_B'w_r, pt = q - W_M'w_r, V' = W_B): W_B and W_M take the two
+// halves of slot sX, sA keeps the suffix, At, bt, pt stay in registers, and
+// Pt waits in the leaf's P slot (ws_P1: stored and read back by the same
+// lanes, so it stays in the cache) until the combine's last product, as in
+// leaf_combine.  The same arithmetic in the same order as the element
+// kernel followed by leaf_combine.
+template <class E, int MB, typename S>
+__device__ __forceinline__ void leaf_elem_combine(const E& e, Lds<E>& L, const Plan& p, const Ptr<S>& P, int64_t b,
+                                                  int k, S* ws_P1, const S* P2, const S* p2v, S* outP, S* outp,
+                                                  bool& okp, typename E::T& kappa, bool& okR,
+                                                  typename E::T& kappaR, typename E::T* carry) {
+    using T = typename E::T;
+    static_assert(2 * MB * E::G <= E::NP, "W_B and W_M share one slot");
+    const int n = p.n, m = p.m;
+    T* sW = L.sX + MB * E::G * E::LD;               // W_M below V'
+    typename E::Tile W[2];
+    T vv[1];
+    {
+        typename E::Tile tR;
+        e.load(tR, P.R(b, k), m, m, m);
+        e.template load<true>(W[0], P.B(b, k), m, n, m);   // B'
+        e.template load<true>(W[1], P.M(b, k), m, n, m);   // M'
+        vv[0] = e.vload(P.r(b, k), m);
+        T dmin, dmax, nov[1];
+        T dlR;
+        okR = e.template chol<0, MB>(tR, m, L.cb, dlR, nov, dmin, dmax);
+        kappaR = cond_est(dmin, dmax);
+        e.template to_lds_rows<MB>(tR, L.sX);       // L_R
+        wg_sync();
+        e.template trsm<true, 2, 1, MB>(L.sX, dlR, m, W, vv, L.rb);
+    }
+    e.template to_lds_rows<MB>(W[0], L.sX);         // V' = W_B
+    e.template to_lds_rows<MB>(W[1], sW);           // W_M
+    typename E::Tile tA1, tP1;
+    e.load(tA1, P.A(b, k), n, n, n);
+    e.load(tP1, P.Q(b, k), n, n, n);
+    const T cpre = e.vload(P.c(b, k), n), qpre = e.vload(P.q(b, k), n);
+    if (P2) e.g2s_batched(L.sA, P2, n, n, n);       // sA = P2
+    const T p2 = P2 ? e.vload(p2v, n) : *carry;
+    wg_sync();
+    e.template gemm_sub<true, false>(tA1, L.sX, sW, m);                             // At
+    e.template gemm_sub<true, false, true>(tP1, sW, sW, m);                         // Pt (lower)
+    e.store(tP1, ws_P1, n, n, n);
+    const T b1 = cpre - e.template matvec<true>(L.sX, L.vb, vv[0], m, n);           // bt
+    const T p1 = qpre - e.template matvec<true>(sW, L.vb, vv[0], m, n);             // pt
+    wg_sync();
+    leaf_core<E, MB, true>(e, L, n, m, tA1, tP1, (const S*)ws_P1, b1, p1, p2, outP, outp, okp, kappa, carry);
 }
 
 template <typename S, class E>
@@ -998,6 +1067,48 @@ __global__ __launch_bounds__(E::NT, combine_min_waves<E>()) void k_chunk_mid(Pla
         E::sync();
     }
     fb_flag<E::NT>(p, ok_all, kmax, b, status, 4);
+}
+
+// Chunk length 1 with the leaves built in the sweep (p.fuse_elem): the
+// whole reverse scan of an instance in one task unit, from the terminal
+// element (P_N = Q_N, p_N = q_N, read from the inputs) back to stage 0, each
+// step leaf_elem_combine.  A factorization of R_k that fails or exceeds the
+// condition threshold marks the instance as the element kernel would (bit 2
+// without the fallback), a combine as the sweep would (bit 4).
+template <typename S, class E, int LW>
+__global__ __launch_bounds__(E::NT, combine_min_waves<E>()) void k_chunk_mid_elem(Plan p, In<S> in, S* ws,
+                                                                                  int32_t* status) {
+    static_assert(!E::BIG && LW > 0, "wavefront engine, leaf form");
+    __shared__ Lds<E> L;
+    const int64_t b = blockIdx.x;
+    const E e(unit_tid<E::NT>());
+    const int N = p.N, n = p.n, nn = n * n;
+    const Ptr<S> P(p, in);
+    S* suf = ws + b * p.stride + p.o_suf;
+    S* tree = ws + b * p.stride + p.o_tree;
+    {
+        S* out = suf + (int64_t)suffix_id(p.rt, 0, N) * p.srec;
+        coop_copy<E::NT>(out, P.Q(b, N), nn);
+        coop_copy<E::NT>(out + nn, P.q(b, N), n);
+    }
+    bool okc_all = true, okR_all = true;
+    typename E::T kc_max = 0, kR_max = 0;
+    typename E::T pcar = 0;
+    for (int k = N - 1; k >= 0; --k) {
+        S* out = suf + (int64_t)suffix_id(p.rt, 0, k) * p.srec;
+        bool okc, okR;
+        typename E::T kc, kR;
+        leaf_elem_combine<E, LW>(e, L, p, P, b, k, tree + (int64_t)(p.rt.off[0] + k) * p.rec + 2 * nn,
+                                 k == N - 1 ? P.Q(b, N) : (const S*)nullptr, P.q(b, N), out, out + nn, okc, kc, okR,
+                                 kR, &pcar);
+        okc_all = okc_all && okc;
+        okR_all = okR_all && okR;
+        if (!(kc <= kc_max)) kc_max = kc;
+        if (!(kR <= kR_max)) kR_max = kR;
+        E::sync();
+    }
+    fb_flag<E::NT>(p, okR_all, kR_max, b, status, 2);
+    fb_flag<E::NT>(p, okc_all, kc_max, b, status, 4);
 }
 
 // phase 3: the other leaves of every chunk, one task unit per chunk (LW > 0:

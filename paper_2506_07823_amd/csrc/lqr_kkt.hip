@@ -139,6 +139,12 @@ Plan make_plan(int64_t batch, int N, int n, int m, size_t esize, const lqr_opts&
     // chunk length 1 and a sweep of the terminal element only: every leaf
     // is combined in the leaf form, none reads its C
     p.noC = p.leafv && p.chunk == 1 && p.tail == N ? 1 : 0;
+    // and then the sweep builds each leaf itself where V' and W_M fit the
+    // two halves of one LDS slot (2 ceil(m/8) <= the tile's blocks)
+    {
+        const int lw = m <= 8 ? 1 : 2, ts = pick_ts(n, m, tun);
+        p.fuse_elem = p.noC && ts != kBigTS && 2 * lw <= ts ? 1 : 0;
+    }
     if (big) {
         if (p.fused == 2) p.fused = 1;   // the one-launch solve is a wavefront-engine form
         const int64_t d = n > m ? n : m;

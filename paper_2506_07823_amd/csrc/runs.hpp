@@ -136,6 +136,9 @@ struct Work {
     // (V'P2, V'P2V, the m x m factorization and solve, P2 - U'U, M A1,
     // A1'(M A1) at their symmetric/triangular cost)
     double leaf_b() const { return es * (2 * n * n + 2 * n + n * m + srec + n); }
+    // a stage's inputs (A, B, Q, R, M, c, q, r): what a sweep that builds its
+    // leaves reads per step besides the suffix it writes
+    double elem_in_b() const { return es * (2 * n * n + 2 * n * m + m * m + 2 * n + m); }
     double leaf_min() const { return 3 * n * n * n + 3 * n * n * m + 2 * n * m * m + m * m * m / 3; }
     double pol_f() const { return 6 * n * n * m + 4 * n * m * m + m * m * m / 3; }
     double pol_b() const { return es * (n * n + 2 * n * m + m * m + 2 * n + m + srec + n * m + m + m * m + frec); }
@@ -247,11 +250,14 @@ int run_scan(const Plan& p, hipStream_t s, const In<S>& in, const Out<S>& out, S
     int32_t* st = out.status;
     LCHK(launch_nt(256, F_CLEAR, 0, 4.0 * Bi, k_clear<int32_t>, (Bi + 255) / 256, s, st, Bi));
     // a1: elements
-    LCHK(with_mb<TS>(p.m, [&](auto mb) {
-        constexpr int MB = decltype(mb)::value;
-        return launch_nt(NT, F_ELEM, B * N * w.elem_f(), B * N * w.elem_b(), k_element<S, E, MB>,
-                         task_grid<E>(p, Bi * (N + 1)), s, p, in, ws, st);
-    }));
+    // (the chunk-1 sweep that builds its leaves itself needs no element launch)
+    if (!p.fuse_elem) {
+        LCHK(with_mb<TS>(p.m, [&](auto mb) {
+            constexpr int MB = decltype(mb)::value;
+            return launch_nt(NT, F_ELEM, B * N * w.elem_f(), B * N * w.elem_b(), k_element<S, E, MB>,
+                             task_grid<E>(p, Bi * (N + 1)), s, p, in, ws, st);
+        }));
+    }
     // a3: reverse scan
     if (p.sched == 0) {
         // balanced tree: up-sweep, root, down-sweep
@@ -293,6 +299,21 @@ int run_scan(const Plan& p, hipStream_t s, const In<S>& in, const Out<S>& out, S
                 LCHK(launch_w(NT, F_DOWN, u * w.cheap_f(), u * w.cheap_b(), u * w.cheap_min(), k_down<S, E>, Bi * h,
                               s, p, ws, l, st));
             }
+        } else if (p.fuse_elem) {
+            // chunk length 1, leaves built in the sweep: one launch for the
+            // whole reverse scan (elements included)
+            const double u = B * N;
+            LCHK(with_lw<TS>(p, [&](auto lw) {
+                constexpr int LW = decltype(lw)::value;
+                if constexpr (LW > 0 && 2 * LW <= TS) {
+                    return launch_w(NT, F_CHUNK_MID, u * (w.cheap_f() + w.elem_f()),
+                                    u * (w.elem_in_b() + w.es * p.srec) + B * w.es * 2 * p.srec,
+                                    u * (w.leaf_min() + w.elem_f()), k_chunk_mid_elem<S, E, LW>, Bi, s, p, in, ws,
+                                    st);
+                } else {
+                    return (int)fail(LQR_EUNSUPPORTED, "leaf-building sweep planned for an unsupported shape");
+                }
+            }));
         } else {
             // chunked: chunk aggregates beside the sweep, suffixes at the
             // chunk starts, then the other leaves of every chunk
