@@ -657,18 +657,17 @@ __device__ __forceinline__ void combine(const E& e, Lds<E>& L, int n, const S* e
 // V' (m x n, row-major).  P2 == nullptr: the suffix is the one the previous
 // call left in slot sA and *carry (the carry convention of combine).
 // ---------------------------------------------------------------------------
-// The combine proper: V' staged in the first MB row blocks of sX, P2 in sA,
-// the leaf's A1 (tile), b1, p1 (lane vectors) and P1 given (LATE_P1: loaded
-// from P1g after the factorization, whose latency it then overlaps; else
-// already in tP1, lower triangle).
-template <class E, int MB, bool LATE_P1, typename S>
-__device__ __forceinline__ void leaf_core(const E& e, Lds<E>& L, int n, int m, typename E::Tile& tA1,
-                                          typename E::Tile& tP1, const S* P1g, typename E::T b1, typename E::T p1,
-                                          typename E::T p2, S* outP, S* outp, bool& okp, typename E::T& kappa,
-                                          typename E::T* carry) {
+// The combine proper: V' staged in the first MB row blocks of sX (the rows
+// past them are left as they are), P2 in sA, the leaf's A1 (tile), b1, p1
+// (lane vectors); get_p1(tile) forms the leaf's P1 (lower triangle) after
+// the factorization, whose latency its loads then overlap.
+template <class E, int MB, typename S, class GetP1>
+__device__ __forceinline__ void leaf_core(const E& e, Lds<E>& L, int n, int m, typename E::Tile& tA1, GetP1&& get_p1,
+                                          typename E::T b1, typename E::T p1, typename E::T p2, S* outP, S* outp,
+                                          bool& okp, typename E::T& kappa, typename E::T* carry) {
     using T = typename E::T;
     static_assert(MB >= 1 && MB < E::TS, "m spans fewer row blocks than the order");
-    typename E::Tile tM, tS;
+    typename E::Tile tM, tS, tP1;
     typename E::Tile TU[1];
     e.from_lds(tM, L.sA);                           // P2
     e.zero(TU[0]);
@@ -683,11 +682,11 @@ __device__ __forceinline__ void leaf_core(const E& e, Lds<E>& L, int n, int m, t
     e.add_identity(tS, m);
     T dl, dmin, dmax;
     const bool ok = e.template chol<1, MB>(tS, m, L.cb, dl, w, dmin, dmax);        // L_S; w = L_S^{-1} V' z
-    e.to_lds(tS, L.sX);                             // sX = L_S
+    e.template to_lds_rows<MB>(tS, L.sX);           // sX = L_S (its MB row blocks)
     wg_sync();
     T nov[1];
     e.template trsm<true, 1, 0, MB>(L.sX, dl, m, TU, nov, L.rb);                    // U = L_S^{-1} V' P2
-    if constexpr (LATE_P1) e.load(tP1, P1g, n, n, n);
+    get_p1(tP1);
     e.to_lds(TU[0], L.sA);                          // sA = U
     wg_sync();
     e.template gemm_sub<true, false, true>(tM, L.sA, L.sA, m);                      // P2 - U'U (lower)
@@ -720,7 +719,7 @@ __device__ __forceinline__ void leaf_combine(const E& e, Lds<E>& L, int n, int m
                                              typename E::T& kappa, typename E::T* carry) {
     using T = typename E::T;
     const int nn = n * n;
-    typename E::Tile tA1, tP1;
+    typename E::Tile tA1;
     e.load(tA1, e1, n, n, n);                       // its latency overlaps the products
     const T b1 = e.vload(e1 + 3 * nn, n);
     const T p1 = e.vload(e1 + 3 * nn + n, n);
@@ -732,7 +731,8 @@ __device__ __forceinline__ void leaf_combine(const E& e, Lds<E>& L, int n, int m
     }
     const T p2 = P2 ? e.vload(p2v, n) : *carry;
     wg_sync();
-    leaf_core<E, MB, true>(e, L, n, m, tA1, tP1, e1 + 2 * nn, b1, p1, p2, outP, outp, okp, kappa, carry);
+    leaf_core<E, MB>(e, L, n, m, tA1, [&](typename E::Tile& t) { e.load(t, e1 + 2 * nn, n, n, n); }, b1, p1, p2,
+                     outP, outp, okp, kappa, carry);
 }
 
 // The same step with the leaf built in place from the stage inputs
@@ -740,15 +740,14 @@ __device__ __forceinline__ void leaf_combine(const E& e, Lds<E>& L, int n, int m
 // L_R^{-1} [B'; M'], w_r = L_R^{-1} r, At = A - W_B'W_M, Pt = Q - W_M'W_M,
 // bt = c - W_B'w_r, pt = q - W_M'w_r, V' = W_B): W_B and W_M take the two
 // halves of slot sX, sA keeps the suffix, At, bt, pt stay in registers, and
-// Pt waits in the leaf's P slot (ws_P1: stored and read back by the same
-// lanes, so it stays in the cache) until the combine's last product, as in
-// leaf_combine.  The same arithmetic in the same order as the element
-// kernel followed by leaf_combine.
+// Pt is formed where the combine needs it, from W_M, which the combine
+// leaves in place until then.  The same arithmetic in the same order as
+// the element kernel followed by leaf_combine.
 template <class E, int MB, typename S>
 __device__ __forceinline__ void leaf_elem_combine(const E& e, Lds<E>& L, const Plan& p, const Ptr<S>& P, int64_t b,
-                                                  int k, S* ws_P1, const S* P2, const S* p2v, S* outP, S* outp,
-                                                  bool& okp, typename E::T& kappa, bool& okR,
-                                                  typename E::T& kappaR, typename E::T* carry) {
+                                                  int k, const S* P2, const S* p2v, S* outP, S* outp, bool& okp,
+                                                  typename E::T& kappa, bool& okR, typename E::T& kappaR,
+                                                  typename E::T* carry) {
     using T = typename E::T;
     static_assert(2 * MB * E::G <= E::NP, "W_B and W_M share one slot");
     const int n = p.n, m = p.m;
@@ -771,20 +770,23 @@ __device__ __forceinline__ void leaf_elem_combine(const E& e, Lds<E>& L, const P
     }
     e.template to_lds_rows<MB>(W[0], L.sX);         // V' = W_B
     e.template to_lds_rows<MB>(W[1], sW);           // W_M
-    typename E::Tile tA1, tP1;
+    typename E::Tile tA1;
     e.load(tA1, P.A(b, k), n, n, n);
-    e.load(tP1, P.Q(b, k), n, n, n);
     const T cpre = e.vload(P.c(b, k), n), qpre = e.vload(P.q(b, k), n);
     if (P2) e.g2s_batched(L.sA, P2, n, n, n);       // sA = P2
     const T p2 = P2 ? e.vload(p2v, n) : *carry;
     wg_sync();
     e.template gemm_sub<true, false>(tA1, L.sX, sW, m);                             // At
-    e.template gemm_sub<true, false, true>(tP1, sW, sW, m);                         // Pt (lower)
-    e.store(tP1, ws_P1, n, n, n);
     const T b1 = cpre - e.template matvec<true>(L.sX, L.vb, vv[0], m, n);           // bt
     const T p1 = qpre - e.template matvec<true>(sW, L.vb, vv[0], m, n);             // pt
     wg_sync();
-    leaf_core<E, MB, true>(e, L, n, m, tA1, tP1, (const S*)ws_P1, b1, p1, p2, outP, outp, okp, kappa, carry);
+    leaf_core<E, MB>(
+        e, L, n, m, tA1,
+        [&](typename E::Tile& t) {
+            e.load(t, P.Q(b, k), n, n, n);
+            e.template gemm_sub<true, false, true>(t, sW, sW, m);                   // Pt (lower)
+        },
+        b1, p1, p2, outP, outp, okp, kappa, carry);
 }
 
 template <typename S, class E>
@@ -1085,7 +1087,6 @@ __global__ __launch_bounds__(E::NT, combine_min_waves<E>()) void k_chunk_mid_ele
     const int N = p.N, n = p.n, nn = n * n;
     const Ptr<S> P(p, in);
     S* suf = ws + b * p.stride + p.o_suf;
-    S* tree = ws + b * p.stride + p.o_tree;
     {
         S* out = suf + (int64_t)suffix_id(p.rt, 0, N) * p.srec;
         coop_copy<E::NT>(out, P.Q(b, N), nn);
@@ -1098,9 +1099,8 @@ __global__ __launch_bounds__(E::NT, combine_min_waves<E>()) void k_chunk_mid_ele
         S* out = suf + (int64_t)suffix_id(p.rt, 0, k) * p.srec;
         bool okc, okR;
         typename E::T kc, kR;
-        leaf_elem_combine<E, LW>(e, L, p, P, b, k, tree + (int64_t)(p.rt.off[0] + k) * p.rec + 2 * nn,
-                                 k == N - 1 ? P.Q(b, N) : (const S*)nullptr, P.q(b, N), out, out + nn, okc, kc, okR,
-                                 kR, &pcar);
+        leaf_elem_combine<E, LW>(e, L, p, P, b, k, k == N - 1 ? P.Q(b, N) : (const S*)nullptr, P.q(b, N), out,
+                                 out + nn, okc, kc, okR, kR, &pcar);
         okc_all = okc_all && okc;
         okR_all = okR_all && okR;
         if (!(kc <= kc_max)) kc_max = kc;
