@@ -238,6 +238,30 @@ def test_chunked_leaf_form_in_a_graph_replays_identically():
         L.set_tuning(count, N, n, m, torch.float32, clear=True)
 
 
+def test_leaf_building_sweep_status_bits():
+    """At a shape whose chunk-1 sweep builds its leaves itself (n = 40,
+    m = 8): an R_k of condition 1e7 sends only its instance to the FP64 redo
+    (bit 8), which meets the oracle; with the fallback off an indefinite R_k
+    sets bit 2 of only its instance."""
+    N, n, m, count = 20, 40, 8, 4
+    b = synth.gen_batch(lambda i: synth.gen_c1_like(N, n, m, [969, i], dt=0.01), count, np.float32)
+    sched = _chunked(1, 1, True)
+    ill = {k: v.copy() for k, v in b.items()}
+    ill["R"][2, 7] = np.diag([1e-7] + [1.0] * (m - 1))
+    say("[leaf-building sweep, ill-conditioned R]")
+    out = _pinned(ill, np.float32, sched, want_resid=True, refine=1)
+    assert out["status"][2] == 8 and not out["status"][[0, 1, 3]].any(), out["status"]
+    errs, res = oracle_check(ill, out, 2, as_f32=True)
+    say(f"  redone instance: elem err {errs}, resid gpu {out['resid'][2]:.2e} oracle {res:.2e}")
+    assert out["resid"][2] <= RESID_TOL and res <= RESID_TOL
+    bad = {k: v.copy() for k, v in b.items()}
+    bad["R"][1, 3] = -100.0 * np.eye(m)
+    say("[leaf-building sweep, indefinite R, fallback off]")
+    out = _pinned(bad, np.float32, sched, fallback=False)
+    assert out["status"][1] & 2 and not out["status"][1] & 8, out["status"]
+    assert not out["status"][[0, 2, 3]].any(), out["status"]
+
+
 def test_chunked_mappings_rejected():
     import torch
     import paper_2506_07823_amd as L
