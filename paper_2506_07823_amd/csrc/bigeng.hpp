@@ -139,7 +139,7 @@ struct BigEng {
     }
 
     // (the wavefront engine's prefetching form; here the same product)
-    template <bool TR, typename S>
+    template <bool TR, bool WIDE = false, typename S>
     __device__ __forceinline__ T gmv_pf(const S* M, int rows, int cols, int ld, const T* vb) const {
         return gmv_v<TR>(M, rows, cols, ld, vb);
     }

@@ -430,11 +430,13 @@ struct Eng {
     // its stages: nothing else on the SIMD hides their load latency): the
     // loads go out in groups (8 column entries, or 5 16-byte row pieces) and
     // the FMAs follow in gmv_v's order, so the result is the same to the bit
-    template <bool TR, typename S>
+    // WIDE: one group for the whole matrix (one wait per product; about 40
+    // more registers in flight), for sweeps whose register budget has room
+    template <bool TR, bool WIDE = false, typename S>
     __device__ __forceinline__ T gmv_pf(const S* M, int rows, int cols, int ld, const T* vb) const {
         T s = T(0);
         if (TR) {
-            constexpr int U = 8;
+            constexpr int U = WIDE ? NP : 8;
             // the group loop stays a loop: unrolled, the compiler would
             // hoist every group's loads together (registers past the
             // sweep's budget)
@@ -453,7 +455,7 @@ struct Eng {
         constexpr int V = 16 / (int)sizeof(S);
         if ((cols % V) == 0 && (ld % V) == 0 && ((uintptr_t)M & 15) == 0) {
             using S4 = typename std::conditional<sizeof(S) == 4, float4, double2>::type;
-            constexpr int NV4 = (NP + V - 1) / V, U = 5;
+            constexpr int NV4 = (NP + V - 1) / V, U = WIDE ? NV4 : 5;
             const S4* r4 = reinterpret_cast<const S4*>(M + (int64_t)lg * ld);
             const int nv = cols / V;
 #pragma unroll 1

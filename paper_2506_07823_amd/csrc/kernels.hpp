@@ -1679,7 +1679,10 @@ __global__ __launch_bounds__(E::NT) void k_ref_kff(Plan p, In<S> in, S* ws) {
 
 // ---------------------------------------------------------------------------
 // Sequential vector passes (plan.fwdseq): one task unit per instance walks
-// the stages in order and needs only the closed-loop leaf maps, so the
+// the stages in order (the forward sweep with each product's whole matrix of
+// loads in flight at once, gmv_pf WIDE, so its chain waits once per product;
+// the backward sweep's four products in groups, since whole ones there would
+// be hoisted together past the register file) and needs only the closed-loop leaf maps, so the
 // forward tree's map products (2n^3 per node) are never formed.  For a batch
 // that fills the GPU this trades the O(log N) depth of the forward scan for
 // O(N n^2) work; the autotuner weighs the two.
@@ -1716,7 +1719,7 @@ __device__ __forceinline__ void fwd_seq_body(LT& L, const Plan& p, S* ws, const 
         // x_k staged once for its three products (P_k, K_k, Abar_k), whose
         // loads then go out together
         e.stage_vec(L.vb[0], x);
-        const T lam = e.template gmv_pf<false>(Pk, n, n, n, L.vb[0]) + e.vload(pv, n);
+        const T lam = e.template gmv_pf<false, true>(Pk, n, n, n, L.vb[0]) + e.vload(pv, n);
         S* xo = out.x + (b * (N + 1) + k) * n;
         S* lo = out.lam + (b * (N + 1) + k) * n;
         if (e.lg < n) {
@@ -1728,7 +1731,7 @@ __device__ __forceinline__ void fwd_seq_body(LT& L, const Plan& p, S* ws, const 
         }
         if (k == N) break;
         const S* kf = inst + (ALT ? p.o_kffp : p.o_kff) + (int64_t)k * m;
-        const T u = e.template gmv_pf<false>(inst + p.o_K + (int64_t)k * m * n, m, n, n, L.vb[0]) + e.vload(kf, m);
+        const T u = e.template gmv_pf<false, true>(inst + p.o_K + (int64_t)k * m * n, m, n, n, L.vb[0]) + e.vload(kf, m);
         S* uo = out.u + (b * N + k) * m;
         if (e.lg < m) {
             const T uv = ADD ? T(uo[e.lg]) + u : u;
@@ -1736,7 +1739,7 @@ __device__ __forceinline__ void fwd_seq_body(LT& L, const Plan& p, S* ws, const 
             fin = fin && finite_(uv);
         }
         const S* leaf = inst + p.o_ftree + (int64_t)k * p.frec;
-        x = e.template gmv_pf<false>(leaf, n, n, n, L.vb[0]) + e.vload(leaf + nn, n);
+        x = e.template gmv_pf<false, true>(leaf, n, n, n, L.vb[0]) + e.vload(leaf + nn, n);
     }
     if (!E::all(fin)) set_status<E::NT>(out.status, b, 1);
 }
