@@ -63,18 +63,20 @@ def test_chunked_fp64_meets_oracle(N, n, m, chunk, sweep, fwd_seq):
 
 # Shapes whose chunked sweeps combine each leaf through its rank-m factor
 # V = B R^{-1/2} (orders 17..64 with m <= 16): factors of one and two row
-# blocks, tile orders 3, 5, 6 and 8, m = 1 and m = 16 at the class edges.
+# blocks, tile orders 3, 4, 5, 6 and 8, m = 1 and m = 16 at the class edges,
+# a one-stage horizon (the sweep's single step starts from Q_N).
 # Schedules: chunk 1 (every chunk-start suffix in the leaf form), chunks of
 # 4 behind a 3-leaf sweep (the chunk interiors in the leaf form), chunk 1
 # behind a 5-leaf sweep (the leaf form takes over a suffix the general form
 # stored), chunks of 5 with a short last chunk.
-LEAF_SHAPES = [(9, 17, 16), (20, 24, 1), (12, 40, 8), (7, 64, 16), (30, 50, 5)]
+LEAF_SHAPES = [(9, 17, 16), (20, 24, 1), (12, 40, 8), (7, 64, 16), (30, 50, 5), (1, 32, 16), (3, 17, 8)]
 LEAF_SCHEDS = [(1, 1), (4, 3), (1, 5), (5, 1)]
 
 
 @pytest.mark.parametrize("N,n,m", LEAF_SHAPES)
 @pytest.mark.parametrize("chunk,sweep", LEAF_SCHEDS)
 def test_chunked_leaf_form_fp64(N, n, m, chunk, sweep):
+    sweep = min(sweep, N + 1)
     batch = synth.gen_batch(lambda i: synth.gen_rand(N, n, m, seed=[966, N, n, m, i]), 3, np.float64)
     say(f"[chunked leaf form fp64] N={N} n={n} m={m} chunk={chunk} sweep={sweep}")
     out = _pinned(batch, np.float64, _chunked(chunk, sweep, True))
