@@ -1681,8 +1681,9 @@ __global__ __launch_bounds__(E::NT) void k_ref_kff(Plan p, In<S> in, S* ws) {
 // Sequential vector passes (plan.fwdseq): one task unit per instance walks
 // the stages in order (the forward sweep with each product's whole matrix of
 // loads in flight at once, gmv_pf WIDE, so its chain waits once per product;
-// the backward sweep's four products in groups, since whole ones there would
-// be hoisted together past the register file) and needs only the closed-loop leaf maps, so the
+// in the backward sweep only the first product, since more whole ones there
+// are hoisted together past the register file) and needs only the
+// closed-loop leaf maps, so the
 // forward tree's map products (2n^3 per node) are never formed.  For a batch
 // that fills the GPU this trades the O(log N) depth of the forward scan for
 // O(N n^2) work; the autotuner weighs the two.
@@ -1777,7 +1778,7 @@ __device__ __forceinline__ void bwd_seq_body(LT& L, const Plan& p, const In<S>& 
         // first, then (B' v, Abar' v), so each group's loads go out together
         e.stage_vec(L.vb[0], cpv);
         e.stage_vec(L.vb[1], rpv);
-        const T v = pn + e.template gmv_pf<false>(Pn, n, n, n, L.vb[0]);
+        const T v = pn + e.template gmv_pf<false, true>(Pn, n, n, n, L.vb[0]);
         const T kr = e.template gmv_pf<true>(inst + p.o_K + (int64_t)k * m * n, m, n, n, L.vb[1]);
         e.stage_vec(L.vb[0], v);
         const T h = e.template gmv_pf<true>(P.B(b, k), n, m, m, L.vb[0]) + rpv;
