@@ -55,7 +55,7 @@ LAT_REPLAYS = 200   # graph replays of the dedicated p50/p99 loops
 # FETCH_SIZE / WRITE_SIZE runs, calibrated against a copy of known size;
 # valid only for the kernel and launch sources they were taken on (hash of
 # every source file of the library)
-TRAFFIC = {"kernel": "chunk_mid", "src_hash": "c32c8e377441b15a", "bytes_per_launch": 9.311e9,
+TRAFFIC = {"kernel": "chunk_mid", "src_hash": "a5cc678d0e1ffec9", "bytes_per_launch": 9.311e9,
            "note": "rocprofv3 FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (factors from a 1 GiB device copy), "
                    "4 eager one-stream dispatches of k_chunk_mid_elem (leaf-building sweep) at batch 4096, "
                    "chunk 1: 7.077 + 2.234 GB per launch"}
