@@ -86,7 +86,7 @@ def test_chunked_leaf_form_fp64(N, n, m, chunk, sweep):
     assert res.max() <= 1e-11
 
 
-@pytest.mark.parametrize("N,n,m", [(60, 24, 8), (50, 48, 16), (40, 64, 3)])
+@pytest.mark.parametrize("N,n,m", [(60, 24, 8), (50, 48, 16), (40, 64, 3), (60, 20, 12)])
 @pytest.mark.parametrize("chunk,sweep", [(1, 1), (4, 3)])
 def test_chunked_leaf_form_fp32_refined(N, n, m, chunk, sweep):
     batch = synth.gen_batch(lambda i: synth.gen_c1_like(N, n, m, [967, N, n, m, i], dt=0.01), 5, np.float32)
